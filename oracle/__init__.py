@@ -1,0 +1,186 @@
+"""CPU FP64 oracle for the P3T distant-force path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package. The product library never calls it, and the two share no
+code: this side is plain C (``pbh_oracle.c``, built with ``-ffp-contract=off``)
+driven through ctypes.
+
+Functions follow Arnold, Baumgardt & Wang (2021), Section 2.1 (the P3T force
+split, eq. fi and the changeover function eq. duncan) and Section 2.4 (the
+Barnes-Hut tree with opening angle theta). See ``pbh_oracle.c`` for the exact
+definitions, including the readings taken where the paper is silent.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pbh_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_d = C.c_double
+_i64 = C.c_int64
+_p = C.c_void_p
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (OpenMP, -O2, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-std=c11", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        L.orc_W.restype = _d
+        L.orc_W.argtypes = [_d, _d, _d]
+        L.orc_phiR.restype = _d
+        L.orc_phiR.argtypes = [_d, _d, _d]
+        L.orc_phiR_coeffs.argtypes = [_d, _d, _p, _p]
+        L.orc_direct.argtypes = [_i64, _p, _p, _d, _d, _d, _i64, _p, _p, _p]
+        L.orc_full_direct.argtypes = [_i64, _p, _p, _d, _p, _p]
+        L.orc_nbr_brute.restype = _i64
+        L.orc_nbr_brute.argtypes = [_i64, _p, _d, _p, _p, _i64]
+        L.orc_nbr_cells.restype = _i64
+        L.orc_nbr_cells.argtypes = [_i64, _p, _d, _p, _p, _i64]
+        L.orc_keys.argtypes = [_i64, _p, C.c_int, _p]
+        L.orc_tree.argtypes = [_i64, _p, _p, _d, _d, _d, _d, C.c_int, C.c_int, C.c_int, _p, _p, _p]
+        L.orc_tree_nodes.restype = _i64
+        L.orc_tree_nodes.argtypes = [_i64, _p, _p, C.c_int, C.c_int, _i64, _p, _p, _p]
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a, shape=None) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def W(s: float, r_in: float, r_out: float) -> float:
+    """Changeover weight W = 1 - K of eq. duncan (Section 2.1)."""
+    return lib().orc_W(float(s), float(r_in), float(r_out))
+
+
+def phiR(s: float, r_in: float, r_out: float) -> float:
+    """Regular potential: dPhi_R/ds = W(s)/s^2, Phi_R(s) = -1/s for s >= r_out."""
+    return lib().orc_phiR(float(s), float(r_in), float(r_out))
+
+
+def phiR_coeffs(r_in: float, r_out: float):
+    d = np.zeros(8)
+    g1 = np.zeros(1)
+    lib().orc_phiR_coeffs(float(r_in), float(r_out), _ptr(d), _ptr(g1))
+    return d, float(g1[0])
+
+
+def direct(pos, mass, r_in, r_out, eps, targets=None):
+    """O(N^2) regular acceleration and potential (eq. fi with F_R = total - F_I).
+
+    Returns (acc [n_t,3], pot [n_t]) for all particles or the given targets.
+    """
+    pos = _f64(pos)
+    n = pos.shape[0]
+    mass = _f64(mass, (n,))
+    if targets is None:
+        nt = n
+        tgt = None
+    else:
+        tgt = np.ascontiguousarray(targets, dtype=np.int64)
+        nt = tgt.size
+    acc = np.zeros((nt, 3))
+    pot = np.zeros(nt)
+    lib().orc_direct(n, _ptr(pos), _ptr(mass), float(r_in), float(r_out), float(eps),
+                     nt, None if tgt is None else _ptr(tgt), _ptr(acc), _ptr(pot))
+    return acc, pot
+
+
+def full_direct(pos, mass, eps):
+    """Plain softened gravity (whole force, no changeover)."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    mass = _f64(mass, (n,))
+    acc = np.zeros((n, 3))
+    pot = np.zeros(n)
+    lib().orc_full_direct(n, _ptr(pos), _ptr(mass), float(eps), _ptr(acc), _ptr(pot))
+    return acc, pot
+
+
+def _nbr(fn, pos, r_out):
+    pos = _f64(pos)
+    n = pos.shape[0]
+    off = np.zeros(n + 1, dtype=np.int64)
+    total = fn(n, _ptr(pos), float(r_out), _ptr(off), None, 0)
+    idx = np.zeros(max(total, 1), dtype=np.int32)
+    fn(n, _ptr(pos), float(r_out), _ptr(off), _ptr(idx), total)
+    return off, idx[:total]
+
+
+def nbr_brute(pos, r_out):
+    """Neighbour CSR by brute force: j != i with (dx*dx + dy*dy) + dz*dz < r_out*r_out."""
+    return _nbr(lib().orc_nbr_brute, pos, r_out)
+
+
+def nbr_cells(pos, r_out):
+    """Neighbour CSR from a cell list with cells of side r_out (lists ascending)."""
+    return _nbr(lib().orc_nbr_cells, pos, r_out)
+
+
+def keys(pos, D: int = 21) -> np.ndarray:
+    """Morton keys of one cluster, D bits per dimension."""
+    pos = _f64(pos)
+    k = np.zeros(pos.shape[0], dtype=np.uint64)
+    lib().orc_keys(pos.shape[0], _ptr(pos), int(D), _ptr(k))
+    return k
+
+
+def tree(pos, mass, r_in, r_out, theta, eps, n_leaf=16, n_crit=64, D=21):
+    """CPU Barnes-Hut walk with the same tree, group and opening rules as the GPU.
+
+    Returns (acc, pot, stats) with stats = dict(nodes, leaves, groups, pn, pp_far, pp_near).
+    """
+    pos = _f64(pos)
+    n = pos.shape[0]
+    mass = _f64(mass, (n,))
+    acc = np.zeros((n, 3))
+    pot = np.zeros(n)
+    st = np.zeros(6, dtype=np.int64)
+    lib().orc_tree(n, _ptr(pos), _ptr(mass), float(r_in), float(r_out), float(theta), float(eps),
+                   int(n_leaf), int(n_crit), int(D), _ptr(acc), _ptr(pot), _ptr(st))
+    names = ("nodes", "leaves", "groups", "pn", "pp_far", "pp_near")
+    return acc, pot, dict(zip(names, (int(v) for v in st)))
+
+
+def tree_nodes(pos, mass, n_leaf=16, D=21):
+    """Octree export: (order, ints [nodes,4] = begin,count,nchild,level,
+    doubles [nodes,16] = M, com[3], q[6] (xx,yy,zz,xy,xz,yz), lo[3], hi[3])."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    mass = _f64(mass, (n,))
+    order = np.zeros(n, dtype=np.int64)
+    nn = lib().orc_tree_nodes(n, _ptr(pos), _ptr(mass), int(n_leaf), int(D), 0, _ptr(order), None, None)
+    ib = np.zeros((nn, 4), dtype=np.int64)
+    db = np.zeros((nn, 16))
+    lib().orc_tree_nodes(n, _ptr(pos), _ptr(mass), int(n_leaf), int(D), nn, _ptr(order), _ptr(ib), _ptr(db))
+    return order, ib, db
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())

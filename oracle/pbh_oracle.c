@@ -1,0 +1,798 @@
+/*
+ * pbh_oracle.c -- plain CPU FP64 oracle for the P3T distant-force path.
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library. The product path
+ * (libpbh) never calls into it and shares no code with it.
+ *
+ * Built with -O2 -ffp-contract=off so that every double expression below is
+ * evaluated as written (IEEE round-to-nearest, no fused multiply-add).
+ *
+ * What it computes (Arnold, Baumgardt & Wang 2021, Section 2.1):
+ *   The P3T split divides gravity between the neighbour (irregular) force
+ *   F_I = sum_j m_j K(r_ij) r_ij / r_ij^3 and the regular force
+ *   F_R = (total) - F_I, with the changeover function K of eq. (duncan):
+ *   K = 1 - g(x), g(x) = 35x^4 - 84x^5 + 70x^6 - 20x^7 for 0 <= x < 1,
+ *   x = (r - r_in)/(r_cut - r_in), and K = 1 (0) below r_in (above r_cut).
+ *   Hence the regular acceleration is sum_j m_j W(s) d_ij / s^3 with
+ *   W = 1 - K and d_ij = x_j - x_i (attractive gravity, G = 1).
+ *   Softening enters as s^2 = r^2 + eps^2 (eps = 0 recovers the paper).
+ *   The regular potential Phi_R is the one whose radial derivative is
+ *   W(s)/s^2 and which equals -1/s beyond r_cut; below r_in it is constant.
+ *   The neighbour set of i is { j != i : r_ij^2 < r_cut^2 } (unsoftened).
+ *   In this file r_cut is called r_out.
+ *
+ * Functions:
+ *   orc_W, orc_phiR           the changeover weight and regular potential
+ *   orc_direct                O(N^2) direct sum (all or a subset of targets)
+ *   orc_full_direct           plain softened gravity (no split)
+ *   orc_nbr_brute/orc_nbr_cells neighbour sets, brute force and cell list
+ *   orc_keys                  Morton keys of the octree
+ *   orc_tree                  Barnes-Hut octree walk with the same tree,
+ *                             group and opening rules as the GPU path
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Changeover weight W = 1 - K (Section 2.1, eq. duncan)                     */
+/* ------------------------------------------------------------------------ */
+
+static double g_poly(double x)
+{
+    /* g(x) = 35 x^4 - 84 x^5 + 70 x^6 - 20 x^7 */
+    double x2 = x * x;
+    double x4 = x2 * x2;
+    double x5 = x4 * x;
+    double x6 = x5 * x;
+    double x7 = x6 * x;
+    return 35.0 * x4 - 84.0 * x5 + 70.0 * x6 - 20.0 * x7;
+}
+
+double orc_W(double s, double r_in, double r_out)
+{
+    if (s >= r_out) return 1.0;  /* wholly regular beyond the outer radius */
+    if (s < r_in) return 0.0;    /* wholly irregular inside the inner radius */
+    return g_poly((s - r_in) / (r_out - r_in));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Regular potential Phi_R(s), dPhi_R/ds = W(s)/s^2, Phi_R = -1/s past r_out */
+/*                                                                          */
+/* With D = r_out - r_in, a = r_in/D and t = s/D, g(t - a) = sum_k d_k t^k.  */
+/* Integrating g(t-a)/t^2 term by term gives                                */
+/*   G(t) = -d0/t + d1 ln t + sum_{k=2..7} d_k t^(k-1)/(k-1)                */
+/* and Phi_R(s) = -1/r_out - (G(a+1) - G(s/D)) / D on [r_in, r_out).        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double r_in, r_out, D, a;
+    double d[8];
+    double G1;      /* G(a + 1) */
+    double inner;   /* Phi_R(r_in) */
+    int mode;       /* 0: plain gravity (r_out = 0), 1: step (D = 0), 2: smooth */
+} phir_t;
+
+static double binom(int n, int k)
+{
+    double b = 1.0;
+    for (int i = 1; i <= k; ++i) b = b * (double)(n - k + i) / (double)i;
+    return b;
+}
+
+static double G_of_t(const phir_t* p, double t)
+{
+    double G = 0.0;
+    if (p->d[0] != 0.0) G += -p->d[0] / t;
+    if (p->d[1] != 0.0) G += p->d[1] * log(t);
+    for (int k = 2; k <= 7; ++k) G += p->d[k] * pow(t, (double)(k - 1)) / (double)(k - 1);
+    return G;
+}
+
+static double phir_eval(const phir_t* p, double s)
+{
+    if (p->mode == 0) return -1.0 / s;
+    if (s >= p->r_out) return -1.0 / s;
+    if (p->mode == 1) return -1.0 / p->r_out;  /* W = 0 everywhere below r_out */
+    if (s < p->r_in) return p->inner;
+    return -1.0 / p->r_out - (p->G1 - G_of_t(p, s / p->D)) / p->D;
+}
+
+static void phir_init(phir_t* p, double r_in, double r_out)
+{
+    static const double c[8] = {0, 0, 0, 0, 35.0, -84.0, 70.0, -20.0};
+    memset(p, 0, sizeof(*p));
+    p->r_in = r_in;
+    p->r_out = r_out;
+    p->D = r_out - r_in;
+    if (r_out == 0.0) { p->mode = 0; return; }
+    if (p->D == 0.0) { p->mode = 1; p->inner = -1.0 / r_out; return; }
+    p->mode = 2;
+    p->a = r_in / p->D;
+    /* expand g(t - a) = sum_p c_p (t - a)^p = sum_k d_k t^k */
+    for (int k = 0; k <= 7; ++k) {
+        double dk = 0.0;
+        for (int q = 4; q <= 7; ++q) {
+            if (k > q) continue;
+            double term = c[q] * binom(q, k);
+            for (int e = 0; e < q - k; ++e) term = term * (-p->a);
+            dk += term;
+        }
+        p->d[k] = dk;
+    }
+    p->G1 = G_of_t(p, p->a + 1.0);
+    /* s = r_in takes the smooth branch; for r_in = 0 (a = 0) d0 = d1 = 0 and
+       G is a polynomial, so Phi_R(0) is finite */
+    p->inner = phir_eval(p, r_in);
+}
+
+double orc_phiR(double s, double r_in, double r_out)
+{
+    phir_t p;
+    phir_init(&p, r_in, r_out);
+    return phir_eval(&p, s);
+}
+
+/* Coefficients d_0..d_7 of g(t - a) and G(a+1), for tests. */
+void orc_phiR_coeffs(double r_in, double r_out, double* d8, double* G1)
+{
+    phir_t p;
+    phir_init(&p, r_in, r_out);
+    for (int k = 0; k < 8; ++k) d8[k] = p.d[k];
+    *G1 = p.G1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O(N^2) direct sum of the regular force and potential                      */
+/* ------------------------------------------------------------------------ */
+
+/* One source j acting on target i (j != i): regular acceleration and potential. */
+static void pair_regular(const phir_t* p, double eps2,
+                         double xi, double yi, double zi,
+                         double xj, double yj, double zj, double mj,
+                         double* ax, double* ay, double* az, double* pot)
+{
+    double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double s2 = r2 + eps2;
+    double s = sqrt(s2);
+    double w = orc_W(s, p->r_in, p->r_out);
+    if (p->mode == 0) w = 1.0;
+    if (w != 0.0) {
+        double f = mj * w / (s2 * s);
+        *ax += f * dx;
+        *ay += f * dy;
+        *az += f * dz;
+    }
+    *pot += mj * phir_eval(p, s);
+}
+
+/*
+ * Regular acceleration and potential by direct summation over all sources.
+ * pos: [n][3], mass: [n]. If tgt != NULL only the n_tgt listed targets are
+ * computed and acc/pot are [n_tgt][3] / [n_tgt]; otherwise all n.
+ */
+void orc_direct(int64_t n, const double* pos, const double* mass,
+                double r_in, double r_out, double eps,
+                int64_t n_tgt, const int64_t* tgt, double* acc, double* pot)
+{
+    phir_t p;
+    phir_init(&p, r_in, r_out);
+    double eps2 = eps * eps;
+    int64_t nt = tgt ? n_tgt : n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t i = tgt ? tgt[t] : t;
+        double ax = 0, ay = 0, az = 0, ph = 0;
+        double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            pair_regular(&p, eps2, xi, yi, zi, pos[3 * j], pos[3 * j + 1], pos[3 * j + 2],
+                         mass[j], &ax, &ay, &az, &ph);
+        }
+        acc[3 * t] = ax;
+        acc[3 * t + 1] = ay;
+        acc[3 * t + 2] = az;
+        pot[t] = ph;
+    }
+}
+
+/* Plain softened gravity (the whole force, no changeover), for split checks. */
+void orc_full_direct(int64_t n, const double* pos, const double* mass, double eps,
+                     double* acc, double* pot)
+{
+    double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double ax = 0, ay = 0, az = 0, ph = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = pos[3 * j] - pos[3 * i];
+            double dy = pos[3 * j + 1] - pos[3 * i + 1];
+            double dz = pos[3 * j + 2] - pos[3 * i + 2];
+            double s2 = dx * dx + dy * dy + dz * dz + eps2;
+            double s = sqrt(s2);
+            double f = mass[j] / (s2 * s);
+            ax += f * dx;
+            ay += f * dy;
+            az += f * dz;
+            ph += -mass[j] / s;
+        }
+        acc[3 * i] = ax;
+        acc[3 * i + 1] = ay;
+        acc[3 * i + 2] = az;
+        pot[i] = ph;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbour sets: j != i with ((dx*dx + dy*dy) + dz*dz) < r_out*r_out       */
+/* ------------------------------------------------------------------------ */
+
+static int is_nbr(const double* pos, int64_t i, int64_t j, double rout2)
+{
+    double dx = pos[3 * j] - pos[3 * i];
+    double dy = pos[3 * j + 1] - pos[3 * i + 1];
+    double dz = pos[3 * j + 2] - pos[3 * i + 2];
+    double r2 = dx * dx + dy * dy + dz * dz;
+    return r2 < rout2;
+}
+
+/*
+ * Brute force. Writes counts to off[0..n] as a CSR offset array (off[0] = 0)
+ * and, if idx != NULL and the total fits in cap, the ascending neighbour
+ * indices of each particle. Returns the total number of entries.
+ */
+int64_t orc_nbr_brute(int64_t n, const double* pos, double r_out,
+                      int64_t* off, int32_t* idx, int64_t cap)
+{
+    double rout2 = r_out * r_out;
+    off[0] = 0;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = 0;
+        for (int64_t j = 0; j < n; ++j)
+            if (j != i && is_nbr(pos, i, j, rout2)) ++c;
+        off[i + 1] = c;
+    }
+    for (int64_t i = 0; i < n; ++i) off[i + 1] += off[i];
+    int64_t total = off[n];
+    if (idx && total <= cap) {
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t w = off[i];
+            for (int64_t j = 0; j < n; ++j)
+                if (j != i && is_nbr(pos, i, j, rout2)) idx[w++] = (int32_t)j;
+        }
+    }
+    return total;
+}
+
+/* Cell list with cells of side r_out: candidates come from the 27 cells around i. */
+typedef struct { int64_t c[3]; int64_t i; } cellrec;
+
+static int cell_cmp(const void* pa, const void* pb)
+{
+    const cellrec* a = (const cellrec*)pa;
+    const cellrec* b = (const cellrec*)pb;
+    for (int d = 0; d < 3; ++d) {
+        if (a->c[d] < b->c[d]) return -1;
+        if (a->c[d] > b->c[d]) return 1;
+    }
+    return (a->i < b->i) ? -1 : (a->i > b->i);
+}
+
+static int cell_key_cmp(const int64_t* c, const cellrec* r)
+{
+    for (int d = 0; d < 3; ++d) {
+        if (c[d] < r->c[d]) return -1;
+        if (c[d] > r->c[d]) return 1;
+    }
+    return 0;
+}
+
+/* first record whose cell is >= c */
+static int64_t cell_lower(const cellrec* recs, int64_t n, const int64_t* c)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (cell_key_cmp(c, &recs[mid]) > 0) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+static int cmp_i32(const void* a, const void* b)
+{
+    int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    return (x > y) - (x < y);
+}
+
+int64_t orc_nbr_cells(int64_t n, const double* pos, double r_out,
+                      int64_t* off, int32_t* idx, int64_t cap)
+{
+    off[0] = 0;
+    if (!(r_out > 0.0) || n < 2) {
+        for (int64_t i = 0; i < n; ++i) off[i + 1] = 0;
+        return 0;
+    }
+    double lo[3] = {pos[0], pos[1], pos[2]};
+    for (int64_t i = 1; i < n; ++i)
+        for (int d = 0; d < 3; ++d)
+            if (pos[3 * i + d] < lo[d]) lo[d] = pos[3 * i + d];
+    cellrec* recs = (cellrec*)malloc(sizeof(cellrec) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int d = 0; d < 3; ++d) recs[i].c[d] = (int64_t)floor((pos[3 * i + d] - lo[d]) / r_out);
+        recs[i].i = i;
+    }
+    qsort(recs, (size_t)n, sizeof(cellrec), cell_cmp);
+    double rout2 = r_out * r_out;
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            for (int64_t i = 0; i < n; ++i) off[i + 1] += off[i];
+            if (!idx || off[n] > cap) break;
+        }
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t ci[3];
+            for (int d = 0; d < 3; ++d) ci[d] = (int64_t)floor((pos[3 * i + d] - lo[d]) / r_out);
+            int64_t cnt = 0;
+            int64_t w = pass ? off[i] : 0;
+            for (int ox = -1; ox <= 1; ++ox)
+                for (int oy = -1; oy <= 1; ++oy)
+                    for (int oz = -1; oz <= 1; ++oz) {
+                        int64_t c[3] = {ci[0] + ox, ci[1] + oy, ci[2] + oz};
+                        for (int64_t k = cell_lower(recs, n, c); k < n && cell_key_cmp(c, &recs[k]) == 0; ++k) {
+                            int64_t j = recs[k].i;
+                            if (j != i && is_nbr(pos, i, j, rout2)) {
+                                if (pass) idx[w++] = (int32_t)j; else ++cnt;
+                            }
+                        }
+                    }
+            if (pass == 0) off[i + 1] = cnt;
+            else qsort(idx + off[i], (size_t)(off[i + 1] - off[i]), sizeof(int32_t), cmp_i32);
+        }
+    }
+    free(recs);
+    return off[n];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Barnes-Hut octree (Section 2.4 uses a GPU Barnes-Hut tree with opening   */
+/* angle theta; theta = 0 reduces it to direct summation).                  */
+/*                                                                          */
+/* Tree definition shared with the GPU path (written independently there):  */
+/*  keys   L = max extent of the cluster's bounding box (1 if 0);           */
+/*         i_d = min(floor((x_d - lo_d) * (2^D / L)), 2^D - 1);             */
+/*         key = x,y,z bits interleaved, x most significant per level.      */
+/*  order  particles sorted by (key, original index).                       */
+/*  nodes  the root holds all particles; a node at level l < D with more    */
+/*         than n_leaf particles has one child per distinct octant digit    */
+/*         at level l+1 (in key order); nodes are numbered breadth first.   */
+/*  moments bottom-up: a leaf combines its particles, an inner node its     */
+/*         children, in order: M = sum m; COM = sum m x / M;                */
+/*         Q_ab = sum [Q_c,ab + m (3 d_a d_b - |d|^2 delta_ab)], d = x-COM; */
+/*         tight box lo/hi; l = max extent; delta = |COM - box centre|.     */
+/*  groups consecutive runs of n_crit sorted particles; tight group box.    */
+/*  walk   per group and node: dbox2 = squared distance between the group   */
+/*         box and the node box; near if dbox2 < r_out^2 or dbox2 == 0;     */
+/*         accept (multipole) if not near, theta > 0 and the squared        */
+/*         distance from the group box to COM exceeds (l/theta + delta)^2;  */
+/*         otherwise open: a leaf gives particle-particle interactions      */
+/*         (with the changeover when near), an inner node its children.     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t begin, count;
+    int64_t first_child;
+    int32_t nchild, level;
+    double M, com[3], q[6]; /* q: xx, yy, zz, xy, xz, yz */
+    double lo[3], hi[3];
+    double rcrit2;
+} onode_t;
+
+static uint64_t spread3(uint64_t v, int D)
+{
+    uint64_t out = 0;
+    for (int b = 0; b < D; ++b) out |= ((v >> b) & 1ULL) << (3 * b);
+    return out;
+}
+
+/* Morton keys of one cluster with D bits per dimension (D <= 21). */
+void orc_keys(int64_t n, const double* pos, int D, uint64_t* keys)
+{
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) lo[d] = hi[d] = pos[d];
+    for (int64_t i = 1; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            double v = pos[3 * i + d];
+            if (v < lo[d]) lo[d] = v;
+            if (v > hi[d]) hi[d] = v;
+        }
+    double L = 0.0;
+    for (int d = 0; d < 3; ++d)
+        if (hi[d] - lo[d] > L) L = hi[d] - lo[d];
+    if (L == 0.0) L = 1.0;
+    double scale = ldexp(1.0, D) / L;
+    int64_t maxc = ((int64_t)1 << D) - 1;
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t key = 0;
+        for (int d = 0; d < 3; ++d) {
+            double f = floor((pos[3 * i + d] - lo[d]) * scale);
+            int64_t c = (int64_t)f;
+            if (c > maxc) c = maxc;
+            if (c < 0) c = 0;
+            key |= spread3((uint64_t)c, D) << (2 - d);
+        }
+        keys[i] = key;
+    }
+}
+
+typedef struct { uint64_t key; int64_t i; } keyrec;
+
+static int key_cmp(const void* pa, const void* pb)
+{
+    const keyrec* a = (const keyrec*)pa;
+    const keyrec* b = (const keyrec*)pb;
+    if (a->key != b->key) return (a->key < b->key) ? -1 : 1;
+    return (a->i < b->i) ? -1 : (a->i > b->i);
+}
+
+/* add child (mass m, centre c, quadrupole qc about c) into a node about com */
+static void quad_add(double* q, const double* qc, double m, const double* c, const double* com)
+{
+    double dx = c[0] - com[0], dy = c[1] - com[1], dz = c[2] - com[2];
+    double r2 = dx * dx + dy * dy + dz * dz;
+    q[0] = q[0] + (qc[0] + m * (3.0 * dx * dx - r2));
+    q[1] = q[1] + (qc[1] + m * (3.0 * dy * dy - r2));
+    q[2] = q[2] + (qc[2] + m * (3.0 * dz * dz - r2));
+    q[3] = q[3] + (qc[3] + m * (3.0 * dx * dy));
+    q[4] = q[4] + (qc[4] + m * (3.0 * dx * dz));
+    q[5] = q[5] + (qc[5] + m * (3.0 * dy * dz));
+}
+
+typedef struct {
+    int64_t n;
+    onode_t* nodes;
+    int64_t n_nodes, cap_nodes;
+    int64_t* order;     /* sorted position -> original index */
+    double *x, *y, *z, *m; /* sorted copies */
+    uint64_t* keys;     /* sorted keys */
+} otree_t;
+
+static int64_t push_node(otree_t* t)
+{
+    if (t->n_nodes == t->cap_nodes) {
+        t->cap_nodes = t->cap_nodes ? 2 * t->cap_nodes : 1024;
+        t->nodes = (onode_t*)realloc(t->nodes, sizeof(onode_t) * (size_t)t->cap_nodes);
+    }
+    memset(&t->nodes[t->n_nodes], 0, sizeof(onode_t));
+    return t->n_nodes++;
+}
+
+static void tree_build(otree_t* t, int64_t n, const double* pos, const double* mass,
+                       int n_leaf, int D)
+{
+    memset(t, 0, sizeof(*t));
+    t->n = n;
+    t->keys = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
+    orc_keys(n, pos, D, t->keys);
+    keyrec* kr = (keyrec*)malloc(sizeof(keyrec) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) { kr[i].key = t->keys[i]; kr[i].i = i; }
+    qsort(kr, (size_t)n, sizeof(keyrec), key_cmp);
+    t->order = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    t->x = (double*)malloc(sizeof(double) * (size_t)n);
+    t->y = (double*)malloc(sizeof(double) * (size_t)n);
+    t->z = (double*)malloc(sizeof(double) * (size_t)n);
+    t->m = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t i = kr[k].i;
+        t->order[k] = i;
+        t->keys[k] = kr[k].key;
+        t->x[k] = pos[3 * i];
+        t->y[k] = pos[3 * i + 1];
+        t->z[k] = pos[3 * i + 2];
+        t->m[k] = mass[i];
+    }
+    free(kr);
+
+    /* topology, breadth first: children of node k are appended when k is visited */
+    int64_t root = push_node(t);
+    t->nodes[root].begin = 0;
+    t->nodes[root].count = n;
+    t->nodes[root].level = 0;
+    for (int64_t k = 0; k < t->n_nodes; ++k) {
+        onode_t nd = t->nodes[k];
+        t->nodes[k].nchild = 0;
+        if (!(nd.count > n_leaf && nd.level < D)) continue;
+        int shift = 3 * (D - 1 - nd.level);
+        int64_t first = t->n_nodes;
+        int64_t s = nd.begin;
+        while (s < nd.begin + nd.count) {
+            unsigned dig = (unsigned)((t->keys[s] >> shift) & 7ULL);
+            int64_t e = s;
+            while (e < nd.begin + nd.count && (unsigned)((t->keys[e] >> shift) & 7ULL) == dig) ++e;
+            int64_t c = push_node(t);
+            t->nodes[c].begin = s;
+            t->nodes[c].count = e - s;
+            t->nodes[c].level = nd.level + 1;
+            s = e;
+        }
+        t->nodes[k].first_child = first;
+        t->nodes[k].nchild = (int32_t)(t->n_nodes - first);
+    }
+
+    /* moments, children before parents (reverse breadth-first order) */
+    for (int64_t k = t->n_nodes - 1; k >= 0; --k) {
+        onode_t* nd = &t->nodes[k];
+        double M = 0, sx = 0, sy = 0, sz = 0;
+        int64_t nsub = nd->nchild ? nd->nchild : nd->count;
+        for (int64_t u = 0; u < nsub; ++u) {
+            double mu, cu[3];
+            if (nd->nchild) {
+                const onode_t* c = &t->nodes[nd->first_child + u];
+                mu = c->M; cu[0] = c->com[0]; cu[1] = c->com[1]; cu[2] = c->com[2];
+            } else {
+                int64_t j = nd->begin + u;
+                mu = t->m[j]; cu[0] = t->x[j]; cu[1] = t->y[j]; cu[2] = t->z[j];
+            }
+            M = M + mu;
+            sx = sx + mu * cu[0];
+            sy = sy + mu * cu[1];
+            sz = sz + mu * cu[2];
+            for (int d = 0; d < 3; ++d) {
+                double lo_u = nd->nchild ? t->nodes[nd->first_child + u].lo[d] : cu[d];
+                double hi_u = nd->nchild ? t->nodes[nd->first_child + u].hi[d] : cu[d];
+                if (u == 0 || lo_u < nd->lo[d]) nd->lo[d] = lo_u;
+                if (u == 0 || hi_u > nd->hi[d]) nd->hi[d] = hi_u;
+            }
+        }
+        nd->M = M;
+        if (M > 0.0) {
+            nd->com[0] = sx / M; nd->com[1] = sy / M; nd->com[2] = sz / M;
+        } else {
+            for (int d = 0; d < 3; ++d) nd->com[d] = (nd->lo[d] + nd->hi[d]) * 0.5;
+        }
+        for (int e = 0; e < 6; ++e) nd->q[e] = 0.0;
+        static const double zero6[6] = {0, 0, 0, 0, 0, 0};
+        for (int64_t u = 0; u < nsub; ++u) {
+            if (nd->nchild) {
+                const onode_t* c = &t->nodes[nd->first_child + u];
+                quad_add(nd->q, c->q, c->M, c->com, nd->com);
+            } else {
+                int64_t j = nd->begin + u;
+                double cu[3] = {t->x[j], t->y[j], t->z[j]};
+                quad_add(nd->q, zero6, t->m[j], cu, nd->com);
+            }
+        }
+    }
+}
+
+static void tree_free(otree_t* t)
+{
+    free(t->nodes); free(t->order); free(t->x); free(t->y); free(t->z); free(t->m); free(t->keys);
+}
+
+/* squared distance between boxes [alo, ahi] and [blo, bhi]; per axis gap >= 0 */
+static double box_box_d2(const double* alo, const double* ahi, const double* blo, const double* bhi)
+{
+    double g[3];
+    for (int d = 0; d < 3; ++d) {
+        double a = blo[d] - ahi[d];
+        double b = alo[d] - bhi[d];
+        double v = a > b ? a : b;
+        g[d] = v > 0.0 ? v : 0.0;
+    }
+    return g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+}
+
+/* squared distance from point c to box [lo, hi] */
+static double box_pt_d2(const double* lo, const double* hi, const double* c)
+{
+    double g[3];
+    for (int d = 0; d < 3; ++d) {
+        double a = lo[d] - c[d];
+        double b = c[d] - hi[d];
+        double v = a > b ? a : b;
+        g[d] = v > 0.0 ? v : 0.0;
+    }
+    return g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+}
+
+typedef struct {
+    const otree_t* t;
+    const phir_t* p;
+    double eps2, rout2, theta;
+    int64_t gbeg, gcnt;
+    double glo[3], ghi[3];
+    double* ax; double* ay; double* az; double* ph; /* per group member */
+    int64_t n_pn, n_far, n_near;
+} walkctx;
+
+/* Monopole + traceless quadrupole of a node acting on the group's members. */
+static void eval_pn(walkctx* w, const onode_t* nd)
+{
+    const otree_t* t = w->t;
+    for (int64_t u = 0; u < w->gcnt; ++u) {
+        int64_t i = w->gbeg + u;
+        /* R = x_i - COM */
+        double Rx = t->x[i] - nd->com[0], Ry = t->y[i] - nd->com[1], Rz = t->z[i] - nd->com[2];
+        double s2 = Rx * Rx + Ry * Ry + Rz * Rz + w->eps2;
+        double s = sqrt(s2);
+        double inv = 1.0 / s;
+        double inv2 = inv * inv;
+        double inv3 = inv * inv2;
+        double inv5 = inv3 * inv2;
+        double inv7 = inv5 * inv2;
+        /* QR and R^T Q R with q = (xx, yy, zz, xy, xz, yz) */
+        double qx = nd->q[0] * Rx + nd->q[3] * Ry + nd->q[4] * Rz;
+        double qy = nd->q[3] * Rx + nd->q[1] * Ry + nd->q[5] * Rz;
+        double qz = nd->q[4] * Rx + nd->q[5] * Ry + nd->q[2] * Rz;
+        double rqr = Rx * qx + Ry * qy + Rz * qz;
+        /* phi = -M/s - (1/2) R^T Q R / s^5 ; a = -grad phi */
+        double cr = -nd->M * inv3 - 2.5 * rqr * inv7;
+        w->ax[u] += cr * Rx + qx * inv5;
+        w->ay[u] += cr * Ry + qy * inv5;
+        w->az[u] += cr * Rz + qz * inv5;
+        w->ph[u] += -nd->M * inv - 0.5 * rqr * inv5;
+    }
+    w->n_pn += w->gcnt;
+}
+
+static void eval_pp(walkctx* w, const onode_t* nd, int near)
+{
+    const otree_t* t = w->t;
+    for (int64_t u = 0; u < w->gcnt; ++u) {
+        int64_t i = w->gbeg + u;
+        for (int64_t j = nd->begin; j < nd->begin + nd->count; ++j) {
+            if (j == i) continue;
+            if (near) {
+                pair_regular(w->p, w->eps2, t->x[i], t->y[i], t->z[i], t->x[j], t->y[j], t->z[j],
+                             t->m[j], &w->ax[u], &w->ay[u], &w->az[u], &w->ph[u]);
+            } else {
+                /* every pair of a far leaf is at r >= r_out, where W = 1 */
+                double dx = t->x[j] - t->x[i], dy = t->y[j] - t->y[i], dz = t->z[j] - t->z[i];
+                double s2 = dx * dx + dy * dy + dz * dz + w->eps2;
+                double s = sqrt(s2);
+                double f = t->m[j] / (s2 * s);
+                w->ax[u] += f * dx;
+                w->ay[u] += f * dy;
+                w->az[u] += f * dz;
+                w->ph[u] += -t->m[j] / s;
+            }
+        }
+    }
+    if (near) w->n_near += w->gcnt * nd->count; else w->n_far += w->gcnt * nd->count;
+}
+
+static void visit(walkctx* w, int64_t k)
+{
+    const onode_t* nd = &w->t->nodes[k];
+    double dbox2 = box_box_d2(w->glo, w->ghi, nd->lo, nd->hi);
+    int near = (dbox2 < w->rout2) || (dbox2 == 0.0);
+    if (!near && w->theta > 0.0 && box_pt_d2(w->glo, w->ghi, nd->com) > nd->rcrit2) {
+        eval_pn(w, nd);
+        return;
+    }
+    if (nd->nchild == 0) {
+        eval_pp(w, nd, near);
+        return;
+    }
+    for (int32_t c = 0; c < nd->nchild; ++c) visit(w, nd->first_child + c);
+}
+
+/*
+ * Tree walk of one cluster. Outputs acc [n][3], pot [n] in the caller's order.
+ * stats (optional, int64[6]): n_nodes, n_leaves, n_groups, PN, PP-far, PP-near
+ * interaction counts (PN counted once per group member, PP once per pair
+ * evaluated, the excluded self pair included in PP-near).
+ */
+void orc_tree(int64_t n, const double* pos, const double* mass,
+              double r_in, double r_out, double theta, double eps,
+              int n_leaf, int n_crit, int D,
+              double* acc, double* pot, int64_t* stats)
+{
+    otree_t t;
+    tree_build(&t, n, pos, mass, n_leaf, D);
+    for (int64_t k = 0; k < t.n_nodes; ++k) {
+        onode_t* nd = &t.nodes[k];
+        double l = 0.0;
+        for (int d = 0; d < 3; ++d)
+            if (nd->hi[d] - nd->lo[d] > l) l = nd->hi[d] - nd->lo[d];
+        double ctr[3], dd[3];
+        for (int d = 0; d < 3; ++d) {
+            ctr[d] = (nd->lo[d] + nd->hi[d]) * 0.5;
+            dd[d] = nd->com[d] - ctr[d];
+        }
+        double delta = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+        double rc = theta > 0.0 ? l / theta + delta : 0.0;
+        nd->rcrit2 = rc * rc;
+    }
+    phir_t p;
+    phir_init(&p, r_in, r_out);
+    int64_t ngroups = (n + n_crit - 1) / n_crit;
+    int64_t s_pn = 0, s_far = 0, s_near = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : s_pn, s_far, s_near)
+    for (int64_t g = 0; g < ngroups; ++g) {
+        walkctx w;
+        memset(&w, 0, sizeof(w));
+        w.t = &t;
+        w.p = &p;
+        w.eps2 = eps * eps;
+        w.rout2 = r_out * r_out;
+        w.theta = theta;
+        w.gbeg = g * n_crit;
+        w.gcnt = (w.gbeg + n_crit <= n) ? n_crit : n - w.gbeg;
+        for (int64_t u = 0; u < w.gcnt; ++u) {
+            int64_t i = w.gbeg + u;
+            double v[3] = {t.x[i], t.y[i], t.z[i]};
+            for (int d = 0; d < 3; ++d) {
+                if (u == 0 || v[d] < w.glo[d]) w.glo[d] = v[d];
+                if (u == 0 || v[d] > w.ghi[d]) w.ghi[d] = v[d];
+            }
+        }
+        double* buf = (double*)calloc((size_t)(4 * w.gcnt), sizeof(double));
+        w.ax = buf; w.ay = buf + w.gcnt; w.az = buf + 2 * w.gcnt; w.ph = buf + 3 * w.gcnt;
+        visit(&w, 0);
+        for (int64_t u = 0; u < w.gcnt; ++u) {
+            int64_t i = t.order[w.gbeg + u];
+            acc[3 * i] = w.ax[u];
+            acc[3 * i + 1] = w.ay[u];
+            acc[3 * i + 2] = w.az[u];
+            pot[i] = w.ph[u];
+        }
+        free(buf);
+        s_pn += w.n_pn; s_far += w.n_far; s_near += w.n_near;
+    }
+    if (stats) {
+        int64_t leaves = 0;
+        for (int64_t k = 0; k < t.n_nodes; ++k) leaves += (t.nodes[k].nchild == 0);
+        stats[0] = t.n_nodes; stats[1] = leaves; stats[2] = ngroups;
+        stats[3] = s_pn; stats[4] = s_far; stats[5] = s_near;
+    }
+    tree_free(&t);
+}
+
+/*
+ * Tree structure export for stage-level tests: sorted order [n], and for
+ * each node (up to cap) begin, count, nchild, level, M, com[3], q[6], lo[3], hi[3].
+ * Returns the node count (arrays untouched if it exceeds cap).
+ */
+int64_t orc_tree_nodes(int64_t n, const double* pos, const double* mass, int n_leaf, int D,
+                       int64_t cap, int64_t* order, int64_t* ibuf /* [cap][4] */,
+                       double* dbuf /* [cap][16] */)
+{
+    otree_t t;
+    tree_build(&t, n, pos, mass, n_leaf, D);
+    int64_t nn = t.n_nodes;
+    if (order) memcpy(order, t.order, sizeof(int64_t) * (size_t)n);
+    if (nn <= cap) {
+        for (int64_t k = 0; k < nn; ++k) {
+            const onode_t* nd = &t.nodes[k];
+            ibuf[4 * k] = nd->begin;
+            ibuf[4 * k + 1] = nd->count;
+            ibuf[4 * k + 2] = nd->nchild;
+            ibuf[4 * k + 3] = nd->level;
+            double* o = dbuf + 16 * k;
+            o[0] = nd->M;
+            for (int d = 0; d < 3; ++d) { o[1 + d] = nd->com[d]; o[10 + d] = nd->lo[d]; o[13 + d] = nd->hi[d]; }
+            for (int e = 0; e < 6; ++e) o[4 + e] = nd->q[e];
+        }
+    }
+    tree_free(&t);
+    return nn;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

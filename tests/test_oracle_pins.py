@@ -1,0 +1,431 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each check uses a closed form,
+an invariant, a textbook special case, brute force, or an independent
+numerical method (quadrature, finite differences, numpy recomputation).
+Paper references are to Arnold, Baumgardt & Wang (2021).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_11658_amd import ic
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def g_of(x):
+    """g(x) through the oracle's W with r_in = 1, r_out = 2 (so x = s - 1)."""
+    return oracle.W(1.0 + x, 1.0, 2.0)
+
+
+# --- P-1: changeover polynomial (Section 2.1, eq. duncan) -------------------
+
+def test_changeover_polynomial_fixed_points():
+    assert g_of(0.0) == 0.0
+    assert g_of(1.0 - 1e-16) == pytest.approx(1.0, abs=1e-12)
+    assert g_of(0.5) == pytest.approx(0.5, abs=1e-15)
+    for x in np.linspace(0.01, 0.99, 37):
+        assert g_of(x) + g_of(1.0 - x) == pytest.approx(1.0, abs=1e-13)
+
+
+def test_changeover_derivative_closed_form():
+    # g'(x) = 140 x^3 (1-x)^3 (the bracket of eq. duncan2)
+    h = 1e-6
+    for x in np.linspace(0.05, 0.95, 19):
+        fd = (g_of(x + h) - g_of(x - h)) / (2 * h)
+        # rounding noise of the difference quotient is ~ 84 * 2^-52 / h
+        assert fd == pytest.approx(140 * x**3 * (1 - x) ** 3, rel=1e-7, abs=5e-8)
+
+
+def test_changeover_regions_and_boundaries():
+    r_in, r_out = 0.01, 0.1
+    assert oracle.W(0.0, r_in, r_out) == 0.0
+    assert oracle.W(r_in * (1 - 1e-12), r_in, r_out) == 0.0
+    assert oracle.W(r_in, r_in, r_out) == 0.0            # x = 0
+    assert oracle.W(r_out, r_in, r_out) == 1.0           # x = 1: wholly regular
+    assert oracle.W(5.0, r_in, r_out) == 1.0
+    assert oracle.W(r_in + 0.5 * (r_out - r_in), r_in, r_out) == pytest.approx(0.5, abs=1e-15)
+    # K = 1 - W is monotone non-increasing: W monotone non-decreasing
+    s = np.linspace(0, 0.12, 500)
+    w = np.array([oracle.W(v, r_in, r_out) for v in s])
+    assert np.all(np.diff(w) >= -1e-15)
+    # degenerate radii: step at r_in = r_out, plain gravity at r_out = 0
+    assert oracle.W(0.0999, 0.1, 0.1) == 0.0 and oracle.W(0.1, 0.1, 0.1) == 1.0
+    assert oracle.W(0.0, 0.0, 0.0) == 1.0
+
+
+# --- P-2 / P-3: regular potential --------------------------------------------
+
+def _phi_quadrature(s, r_in, r_out, npts=48):
+    """-1/r_out - int_s^r_out W(u)/u^2 du by piecewise Gauss-Legendre."""
+    xg, wg = np.polynomial.legendre.leggauss(npts)
+    total = 0.0
+    # split at r_in: W has a kink-free but piecewise definition there
+    edges = [s, r_out] if s >= r_in else [s, r_in, r_out]
+    for a, b in zip(edges[:-1], edges[1:]):
+        if b <= a:
+            continue
+        u = 0.5 * (b - a) * xg + 0.5 * (b + a)
+        f = np.array([oracle.W(v, r_in, r_out) for v in u]) / u**2
+        total += 0.5 * (b - a) * np.dot(wg, f)
+    return -1.0 / r_out - total
+
+
+@pytest.mark.parametrize("r_in,r_out", [(0.005, 0.05), (0.0, 0.05), (0.03, 0.05), (0.1, 1.0)])
+def test_regular_potential_matches_quadrature(r_in, r_out):
+    # the closed form expands g(t - a) in powers of t, which cancels like (1 + a)^7
+    a = r_in / (r_out - r_in)
+    tol = 1e-13 * max(1.0, (1.0 + a) ** 7)
+    for s in np.linspace(max(r_in, 1e-4), r_out, 23):
+        phi = oracle.phiR(s, r_in, r_out)
+        ref = _phi_quadrature(s, r_in, r_out)
+        assert phi == pytest.approx(ref, rel=tol, abs=tol / r_out)
+
+
+def test_regular_potential_gradient_and_continuity():
+    r_in, r_out = 0.005, 0.05
+    for s in np.linspace(0.0055, 0.0495, 17):
+        h = 1e-4 * s
+        f = [oracle.phiR(s + k * h, r_in, r_out) for k in (-2, -1, 1, 2)]
+        fd = (f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * h)   # 4th-order stencil
+        # tolerance: truncation ~h^4 and rounding ~2^-52 |Phi| / h
+        assert fd == pytest.approx(oracle.W(s, r_in, r_out) / s**2, rel=1e-7, abs=1e-11 / (s * h))
+    assert oracle.phiR(r_out, r_in, r_out) == pytest.approx(-1.0 / r_out, rel=1e-15)
+    assert oracle.phiR(r_out * (1 - 1e-12), r_in, r_out) == pytest.approx(-1.0 / r_out, rel=1e-9)
+    inner = oracle.phiR(r_in, r_in, r_out)
+    for s in (0.0, 1e-6, 0.5 * r_in, r_in * (1 - 1e-12)):
+        assert oracle.phiR(s, r_in, r_out) == inner
+    assert oracle.phiR(2.0, r_in, r_out) == -0.5
+    # Beyond r_out the potential is plain -1/s; inside, W <= 1 makes it shallower
+    assert oracle.phiR(0.01, r_in, r_out) > -1.0 / 0.01
+
+
+def test_inner_constant_scales_with_r_out():
+    # Phi_R(s < r_in) = -C(gamma)/r_out depends only on gamma = r_in/r_out;
+    # C(gamma) = 1 + int_gamma^1 g((y-gamma)/(1-gamma))/y^2 dy (quadrature)
+    from scipy.integrate import quad
+    gam = 0.1
+    Cq = 1.0 + quad(lambda y: oracle.W(y, gam, 1.0) / y**2, gam, 1.0, epsabs=1e-15, epsrel=1e-14)[0]
+    for r_out in (0.01, 0.05, 1.0, 7.0):
+        assert -oracle.phiR(0.0, gam * r_out, r_out) * r_out == pytest.approx(Cq, rel=1e-13)
+
+
+def test_potential_coefficients_reproduce_polynomial():
+    # g(t - a) = sum d_k t^k with a = r_in / (r_out - r_in)
+    r_in, r_out = 0.005, 0.05
+    d, _ = oracle.phiR_coeffs(r_in, r_out)
+    a = r_in / (r_out - r_in)
+    for x in np.linspace(0, 1, 11):
+        t = x + a
+        assert np.polyval(d[::-1], t) == pytest.approx(
+            35 * x**4 - 84 * x**5 + 70 * x**6 - 20 * x**7, abs=1e-12)
+
+
+# --- P-5: two- and three-body analytic cases --------------------------------
+
+def test_two_body_changeover():
+    r_in, r_out = 0.01, 0.1
+    s_half = r_in + 0.5 * (r_out - r_in)   # W = 1/2 here
+    pos = np.array([[0.0, 0.0, 0.0], [s_half, 0.0, 0.0]])
+    mass = np.array([0.3, 0.7])
+    acc, pot = oracle.direct(pos, mass, r_in, r_out, 0.0)
+    assert acc[0, 0] == pytest.approx(0.7 * 0.5 / s_half**2, rel=1e-14)
+    assert acc[1, 0] == pytest.approx(-0.3 * 0.5 / s_half**2, rel=1e-14)
+    assert np.all(acc[:, 1:] == 0)
+    # beyond r_out: Newtonian
+    pos[1, 0] = 0.25
+    acc, pot = oracle.direct(pos, mass, r_in, r_out, 0.0)
+    assert acc[0, 0] == pytest.approx(0.7 / 0.0625, rel=1e-15)
+    assert pot[0] == pytest.approx(-0.7 / 0.25, rel=1e-15)
+    # inside r_in: no regular force, constant potential
+    pos[1, 0] = 0.5 * r_in
+    acc, pot = oracle.direct(pos, mass, r_in, r_out, 0.0)
+    assert np.all(acc == 0)
+    assert pot[0] == pytest.approx(0.7 * oracle.phiR(0.0, r_in, r_out), rel=1e-15)
+
+
+def test_three_body_superposition_and_softening():
+    r_in, r_out, eps = 0.01, 0.1, 0.003
+    pos = np.array([[0.0, 0.0, 0.0], [0.05, 0.0, 0.0], [0.0, -0.2, 0.0]])
+    mass = np.array([1.0, 2.0, 3.0])
+    acc, pot = oracle.direct(pos, mass, r_in, r_out, eps)
+    s1 = math.sqrt(0.05**2 + eps**2)
+    s2 = math.sqrt(0.2**2 + eps**2)
+    ax = 2.0 * oracle.W(s1, r_in, r_out) * 0.05 / s1**3
+    ay = -3.0 * 0.2 / s2**3
+    assert acc[0, 0] == pytest.approx(ax, rel=1e-14)
+    assert acc[0, 1] == pytest.approx(ay, rel=1e-14)
+    assert pot[0] == pytest.approx(2.0 * oracle.phiR(s1, r_in, r_out) - 3.0 / s2, rel=1e-14)
+
+
+def test_coincident_pair_is_finite():
+    # j != i at the same place: W = 0 below r_in, potential Phi_R(eps)
+    pos = np.zeros((2, 3))
+    mass = np.array([0.5, 0.5])
+    acc, pot = oracle.direct(pos, mass, 0.01, 0.1, 0.0)
+    assert np.all(acc == 0)
+    assert pot[0] == pytest.approx(0.5 * oracle.phiR(0.0, 0.01, 0.1))
+
+
+# --- P-4 / P-6: split identity and Newton's third law -------------------------
+
+def test_split_identity_and_newton3():
+    c = ic.plummer(2048, seed=11, masses="kroupa")
+    r_out = 0.12
+    r_in = 0.1 * r_out
+    eps = 1e-4
+    acc, pot = oracle.direct(c.pos, c.mass, r_in, r_out, eps)
+    full, _ = oracle.full_direct(c.pos, c.mass, eps)
+    off, idx = oracle.nbr_brute(c.pos, r_out)
+    # irregular part F_I = sum_{j in nbr(i)} m_j K d / s^3 with K = 1 - W
+    fi = np.zeros_like(acc)
+    for i in range(c.n):
+        for j in idx[off[i]:off[i + 1]]:
+            d = c.pos[j] - c.pos[i]
+            s = math.sqrt(d @ d + eps * eps)
+            fi[i] += c.mass[j] * (1.0 - oracle.W(s, r_in, r_out)) * d / s**3
+    err = np.linalg.norm(acc + fi - full, axis=1) / np.linalg.norm(full, axis=1)
+    assert err.max() < 1e-12
+    assert off[-1] > 1000  # the identity is exercised on many pairs
+    # Newton III on the antisymmetric pair sum
+    mom = (c.mass[:, None] * acc).sum(0)
+    assert np.linalg.norm(mom) <= 1e-12 * (c.mass * np.linalg.norm(acc, axis=1)).sum()
+
+
+# --- P-7: Plummer potential, inward field, virial energy ---------------------
+
+def test_plummer_field_henon_units():
+    n = 32768
+    c = ic.plummer(n, seed=7)
+    acc, pot = oracle.direct(c.pos, c.mass, 0.0, 0.0, 0.0)   # r_out = 0: whole gravity
+    a = ic.PLUMMER_A_HENON
+    r = np.linalg.norm(c.pos, axis=1)
+    phi_an = -1.0 / np.sqrt(r * r + a * a)
+    rel = np.abs(pot - phi_an) / np.abs(phi_an)
+    assert np.median(rel) < 1e-2
+    radial = np.einsum("ij,ij->i", acc, c.pos) / np.maximum(r, 1e-30)
+    assert np.mean(radial < 0) > 0.95           # the field points inward
+    epot = 0.5 * np.dot(c.mass, pot)
+    ekin = 0.5 * np.dot(c.mass, (c.vel**2).sum(1))
+    assert epot == pytest.approx(-0.5, abs=0.02)   # Henon units: W = -1/2
+    assert ekin + epot == pytest.approx(-0.25, abs=0.02)  # E = -1/4
+
+
+# --- Morton keys, sort order and tree structure ------------------------------
+
+def test_morton_key_worked_example():
+    # box [0,1]^3 fixed by two corner points; D = 2 -> 4 cells per axis
+    pos = np.array([[0.0, 0.0, 0.0], [1.0, 1.0, 1.0], [0.3, 0.6, 0.9]])
+    k = oracle.keys(pos, D=2)
+    # (0.3,0.6,0.9)*4 -> cells (1,2,3): level-1 digit (0,1,1)=3, level-2 digit (1,0,1)=5
+    assert list(k) == [0, 63, 3 * 8 + 5]
+
+
+def test_keys_degenerate_box_and_clamp():
+    pos = np.tile([[0.25, -1.0, 3.0]], (5, 1))
+    assert np.all(oracle.keys(pos, D=21) == 0)     # zero extent -> L = 1, all in cell 0
+    pos = np.array([[0.0, 0.0, 0.0], [2.0, 0.0, 0.0]])
+    k = oracle.keys(pos, D=21)
+    assert k[1] == np.uint64(int("100" * 21, 2))   # x clamped to 2^21 - 1, x bits only
+
+
+def _brute_tree(keys_sorted, n_leaf, D):
+    """Independent recursive construction: list of (begin, count, level, nchild) breadth first."""
+    nodes = [(0, len(keys_sorted), 0)]
+    out = []
+    k = 0
+    while k < len(nodes):
+        b, c, lev = nodes[k]
+        kids = []
+        if c > n_leaf and lev < D:
+            shift = 3 * (D - 1 - lev)
+            dig = (keys_sorted[b:b + c] >> np.uint64(shift)) & np.uint64(7)
+            for v in np.unique(dig):
+                sel = np.nonzero(dig == v)[0]
+                kids.append((b + int(sel[0]), int(sel.size), lev + 1))
+        out.append((b, c, lev, len(kids)))
+        nodes.extend(kids)
+        k += 1
+    return out
+
+
+@pytest.mark.parametrize("seed,n,n_leaf", [(3, 3000, 16), (4, 500, 1), (5, 2000, 8)])
+def test_tree_topology_against_brute(seed, n, n_leaf):
+    c = ic.plummer(n, seed=seed, masses="kroupa")
+    keys = oracle.keys(c.pos, 21)
+    order, ib, db = oracle.tree_nodes(c.pos, c.mass, n_leaf=n_leaf, D=21)
+    assert np.array_equal(order, np.argsort(keys, kind="stable"))
+    ref = _brute_tree(keys[order], n_leaf, 21)
+    assert len(ref) == ib.shape[0]
+    got = [tuple(int(v) for v in (r[0], r[1], r[3], r[2])) for r in ib]
+    assert got == [(b, cnt, lev, nk) for (b, cnt, lev, nk) in ref]
+    # every particle in exactly one leaf; child counts sum to the parent's
+    leaves = ib[ib[:, 2] == 0]
+    cover = np.zeros(n, dtype=int)
+    for b, cnt, _, _ in leaves:
+        cover[b:b + cnt] += 1
+    assert np.all(cover == 1)
+
+
+def test_sort_ties_keep_original_order():
+    rng = np.random.default_rng(0)
+    base = rng.random((50, 3))
+    pos = np.concatenate([base, base[::-1], base])   # many exact duplicates
+    keys = oracle.keys(pos, 21)
+    order, _, _ = oracle.tree_nodes(pos, np.ones(150), n_leaf=4, D=21)
+    assert np.array_equal(order, np.argsort(keys, kind="stable"))
+
+
+def test_node_moments_against_direct_sums():
+    c = ic.plummer(4000, seed=9, masses="kroupa")
+    order, ib, db = oracle.tree_nodes(c.pos, c.mass, n_leaf=8, D=21)
+    xs = c.pos[order]
+    ms = c.mass[order]
+    for k in range(0, ib.shape[0], 7):
+        b, cnt = ib[k, 0], ib[k, 1]
+        x = xs[b:b + cnt]
+        m = ms[b:b + cnt]
+        M = m.sum()
+        com = (m[:, None] * x).sum(0) / M
+        d = x - com
+        r2 = (d * d).sum(1)
+        Q = 3 * np.einsum("i,ia,ib->ab", m, d, d) - np.eye(3) * (m * r2).sum()
+        q6 = np.array([Q[0, 0], Q[1, 1], Q[2, 2], Q[0, 1], Q[0, 2], Q[1, 2]])
+        scale = M * max((r2.max() if cnt else 0.0), 1e-300)
+        assert db[k, 0] == pytest.approx(M, rel=1e-13)
+        assert np.allclose(db[k, 1:4], com, rtol=0, atol=1e-13 * (1 + np.abs(com).max()))
+        assert np.allclose(db[k, 4:10], q6, rtol=0, atol=1e-12 * scale + 1e-300)
+        assert np.abs(q6[:3].sum()) <= 1e-12 * scale + 1e-300   # traceless
+        assert np.array_equal(db[k, 10:13], x.min(0)) and np.array_equal(db[k, 13:16], x.max(0))
+
+
+# --- P-8: theta = 0 tree equals direct summation (Section 2.4) ----------------
+
+@pytest.mark.parametrize("n_leaf,n_crit", [(16, 64), (1, 1), (8, 32)])
+def test_tree_theta0_equals_direct(n_leaf, n_crit):
+    c = ic.plummer(3000, seed=21, masses="kroupa")
+    r_out = 0.1
+    args = (c.pos, c.mass, 0.1 * r_out, r_out)
+    acc, pot = oracle.direct(*args, 1e-4)
+    at, pt, st = oracle.tree(*args, 0.0, 1e-4, n_leaf=n_leaf, n_crit=n_crit)
+    assert st["pn"] == 0 and st["pp_far"] + st["pp_near"] == c.n * c.n
+    assert np.max(np.linalg.norm(at - acc, axis=1) / np.linalg.norm(acc, axis=1)) < 1e-12
+    assert np.max(np.abs(pt - pot) / np.abs(pot)) < 1e-12
+
+
+# --- P-9 / P-10: neighbour sets ----------------------------------------------
+
+def _nbr_numpy(pos, r_out):
+    d = pos[None, :, :] - pos[:, None, :]
+    r2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+    m = r2 < r_out * r_out
+    np.fill_diagonal(m, False)
+    return [np.nonzero(row)[0] for row in m]
+
+
+def test_lattice_ties_are_not_neighbours():
+    g = np.arange(4, dtype=float)
+    pos = np.array(np.meshgrid(g, g, g, indexing="ij")).reshape(3, -1).T.copy()
+    off, idx = oracle.nbr_cells(pos, 1.0)   # r = r_out exactly: excluded (strict)
+    assert off[-1] == 0
+    off, idx = oracle.nbr_cells(pos, 1.0 + 1e-9)
+    cnt = np.diff(off)
+    # corner 3, edge 4, face 5, interior 6 face-neighbours
+    assert sorted(set(cnt.tolist())) == [3, 4, 5, 6]
+    assert cnt.sum() == 2 * 3 * 4 * 4 * 3
+    ref = _nbr_numpy(pos, 1.0 + 1e-9)
+    for i in range(pos.shape[0]):
+        assert np.array_equal(idx[off[i]:off[i + 1]], ref[i])
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_neighbour_sets_cells_brute_numpy(seed):
+    c = ic.plummer(1500, seed=seed)
+    r_out = 0.15
+    off, idx = oracle.nbr_cells(c.pos, r_out)
+    off_b, idx_b = oracle.nbr_brute(c.pos, r_out)
+    assert np.array_equal(off, off_b) and np.array_equal(idx, idx_b)
+    ref = _nbr_numpy(c.pos, r_out)
+    pairs = set()
+    for i in range(c.n):
+        li = idx[off[i]:off[i + 1]]
+        assert np.array_equal(li, ref[i])
+        pairs.update((i, int(j)) for j in li)
+    assert all((j, i) in pairs for (i, j) in pairs)     # symmetric
+    assert off[-1] > 0
+
+
+def test_neighbour_edge_cases():
+    pos = np.zeros((1, 3))
+    off, idx = oracle.nbr_cells(pos, 0.1)
+    assert list(off) == [0, 0]
+    pos = np.array([[0.0, 0, 0], [0.0, 0, 0], [0.05, 0, 0]])
+    off, idx = oracle.nbr_cells(pos, 0.0)     # r_out = 0: no lists
+    assert off[-1] == 0
+    off, idx = oracle.nbr_cells(pos, 0.06)
+    assert list(np.diff(off)) == [2, 2, 2]    # coincident pair are neighbours
+
+
+# --- P-11: multipole order ----------------------------------------------------
+
+def _two_clump_error(R, s):
+    """Relative force error on a lone particle from a 2-particle clump at distance R."""
+    rng = np.random.default_rng(5)
+    u = rng.normal(size=3)
+    u /= np.linalg.norm(u)
+    centre = np.array([R, 0.3 * R, -0.2 * R])
+    pos = np.array([[0.0, 0.0, 0.0], centre + 0.5 * s * u, centre - 0.3 * s * u])
+    mass = np.array([1.0, 0.2, 0.9])
+    acc, _ = oracle.direct(pos, mass, 0.0, 0.0, 0.0)
+    at, _, st = oracle.tree(pos, mass, 0.0, 0.0, 1.0, 0.0, n_leaf=1, n_crit=1)
+    return np.linalg.norm(at[0] - acc[0]) / np.linalg.norm(acc[0]), st["pn"]
+
+
+def test_quadrupole_error_scales_as_third_power():
+    e1, pn1 = _two_clump_error(1.0, 0.05)
+    e2, pn2 = _two_clump_error(1.0, 0.025)
+    assert pn1 > 0 and pn2 > 0                    # the clump is taken as a multipole
+    ratio = e1 / e2
+    assert 6.0 < ratio < 10.5                     # octupole-limited: (s/R)^3
+
+
+def test_quadrupole_beats_monopole_and_theta_order():
+    c = ic.plummer(20000, seed=13, masses="kroupa")
+    r_out = ic.r_out_for_nbar(c.n, 8.0)
+    args = (c.pos, c.mass, 0.1 * r_out, r_out)
+    tgt = np.arange(0, c.n, 7)
+    acc, pot = oracle.direct(*args, 1e-5, targets=tgt)
+    med = []
+    for th in (0.7, 0.5, 0.3):
+        at, pt, st = oracle.tree(*args, th, 1e-5)
+        e = np.linalg.norm(at[tgt] - acc, axis=1) / np.linalg.norm(acc, axis=1)
+        med.append(np.median(e))
+    assert med[0] > med[1] > med[2]
+    assert med[1] < 1e-3     # theta = 0.5 with quadrupoles
+
+
+# --- P-12: mean neighbour count of a Plummer sphere --------------------------
+
+def test_mean_neighbour_count_plummer():
+    n = 65536
+    c = ic.plummer(n, seed=17)
+    r_out = ic.r_out_for_nbar(n, 16.0)
+    off, _ = oracle.nbr_cells(c.pos, r_out)
+    assert off[-1] / n == pytest.approx(16.0, rel=0.05)
+    # paper's radius rule r_cut = 4 tau gives fewer than one neighbour on
+    # average (Section 2.3: "usually < 1")
+    rc = ic.paper_radii(n)["r_cut"]
+    off, _ = oracle.nbr_cells(c.pos, rc)
+    assert off[-1] / n < 1.0
+
+
+def test_paper_parameter_rule():
+    p = ic.paper_radii(1 << 20)
+    assert p["tau"] == pytest.approx(2.0**-9)
+    assert p["r_cut"] == pytest.approx(2.0**-7)
+    assert p["dt_reg"] == 2.0**-9 and p["dt_max"] == 2.0**-11
+    p = ic.paper_radii(1 << 22)
+    assert p["dt_reg"] == 2.0**-10
