@@ -1,0 +1,195 @@
+/*
+ * pbh.h -- C ABI of libpbh: GPU Barnes-Hut distant ("regular") forces and
+ * neighbour lists for the P3T scheme, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Arnold, Baumgardt & Wang (2021), "Accelerating NBODY6 with a
+ * GPU-Enabled Particle-Particle Particle-Tree Scheme".
+ *   - Section 2.1, eq. (fi) and the regular force F_R = (total) - F_I, with
+ *     the changeover function K of eq. (duncan): every pair contributes
+ *     m_j W(s) d/s^3 to F_R, W = 1 - K, d = x_j - x_i, s^2 = r^2 + eps^2.
+ *   - Section 2.3: a constant neighbour radius; empty neighbour lists are
+ *     legal. The list of i is { j != i : r_ij^2 < r_out^2 }.
+ *   - Section 2.4: a Barnes-Hut tree with opening angle theta computes the
+ *     regular force and fills the neighbour lists (REGF in the routine table
+ *     of Appendix A); theta = 0 reduces to direct summation.
+ *   - Section 2.2, eq. (kick): the leapfrog velocity kick with the regular
+ *     force, used by pbh_kdk.
+ *
+ * Conventions (all functions):
+ *   - G = 1. r_out is the paper's r_cut; r_in its inner radius.
+ *   - Pointers are DEVICE pointers unless marked "host". The caller owns
+ *     every buffer it passes; the library owns its tree scratch.
+ *   - pos is FP64 [n][3] row-major (x, y, z per particle), mass FP64 [n],
+ *     acc FP64 [n][3], pot FP64 [n], all in the caller's particle order.
+ *   - Neighbour lists are CSR: nbr_off int64 [n+1] (nbr_off[0] = 0),
+ *     nbr_idx int32 [nbr_cap] holding caller-order indices. The order inside
+ *     one list is unspecified (a list is a set) but deterministic.
+ *   - The potential returned is the regular potential Phi_R, defined by
+ *     dPhi_R/ds = W(s)/s^2 and Phi_R(s) = -1/s for s >= r_out (constant for
+ *     s < r_in), so that F_R = -grad Phi_R exactly.
+ *   - stream is a hipStream_t (NULL = the default stream). All work of a
+ *     call is enqueued on it; calls return without waiting unless stated.
+ *   - A context is not thread-safe: one call in flight per context.
+ *   - Every call returns a status; on error pbh_last_error() gives a
+ *     message. Nothing is printed.
+ */
+#ifndef PBH_H
+#define PBH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pbh_ctx pbh_ctx;
+typedef void* pbh_stream_t; /* hipStream_t */
+
+typedef enum {
+    PBH_OK = 0,
+    PBH_E_ARG = 1,           /* invalid argument (sizes, radii, theta, eps, NULL) */
+    PBH_E_OOM = 2,           /* device allocation failed */
+    PBH_E_HIP = 3,           /* a HIP runtime call failed */
+    PBH_E_NONFINITE = 4,     /* NaN or Inf in pos or mass */
+    PBH_E_NBR_OVERFLOW = 5,  /* nbr_cap too small; *nbr_total holds the size needed */
+    PBH_E_STATE = 6,         /* force called without a matching build */
+    PBH_E_INTERNAL = 7       /* a device-side capacity guard tripped */
+} pbh_status;
+
+typedef enum { PBH_FP64 = 0, PBH_MIXED = 1 } pbh_prec;
+
+/*
+ * Tuning parameters; 0 selects the default.
+ *   leaf_size  n_leaf: a node with more particles is split (default 16)
+ *   n_crit     particles per walk group, 1..128 (default 64)
+ *   key_bits   Morton bits per axis D, 1..21 (default 21 for one cluster;
+ *              batched builds use min(21, (63 - cluster bits) / 3))
+ *   prec       PBH_MIXED (FP32 interactions, FP64 positions and sums) or
+ *              PBH_FP64 (every interaction in FP64). Default PBH_MIXED.
+ */
+typedef struct {
+    int32_t leaf_size;
+    int32_t n_crit;
+    int32_t key_bits;
+    int32_t prec;
+} pbh_params;
+
+/* Counters of the last build and force call (pbh_get_stats waits for the stream). */
+typedef struct {
+    int64_t n;            /* particles */
+    int64_t n_clusters;
+    int64_t n_nodes;
+    int64_t n_leaves;
+    int64_t n_groups;
+    int64_t max_level;
+    int64_t n_pn;         /* particle-node (multipole) interactions */
+    int64_t n_pp_far;     /* particle-particle pairs outside r_out (W = 1) */
+    int64_t n_pp_near;    /* pairs inside near leaves (changeover applied; self pairs counted) */
+    int64_t nbr_total;    /* neighbour entries of the last force call */
+    int64_t error_flags;  /* device-side guard bits; 0 when healthy */
+} pbh_stats;
+
+/* Create a context on HIP device `device`. params may be NULL (defaults). */
+pbh_status pbh_create(int device, const pbh_params* params, pbh_ctx** out);
+void pbh_destroy(pbh_ctx* ctx);
+/* Replace the tuning parameters; takes effect at the next build. */
+pbh_status pbh_set_params(pbh_ctx* ctx, const pbh_params* params);
+pbh_status pbh_get_params(const pbh_ctx* ctx, pbh_params* out);
+
+/*
+ * Build the octree of one cluster (Section 2.4): bounding box and finiteness
+ * check, Morton keys, stable radix sort, octree topology, FP64 monopole and
+ * traceless quadrupole moments about each node's centre of mass, and walk
+ * groups. n >= 1. pos/mass are read during the call's stream work only; the
+ * library keeps its own sorted copy. Returns PBH_E_NONFINITE (after waiting
+ * for the stream) if any coordinate or mass is NaN/Inf.
+ */
+pbh_status pbh_build(pbh_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                     pbh_stream_t stream);
+
+/*
+ * Regular force, regular potential and neighbour lists of the last build
+ * (Section 2.1 eq. fi / F_R, eq. duncan; Section 2.3; Section 2.4).
+ *   r_in, r_out  changeover radii, 0 <= r_in <= r_out (r_out = 0: plain
+ *                softened gravity and empty lists; r_in = r_out: step W)
+ *   theta        opening angle >= 0 (0 = direct summation through the tree)
+ *   eps          Plummer softening >= 0 (enters s, W and Phi_R, not the list)
+ *   acc, pot     outputs [n][3], [n]
+ *   nbr_off      [n+1] output, or NULL to skip the neighbour lists
+ *   nbr_idx      [nbr_cap] output (may be NULL when nbr_cap = 0)
+ *   nbr_total    host int64 out, or NULL. If non-NULL the call waits for the
+ *                counts, stores the total, and returns PBH_E_NBR_OVERFLOW
+ *                without filling nbr_idx when it exceeds nbr_cap (acc, pot
+ *                and nbr_off are valid; resize and call again: the tree is
+ *                reused). If NULL nothing waits; entries beyond nbr_cap are
+ *                dropped and error_flags bit 0 is set in pbh_stats.
+ * pos/mass must be the arrays of the last build (they are not re-read).
+ */
+pbh_status pbh_force(pbh_ctx* ctx, double r_in, double r_out, double theta, double eps,
+                     double* acc, double* pot,
+                     int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap, int64_t* nbr_total,
+                     pbh_stream_t stream);
+
+/*
+ * Ensemble of independent clusters built as one forest: cluster k holds
+ * particles [offsets[k], offsets[k+1]) (host array, n_clusters + 1 entries,
+ * offsets[0] = 0, each cluster non-empty). Keys carry the cluster id above
+ * per-cluster Morton bits, so one sort orders every cluster; each cluster
+ * gets its own root, bounding box and groups. 1 <= n_clusters <= 65536.
+ */
+pbh_status pbh_build_batched(pbh_ctx* ctx, int32_t n_clusters, const int64_t* offsets,
+                             const double* pos, const double* mass, pbh_stream_t stream);
+
+/*
+ * Forces of every cluster of the last batched build in one persistent walk
+ * launch. r_in/r_out are host arrays [n_clusters] (per-cluster changeover
+ * radii); clusters never interact. Other arguments as pbh_force; neighbour
+ * indices are global (caller-order) indices.
+ */
+pbh_status pbh_force_batched(pbh_ctx* ctx, const double* r_in, const double* r_out,
+                             double theta, double eps, double* acc, double* pot,
+                             int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap,
+                             int64_t* nbr_total, pbh_stream_t stream);
+
+/*
+ * Kick-drift-kick leapfrog under the regular force (Section 2.2, eq. kick and
+ * the loop that follows it), with a full tree rebuild every step:
+ *   a = F_R(x); repeat steps times { v += dt/2 a; x += dt v; rebuild;
+ *   a = F_R(x); v += dt/2 a; E = sum m v^2/2 + sum m Phi_R/2 }.
+ * One step is captured once into a hipGraph and replayed `steps` times.
+ * pos/vel [n][3] are updated in place; energy_out is a device array
+ * [steps+1] (energy before the first step, then after each). n is fixed at
+ * the first call for this context; later calls with the same n reuse the graph.
+ */
+pbh_status pbh_kdk(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
+                   double dt, int32_t steps, double r_in, double r_out, double theta,
+                   double eps, double* energy_out, pbh_stream_t stream);
+
+/* Same step sequence launched eagerly (no graph), for replay checks. */
+pbh_status pbh_kdk_eager(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
+                         double dt, int32_t steps, double r_in, double r_out, double theta,
+                         double eps, double* energy_out, pbh_stream_t stream);
+
+/* Waits for the stream of the last call, then fills *out. */
+pbh_status pbh_get_stats(pbh_ctx* ctx, pbh_stats* out);
+
+/*
+ * Debug export of the last build (waits for the stream). Host buffers:
+ *   order [n]          sorted position -> caller index (int32)
+ *   keys  [n]          sorted keys (uint64)
+ *   nodes_i [cap][4]   begin, count, nchild, level (int64) in pre-order
+ *   nodes_d [cap][16]  M, com[3], q[6] (xx,yy,zz,xy,xz,yz), lo[3], hi[3]
+ * Any pointer may be NULL. Returns PBH_E_ARG if cap < node count (which is
+ * written to *n_nodes).
+ */
+pbh_status pbh_debug_tree(pbh_ctx* ctx, int32_t* order, uint64_t* keys, int64_t cap,
+                          int64_t* nodes_i, double* nodes_d, int64_t* n_nodes);
+
+const char* pbh_last_error(const pbh_ctx* ctx);
+const char* pbh_status_string(pbh_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBH_H */

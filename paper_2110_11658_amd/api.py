@@ -1,0 +1,188 @@
+"""Thin torch-facing wrapper of the libpbh C ABI (same entry points, tensors in).
+
+All tensors must live on the context's GPU: positions/velocities float64
+(n, 3) contiguous, masses float64 (n,). Calls enqueue on torch's current
+stream. Neighbour lists come back as CSR (int64 offsets [n+1], int32 indices
+in caller order); the order inside one list is unspecified.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PBH_E_NBR_OVERFLOW, PBH_FP64, PBH_MIXED, PbhError, check, pbh_params, pbh_stats
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t: torch.Tensor, shape, name: str, dtype=torch.float64):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {tuple(shape)}, "
+                         f"got {t.dtype} {tuple(t.shape)}")
+
+
+class Pbh:
+    """One libpbh context (tree scratch lives on the GPU between calls)."""
+
+    def __init__(self, device: int = 0, leaf_size: int = 16, n_crit: int = 64, key_bits: int = 0,
+                 prec: str = "mixed"):
+        self.L = _lib.load()
+        self.device = device
+        self.ctx = C.c_void_p()
+        p = self._params(leaf_size, n_crit, key_bits, prec)
+        st = self.L.pbh_create(device, C.byref(p), C.byref(self.ctx))
+        if st != 0:
+            raise PbhError(st, self.L.pbh_status_string(st).decode())
+        self.n = 0
+        self.n_clusters = 0
+        self._nbr_cap = 0
+
+    @staticmethod
+    def _params(leaf_size, n_crit, key_bits, prec):
+        pr = {"mixed": PBH_MIXED, "fp64": PBH_FP64}[prec]
+        return pbh_params(int(leaf_size), int(n_crit), int(key_bits), pr)
+
+    def set_params(self, leaf_size=16, n_crit=64, key_bits=0, prec="mixed"):
+        p = self._params(leaf_size, n_crit, key_bits, prec)
+        check(self.ctx, self.L.pbh_set_params(self.ctx, C.byref(p)))
+
+    def params(self) -> dict:
+        p = pbh_params()
+        check(self.ctx, self.L.pbh_get_params(self.ctx, C.byref(p)))
+        return {"leaf_size": p.leaf_size, "n_crit": p.n_crit, "key_bits": p.key_bits,
+                "prec": "mixed" if p.prec == PBH_MIXED else "fp64"}
+
+    def close(self):
+        if self.ctx:
+            self.L.pbh_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- pbh_build / pbh_build_batched ---------------------------------------
+    def build(self, pos: torch.Tensor, mass: torch.Tensor):
+        n = pos.shape[0]
+        _need(pos, (n, 3), "pos")
+        _need(mass, (n,), "mass")
+        check(self.ctx, self.L.pbh_build(self.ctx, n, _ptr(pos), _ptr(mass), _stream()))
+        self.n = n
+        self.n_clusters = 1
+
+    def build_batched(self, offsets: Sequence[int], pos: torch.Tensor, mass: torch.Tensor):
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        n = int(off[-1])
+        _need(pos, (n, 3), "pos")
+        _need(mass, (n,), "mass")
+        check(self.ctx, self.L.pbh_build_batched(self.ctx, off.size - 1,
+                                                 off.ctypes.data_as(C.c_void_p),
+                                                 _ptr(pos), _ptr(mass), _stream()))
+        self.n = n
+        self.n_clusters = off.size - 1
+
+    # -- pbh_force / pbh_force_batched ---------------------------------------
+    def _force(self, call, neighbours: bool, nbr_cap: Optional[int]):
+        dev = torch.device("cuda", self.device)
+        acc = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        pot = torch.empty((self.n,), dtype=torch.float64, device=dev)
+        if not neighbours:
+            check(self.ctx, call(acc, pot, None, None, 0, None))
+            return acc, pot, None, None
+        off = torch.empty((self.n + 1,), dtype=torch.int64, device=dev)
+        cap = int(nbr_cap if nbr_cap is not None else self._nbr_cap)
+        for _ in range(2):
+            idx = torch.empty((max(cap, 1),), dtype=torch.int32, device=dev)
+            total = C.c_int64(0)
+            st = call(acc, pot, off, idx, cap, C.byref(total))
+            if st == PBH_E_NBR_OVERFLOW:
+                cap = int(total.value * 1.25) + 1024
+                continue
+            check(self.ctx, st)
+            self._nbr_cap = max(self._nbr_cap, cap)
+            return acc, pot, off, idx[: total.value]
+        raise PbhError(PBH_E_NBR_OVERFLOW, "neighbour capacity still too small")
+
+    def force(self, r_in: float, r_out: float, theta: float, eps: float, neighbours: bool = True,
+              nbr_cap: Optional[int] = None):
+        """(acc [n,3], pot [n], nbr_off [n+1] | None, nbr_idx [total] | None)."""
+        def call(acc, pot, off, idx, cap, total):
+            return self.L.pbh_force(self.ctx, float(r_in), float(r_out), float(theta), float(eps),
+                                    _ptr(acc), _ptr(pot), _ptr(off), _ptr(idx), int(cap), total,
+                                    _stream())
+        return self._force(call, neighbours, nbr_cap)
+
+    def force_batched(self, r_in: Sequence[float], r_out: Sequence[float], theta: float, eps: float,
+                      neighbours: bool = True, nbr_cap: Optional[int] = None):
+        ri = np.ascontiguousarray(np.asarray(r_in, dtype=np.float64))
+        ro = np.ascontiguousarray(np.asarray(r_out, dtype=np.float64))
+        if ri.size != self.n_clusters or ro.size != self.n_clusters:
+            raise ValueError("need one r_in and r_out per cluster")
+
+        def call(acc, pot, off, idx, cap, total):
+            return self.L.pbh_force_batched(self.ctx, ri.ctypes.data_as(C.c_void_p),
+                                            ro.ctypes.data_as(C.c_void_p), float(theta), float(eps),
+                                            _ptr(acc), _ptr(pot), _ptr(off), _ptr(idx), int(cap),
+                                            total, _stream())
+        return self._force(call, neighbours, nbr_cap)
+
+    def force_into(self, r_in, r_out, theta, eps, acc: torch.Tensor, pot: torch.Tensor):
+        """Forces into caller-owned tensors, no neighbour lists, no host wait."""
+        _need(acc, (self.n, 3), "acc")
+        _need(pot, (self.n,), "pot")
+        check(self.ctx, self.L.pbh_force(self.ctx, float(r_in), float(r_out), float(theta),
+                                         float(eps), _ptr(acc), _ptr(pot), None, None, 0, None,
+                                         _stream()))
+
+    # -- pbh_kdk --------------------------------------------------------------
+    def kdk(self, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor, dt: float, steps: int,
+            r_in: float, r_out: float, theta: float, eps: float, graph: bool = True,
+            energy: Optional[torch.Tensor] = None) -> torch.Tensor:
+        n = pos.shape[0]
+        _need(pos, (n, 3), "pos")
+        _need(vel, (n, 3), "vel")
+        _need(mass, (n,), "mass")
+        if energy is None:
+            energy = torch.empty((steps + 1,), dtype=torch.float64, device=pos.device)
+        _need(energy, (steps + 1,), "energy")
+        fn = self.L.pbh_kdk if graph else self.L.pbh_kdk_eager
+        check(self.ctx, fn(self.ctx, n, _ptr(pos), _ptr(vel), _ptr(mass), float(dt), int(steps),
+                           float(r_in), float(r_out), float(theta), float(eps), _ptr(energy),
+                           _stream()))
+        self.n = n
+        self.n_clusters = 1
+        return energy
+
+    # -- stats / debug ----------------------------------------------------------
+    def stats(self) -> dict:
+        s = pbh_stats()
+        check(self.ctx, self.L.pbh_get_stats(self.ctx, C.byref(s)))
+        return {name: int(getattr(s, name)) for name, _ in pbh_stats._fields_}
+
+    def debug_tree(self):
+        """(order int32 [n], keys uint64 [n], nodes_i int64 [nodes,4], nodes_d f64 [nodes,16])."""
+        nn = C.c_int64(0)
+        check(self.ctx, self.L.pbh_debug_tree(self.ctx, None, None, 0, None, None, C.byref(nn)))
+        order = np.zeros(self.n, dtype=np.int32)
+        keys = np.zeros(self.n, dtype=np.uint64)
+        ni = np.zeros((nn.value, 4), dtype=np.int64)
+        nd = np.zeros((nn.value, 16), dtype=np.float64)
+        check(self.ctx, self.L.pbh_debug_tree(self.ctx, order.ctypes.data_as(C.c_void_p),
+                                              keys.ctypes.data_as(C.c_void_p), nn.value,
+                                              ni.ctypes.data_as(C.c_void_p),
+                                              nd.ctypes.data_as(C.c_void_p), C.byref(nn)))
+        return order, keys, ni, nd

@@ -1,0 +1,532 @@
+// build.hip -- octree construction on gfx950.
+//
+// Steps (Barnes-Hut tree of Section 2.4 of Arnold, Baumgardt & Wang 2021):
+//   bbox     per-cluster bounding box and NaN/Inf check (two-level reduction)
+//   keys     cluster id above D-bit-per-axis Morton codes (x, y, z interleaved)
+//   sort     stable radix sort (sort.hip) -> sorted keys and permutation
+//   gather   sorted FP64 SoA copies of x, y, z, m
+//   topology a node is a run of sorted particles sharing a key prefix whose
+//            parent holds more than n_leaf particles; each particle knows the
+//            levels of the nodes it starts, so one scan numbers the nodes in
+//            pre-order; a one-pass counting sort by level then gives the
+//            breadth-first order in which every node's children are contiguous
+//   moments  bottom-up, one launch per level: M, centre of mass, traceless
+//            quadrupole about it (parallel-axis sums over children), tight box
+//   groups   runs of n_crit sorted particles per cluster with a tight box
+//
+// FP64 arithmetic that decides the tree (keys, moments) is evaluated without
+// fused multiply-add so it rounds exactly as written.
+#include "pbh_internal.hpp"
+
+namespace pbh {
+
+namespace {
+
+constexpr int BB_T = 256;
+
+// ------------------------------------------------------------------ bbox
+__global__ __launch_bounds__(BB_T) void k_bbox_part(const double* __restrict__ pos,
+                                                    const double* __restrict__ mass,
+                                                    const int64_t* __restrict__ range,
+                                                    double* __restrict__ part,
+                                                    int32_t* __restrict__ bad) {
+    __shared__ double s_v[6][BB_T];
+    __shared__ int s_bad;
+    const int t = threadIdx.x;
+    if (t == 0) s_bad = 0;
+    const int64_t b0 = range[2 * blockIdx.x], b1 = range[2 * blockIdx.x + 1];
+    double lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY;
+    double hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
+    int nf = 0;
+    for (int64_t i = b0 + t; i < b1; i += BB_T) {
+        const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2], mm = mass[i];
+        nf |= !(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(mm));
+        lo0 = fmin(lo0, x); lo1 = fmin(lo1, y); lo2 = fmin(lo2, z);
+        hi0 = fmax(hi0, x); hi1 = fmax(hi1, y); hi2 = fmax(hi2, z);
+    }
+    s_v[0][t] = lo0; s_v[1][t] = lo1; s_v[2][t] = lo2;
+    s_v[3][t] = hi0; s_v[4][t] = hi1; s_v[5][t] = hi2;
+    __syncthreads();
+    if (nf) atomicOr(&s_bad, 1);
+    for (int o = BB_T / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            for (int k = 0; k < 3; ++k) s_v[k][t] = fmin(s_v[k][t], s_v[k][t + o]);
+            for (int k = 3; k < 6; ++k) s_v[k][t] = fmax(s_v[k][t], s_v[k][t + o]);
+        }
+        __syncthreads();
+    }
+    if (t < 6) part[6 * blockIdx.x + t] = s_v[t][0];
+    if (t == 0) bad[blockIdx.x] = s_bad;
+}
+
+// one thread per cluster; blocks of cluster c are [cblk[c], cblk[c+1])
+__global__ void k_bbox_final(const double* __restrict__ part, const int32_t* __restrict__ bad,
+                             const int32_t* __restrict__ cblk, int nc, double* __restrict__ box,
+                             unsigned long long* __restrict__ cnt) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    int nf = 0;
+    for (int b = cblk[c]; b < cblk[c + 1]; ++b) {
+        for (int k = 0; k < 3; ++k) v[k] = fmin(v[k], part[6 * b + k]);
+        for (int k = 3; k < 6; ++k) v[k] = fmax(v[k], part[6 * b + k]);
+        nf |= bad[b];
+    }
+    for (int k = 0; k < 6; ++k) box[6 * c + k] = v[k];
+    if (nf) atomicOr(&cnt[kErr], kErrNonFinite);
+}
+
+// ------------------------------------------------------------------ keys
+__device__ inline uint64_t spread_bits3(uint64_t v) {
+    // spread the low 21 bits of v to every third bit
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__global__ __launch_bounds__(BB_T) void k_keys(const double* __restrict__ pos,
+                                               const int64_t* __restrict__ range,
+                                               const int32_t* __restrict__ blk_cluster,
+                                               const double* __restrict__ box, int D,
+                                               uint64_t* __restrict__ keys) {
+#pragma clang fp contract(off)
+    const int c = blk_cluster[blockIdx.x];
+    const int64_t b0 = range[2 * blockIdx.x], b1 = range[2 * blockIdx.x + 1];
+    const double lo0 = box[6 * c], lo1 = box[6 * c + 1], lo2 = box[6 * c + 2];
+    double L = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double e = box[6 * c + 3 + k] - box[6 * c + k];
+        if (e > L) L = e;
+    }
+    if (L == 0.0) L = 1.0;
+    const double scale = ldexp(1.0, D) / L;
+    const int64_t maxc = ((int64_t)1 << D) - 1;
+    const uint64_t cid = (uint64_t)c << (3 * D);
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += BB_T) {
+        const double v[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+        const double lo[3] = {lo0, lo1, lo2};
+        uint64_t key = 0;
+        for (int k = 0; k < 3; ++k) {
+            int64_t q = (int64_t)floor((v[k] - lo[k]) * scale);
+            q = q > maxc ? maxc : (q < 0 ? 0 : q);
+            key |= spread_bits3((uint64_t)q) << (2 - k);
+        }
+        keys[i] = cid | key;
+    }
+}
+
+__global__ void k_gather(const double* __restrict__ pos, const double* __restrict__ mass,
+                         const int32_t* __restrict__ perm, int64_t n, double* __restrict__ x,
+                         double* __restrict__ y, double* __restrict__ z, double* __restrict__ m) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = perm[k];
+        x[k] = pos[3 * i];
+        y[k] = pos[3 * i + 1];
+        z[k] = pos[3 * i + 2];
+        m[k] = mass[i];
+    }
+}
+
+// -------------------------------------------------------------- topology
+// Key layout: [cluster id | D levels of 3 bits]. Level l >= 1 prefix = key >> 3(D-l).
+__device__ inline uint64_t prefix(uint64_t key, int l, int D) { return key >> (3 * (D - l)); }
+
+__device__ inline int cluster_of(uint64_t key, int D) { return (int)(key >> (3 * D)); }
+
+// Number of nodes started by sorted particle i and the first level.
+__global__ void k_topo_count(const uint64_t* __restrict__ keys, const int64_t* __restrict__ cl_off,
+                             int64_t n, int D, int n_leaf, int32_t* __restrict__ p_first,
+                             int32_t* __restrict__ p_nn) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = keys[i];
+        const int c = cluster_of(key, D);
+        const int64_t cs = cl_off[c], ce = cl_off[c + 1];
+        int lf;
+        if (i == cs) {
+            lf = 0;
+        } else {
+            const uint64_t x = key ^ keys[i - 1];
+            if (x == 0) {
+                p_first[i] = D + 1;
+                p_nn[i] = 0;
+                continue;
+            }
+            const int h = 63 - __clzll(x);
+            lf = D - h / 3;
+            // the parent run (level lf-1) contains i-1 and i: it must hold more than n_leaf
+            const uint64_t pp = prefix(key, lf - 1, D);
+            int64_t a = i - 1, b = i + 1;
+            while (a > cs && b - a <= n_leaf && prefix(keys[a - 1], lf - 1, D) == pp) --a;
+            while (b < ce && b - a <= n_leaf && prefix(keys[b], lf - 1, D) == pp) ++b;
+            if (b - a <= n_leaf) {
+                p_first[i] = lf;
+                p_nn[i] = 0;
+                continue;
+            }
+        }
+        // levels lf+1.. exist while the run of level l-1 starting at i holds > n_leaf
+        int last = lf;
+        for (int l = lf + 1; l <= D; ++l) {
+            const int64_t j = i + n_leaf;
+            if (j < ce && prefix(keys[j], l - 1, D) == prefix(key, l - 1, D)) last = l;
+            else break;
+        }
+        p_first[i] = lf;
+        p_nn[i] = last - lf + 1;
+    }
+}
+
+// end of the level-l run that starts at i (exclusive)
+__device__ inline int64_t run_end(const uint64_t* keys, int64_t i, int64_t ce, int l, int D) {
+    if (l == 0) return ce;
+    const uint64_t p = prefix(keys[i], l, D);
+    int64_t step = 1, lo = i, hi;
+    // exponential search for the first index with a different prefix
+    for (;;) {
+        hi = lo + step;
+        if (hi >= ce || prefix(keys[hi], l, D) != p) break;
+        lo = hi;
+        step <<= 1;
+    }
+    if (hi > ce) hi = ce;
+    // invariant: keys[lo] has prefix p; keys[hi] (if < ce) does not
+    while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (prefix(keys[mid], l, D) == p) lo = mid; else hi = mid;
+    }
+    return hi;
+}
+
+// start of the level-l run containing i
+__device__ inline int64_t run_start(const uint64_t* keys, int64_t i, int64_t cs, int l, int D) {
+    if (l == 0) return cs;
+    const uint64_t p = prefix(keys[i], l, D);
+    int64_t step = 1, hi = i, lo;
+    for (;;) {
+        lo = hi - step;
+        if (lo < cs || prefix(keys[lo], l, D) != p) break;
+        hi = lo;
+        step <<= 1;
+    }
+    if (lo < cs - 1) lo = cs - 1;
+    // keys[hi] has prefix p; keys[lo] (if >= cs) does not
+    while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (prefix(keys[mid], l, D) == p) hi = mid; else lo = mid;
+    }
+    return hi;
+}
+
+__global__ void k_topo_emit(const uint64_t* __restrict__ keys, const int64_t* __restrict__ cl_off,
+                            int64_t n, int D, int n_leaf, const int32_t* __restrict__ p_first,
+                            const int32_t* __restrict__ p_base, int64_t cap,
+                            int32_t* __restrict__ pre_begin, int32_t* __restrict__ pre_count,
+                            int32_t* __restrict__ pre_level, int32_t* __restrict__ pre_nchild,
+                            uint64_t* __restrict__ lvl_key, unsigned long long* __restrict__ cnt) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int nn = p_base[i + 1] - p_base[i];
+        if (nn == 0) continue;
+        const uint64_t key = keys[i];
+        const int c = cluster_of(key, D);
+        const int64_t cs = cl_off[c], ce = cl_off[c + 1];
+        const int lf = p_first[i];
+        for (int k = 0; k < nn; ++k) {
+            const int l = lf + k;
+            const int64_t node = (int64_t)p_base[i] + k;
+            if (node >= cap) {
+                atomicOr(&cnt[kErr], kErrNodeCap);
+                break;
+            }
+            const int64_t e = run_end(keys, i, ce, l, D);
+            pre_begin[node] = (int32_t)i;
+            pre_count[node] = (int32_t)(e - i);
+            pre_level[node] = l;
+            lvl_key[node] = (uint64_t)l;
+            // register with the parent: its node index is known from the particle
+            // that starts it (i itself for k > 0)
+            if (l > 0) {
+                int64_t parent;
+                if (k > 0) {
+                    parent = node - 1;
+                } else {
+                    const int64_t s = run_start(keys, i, cs, l - 1, D);
+                    parent = (int64_t)p_base[s] + (l - 1 - p_first[s]);
+                }
+                if (parent < cap) atomicAdd(&pre_nchild[parent], 1);
+            }
+        }
+    }
+}
+
+__global__ void k_zero_i32(int32_t* __restrict__ p, const int32_t* __restrict__ n_dev, int64_t cap) {
+    const int64_t n = min(cap, (int64_t)*n_dev);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// breadth-first level offsets: lvl_off[l] = first sorted slot with level >= l
+__global__ void k_level_offsets(const uint64_t* __restrict__ lvl_sorted,
+                                const int32_t* __restrict__ n_dev, int64_t cap,
+                                int32_t* __restrict__ lvl_off, unsigned long long* __restrict__ cnt) {
+    const int l = threadIdx.x;
+    const int64_t n = min(cap, (int64_t)*n_dev);
+    if (l <= kMaxLevels) {
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (lvl_sorted[mid] < (uint64_t)l) lo = mid + 1; else hi = mid;
+        }
+        lvl_off[l] = (int32_t)lo;
+    }
+    if (l == 0) {
+        cnt[kCntNodes] = (unsigned long long)n;
+        cnt[kCntMaxLevel] = n ? lvl_sorted[n - 1] : 0ull;
+    }
+}
+
+__global__ void k_invert(const int32_t* __restrict__ bfs2pre, const int32_t* __restrict__ n_dev,
+                         int64_t cap, int32_t* __restrict__ pre2bfs) {
+    const int64_t n = min(cap, (int64_t)*n_dev);
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n;
+         b += (int64_t)gridDim.x * blockDim.x)
+        pre2bfs[bfs2pre[b]] = (int32_t)b;
+}
+
+__global__ void k_nodes_init(const int32_t* __restrict__ bfs2pre, const int32_t* __restrict__ pre2bfs,
+                             const int32_t* __restrict__ n_dev, int64_t cap,
+                             const int32_t* __restrict__ pre_begin, const int32_t* __restrict__ pre_count,
+                             const int32_t* __restrict__ pre_nchild, WNode* __restrict__ node,
+                             unsigned long long* __restrict__ cnt) {
+    const int64_t n = min(cap, (int64_t)*n_dev);
+    unsigned long long leaves = 0;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = bfs2pre[b];
+        // pre-order: the first child follows its parent (guarded for a truncated node list)
+        const int32_t nc = (p + 1 < n) ? pre_nchild[p] : 0;
+        WNode& w = node[b];
+        w.begin = pre_begin[p];
+        w.count = pre_count[p];
+        w.nchild = nc;
+        w.first_child = nc ? pre2bfs[p + 1] : -1;
+        leaves += (nc == 0);
+    }
+    if (leaves) atomicAdd(&cnt[kCntLeaves], leaves);
+}
+
+// ----------------------------------------------------------------- moments
+// One node per thread for the nodes of one level. Leaves sum their particles,
+// inner nodes their (contiguous) children, in order.
+__global__ void k_moments_level(const int32_t* __restrict__ lvl_off, int level,
+                                const double* __restrict__ x, const double* __restrict__ y,
+                                const double* __restrict__ z, const double* __restrict__ m,
+                                WNode* __restrict__ node, Mom64* __restrict__ q64,
+                                Mom32* __restrict__ q32) {
+#pragma clang fp contract(off)
+    const int64_t b0 = lvl_off[level], b1 = lvl_off[level + 1];
+    for (int64_t b = b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < b1;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        WNode w = node[b];
+        const bool leaf = w.nchild == 0;
+        const int nsub = leaf ? w.count : w.nchild;
+        double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+        double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int u = 0; u < nsub; ++u) {
+            double mu, cu[3], lu[3], hu[3];
+            if (leaf) {
+                const int j = w.begin + u;
+                mu = m[j]; cu[0] = x[j]; cu[1] = y[j]; cu[2] = z[j];
+                for (int k = 0; k < 3; ++k) { lu[k] = cu[k]; hu[k] = cu[k]; }
+            } else {
+                const int c = w.first_child + u;
+                mu = q64[c].M;
+                for (int k = 0; k < 3; ++k) {
+                    cu[k] = node[c].com[k];
+                    lu[k] = node[c].lo[k];
+                    hu[k] = node[c].hi[k];
+                }
+            }
+            M = M + mu;
+            sx = sx + mu * cu[0];
+            sy = sy + mu * cu[1];
+            sz = sz + mu * cu[2];
+            for (int k = 0; k < 3; ++k) {
+                if (u == 0 || lu[k] < lo[k]) lo[k] = lu[k];
+                if (u == 0 || hu[k] > hi[k]) hi[k] = hu[k];
+            }
+        }
+        double com[3];
+        if (M > 0.0) {
+            com[0] = sx / M; com[1] = sy / M; com[2] = sz / M;
+        } else {
+            for (int k = 0; k < 3; ++k) com[k] = (lo[k] + hi[k]) * 0.5;
+        }
+        double q[6] = {0, 0, 0, 0, 0, 0};
+        for (int u = 0; u < nsub; ++u) {
+            double mu, cu[3], qc[6];
+            if (leaf) {
+                const int j = w.begin + u;
+                mu = m[j]; cu[0] = x[j]; cu[1] = y[j]; cu[2] = z[j];
+                for (int e = 0; e < 6; ++e) qc[e] = 0.0;
+            } else {
+                const int c = w.first_child + u;
+                const Mom64 mc = q64[c];
+                mu = mc.M;
+                for (int k = 0; k < 3; ++k) cu[k] = node[c].com[k];
+                qc[0] = mc.qxx; qc[1] = mc.qyy; qc[2] = mc.qzz;
+                qc[3] = mc.qxy; qc[4] = mc.qxz; qc[5] = mc.qyz;
+            }
+            const double dx = cu[0] - com[0], dy = cu[1] - com[1], dz = cu[2] - com[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            q[0] = q[0] + (qc[0] + mu * (3.0 * dx * dx - r2));
+            q[1] = q[1] + (qc[1] + mu * (3.0 * dy * dy - r2));
+            q[2] = q[2] + (qc[2] + mu * (3.0 * dz * dz - r2));
+            q[3] = q[3] + (qc[3] + mu * (3.0 * dx * dy));
+            q[4] = q[4] + (qc[4] + mu * (3.0 * dx * dz));
+            q[5] = q[5] + (qc[5] + mu * (3.0 * dy * dz));
+        }
+        for (int k = 0; k < 3; ++k) {
+            node[b].lo[k] = lo[k];
+            node[b].hi[k] = hi[k];
+            node[b].com[k] = com[k];
+        }
+        Mom64 o;
+        o.M = M; o.qxx = q[0]; o.qyy = q[1]; o.qzz = q[2]; o.qxy = q[3]; o.qxz = q[4]; o.qyz = q[5];
+        o.pad = 0.0;
+        q64[b] = o;
+        Mom32 f;
+        f.M = (float)M; f.qxx = (float)q[0]; f.qyy = (float)q[1]; f.qzz = (float)q[2];
+        f.qxy = (float)q[3]; f.qxz = (float)q[4]; f.qyz = (float)q[5]; f.pad = 0.0f;
+        q32[b] = f;
+    }
+}
+
+// ------------------------------------------------------------------ groups
+// One wave per group: particles [begin, begin+count) of one cluster.
+__global__ __launch_bounds__(64) void k_groups(const int32_t* __restrict__ grp_first, int nc,
+                                               const int64_t* __restrict__ cl_off, int n_crit,
+                                               int64_t G, const int32_t* __restrict__ p_base,
+                                               const int32_t* __restrict__ pre2bfs,
+                                               const double* __restrict__ x,
+                                               const double* __restrict__ y,
+                                               const double* __restrict__ z, GroupArrays g) {
+    const int64_t gi = blockIdx.x;
+    if (gi >= G) return;
+    // cluster: last c with grp_first[c] <= gi
+    int lo = 0, hi = nc;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (grp_first[mid] <= gi) lo = mid; else hi = mid;
+    }
+    const int c = lo;
+    const int64_t cs = cl_off[c], ce = cl_off[c + 1];
+    const int64_t b = cs + (gi - grp_first[c]) * (int64_t)n_crit;
+    const int cntg = (int)((ce - b) < n_crit ? (ce - b) : n_crit);
+    const int lane = threadIdx.x;
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int k = lane; k < cntg; k += 64) {
+        const double p[3] = {x[b + k], y[b + k], z[b + k]};
+        for (int d = 0; d < 3; ++d) {
+            v[d] = fmin(v[d], p[d]);
+            v[3 + d] = fmax(v[3 + d], p[d]);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        for (int d = 0; d < 3; ++d) {
+            v[d] = fmin(v[d], __shfl_xor(v[d], o, 64));
+            v[3 + d] = fmax(v[3 + d], __shfl_xor(v[3 + d], o, 64));
+        }
+    }
+    if (lane == 0) {
+        g.begin[gi] = (int32_t)b;
+        g.count[gi] = cntg;
+        g.cluster[gi] = c;
+        g.root[gi] = pre2bfs[p_base[cs]];   // level-0 node started by the cluster's first particle
+        for (int d = 0; d < 3; ++d) {
+            g.lo[3 * gi + d] = v[d];
+            g.hi[3 * gi + d] = v[3 + d];
+        }
+    }
+}
+
+inline int grid_for(int64_t n, int threads, int maxb = 4096) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > maxb) b = maxb;
+    return (int)b;
+}
+
+}  // namespace
+
+void launch_bbox(Dev& d, const BuildCfg& c, const double* pos, const double* mass, int nblk,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(k_bbox_part, dim3(nblk), dim3(BB_T), 0, s, pos, mass,
+                       (const int64_t*)d.blk_range, d.blk_part, d.blk_bad);
+    // d.blk_cluster is followed by the per-cluster block offsets (see host setup)
+    const int32_t* cblk = d.blk_cluster + nblk;
+    hipLaunchKernelGGL(k_bbox_final, dim3((c.n_clusters + 63) / 64), dim3(64), 0, s,
+                       (const double*)d.blk_part, (const int32_t*)d.blk_bad, cblk, c.n_clusters,
+                       d.cl_box, d.cnt);
+}
+
+void launch_keys(Dev& d, const BuildCfg& c, const double* pos, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL(k_keys, dim3(nblk), dim3(BB_T), 0, s, pos, (const int64_t*)d.blk_range,
+                       (const int32_t*)d.blk_cluster, (const double*)d.cl_box, c.D, d.keys);
+}
+
+void launch_gather(Dev& d, const BuildCfg& c, const double* pos, const double* mass, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(c.n, 256)), dim3(256), 0, s, pos, mass,
+                       (const int32_t*)d.perm, c.n, d.x, d.y, d.z, d.m);
+}
+
+void launch_topology(Dev& d, const BuildCfg& c, hipStream_t s) {
+    const int64_t n = c.n;
+    const int64_t cap = c.node_cap;
+    hipLaunchKernelGGL(k_topo_count, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                       (const uint64_t*)d.keys, (const int64_t*)d.cl_off, n, c.D, c.n_leaf,
+                       d.p_first, d.p_nn);
+    exclusive_scan_i32(d.p_nn, d.p_nn, n, d.scan_tmp, s);   // p_nn[n] = node count
+    const int32_t* n_nodes = d.p_nn + n;
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(cap, 256)), dim3(256), 0, s, d.pre_nchild,
+                       n_nodes, cap);
+    hipLaunchKernelGGL(k_topo_emit, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                       (const uint64_t*)d.keys, (const int64_t*)d.cl_off, n, c.D, c.n_leaf,
+                       (const int32_t*)d.p_first, (const int32_t*)d.p_nn, cap, d.pre_begin,
+                       d.pre_count, d.pre_level, d.pre_nchild, d.lvl_key, d.cnt);
+    // breadth-first order: stable sort of pre-order nodes by level (one 8-bit pass)
+    radix_sort_pairs(d.lvl_key, d.bfs2pre, d.lvl_key_alt, d.lvl_val, cap, 8, d.rs_hist, d.scan_tmp,
+                     s, true, n_nodes);
+    hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, (const uint64_t*)d.lvl_key,
+                       n_nodes, cap, d.lvl_off, d.cnt);
+    hipLaunchKernelGGL(k_invert, dim3(grid_for(cap, 256)), dim3(256), 0, s,
+                       (const int32_t*)d.bfs2pre, n_nodes, cap, d.pre2bfs);
+    hipLaunchKernelGGL(k_nodes_init, dim3(grid_for(cap, 256)), dim3(256), 0, s,
+                       (const int32_t*)d.bfs2pre, (const int32_t*)d.pre2bfs, n_nodes, cap,
+                       (const int32_t*)d.pre_begin, (const int32_t*)d.pre_count,
+                       (const int32_t*)d.pre_nchild, d.node, d.cnt);
+}
+
+void launch_moments(Dev& d, const BuildCfg& c, hipStream_t s) {
+    for (int l = c.D; l >= 0; --l) {
+        hipLaunchKernelGGL(k_moments_level, dim3(grid_for(c.node_cap, 128, 2048)), dim3(128), 0, s,
+                           (const int32_t*)d.lvl_off, l, (const double*)d.x, (const double*)d.y,
+                           (const double*)d.z, (const double*)d.m, d.node, d.q64, d.q32);
+    }
+}
+
+void launch_groups(Dev& d, const BuildCfg& c, const int32_t* grp_first, hipStream_t s) {
+    hipLaunchKernelGGL(k_groups, dim3(c.n_groups), dim3(64), 0, s, grp_first, c.n_clusters,
+                       (const int64_t*)d.cl_off, c.n_crit, c.n_groups, (const int32_t*)d.p_nn,
+                       (const int32_t*)d.pre2bfs, (const double*)d.x, (const double*)d.y,
+                       (const double*)d.z, d.g);
+}
+
+}  // namespace pbh

@@ -1,0 +1,729 @@
+// host.cpp -- the C ABI of libpbh (declared in include/pbh.h).
+//
+// Owns the device buffers of a context, validates arguments, computes the
+// per-cluster changeover constants, and enqueues the kernels of build.hip,
+// sort.hip, walk.hip, nbr.hip and kdk.hip on the caller's stream. Every
+// numerical step runs on the GPU; the host only marshals sizes and constants.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pbh.h"
+#include "pbh_internal.hpp"
+
+using namespace pbh;
+
+namespace {
+
+constexpr int kBoxChunk = 16384;     // particles per bbox/key block
+constexpr int kStackCap = 16384;     // traversal stack entries per persistent wave
+constexpr int kCntKdkStep = 11;      // counter slot: KDK energy output index
+
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct pbh_ctx {
+    int device = 0;
+    pbh_params params{16, 64, 0, PBH_MIXED};
+    std::string err;
+    hipStream_t last = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int cus = 0;
+
+    // build state
+    bool built = false;
+    bool batched = false;
+    BuildCfg cfg;
+    Dev d;
+    std::vector<Buf> bufs;
+    std::vector<int64_t> cl_off_h;
+    std::vector<int32_t> grp_first_h;
+    int32_t* grp_first_d = nullptr;
+    int nblk_box = 0;
+    // allocation sizes
+    int64_t a_n = -1, a_cap = -1, a_G = -1, a_C = -1, a_nblk = -1, a_stack = -1;
+    int64_t alloc_gen = 0;   // bumped whenever device buffers are reallocated
+    int grid_mixed = 0, grid_fp64 = 0;
+
+    // kdk
+    double* k_acc = nullptr;
+    double* k_pot = nullptr;
+    double* k_epart = nullptr;
+    int k_nblk = 0;
+    int64_t k_n = -1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<double> gkey;   // parameters the captured graph was made with
+};
+
+namespace {
+
+pbh_status fail(pbh_ctx* c, pbh_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIP_TRY(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(ctx, PBH_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void free_all(pbh_ctx* ctx) {
+    for (auto& b : ctx->bufs)
+        if (b.p) (void)hipFree(b.p);
+    ctx->bufs.clear();
+    ctx->d = Dev();
+    ctx->grp_first_d = nullptr;
+    ctx->a_n = ctx->a_cap = ctx->a_G = ctx->a_C = ctx->a_nblk = ctx->a_stack = -1;
+}
+
+template <typename T>
+bool dalloc(pbh_ctx* ctx, T** p, int64_t count) {
+    size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) return false;
+    ctx->bufs.push_back({q, bytes});
+    *p = (T*)q;
+    return true;
+}
+
+int cluster_bits(int32_t C) {
+    int b = 0;
+    while ((1ll << b) < C) ++b;
+    return b;
+}
+
+int64_t node_capacity(int64_t n, int D, int n_leaf, int C) {
+    // leaves <= n, branching inner nodes < leaves, single-child inner nodes
+    // <= one per (n_leaf+1) particles per level
+    return 2 * n + (int64_t)D * ((n + n_leaf) / (n_leaf + 1)) + C + 64;
+}
+
+pbh_status ensure_buffers(pbh_ctx* ctx) {
+    const BuildCfg& c = ctx->cfg;
+    const int64_t n = c.n, cap = c.node_cap, G = c.n_groups, C = c.n_clusters;
+    const int64_t nblk = ctx->nblk_box;
+    const int64_t stack = (int64_t)std::max(ctx->grid_mixed, ctx->grid_fp64) * kStackCap;
+    if (n <= ctx->a_n && cap <= ctx->a_cap && G <= ctx->a_G && C <= ctx->a_C &&
+        nblk <= ctx->a_nblk && stack <= ctx->a_stack)
+        return PBH_OK;
+    free_all(ctx);
+    Dev& d = ctx->d;
+    const int64_t big = std::max(n, cap);
+    const int64_t scan_len = scan_tmp_need(std::max(big, radix_hist_need(big)) + 1);
+    bool ok = dalloc(ctx, &d.x, n) && dalloc(ctx, &d.y, n) && dalloc(ctx, &d.z, n) &&
+              dalloc(ctx, &d.m, n) && dalloc(ctx, &d.perm, n) && dalloc(ctx, &d.keys, n) &&
+              dalloc(ctx, &d.keys_alt, n) && dalloc(ctx, &d.vals_alt, big) &&
+              dalloc(ctx, &d.cl_off, C + 1) && dalloc(ctx, &d.cl_box, 6 * C) &&
+              dalloc(ctx, &d.blk_cluster, nblk + C + 1) && dalloc(ctx, &d.blk_range, 2 * nblk) &&
+              dalloc(ctx, &d.blk_part, 6 * nblk) && dalloc(ctx, &d.blk_bad, nblk) &&
+              dalloc(ctx, &d.cparams, C) && dalloc(ctx, &d.p_first, n) &&
+              dalloc(ctx, &d.p_nn, n + 1) && dalloc(ctx, &d.pre_begin, cap) &&
+              dalloc(ctx, &d.pre_count, cap) && dalloc(ctx, &d.pre_level, cap) &&
+              dalloc(ctx, &d.pre_nchild, cap) && dalloc(ctx, &d.lvl_key, cap) &&
+              dalloc(ctx, &d.lvl_key_alt, cap) && dalloc(ctx, &d.lvl_val, cap) &&
+              dalloc(ctx, &d.bfs2pre, cap) && dalloc(ctx, &d.pre2bfs, cap) &&
+              dalloc(ctx, &d.lvl_off, 32) && dalloc(ctx, &d.node, cap) &&
+              dalloc(ctx, &d.q64, cap) && dalloc(ctx, &d.q32, cap) &&
+              dalloc(ctx, &d.g.begin, G) && dalloc(ctx, &d.g.count, G) &&
+              dalloc(ctx, &d.g.root, G) && dalloc(ctx, &d.g.cluster, G) &&
+              dalloc(ctx, &d.g.lo, 3 * G) && dalloc(ctx, &d.g.hi, 3 * G) &&
+              dalloc(ctx, &ctx->grp_first_d, C + 1) && dalloc(ctx, &d.scan_tmp, scan_len) &&
+              dalloc(ctx, &d.rs_hist, radix_hist_need(big) + 1) && dalloc(ctx, &d.nbr_cnt, n) &&
+              dalloc(ctx, &d.stack, stack) && dalloc(ctx, &d.cnt, kNumCounters);
+    if (!ok) {
+        free_all(ctx);
+        return fail(ctx, PBH_E_OOM, "device allocation failed");
+    }
+    d.scan_tmp_len = scan_len;
+    d.stack_len = stack;
+    ++ctx->alloc_gen;
+    ctx->a_n = n; ctx->a_cap = cap; ctx->a_G = G; ctx->a_C = C; ctx->a_nblk = nblk;
+    ctx->a_stack = stack;
+    return PBH_OK;
+}
+
+// Host part of a build: sizes, tables, uploads. No kernel runs here.
+pbh_status setup_build(pbh_ctx* ctx, int64_t n, int32_t C, const int64_t* offsets, hipStream_t s) {
+    BuildCfg& c = ctx->cfg;
+    c.n = n;
+    c.n_clusters = C;
+    c.cbits = cluster_bits(C);
+    int D = (63 - c.cbits) / 3;
+    if (D > 21) D = 21;
+    if (ctx->params.key_bits > 0 && ctx->params.key_bits < D) D = ctx->params.key_bits;
+    c.D = D;
+    c.n_leaf = ctx->params.leaf_size;
+    c.n_crit = ctx->params.n_crit;
+    c.node_cap = node_capacity(n, D, c.n_leaf, C);
+    if (c.node_cap >= (1ll << 31)) return fail(ctx, PBH_E_ARG, "too many particles for int32 node indices");
+    ctx->cl_off_h.assign(offsets, offsets + C + 1);
+    ctx->grp_first_h.assign(C + 1, 0);
+    std::vector<int32_t> blk_cluster;
+    std::vector<int64_t> blk_range;
+    std::vector<int32_t> cblk(C + 1, 0);
+    int64_t G = 0;
+    for (int k = 0; k < C; ++k) {
+        const int64_t a = offsets[k], b = offsets[k + 1];
+        ctx->grp_first_h[k] = (int32_t)G;
+        G += (b - a + c.n_crit - 1) / c.n_crit;
+        cblk[k] = (int32_t)blk_cluster.size();
+        for (int64_t q = a; q < b; q += kBoxChunk) {
+            blk_cluster.push_back(k);
+            blk_range.push_back(q);
+            blk_range.push_back(std::min(b, q + kBoxChunk));
+        }
+    }
+    ctx->grp_first_h[C] = (int32_t)G;
+    cblk[C] = (int32_t)blk_cluster.size();
+    c.n_groups = G;
+    ctx->nblk_box = (int)blk_cluster.size();
+    if (ctx->grid_mixed == 0) {
+        ctx->grid_mixed = walk_blocks_per_cu(1) * ctx->cus;
+        ctx->grid_fp64 = walk_blocks_per_cu(0) * ctx->cus;
+    }
+    pbh_status st = ensure_buffers(ctx);
+    if (st != PBH_OK) return st;
+    // block table: cluster of each block, then per-cluster block offsets
+    std::vector<int32_t> tab(blk_cluster);
+    tab.insert(tab.end(), cblk.begin(), cblk.end());
+    HIP_TRY(hipMemcpyAsync(ctx->d.blk_cluster, tab.data(), tab.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ctx->d.blk_range, blk_range.data(), blk_range.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ctx->d.cl_off, ctx->cl_off_h.data(), (C + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ctx->grp_first_d, ctx->grp_first_h.data(), (C + 1) * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));   // the host tables above are temporaries
+    return PBH_OK;
+}
+
+// Device part of a build: kernels only (capturable).
+void enqueue_build(pbh_ctx* ctx, const double* pos, const double* mass, hipStream_t s) {
+    Dev& d = ctx->d;
+    const BuildCfg& c = ctx->cfg;
+    launch_zero_u64(d.cnt, kNumCounters - 5, s);   // keep the KDK slots (>= 11)
+    launch_bbox(d, c, pos, mass, ctx->nblk_box, s);
+    launch_keys(d, c, pos, ctx->nblk_box, s);
+    radix_sort_pairs(d.keys, d.perm, d.keys_alt, d.vals_alt, c.n, 3 * c.D + c.cbits, d.rs_hist,
+                     d.scan_tmp, s, true);
+    launch_gather(d, c, pos, mass, s);
+    launch_topology(d, c, s);
+    launch_moments(d, c, s);
+    launch_groups(d, c, ctx->grp_first_d, s);
+}
+
+// Changeover constants of one cluster (see ClusterParams).
+ClusterParams cluster_params(double r_in, double r_out) {
+    ClusterParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.r_in = r_in;
+    p.r_out = r_out;
+    p.rout2 = r_out * r_out;
+    const double delta = r_out - r_in;
+    if (r_out > 0.0 && delta > 0.0) {
+        // g(t - a) = sum_k dk t^k with g(x) = 35x^4 - 84x^5 + 70x^6 - 20x^7
+        const double a = r_in / delta;
+        const double cg[8] = {0, 0, 0, 0, 35.0, -84.0, 70.0, -20.0};
+        double dk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int q = 4; q <= 7; ++q) {
+            double binom = 1.0;   // C(q, k) built up from k = 0
+            for (int k = 0; k <= q; ++k) {
+                if (k > 0) binom = binom * (double)(q - k + 1) / (double)k;
+                dk[k] += cg[q] * binom * std::pow(-a, (double)(q - k));
+            }
+        }
+        // G(t) = -d0/t + d1 ln t + sum_{k>=2} dk t^(k-1)/(k-1);
+        // Phi_R(s) = -1/r_out - (G(a+1) - G(s/delta))/delta
+        auto Gt = [&](double t) {
+            double g = 0.0;
+            if (dk[0] != 0.0) g += -dk[0] / t;
+            if (dk[1] != 0.0) g += dk[1] * std::log(t);
+            for (int k = 2; k <= 7; ++k) g += dk[k] * std::pow(t, (double)(k - 1)) / (double)(k - 1);
+            return g;
+        };
+        const double G1 = Gt(a + 1.0);
+        p.inv_delta = 1.0 / delta;
+        p.d0 = dk[0];
+        p.l1 = dk[1] / delta;
+        p.c0 = -1.0 / r_out - G1 / delta - (dk[1] != 0.0 ? p.l1 * std::log(delta) : 0.0);
+        for (int k = 2; k <= 7; ++k) p.e[k - 2] = dk[k] / ((double)(k - 1) * delta);
+        p.inner = -1.0 / r_out - (G1 - Gt(a)) / delta;
+        if (r_in == 0.0) p.inner = -1.0 / r_out - (G1 - Gt(0.0)) / delta;
+    } else if (r_out > 0.0) {
+        p.inner = -1.0 / r_out;   // step: W = 0 below r_out
+    }
+    p.f_r_in = (float)p.r_in;
+    p.f_r_out = (float)p.r_out;
+    p.f_inv_delta = (float)p.inv_delta;
+    p.f_c0 = (float)p.c0;
+    p.f_d0 = (float)p.d0;
+    p.f_l1 = (float)p.l1;
+    p.f_inner = (float)p.inner;
+    for (int k = 0; k < 6; ++k) p.f_e[k] = (float)p.e[k];
+    return p;
+}
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+constexpr int kParamsPerStore = 8;
+struct ParamPack {
+    ClusterParams p[kParamsPerStore];
+};
+
+__global__ void k_store_params(ParamPack pk, int n, ClusterParams* dst) {
+    const int i = threadIdx.x;
+    if (i < n) dst[i] = pk.p[i];
+}
+
+// Copy per-cluster constants to the device. Small counts travel as kernel
+// arguments (no host buffer outlives the call, and the copy can be captured);
+// large counts use a copy followed by a wait.
+pbh_status upload_cparams(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, hipStream_t s) {
+    const int C = (int)cps.size();
+    if (C <= 64) {
+        for (int b = 0; b < C; b += kParamsPerStore) {
+            ParamPack pk;
+            const int k = std::min(kParamsPerStore, C - b);
+            for (int i = 0; i < k; ++i) pk.p[i] = cps[b + i];
+            hipLaunchKernelGGL(k_store_params, dim3(1), dim3(kParamsPerStore), 0, s, pk, k,
+                               ctx->d.cparams + b);
+        }
+        HIP_TRY(hipGetLastError());
+        return PBH_OK;
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->d.cparams, cps.data(), cps.size() * sizeof(ClusterParams),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PBH_OK;
+}
+
+pbh_status check_radii(pbh_ctx* ctx, double r_in, double r_out) {
+    if (!finite_nonneg(r_in) || !finite_nonneg(r_out) || r_out < r_in)
+        return fail(ctx, PBH_E_ARG, "need 0 <= r_in <= r_out, both finite");
+    return PBH_OK;
+}
+
+pbh_status finish_build(pbh_ctx* ctx, hipStream_t s) {
+    unsigned long long h[kNumCounters];
+    HIP_TRY(hipMemcpyAsync(h, ctx->d.cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h[kErr] & kErrNonFinite) {
+        ctx->built = false;
+        return fail(ctx, PBH_E_NONFINITE, "non-finite position or mass");
+    }
+    if (h[kErr] & kErrNodeCap) {
+        ctx->built = false;
+        return fail(ctx, PBH_E_INTERNAL, "node capacity exceeded");
+    }
+    ctx->built = true;
+    return PBH_OK;
+}
+
+pbh_status do_force(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, double theta, double eps,
+                    double* acc, double* pot, int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap,
+                    int64_t* nbr_total, hipStream_t s) {
+    if (!ctx->built) return fail(ctx, PBH_E_STATE, "pbh_force called without a successful build");
+    if (!finite_nonneg(theta) || !finite_nonneg(eps)) return fail(ctx, PBH_E_ARG, "theta and eps must be finite and >= 0");
+    if (!acc || !pot) return fail(ctx, PBH_E_ARG, "acc and pot are required");
+    if (nbr_cap < 0 || (nbr_cap > 0 && !nbr_idx)) return fail(ctx, PBH_E_ARG, "bad neighbour buffer");
+    Dev& d = ctx->d;
+    const BuildCfg& c = ctx->cfg;
+    pbh_status up = upload_cparams(ctx, cps, s);
+    if (up != PBH_OK) return up;
+    launch_rcrit(d, c, theta, s);
+    WalkCfg w;
+    w.theta = theta;
+    w.eps = eps;
+    w.mixed = ctx->params.prec == PBH_MIXED;
+    const int gmax = w.mixed ? ctx->grid_mixed : ctx->grid_fp64;
+    w.grid = (int)std::min<int64_t>(gmax, std::max<int64_t>(c.n_groups, 1));
+    w.stack_cap = kStackCap;
+    launch_walk(d, c, w, acc, pot, s);
+    if (nbr_off) {
+        const int grid = (int)std::min<int64_t>(ctx->grid_mixed, std::max<int64_t>(c.n_groups, 1));
+        launch_nbr_count(d, c, grid, kStackCap, s);
+        exclusive_scan_i32_to_i64(d.nbr_cnt, nbr_off, c.n, d.scan_tmp, s);
+        if (nbr_total) {
+            int64_t tot = 0;
+            HIP_TRY(hipMemcpyAsync(&tot, nbr_off + c.n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            *nbr_total = tot;
+            if (tot > nbr_cap)
+                return fail(ctx, PBH_E_NBR_OVERFLOW, "neighbour capacity " + std::to_string(nbr_cap) +
+                                                         " < needed " + std::to_string(tot));
+        }
+        launch_nbr_fill(d, c, grid, kStackCap, nbr_off, nbr_idx, nbr_cap, s);
+        if (nbr_total) {
+            unsigned long long err = 0;
+            HIP_TRY(hipMemcpyAsync(&err, d.cnt + kErr, sizeof(err), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (err & (kErrWalkStack | kErrNbrStack))
+                return fail(ctx, PBH_E_INTERNAL, "traversal stack overflow");
+        }
+    }
+    return PBH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pbh_status_string(pbh_status s) {
+    switch (s) {
+        case PBH_OK: return "ok";
+        case PBH_E_ARG: return "invalid argument";
+        case PBH_E_OOM: return "out of device memory";
+        case PBH_E_HIP: return "HIP runtime error";
+        case PBH_E_NONFINITE: return "non-finite input";
+        case PBH_E_NBR_OVERFLOW: return "neighbour capacity too small";
+        case PBH_E_STATE: return "no matching build";
+        case PBH_E_INTERNAL: return "device capacity guard tripped";
+    }
+    return "unknown status";
+}
+
+const char* pbh_last_error(const pbh_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+static pbh_status resolve_params(pbh_ctx* ctx, const pbh_params* in, pbh_params* out) {
+    pbh_params p{16, 64, 0, PBH_MIXED};
+    if (in) {
+        if (in->leaf_size < 0 || in->n_crit < 0 || in->n_crit > 64 || in->key_bits < 0 ||
+            in->key_bits > 21 || (in->prec != PBH_FP64 && in->prec != PBH_MIXED))
+            return fail(ctx, PBH_E_ARG, "bad parameters (n_crit <= 64, key_bits <= 21)");
+        if (in->leaf_size) p.leaf_size = in->leaf_size;
+        if (in->n_crit) p.n_crit = in->n_crit;
+        p.key_bits = in->key_bits;
+        p.prec = in->prec;
+    }
+    *out = p;
+    return PBH_OK;
+}
+
+pbh_status pbh_create(int device, const pbh_params* params, pbh_ctx** out) {
+    if (!out) return PBH_E_ARG;
+    *out = nullptr;
+    pbh_ctx* ctx = new pbh_ctx();
+    pbh_status st = resolve_params(ctx, params, &ctx->params);
+    if (st != PBH_OK) {
+        delete ctx;
+        return st;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        delete ctx;
+        return PBH_E_ARG;
+    }
+    ctx->device = device;
+    if (hipSetDevice(device) != hipSuccess ||
+        hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete ctx;
+        return PBH_E_HIP;
+    }
+    *out = ctx;
+    return PBH_OK;
+}
+
+void pbh_destroy(pbh_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    free_all(ctx);
+    if (ctx->k_acc) (void)hipFree(ctx->k_acc);
+    if (ctx->k_pot) (void)hipFree(ctx->k_pot);
+    if (ctx->k_epart) (void)hipFree(ctx->k_epart);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+}
+
+pbh_status pbh_set_params(pbh_ctx* ctx, const pbh_params* params) {
+    if (!ctx) return PBH_E_ARG;
+    pbh_params p;
+    pbh_status st = resolve_params(ctx, params, &p);
+    if (st != PBH_OK) return st;
+    ctx->params = p;
+    ctx->built = false;
+    return PBH_OK;
+}
+
+pbh_status pbh_get_params(const pbh_ctx* ctx, pbh_params* out) {
+    if (!ctx || !out) return PBH_E_ARG;
+    *out = ctx->params;
+    return PBH_OK;
+}
+
+pbh_status pbh_build(pbh_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                     pbh_stream_t stream) {
+    if (!ctx) return PBH_E_ARG;
+    if (n < 1 || !pos || !mass) return fail(ctx, PBH_E_ARG, "need n >= 1 and pos/mass");
+    if (n >= (1ll << 31) - 1) return fail(ctx, PBH_E_ARG, "n must be < 2^31");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    ctx->built = false;
+    ctx->batched = false;
+    ctx->last = s;
+    const int64_t offs[2] = {0, n};
+    pbh_status st = setup_build(ctx, n, 1, offs, s);
+    if (st != PBH_OK) return st;
+    enqueue_build(ctx, pos, mass, s);
+    return finish_build(ctx, s);
+}
+
+pbh_status pbh_build_batched(pbh_ctx* ctx, int32_t n_clusters, const int64_t* offsets,
+                             const double* pos, const double* mass, pbh_stream_t stream) {
+    if (!ctx) return PBH_E_ARG;
+    if (n_clusters < 1 || n_clusters > 65536 || !offsets || !pos || !mass)
+        return fail(ctx, PBH_E_ARG, "need 1 <= n_clusters <= 65536, offsets, pos, mass");
+    if (offsets[0] != 0) return fail(ctx, PBH_E_ARG, "offsets[0] must be 0");
+    for (int k = 0; k < n_clusters; ++k)
+        if (offsets[k + 1] <= offsets[k]) return fail(ctx, PBH_E_ARG, "every cluster must be non-empty");
+    const int64_t n = offsets[n_clusters];
+    if (n >= (1ll << 31) - 1) return fail(ctx, PBH_E_ARG, "n must be < 2^31");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    ctx->built = false;
+    ctx->batched = true;
+    ctx->last = s;
+    pbh_status st = setup_build(ctx, n, n_clusters, offsets, s);
+    if (st != PBH_OK) return st;
+    enqueue_build(ctx, pos, mass, s);
+    return finish_build(ctx, s);
+}
+
+pbh_status pbh_force(pbh_ctx* ctx, double r_in, double r_out, double theta, double eps,
+                     double* acc, double* pot, int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap,
+                     int64_t* nbr_total, pbh_stream_t stream) {
+    if (!ctx) return PBH_E_ARG;
+    pbh_status st = check_radii(ctx, r_in, r_out);
+    if (st != PBH_OK) return st;
+    if (ctx->built && ctx->cfg.n_clusters != 1)
+        return fail(ctx, PBH_E_STATE, "last build was batched: use pbh_force_batched");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    std::vector<ClusterParams> cps(1, cluster_params(r_in, r_out));
+    return do_force(ctx, cps, theta, eps, acc, pot, nbr_off, nbr_idx, nbr_cap, nbr_total, s);
+}
+
+pbh_status pbh_force_batched(pbh_ctx* ctx, const double* r_in, const double* r_out, double theta,
+                             double eps, double* acc, double* pot, int64_t* nbr_off,
+                             int32_t* nbr_idx, int64_t nbr_cap, int64_t* nbr_total,
+                             pbh_stream_t stream) {
+    if (!ctx) return PBH_E_ARG;
+    if (!ctx->built) return fail(ctx, PBH_E_STATE, "no successful build");
+    if (!r_in || !r_out) return fail(ctx, PBH_E_ARG, "r_in and r_out arrays are required");
+    std::vector<ClusterParams> cps;
+    for (int k = 0; k < ctx->cfg.n_clusters; ++k) {
+        pbh_status st = check_radii(ctx, r_in[k], r_out[k]);
+        if (st != PBH_OK) return st;
+        cps.push_back(cluster_params(r_in[k], r_out[k]));
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    return do_force(ctx, cps, theta, eps, acc, pot, nbr_off, nbr_idx, nbr_cap, nbr_total, s);
+}
+
+static pbh_status kdk_prepare(pbh_ctx* ctx, int64_t n, double r_in, double r_out, double theta,
+                              double eps, hipStream_t s) {
+    if (n < 1 || n >= (1ll << 31) - 1) return fail(ctx, PBH_E_ARG, "bad n");
+    pbh_status st = check_radii(ctx, r_in, r_out);
+    if (st != PBH_OK) return st;
+    if (!finite_nonneg(theta) || !finite_nonneg(eps)) return fail(ctx, PBH_E_ARG, "bad theta/eps");
+    const int64_t offs[2] = {0, n};
+    st = setup_build(ctx, n, 1, offs, s);
+    if (st != PBH_OK) return st;
+    if (ctx->k_n != n) {
+        if (ctx->k_acc) (void)hipFree(ctx->k_acc);
+        if (ctx->k_pot) (void)hipFree(ctx->k_pot);
+        if (ctx->k_epart) (void)hipFree(ctx->k_epart);
+        ctx->k_acc = ctx->k_pot = ctx->k_epart = nullptr;
+        ctx->k_n = -1;
+        ctx->k_nblk = (int)std::min<int64_t>(1024, (n + 255) / 256) + 1;
+        HIP_TRY(hipMalloc(&ctx->k_acc, sizeof(double) * 3 * n));
+        HIP_TRY(hipMalloc(&ctx->k_pot, sizeof(double) * n));
+        HIP_TRY(hipMalloc(&ctx->k_epart, sizeof(double) * ctx->k_nblk));
+        ctx->k_n = n;
+    }
+    ctx->batched = false;
+    std::vector<ClusterParams> cps(1, cluster_params(r_in, r_out));
+    return upload_cparams(ctx, cps, s);
+}
+
+// force of the current positions into k_acc / k_pot (kernels only)
+static void kdk_force(pbh_ctx* ctx, const double* pos, const double* mass, double theta, double eps,
+                      hipStream_t s) {
+    enqueue_build(ctx, pos, mass, s);
+    launch_rcrit(ctx->d, ctx->cfg, theta, s);
+    WalkCfg w;
+    w.theta = theta;
+    w.eps = eps;
+    w.mixed = ctx->params.prec == PBH_MIXED;
+    const int gmax = w.mixed ? ctx->grid_mixed : ctx->grid_fp64;
+    w.grid = (int)std::min<int64_t>(gmax, std::max<int64_t>(ctx->cfg.n_groups, 1));
+    w.stack_cap = kStackCap;
+    launch_walk(ctx->d, ctx->cfg, w, ctx->k_acc, ctx->k_pot, s);
+}
+
+__global__ void k_energy_store(const double* e, double* out, unsigned long long* cnt) {
+    // out[cnt[kCntKdkStep]] = *e, then advance the slot
+    const unsigned long long k = cnt[kCntKdkStep];
+    out[k] = *e;
+    cnt[kCntKdkStep] = k + 1;
+}
+
+__global__ void k_set_u64(unsigned long long* p, unsigned long long v) { *p = v; }
+
+static void kdk_energy(pbh_ctx* ctx, const double* vel, const double* mass, double* energy_out,
+                       hipStream_t s) {
+    double* e_tmp = ctx->k_epart + ctx->k_nblk - 1;   // last partial slot reused as the result
+    launch_energy(vel, mass, ctx->k_pot, ctx->cfg.n, ctx->k_epart, ctx->k_nblk - 1, e_tmp, s);
+    hipLaunchKernelGGL(k_energy_store, dim3(1), dim3(1), 0, s, (const double*)e_tmp, energy_out,
+                       ctx->d.cnt);
+}
+
+static void kdk_step(pbh_ctx* ctx, double* pos, double* vel, const double* mass, double dt,
+                     double theta, double eps, double* energy_out, hipStream_t s) {
+    const int64_t n = ctx->cfg.n;
+    launch_kick(vel, ctx->k_acc, 0.5 * dt, n, s);
+    launch_drift(pos, vel, dt, n, s);
+    kdk_force(ctx, pos, mass, theta, eps, s);
+    launch_kick(vel, ctx->k_acc, 0.5 * dt, n, s);
+    kdk_energy(ctx, vel, mass, energy_out, s);
+}
+
+static pbh_status kdk_impl(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
+                           double dt, int32_t steps, double r_in, double r_out, double theta,
+                           double eps, double* energy_out, hipStream_t s, bool graph) {
+    if (!ctx) return PBH_E_ARG;
+    if (!pos || !vel || !mass || !energy_out || steps < 0 || !std::isfinite(dt))
+        return fail(ctx, PBH_E_ARG, "bad kdk arguments");
+    HIP_TRY(hipSetDevice(ctx->device));
+    ctx->last = s;
+    pbh_status st = kdk_prepare(ctx, n, r_in, r_out, theta, eps, s);
+    if (st != PBH_OK) return st;
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, ctx->d.cnt + kCntKdkStep, 0ull);
+    // initial force and energy
+    kdk_force(ctx, pos, mass, theta, eps, s);
+    kdk_energy(ctx, vel, mass, energy_out, s);
+    if (!graph) {
+        for (int k = 0; k < steps; ++k) kdk_step(ctx, pos, vel, mass, dt, theta, eps, energy_out, s);
+    } else if (steps > 0) {
+        const std::vector<double> key = {dt, theta, eps, r_in, r_out, (double)(uintptr_t)pos,
+                                         (double)(uintptr_t)vel, (double)(uintptr_t)mass,
+                                         (double)(uintptr_t)energy_out, (double)ctx->params.prec,
+                                         (double)ctx->params.leaf_size, (double)ctx->params.n_crit,
+                                         (double)ctx->params.key_bits, (double)ctx->alloc_gen,
+                                         (double)(uintptr_t)ctx->k_acc, (double)n};
+        if (!ctx->gexec || ctx->gkey != key) {
+            if (ctx->gexec) { (void)hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
+            if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
+            hipStream_t cs = ctx->cap_stream;
+            HIP_TRY(hipStreamSynchronize(s));
+            HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            kdk_step(ctx, pos, vel, mass, dt, theta, eps, energy_out, cs);
+            HIP_TRY(hipStreamEndCapture(cs, &ctx->graph));
+            HIP_TRY(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
+            ctx->gkey = key;
+        }
+        for (int k = 0; k < steps; ++k) HIP_TRY(hipGraphLaunch(ctx->gexec, s));
+    }
+    ctx->built = true;
+    return PBH_OK;
+}
+
+pbh_status pbh_kdk(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
+                   double dt, int32_t steps, double r_in, double r_out, double theta, double eps,
+                   double* energy_out, pbh_stream_t stream) {
+    return kdk_impl(ctx, n, pos, vel, mass, dt, steps, r_in, r_out, theta, eps, energy_out,
+                    (hipStream_t)stream, true);
+}
+
+pbh_status pbh_kdk_eager(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
+                         double dt, int32_t steps, double r_in, double r_out, double theta,
+                         double eps, double* energy_out, pbh_stream_t stream) {
+    return kdk_impl(ctx, n, pos, vel, mass, dt, steps, r_in, r_out, theta, eps, energy_out,
+                    (hipStream_t)stream, false);
+}
+
+pbh_status pbh_get_stats(pbh_ctx* ctx, pbh_stats* out) {
+    if (!ctx || !out) return PBH_E_ARG;
+    std::memset(out, 0, sizeof(*out));
+    if (!ctx->d.cnt) return PBH_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipStreamSynchronize(ctx->last));
+    unsigned long long h[kNumCounters];
+    HIP_TRY(hipMemcpy(h, ctx->d.cnt, sizeof(h), hipMemcpyDeviceToHost));
+    out->n = ctx->cfg.n;
+    out->n_clusters = ctx->cfg.n_clusters;
+    out->n_nodes = (int64_t)h[kCntNodes];
+    out->n_leaves = (int64_t)h[kCntLeaves];
+    out->n_groups = ctx->cfg.n_groups;
+    out->max_level = (int64_t)h[kCntMaxLevel];
+    out->n_pn = (int64_t)h[kCntPN];
+    out->n_pp_far = (int64_t)h[kCntFar];
+    out->n_pp_near = (int64_t)h[kCntNear];
+    out->error_flags = (int64_t)h[kErr];
+    return PBH_OK;
+}
+
+pbh_status pbh_debug_tree(pbh_ctx* ctx, int32_t* order, uint64_t* keys, int64_t cap,
+                          int64_t* nodes_i, double* nodes_d, int64_t* n_nodes) {
+    if (!ctx) return PBH_E_ARG;
+    if (!ctx->built) return fail(ctx, PBH_E_STATE, "no successful build");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipStreamSynchronize(ctx->last));
+    const int64_t n = ctx->cfg.n;
+    unsigned long long h[kNumCounters];
+    HIP_TRY(hipMemcpy(h, ctx->d.cnt, sizeof(h), hipMemcpyDeviceToHost));
+    const int64_t nn = (int64_t)h[kCntNodes];
+    if (n_nodes) *n_nodes = nn;
+    if (order) HIP_TRY(hipMemcpy(order, ctx->d.perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    if (keys) HIP_TRY(hipMemcpy(keys, ctx->d.keys, sizeof(uint64_t) * n, hipMemcpyDeviceToHost));
+    if (!nodes_i && !nodes_d) return PBH_OK;
+    if (cap < nn) return fail(ctx, PBH_E_ARG, "node buffer too small");
+    std::vector<WNode> w(nn);
+    std::vector<Mom64> q(nn);
+    std::vector<int32_t> lvl(nn);
+    HIP_TRY(hipMemcpy(w.data(), ctx->d.node, sizeof(WNode) * nn, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(q.data(), ctx->d.q64, sizeof(Mom64) * nn, hipMemcpyDeviceToHost));
+    std::vector<uint64_t> lk(nn);
+    HIP_TRY(hipMemcpy(lk.data(), ctx->d.lvl_key, sizeof(uint64_t) * nn, hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < nn; ++k) {
+        if (nodes_i) {
+            nodes_i[4 * k] = w[k].begin;
+            nodes_i[4 * k + 1] = w[k].count;
+            nodes_i[4 * k + 2] = w[k].nchild;
+            nodes_i[4 * k + 3] = (int64_t)lk[k];
+        }
+        if (nodes_d) {
+            double* o = nodes_d + 16 * k;
+            o[0] = q[k].M;
+            for (int j = 0; j < 3; ++j) {
+                o[1 + j] = w[k].com[j];
+                o[10 + j] = w[k].lo[j];
+                o[13 + j] = w[k].hi[j];
+            }
+            o[4] = q[k].qxx; o[5] = q[k].qyy; o[6] = q[k].qzz;
+            o[7] = q[k].qxy; o[8] = q[k].qxz; o[9] = q[k].qyz;
+        }
+    }
+    return PBH_OK;
+}
+
+}  // extern "C"

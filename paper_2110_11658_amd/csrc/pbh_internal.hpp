@@ -1,0 +1,188 @@
+// pbh_internal.hpp -- device data layout and kernel launchers of libpbh.
+//
+// Memory layout in HBM (all device arrays owned by the context):
+//   particles, sorted by key:  x, y, z, m  FP64 SoA [n];  perm int32 [n]
+//                              (sorted position -> caller index)
+//   keys                       uint64 [n] (cluster id above D Morton bits/axis)
+//   nodes (breadth-first, children of a node contiguous, levels contiguous):
+//     WNode  [cap] 96 B  box lo/hi, centre of mass (FP64), rcrit^2, begin,
+//                        count, first child, child count -- the walk's view
+//     q64    [cap] 64 B  M and traceless quadrupole (FP64 master copy)
+//     q32    [cap] 32 B  the same in FP32 for the mixed-precision walk
+//   groups: begin, count, root node, cluster (int32) and tight box (FP64)
+//   clusters: ClusterParams per cluster (radii and potential coefficients)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace pbh {
+
+constexpr int kMaxLevels = 22;     // levels 0..21
+constexpr int kWave = 64;
+
+// device error-flag bits (counters[kErr])
+enum : unsigned long long {
+    kErrNbrOverflow = 1ull,   // neighbour entry dropped: beyond nbr_cap
+    kErrWalkStack = 2ull,     // walk traversal stack full
+    kErrNodeCap = 4ull,       // node capacity exceeded in the build
+    kErrNonFinite = 8ull,     // NaN/Inf in positions or masses
+    kErrNbrStack = 16ull,     // neighbour traversal stack full
+};
+
+// slots of the device counter array
+enum { kCntNodes = 0, kCntPN = 1, kCntFar = 2, kCntNear = 3, kCntNbrTotal = 4, kErr = 5,
+       kQueueWalk = 6, kQueueNbrCount = 7, kQueueNbrFill = 8, kCntMaxLevel = 9,
+       kCntLeaves = 10, kNumCounters = 16 };
+
+struct alignas(16) WNode {
+    double lo[3];
+    double hi[3];
+    double com[3];
+    double rcrit2;       // (l/theta + delta)^2 of the current force call
+    int32_t begin;       // first sorted particle
+    int32_t count;       // particles
+    int32_t first_child; // breadth-first index of the first child (-1 for a leaf)
+    int32_t nchild;      // 0 for a leaf
+};
+static_assert(sizeof(WNode) == 96, "WNode layout");
+
+struct alignas(16) Mom64 { double M, qxx, qyy, qzz, qxy, qxz, qyz, pad; };
+struct alignas(16) Mom32 { float M, qxx, qyy, qzz, qxy, qxz, qyz, pad; };
+
+// Per-cluster constants of the changeover split (computed on the host).
+// Regular potential on [r_in, r_out):
+//   Phi_R(s) = c0 - d0 / s + l1 * ln(s) + t * (e2 + t * (e3 + ... + t * e7)),
+//   t = s / (r_out - r_in); beyond r_out -1/s; below r_in `inner`.
+struct alignas(16) ClusterParams {
+    double r_in, r_out, rout2, inv_delta;
+    double c0, d0, l1, inner;
+    double e[6];   // e2..e7
+    float f_r_in, f_r_out, f_inv_delta, f_c0;
+    float f_d0, f_l1, f_inner, f_pad;
+    float f_e[6];
+    float f_pad2[2];
+};
+
+struct GroupArrays {
+    int32_t* begin = nullptr;
+    int32_t* count = nullptr;
+    int32_t* root = nullptr;
+    int32_t* cluster = nullptr;
+    double* lo = nullptr;  // [G][3]
+    double* hi = nullptr;  // [G][3]
+};
+
+struct BuildCfg {
+    int64_t n = 0;
+    int32_t n_clusters = 1;
+    int32_t D = 21;          // Morton bits per axis
+    int32_t cbits = 0;       // cluster-id bits above the Morton bits
+    int32_t n_leaf = 16;
+    int32_t n_crit = 64;
+    int64_t node_cap = 0;
+    int64_t n_groups = 0;
+};
+
+// Scratch and arrays of one built forest.
+struct Dev {
+    // particles
+    double *x = nullptr, *y = nullptr, *z = nullptr, *m = nullptr;
+    int32_t* perm = nullptr;
+    uint64_t* keys = nullptr;
+    uint64_t* keys_alt = nullptr;
+    int32_t* vals_alt = nullptr;
+    // clusters
+    int64_t* cl_off = nullptr;       // [C+1]
+    double* cl_box = nullptr;        // [C][6] lo xyz, hi xyz
+    int32_t* blk_cluster = nullptr;  // bbox/key block table: cluster of block
+    int64_t* blk_range = nullptr;    // [nblk][2]
+    double* blk_part = nullptr;      // [nblk][6] partial boxes
+    int32_t* blk_bad = nullptr;      // [nblk] non-finite flags
+    ClusterParams* cparams = nullptr;
+    // topology scratch (pre-order)
+    int32_t* p_first = nullptr;      // [n] first level started at i
+    int32_t* p_nn = nullptr;         // [n+1] nodes started at i, then exclusive scan
+    int32_t* pre_begin = nullptr;    // [cap]
+    int32_t* pre_count = nullptr;
+    int32_t* pre_level = nullptr;
+    int32_t* pre_nchild = nullptr;
+    uint64_t* lvl_key = nullptr;     // [cap] level as a sort key
+    int32_t* lvl_val = nullptr;      // [cap] pre-order index
+    uint64_t* lvl_key_alt = nullptr;
+    int32_t* bfs2pre = nullptr;      // [cap]
+    int32_t* pre2bfs = nullptr;      // [cap]
+    int32_t* lvl_off = nullptr;      // [kMaxLevels+1] breadth-first level offsets
+    // nodes (breadth-first)
+    WNode* node = nullptr;
+    Mom64* q64 = nullptr;
+    Mom32* q32 = nullptr;
+    // groups
+    GroupArrays g;
+    // generic scan scratch
+    int64_t* scan_tmp = nullptr;
+    int64_t scan_tmp_len = 0;
+    // radix-sort histogram scratch
+    int64_t* rs_hist = nullptr;
+    int64_t rs_hist_len = 0;
+    // neighbour counts
+    int32_t* nbr_cnt = nullptr;
+    // walk stacks
+    int32_t* stack = nullptr;
+    int64_t stack_len = 0;
+    // counters
+    unsigned long long* cnt = nullptr;
+};
+
+// ---- launchers (all enqueue on `s`, none waits) ----
+// scan.hip / sort.hip
+int64_t scan_tmp_need(int64_t n);
+void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+int64_t radix_hist_need(int64_t n);
+// Stable LSD radix sort of (key, val) on bits [0, nbits). The result ends in
+// (keys, vals); (keys_alt, vals_alt) are scratch of the same size. With
+// vals_are_iota the input values are taken to be 0..n-1 (vals not read). If
+// n_dev is given the element count is min(n, *n_dev), read on the device.
+void radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt,
+                      int64_t n, int nbits, int64_t* hist, int64_t* scan_tmp, hipStream_t s,
+                      bool vals_are_iota, const int32_t* n_dev = nullptr);
+
+// build.hip
+void launch_bbox(Dev& d, const BuildCfg& c, const double* pos, const double* mass, int nblk,
+                 hipStream_t s);
+void launch_keys(Dev& d, const BuildCfg& c, const double* pos, int nblk, hipStream_t s);
+void launch_gather(Dev& d, const BuildCfg& c, const double* pos, const double* mass, hipStream_t s);
+void launch_topology(Dev& d, const BuildCfg& c, hipStream_t s);
+void launch_moments(Dev& d, const BuildCfg& c, hipStream_t s);
+void launch_groups(Dev& d, const BuildCfg& c, const int32_t* grp_cluster_first, hipStream_t s);
+
+// walk.hip
+struct WalkCfg {
+    double theta;
+    double eps;
+    int mixed;
+    int grid;
+    int stack_cap;
+};
+void launch_rcrit(Dev& d, const BuildCfg& c, double theta, hipStream_t s);
+void launch_walk(Dev& d, const BuildCfg& c, const WalkCfg& w, double* acc, double* pot,
+                 hipStream_t s);
+int walk_blocks_per_cu(int mixed);
+
+// nbr.hip
+void launch_nbr_count(Dev& d, const BuildCfg& c, int grid, int stack_cap, hipStream_t s);
+void launch_nbr_fill(Dev& d, const BuildCfg& c, int grid, int stack_cap, const int64_t* off,
+                     int32_t* idx, int64_t cap, hipStream_t s);
+
+// kdk.hip
+void launch_kick(double* vel, const double* acc, double h, int64_t n, hipStream_t s);
+void launch_drift(double* pos, const double* vel, double dt, int64_t n, hipStream_t s);
+void launch_energy(const double* vel, const double* mass, const double* pot, int64_t n,
+                   double* partial, int nblk, double* out, hipStream_t s);
+void launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+
+}  // namespace pbh

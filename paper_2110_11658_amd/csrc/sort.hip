@@ -1,0 +1,276 @@
+// sort.hip -- device-wide exclusive scan and stable LSD radix sort (gfx950).
+//
+// Scan: three launches of fixed size (so they can be captured in a graph):
+// per-tile sums, one workgroup scanning the tile sums, per-tile scan plus
+// offset. Radix sort: 8-bit digits; per pass a tile histogram (LDS atomics),
+// a scan of the digit-major histogram table, and a stable scatter in which
+// each wave ranks equal digits with eight ballots (match by bits) and the
+// waves of a workgroup are ordered through LDS.
+#include "pbh_internal.hpp"
+
+namespace pbh {
+
+namespace {
+
+constexpr int SCAN_T = 256;
+constexpr int SCAN_I = 8;
+constexpr int SCAN_TILE = SCAN_T * SCAN_I;
+
+__device__ inline int64_t wave_incl_scan64(int64_t v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int64_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// exclusive scan over a 256-thread block; returns the exclusive prefix, total in *tot
+__device__ inline int64_t block_excl_scan(int64_t v, int64_t* s_wave, int64_t* tot) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int64_t inc = wave_incl_scan64(v, lane);
+    if (lane == 63) s_wave[w] = inc;
+    __syncthreads();
+    int64_t base = 0, all = 0;
+    for (int k = 0; k < SCAN_T / 64; ++k) {
+        if (k < w) base += s_wave[k];
+        all += s_wave[k];
+    }
+    *tot = all;
+    __syncthreads();
+    return base + inc - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SCAN_T) void k_scan_reduce(const T* __restrict__ in, int64_t n,
+                                                        int64_t* __restrict__ tmp) {
+    __shared__ int64_t s_wave[SCAN_T / 64];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int64_t v = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        int64_t i = base + k * SCAN_T + threadIdx.x;
+        if (i < n) v += (int64_t)in[i];
+    }
+    int64_t tot;
+    block_excl_scan(v, s_wave, &tot);
+    if (threadIdx.x == 0) tmp[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t* __restrict__ tmp, int64_t nb) {
+    __shared__ int64_t s_wave[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = t * per;
+    int64_t sum = 0;
+    for (int64_t k = 0; k < per; ++k)
+        if (b0 + k < nb) sum += tmp[b0 + k];
+    int64_t inc = wave_incl_scan64(sum, lane);
+    if (lane == 63) s_wave[w] = inc;
+    __syncthreads();
+    int64_t base = 0, all = 0;
+    for (int k = 0; k < 16; ++k) {
+        if (k < w) base += s_wave[k];
+        all += s_wave[k];
+    }
+    int64_t run = base + inc - sum;
+    for (int64_t k = 0; k < per; ++k) {
+        if (b0 + k < nb) {
+            int64_t v = tmp[b0 + k];
+            tmp[b0 + k] = run;
+            run += v;
+        }
+    }
+    if (t == 0) tmp[nb] = all;
+}
+
+template <typename T, typename O>
+__global__ __launch_bounds__(SCAN_T) void k_scan_down(const T* in, int64_t n,
+                                                      const int64_t* __restrict__ tmp, O* out,
+                                                      int64_t nb) {
+    __shared__ int64_t s_val[SCAN_TILE];
+    __shared__ int64_t s_wave[SCAN_T / 64];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        int64_t i = base + k * SCAN_T + threadIdx.x;
+        s_val[k * SCAN_T + threadIdx.x] = (i < n) ? (int64_t)in[i] : 0;
+    }
+    __syncthreads();
+    int64_t v[SCAN_I];
+    int64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        v[k] = s_val[threadIdx.x * SCAN_I + k];
+        sum += v[k];
+    }
+    int64_t tot;
+    int64_t run = block_excl_scan(sum, s_wave, &tot) + tmp[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        s_val[threadIdx.x * SCAN_I + k] = run;
+        run += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        int64_t i = base + k * SCAN_T + threadIdx.x;
+        if (i < n) out[i] = (O)s_val[k * SCAN_T + threadIdx.x];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (O)tmp[nb];
+}
+
+template <typename T, typename O>
+void scan_impl(const T* in, O* out, int64_t n, int64_t* tmp, hipStream_t s) {
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb == 0) {
+        // n == 0: out[0] = 0 through the top kernel with nb = 0
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, (int64_t)0);
+        hipLaunchKernelGGL((k_scan_down<T, O>), dim3(1), dim3(SCAN_T), 0, s, in, (int64_t)0,
+                           (const int64_t*)tmp, out, (int64_t)0);
+        return;
+    }
+    hipLaunchKernelGGL((k_scan_reduce<T>), dim3(nb), dim3(SCAN_T), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, nb);
+    hipLaunchKernelGGL((k_scan_down<T, O>), dim3(nb), dim3(SCAN_T), 0, s, in, n,
+                       (const int64_t*)tmp, out, nb);
+}
+
+// ---------------------------------------------------------------- radix sort
+constexpr int RS_T = 256;
+constexpr int RS_R = 16;            // rounds per tile
+constexpr int RS_TILE = RS_T * RS_R;
+constexpr int RS_BINS = 256;
+
+__global__ __launch_bounds__(RS_T) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n,
+                                                  const int32_t* __restrict__ n_dev, int shift,
+                                                  int64_t* __restrict__ hist, int64_t nblk) {
+    __shared__ int s_h[RS_BINS];
+    if (n_dev) n = min(n, (int64_t)*n_dev);
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll 4
+    for (int r = 0; r < RS_R; ++r) {
+        int64_t i = base + r * RS_T + threadIdx.x;
+        if (i < n) atomicAdd(&s_h[(unsigned)(keys[i] >> shift) & 0xFFu], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = s_h[threadIdx.x];
+}
+
+__device__ inline uint64_t lanes_below(int lane) {
+    return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+}
+
+__global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                     const int32_t* __restrict__ vin,
+                                                     uint64_t* __restrict__ kout,
+                                                     int32_t* __restrict__ vout, int64_t n,
+                                                     const int32_t* __restrict__ n_dev, int shift,
+                                                     const int64_t* __restrict__ hist,
+                                                     int64_t nblk, int iota) {
+    if (n_dev) n = min(n, (int64_t)*n_dev);
+    __shared__ int64_t s_goff[RS_BINS];
+    __shared__ int s_run[RS_BINS];
+    __shared__ int s_wc[RS_T / 64][RS_BINS];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    s_goff[t] = hist[(int64_t)t * nblk + blockIdx.x];
+    s_run[t] = 0;
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const uint64_t below = lanes_below(lane);
+    for (int r = 0; r < RS_R; ++r) {
+        const int64_t i = base + r * RS_T + t;
+        const bool valid = i < n;
+        uint64_t key = valid ? kin[i] : 0ull;
+        int32_t val = valid ? (iota ? (int32_t)i : vin[i]) : 0;
+        const unsigned d = (unsigned)(key >> shift) & 0xFFu;
+        for (int k = 0; k < RS_T / 64; ++k) s_wc[k][t] = 0;
+        __syncthreads();
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const int rank = __popcll(peers & below);
+        if (valid && rank == 0) s_wc[w][d] = __popcll(peers);
+        __syncthreads();
+        {
+            int run = s_run[t];
+            for (int k = 0; k < RS_T / 64; ++k) {
+                int c = s_wc[k][t];
+                s_wc[k][t] = run;
+                run += c;
+            }
+            s_run[t] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            const int64_t dst = s_goff[d] + s_wc[w][d] + rank;
+            kout[dst] = key;
+            vout[dst] = val;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_copy_pairs(const uint64_t* __restrict__ ks, const int32_t* __restrict__ vs,
+                             uint64_t* __restrict__ kd, int32_t* __restrict__ vd, int64_t n,
+                             const int32_t* __restrict__ n_dev) {
+    if (n_dev) n = min(n, (int64_t)*n_dev);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        kd[i] = ks[i];
+        vd[i] = vs[i];
+    }
+}
+
+}  // namespace
+
+int64_t scan_tmp_need(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 2; }
+
+void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* tmp,
+                               hipStream_t s) {
+    scan_impl<int32_t, int64_t>(in, out, n, tmp, s);
+}
+
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
+    scan_impl<int32_t, int32_t>(in, out, n, tmp, s);
+}
+
+int64_t radix_hist_need(int64_t n) {
+    const int64_t nblk = (n + RS_TILE - 1) / RS_TILE;
+    return nblk * RS_BINS + 1;
+}
+
+void radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt,
+                      int64_t n, int nbits, int64_t* hist, int64_t* scan_tmp, hipStream_t s,
+                      bool vals_are_iota, const int32_t* n_dev) {
+    if (n <= 0) return;
+    const int64_t nblk = (n + RS_TILE - 1) / RS_TILE;
+    const int passes = (nbits + 7) / 8;
+    uint64_t* ki = keys;
+    int32_t* vi = vals;
+    uint64_t* ko = keys_alt;
+    int32_t* vo = vals_alt;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(RS_T), 0, s, (const uint64_t*)ki, n, n_dev,
+                           shift, hist, nblk);
+        scan_impl<int64_t, int64_t>(hist, hist, nblk * RS_BINS, scan_tmp, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(RS_T), 0, s, (const uint64_t*)ki,
+                           (const int32_t*)vi, ko, vo, n, n_dev, shift, (const int64_t*)hist,
+                           nblk, (int)(vals_are_iota && p == 0));
+        uint64_t* tk = ki; ki = ko; ko = tk;
+        int32_t* tv = vi; vi = vo; vo = tv;
+    }
+    if (ki != keys) {
+        const int nb = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+        hipLaunchKernelGGL(k_copy_pairs, dim3(nb), dim3(256), 0, s, (const uint64_t*)ki,
+                           (const int32_t*)vi, keys, vals, n, n_dev);
+    }
+}
+
+}  // namespace pbh

@@ -1,0 +1,465 @@
+// walk.hip -- grouped Barnes-Hut walk for the regular force (gfx950).
+//
+// Regular acceleration of particle i (Arnold, Baumgardt & Wang 2021, Section
+// 2.1, eq. fi with F_R = total - F_I and eq. duncan):
+//   a_i = sum_j m_j W(s_ij) d_ij / s_ij^3,  d = x_j - x_i,  s^2 = r^2 + eps^2,
+// and the regular potential Phi_R (dPhi_R/ds = W/s^2). Far nodes are taken as
+// monopole + traceless quadrupole about their centre of mass (Section 2.4:
+// Barnes-Hut with opening angle theta).
+//
+// One wavefront walks one group (a run of <= 64 sorted particles, one per
+// lane). Persistent workgroups of one wave pull groups from a global counter.
+// Per step the wave pops up to 64 nodes from its stack (one per lane) and
+// classifies them in FP64 without FMA, exactly like the definition:
+//   near   box-box distance^2 < r_out^2, or the boxes touch
+//   accept not near, theta > 0, distance^2(group box, COM) > rcrit^2
+//   open   otherwise: a leaf becomes particle-particle work, an inner node
+//          pushes its children.
+// Accepted nodes and leaf particles are compacted with ballot + prefix sums
+// into LDS tiles (FP32 in the mixed path: positions relative to the group
+// centre, formed in FP64 first) and evaluated 64+ entries at a time with
+// every lane reading each entry by LDS broadcast. Tile partial sums are
+// folded into FP32 (hi, lo) pairs with TwoSum and returned in FP64.
+#include <type_traits>
+
+#include "pbh_internal.hpp"
+
+namespace pbh {
+
+namespace {
+
+constexpr int TCAP = 128;   // tile capacity: < 64 left over + 64 new entries
+
+template <typename R>
+struct alignas(16) Tiles {
+    R pn[TCAP][12];      // cx cy cz M | qxx qyy qzz qxy | qxz qyz - -
+    R far[TCAP][4];      // x y z m (relative to the group centre)
+    R nearp[TCAP][4];
+    int nearj[TCAP];     // sorted index, to skip the self pair
+    int lf_ex[64];       // leaf expansion: exclusive prefix of particle counts
+    int lf_beg[64];
+};
+
+struct WalkParams {
+    const WNode* node;
+    const Mom32* q32;
+    const Mom64* q64;
+    const double* x;
+    const double* y;
+    const double* z;
+    const double* m;
+    const int32_t* perm;
+    const int32_t* g_begin;
+    const int32_t* g_count;
+    const int32_t* g_root;
+    const int32_t* g_cluster;
+    const double* g_lo;
+    const double* g_hi;
+    const ClusterParams* cp;
+    int64_t G;
+    int use_theta;
+    double eps2;
+    double* acc;
+    double* pot;
+    int32_t* stack;
+    int stack_cap;
+    unsigned long long* cnt;
+};
+
+__device__ inline int popc_below(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+__device__ inline int wave_incl_scan(int v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+__device__ inline void two_sum_acc(float& hi, float& lo, float v) {
+    const float s = hi + v;
+    const float bp = s - hi;
+    const float e = (hi - (s - bp)) + (v - bp);
+    hi = s;
+    lo += e;
+}
+
+// squared distances used by the opening rules, in FP64 without contraction
+__device__ inline double box_box_d2(const double* glo, const double* ghi, const double* lo,
+                                    const double* hi) {
+#pragma clang fp contract(off)
+    double g[3];
+    for (int k = 0; k < 3; ++k) {
+        const double a = lo[k] - ghi[k];
+        const double b = glo[k] - hi[k];
+        const double v = a > b ? a : b;
+        g[k] = v > 0.0 ? v : 0.0;
+    }
+    return g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+}
+
+__device__ inline double box_pt_d2(const double* glo, const double* ghi, const double* c) {
+#pragma clang fp contract(off)
+    double g[3];
+    for (int k = 0; k < 3; ++k) {
+        const double a = glo[k] - c[k];
+        const double b = c[k] - ghi[k];
+        const double v = a > b ? a : b;
+        g[k] = v > 0.0 ? v : 0.0;
+    }
+    return g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+}
+
+template <typename R>
+struct Acc;
+
+template <>
+struct Acc<float> {
+    float hx = 0, hy = 0, hz = 0, hp = 0, lx = 0, ly = 0, lz = 0, lp = 0;
+    __device__ void add(float ax, float ay, float az, float ph) {
+        two_sum_acc(hx, lx, ax);
+        two_sum_acc(hy, ly, ay);
+        two_sum_acc(hz, lz, az);
+        two_sum_acc(hp, lp, ph);
+    }
+    __device__ double gx() const { return (double)hx + (double)lx; }
+    __device__ double gy() const { return (double)hy + (double)ly; }
+    __device__ double gz() const { return (double)hz + (double)lz; }
+    __device__ double gp() const { return (double)hp + (double)lp; }
+};
+
+template <>
+struct Acc<double> {
+    double x = 0, y = 0, z = 0, p = 0;
+    __device__ void add(double ax, double ay, double az, double ph) {
+        x += ax; y += ay; z += az; p += ph;
+    }
+    __device__ double gx() const { return x; }
+    __device__ double gy() const { return y; }
+    __device__ double gz() const { return z; }
+    __device__ double gp() const { return p; }
+};
+
+__device__ inline float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ inline double rsq(double v) { return rsqrt(v); }
+__device__ inline float lnr(float v) { return __logf(v); }
+__device__ inline double lnr(double v) { return log(v); }
+
+// Monopole + traceless quadrupole: phi = -M/s - (R^T Q R)/(2 s^5), a = -grad phi
+template <typename R>
+__device__ inline void eval_pn(const Tiles<R>& T, int cnt, R px, R py, R pz, R eps2, Acc<R>& A) {
+    R ax = 0, ay = 0, az = 0, ph = 0;
+#pragma unroll 2
+    for (int e = 0; e < cnt; ++e) {
+        const R* q = T.pn[e];
+        const R Rx = px - q[0], Ry = py - q[1], Rz = pz - q[2];
+        const R s2 = Rx * Rx + Ry * Ry + Rz * Rz + eps2;
+        const R inv = rsq(s2);
+        const R inv2 = inv * inv;
+        const R inv3 = inv * inv2;
+        const R inv5 = inv3 * inv2;
+        const R inv7 = inv5 * inv2;
+        const R qx = q[4] * Rx + q[7] * Ry + q[8] * Rz;
+        const R qy = q[7] * Rx + q[5] * Ry + q[9] * Rz;
+        const R qz = q[8] * Rx + q[9] * Ry + q[6] * Rz;
+        const R rqr = Rx * qx + Ry * qy + Rz * qz;
+        const R cr = -q[3] * inv3 - R(2.5) * rqr * inv7;
+        ax += cr * Rx + qx * inv5;
+        ay += cr * Ry + qy * inv5;
+        az += cr * Rz + qz * inv5;
+        ph += -q[3] * inv - R(0.5) * rqr * inv5;
+    }
+    A.add(ax, ay, az, ph);
+}
+
+// Pairs of far leaves: every pair is at r >= r_out, where W = 1.
+template <typename R>
+__device__ inline void eval_far(const Tiles<R>& T, int cnt, R px, R py, R pz, R eps2, Acc<R>& A) {
+    R ax = 0, ay = 0, az = 0, ph = 0;
+#pragma unroll 4
+    for (int e = 0; e < cnt; ++e) {
+        const R* q = T.far[e];
+        const R dx = q[0] - px, dy = q[1] - py, dz = q[2] - pz;
+        const R s2 = dx * dx + dy * dy + dz * dz + eps2;
+        const R inv = rsq(s2);
+        const R mi = q[3] * inv;
+        const R mi3 = mi * inv * inv;
+        ax += mi3 * dx;
+        ay += mi3 * dy;
+        az += mi3 * dz;
+        ph -= mi;
+    }
+    A.add(ax, ay, az, ph);
+}
+
+template <typename R>
+struct NearK {
+    R r_in, r_out, inv_delta, c0, d0, l1, inner;
+    R e[6];
+    bool pole;   // r_in > 0: the -d0/s and log terms are present
+};
+
+// Pairs of near leaves: changeover weight W(s) and the regular potential.
+template <typename R>
+__device__ inline void eval_near(const Tiles<R>& T, int cnt, R px, R py, R pz, R eps2, int self,
+                                 const NearK<R>& K, Acc<R>& A) {
+    R ax = 0, ay = 0, az = 0, ph = 0;
+    for (int e = 0; e < cnt; ++e) {
+        const R* q = T.nearp[e];
+        const bool is_self = T.nearj[e] == self;
+        const R dx = q[0] - px, dy = q[1] - py, dz = q[2] - pz;
+        const R s2 = dx * dx + dy * dy + dz * dz + eps2;
+        const R inv = rsq(s2);
+        const R s = s2 > R(0) ? s2 * inv : R(0);
+        const R xx = (s - K.r_in) * K.inv_delta;
+        const R x2 = xx * xx;
+        const R gpoly = x2 * x2 * (R(35) + xx * (R(-84) + xx * (R(70) - R(20) * xx)));
+        const R W = s >= K.r_out ? R(1) : (s < K.r_in ? R(0) : gpoly);
+        const R f = (W > R(0) && !is_self) ? q[3] * W * inv * inv * inv : R(0);
+        ax += f * dx;
+        ay += f * dy;
+        az += f * dz;
+        const R t = s * K.inv_delta;
+        R mid = K.c0 + t * (K.e[0] + t * (K.e[1] + t * (K.e[2] + t * (K.e[3] + t * (K.e[4] + t * K.e[5])))));
+        if (K.pole) mid += -K.d0 * inv + K.l1 * lnr(s);
+        const R phi = s >= K.r_out ? -inv : (s < K.r_in ? K.inner : mid);
+        ph += is_self ? R(0) : q[3] * phi;
+    }
+    A.add(ax, ay, az, ph);
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(64) void k_walk(WalkParams p) {
+    using R = typename std::conditional<MIXED, float, double>::type;
+    __shared__ Tiles<R> T;
+    const int lane = threadIdx.x;
+    int32_t* stack = p.stack + (int64_t)blockIdx.x * p.stack_cap;
+    const R eps2 = (R)p.eps2;
+
+    for (;;) {
+        int g = 0;
+        if (lane == 0) g = (int)atomicAdd(&p.cnt[kQueueWalk], 1ull);
+        g = __shfl(g, 0, 64);
+        if (g >= p.G) break;
+
+        const int gb = p.g_begin[g], gcnt = p.g_count[g], root = p.g_root[g], cl = p.g_cluster[g];
+        double glo[3], ghi[3], ctr[3];
+        for (int k = 0; k < 3; ++k) {
+            glo[k] = p.g_lo[3 * g + k];
+            ghi[k] = p.g_hi[3 * g + k];
+            ctr[k] = (glo[k] + ghi[k]) * 0.5;
+        }
+        const ClusterParams& cp = p.cp[cl];
+        const double rout2 = cp.rout2;
+        NearK<R> K;
+        if (MIXED) {
+            K.r_in = cp.f_r_in; K.r_out = cp.f_r_out; K.inv_delta = cp.f_inv_delta;
+            K.c0 = cp.f_c0; K.d0 = cp.f_d0; K.l1 = cp.f_l1; K.inner = cp.f_inner;
+            for (int k = 0; k < 6; ++k) K.e[k] = cp.f_e[k];
+        } else {
+            K.r_in = cp.r_in; K.r_out = cp.r_out; K.inv_delta = cp.inv_delta;
+            K.c0 = cp.c0; K.d0 = cp.d0; K.l1 = cp.l1; K.inner = cp.inner;
+            for (int k = 0; k < 6; ++k) K.e[k] = cp.e[k];
+        }
+        K.pole = cp.d0 != 0.0;
+
+        const bool active = lane < gcnt;
+        const int me = gb + (active ? lane : 0);
+        const R px = (R)(p.x[me] - ctr[0]);
+        const R py = (R)(p.y[me] - ctr[1]);
+        const R pz = (R)(p.z[me] - ctr[2]);
+        Acc<R> A;
+
+        int npn = 0, nfar = 0, nnear = 0;
+        unsigned long long c_pn = 0, c_far = 0, c_near = 0;
+        if (lane == 0) stack[0] = root;
+        int top = 1;
+        bool overflow = false;
+
+        while (top > 0) {
+            __threadfence_block();
+            const int npop = top < 64 ? top : 64;
+            top -= npop;
+            const bool has = lane < npop;
+            const int nd = has ? stack[top + lane] : root;
+            const WNode w = p.node[nd];
+            const double dbox2 = box_box_d2(glo, ghi, w.lo, w.hi);
+            const bool near = (dbox2 < rout2) || (dbox2 == 0.0);
+            const bool accept = has && !near && p.use_theta && (box_pt_d2(glo, ghi, w.com) > w.rcrit2);
+            const bool open = has && !accept;
+            const bool leaf = w.nchild == 0;
+
+            // multipole entries
+            const uint64_t mk = __ballot(accept);
+            if (mk) {
+                if (accept) {
+                    R* e = T.pn[npn + popc_below(mk)];
+                    e[0] = (R)(w.com[0] - ctr[0]);
+                    e[1] = (R)(w.com[1] - ctr[1]);
+                    e[2] = (R)(w.com[2] - ctr[2]);
+                    if (MIXED) {
+                        const Mom32 q = p.q32[nd];
+                        e[3] = q.M; e[4] = q.qxx; e[5] = q.qyy; e[6] = q.qzz;
+                        e[7] = q.qxy; e[8] = q.qxz; e[9] = q.qyz;
+                    } else {
+                        const Mom64 q = p.q64[nd];
+                        e[3] = q.M; e[4] = q.qxx; e[5] = q.qyy; e[6] = q.qzz;
+                        e[7] = q.qxy; e[8] = q.qxz; e[9] = q.qyz;
+                    }
+                }
+                const int k = __popcll(mk);
+                npn += k;
+                c_pn += k;
+            }
+
+            // children of opened inner nodes
+            const int nch = (open && !leaf) ? w.nchild : 0;
+            const int incl = wave_incl_scan(nch, lane);
+            const int tot = __shfl(incl, 63, 64);
+            if (top + tot > p.stack_cap) {
+                overflow = true;
+                break;
+            }
+            for (int k = 0; k < nch; ++k) stack[top + incl - nch + k] = w.first_child + k;
+            top += tot;
+
+            // leaves: far ones (W = 1) and near ones (changeover)
+            for (int cls = 0; cls < 2; ++cls) {
+                const bool flag = open && leaf && (cls == 0 ? !near : near);
+                const uint64_t lm = __ballot(flag);
+                if (!lm) continue;
+                const int v = flag ? w.count : 0;
+                const int li = wave_incl_scan(v, lane);
+                const int total = __shfl(li, 63, 64);
+                __syncthreads();
+                T.lf_ex[lane] = li - v;
+                T.lf_beg[lane] = w.begin;
+                __syncthreads();
+                if (cls == 0) c_far += total; else c_near += total;
+                for (int base = 0; base < total; base += 64) {
+                    const int s = base + lane;
+                    int k = 0;
+#pragma unroll
+                    for (int st = 32; st > 0; st >>= 1)
+                        if (T.lf_ex[k + st] <= s) k += st;
+                    const int j = T.lf_beg[k] + (s - T.lf_ex[k]);
+                    int& fill = cls == 0 ? nfar : nnear;
+                    if (s < total) {
+                        R* e = cls == 0 ? T.far[fill + lane] : T.nearp[fill + lane];
+                        e[0] = (R)(p.x[j] - ctr[0]);
+                        e[1] = (R)(p.y[j] - ctr[1]);
+                        e[2] = (R)(p.z[j] - ctr[2]);
+                        e[3] = (R)p.m[j];
+                        if (cls == 1) T.nearj[fill + lane] = j;
+                    }
+                    fill += (total - base) < 64 ? (total - base) : 64;
+                    if (fill >= 64) {
+                        __syncthreads();
+                        if (cls == 0) eval_far<R>(T, fill, px, py, pz, eps2, A);
+                        else eval_near<R>(T, fill, px, py, pz, eps2, me, K, A);
+                        fill = 0;
+                        __syncthreads();
+                    }
+                }
+                __syncthreads();
+            }
+
+            if (npn >= 64) {
+                __syncthreads();
+                eval_pn<R>(T, npn, px, py, pz, eps2, A);
+                npn = 0;
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+        if (npn) eval_pn<R>(T, npn, px, py, pz, eps2, A);
+        if (nfar) eval_far<R>(T, nfar, px, py, pz, eps2, A);
+        if (nnear) eval_near<R>(T, nnear, px, py, pz, eps2, me, K, A);
+        __syncthreads();
+
+        if (overflow) {
+            if (lane == 0) atomicOr(&p.cnt[kErr], kErrWalkStack);
+        }
+        if (active) {
+            const int orig = p.perm[gb + lane];
+            p.acc[3 * (int64_t)orig] = A.gx();
+            p.acc[3 * (int64_t)orig + 1] = A.gy();
+            p.acc[3 * (int64_t)orig + 2] = A.gz();
+            p.pot[orig] = A.gp();
+        }
+        if (lane == 0) {
+            atomicAdd(&p.cnt[kCntPN], c_pn * (unsigned long long)gcnt);
+            atomicAdd(&p.cnt[kCntFar], c_far * (unsigned long long)gcnt);
+            atomicAdd(&p.cnt[kCntNear], c_near * (unsigned long long)gcnt);
+        }
+    }
+}
+
+// rcrit^2 = (l/theta + delta)^2 per node, l = largest box extent, delta =
+// |COM - box centre|; also clears the per-call counters and queues.
+__global__ void k_rcrit(WNode* __restrict__ node, const unsigned long long* __restrict__ n_dev,
+                        double theta, unsigned long long* __restrict__ cnt) {
+#pragma clang fp contract(off)
+    const int64_t n = (int64_t)*n_dev;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        cnt[kCntPN] = 0; cnt[kCntFar] = 0; cnt[kCntNear] = 0;
+        cnt[kQueueWalk] = 0; cnt[kQueueNbrCount] = 0; cnt[kQueueNbrFill] = 0;
+    }
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        WNode& w = node[b];
+        double l = 0.0;
+        for (int k = 0; k < 3; ++k)
+            if (w.hi[k] - w.lo[k] > l) l = w.hi[k] - w.lo[k];
+        double dd[3];
+        for (int k = 0; k < 3; ++k) dd[k] = w.com[k] - (w.lo[k] + w.hi[k]) * 0.5;
+        const double delta = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+        const double rc = theta > 0.0 ? l / theta + delta : 0.0;
+        w.rcrit2 = rc * rc;
+    }
+}
+
+}  // namespace
+
+void launch_rcrit(Dev& d, const BuildCfg& c, double theta, hipStream_t s) {
+    int64_t nb = (c.node_cap + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_rcrit, dim3(nb), dim3(256), 0, s, d.node,
+                       (const unsigned long long*)(d.cnt + kCntNodes), theta, d.cnt);
+}
+
+int walk_blocks_per_cu(int mixed) {
+    int nb = 0;
+    if (mixed) hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk<true>, 64, 0);
+    else hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk<false>, 64, 0);
+    return nb > 0 ? nb : 1;
+}
+
+void launch_walk(Dev& d, const BuildCfg& c, const WalkCfg& w, double* acc, double* pot,
+                 hipStream_t s) {
+    WalkParams p;
+    p.node = d.node;
+    p.q32 = d.q32;
+    p.q64 = d.q64;
+    p.x = d.x; p.y = d.y; p.z = d.z; p.m = d.m;
+    p.perm = d.perm;
+    p.g_begin = d.g.begin; p.g_count = d.g.count; p.g_root = d.g.root; p.g_cluster = d.g.cluster;
+    p.g_lo = d.g.lo; p.g_hi = d.g.hi;
+    p.cp = d.cparams;
+    p.G = c.n_groups;
+    p.use_theta = w.theta > 0.0;
+    p.eps2 = w.eps * w.eps;
+    p.acc = acc;
+    p.pot = pot;
+    p.stack = d.stack;
+    p.stack_cap = w.stack_cap;
+    p.cnt = d.cnt;
+    if (w.mixed) hipLaunchKernelGGL(k_walk<true>, dim3(w.grid), dim3(64), 0, s, p);
+    else hipLaunchKernelGGL(k_walk<false>, dim3(w.grid), dim3(64), 0, s, p);
+}
+
+}  // namespace pbh
