@@ -38,6 +38,15 @@ struct NbrParams {
     int queue;
 };
 
+// Wave-uniform helpers (see walk.hip): scalar copies of wave-uniform values
+// and a branch-free work-queue fetch.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ inline int wave_next(unsigned long long* ctr, int lane) {
+    const unsigned long long r = atomicAdd(ctr, lane == 0 ? 1ull : 0ull);
+    return uni((int)r);
+}
+
 __device__ inline int wave_incl_scan(int v, int lane) {
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -73,11 +82,9 @@ __global__ __launch_bounds__(64) void k_nbr(NbrParams p) {
     const int lane = threadIdx.x;
     int32_t* stack = p.stack + (int64_t)blockIdx.x * p.stack_cap;
     for (;;) {
-        int g = 0;
-        if (lane == 0) g = (int)atomicAdd(&p.cnt[p.queue], 1ull);
-        g = __shfl(g, 0, 64);
+        const int g = wave_next(&p.cnt[p.queue], lane);
         if (g >= p.G) break;
-        const int gb = p.g_begin[g], gcnt = p.g_count[g], root = p.g_root[g];
+        const int gb = uni(p.g_begin[g]), gcnt = uni(p.g_count[g]), root = uni(p.g_root[g]);
         const double rout2 = p.cp[p.g_cluster[g]].rout2;
         double glo[3], ghi[3];
         for (int k = 0; k < 3; ++k) {
@@ -93,11 +100,11 @@ __global__ __launch_bounds__(64) void k_nbr(NbrParams p) {
         int count = 0;
         bool overflow = false;
         if (rout2 > 0.0) {
-            if (lane == 0) stack[0] = root;
+            stack[0] = root;   // every lane stores the same value
             int top = 1;
             while (top > 0) {
                 __threadfence_block();
-                const int npop = top < 64 ? top : 64;
+                const int npop = uni(top < 64 ? top : 64);
                 top -= npop;
                 const bool has = lane < npop;
                 const int nd = has ? stack[top + lane] : root;
@@ -106,19 +113,19 @@ __global__ __launch_bounds__(64) void k_nbr(NbrParams p) {
                 const bool leaf = w.nchild == 0;
                 const int nch = (near && !leaf) ? w.nchild : 0;
                 const int incl = wave_incl_scan(nch, lane);
-                const int tot = __shfl(incl, 63, 64);
+                const int tot = uni(__shfl(incl, 63, 64));
                 if (top + tot > p.stack_cap) {
                     overflow = true;
                     break;
                 }
                 for (int k = 0; k < nch; ++k) stack[top + incl - nch + k] = w.first_child + k;
-                top += tot;
+                top = uni(top + tot);
                 uint64_t lm = __ballot(near && leaf);
                 while (lm) {
                     const int k = __ffsll((long long)lm) - 1;
                     lm &= lm - 1;
-                    const int lb = __shfl(w.begin, k, 64);
-                    const int lc = __shfl(w.count, k, 64);
+                    const int lb = uni(__shfl(w.begin, k, 64));
+                    const int lc = uni(__shfl(w.count, k, 64));
                     for (int j = lb; j < lb + lc; ++j) {
                         const bool hit = active && j != me &&
                                          within(xi, yi, zi, p.x[j], p.y[j], p.z[j], rout2);
@@ -136,7 +143,7 @@ __global__ __launch_bounds__(64) void k_nbr(NbrParams p) {
         }
         if (!FILL && active) p.counts[orig] = count;
         const uint64_t ov = __ballot(overflow);
-        if (lane == 0 && ov) atomicOr(&p.cnt[kErr], FILL ? kErrNbrOverflow : kErrNbrStack);
+        if (ov) atomicOr(&p.cnt[kErr], lane == 0 ? (FILL ? kErrNbrOverflow : kErrNbrStack) : 0ull);
     }
 }
 

@@ -80,6 +80,17 @@ __device__ inline int wave_incl_scan(int v, int lane) {
     return v;
 }
 
+// Wave-uniform helpers. A value that every lane holds equally is moved to a
+// scalar register, so loops and branches on it are wave-uniform in the
+// generated code. The work-queue fetch is issued by all lanes with lane 0
+// adding 1 and the rest 0, so no lane-0-only branch precedes the broadcast.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ inline int wave_next(unsigned long long* ctr, int lane) {
+    const unsigned long long r = atomicAdd(ctr, lane == 0 ? 1ull : 0ull);
+    return uni((int)r);
+}
+
 __device__ inline void two_sum_acc(float& hi, float& lo, float v) {
     const float s = hi + v;
     const float bp = s - hi;
@@ -241,12 +252,11 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
     const R eps2 = (R)p.eps2;
 
     for (;;) {
-        int g = 0;
-        if (lane == 0) g = (int)atomicAdd(&p.cnt[kQueueWalk], 1ull);
-        g = __shfl(g, 0, 64);
+        const int g = wave_next(&p.cnt[kQueueWalk], lane);
         if (g >= p.G) break;
 
-        const int gb = p.g_begin[g], gcnt = p.g_count[g], root = p.g_root[g], cl = p.g_cluster[g];
+        const int gb = uni(p.g_begin[g]), gcnt = uni(p.g_count[g]), root = uni(p.g_root[g]);
+        const int cl = uni(p.g_cluster[g]);
         double glo[3], ghi[3], ctr[3];
         for (int k = 0; k < 3; ++k) {
             glo[k] = p.g_lo[3 * g + k];
@@ -276,13 +286,13 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
 
         int npn = 0, nfar = 0, nnear = 0;
         unsigned long long c_pn = 0, c_far = 0, c_near = 0;
-        if (lane == 0) stack[0] = root;
+        stack[0] = root;   // every lane stores the same value
         int top = 1;
         bool overflow = false;
 
         while (top > 0) {
             __threadfence_block();
-            const int npop = top < 64 ? top : 64;
+            const int npop = uni(top < 64 ? top : 64);
             top -= npop;
             const bool has = lane < npop;
             const int nd = has ? stack[top + lane] : root;
@@ -311,21 +321,21 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                         e[7] = q.qxy; e[8] = q.qxz; e[9] = q.qyz;
                     }
                 }
-                const int k = __popcll(mk);
-                npn += k;
+                const int k = uni(__popcll(mk));
+                npn = uni(npn + k);
                 c_pn += k;
             }
 
             // children of opened inner nodes
             const int nch = (open && !leaf) ? w.nchild : 0;
             const int incl = wave_incl_scan(nch, lane);
-            const int tot = __shfl(incl, 63, 64);
+            const int tot = uni(__shfl(incl, 63, 64));
             if (top + tot > p.stack_cap) {
                 overflow = true;
                 break;
             }
             for (int k = 0; k < nch; ++k) stack[top + incl - nch + k] = w.first_child + k;
-            top += tot;
+            top = uni(top + tot);
 
             // leaves: far ones (W = 1) and near ones (changeover)
             for (int cls = 0; cls < 2; ++cls) {
@@ -334,7 +344,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                 if (!lm) continue;
                 const int v = flag ? w.count : 0;
                 const int li = wave_incl_scan(v, lane);
-                const int total = __shfl(li, 63, 64);
+                const int total = uni(__shfl(li, 63, 64));
                 __syncthreads();
                 T.lf_ex[lane] = li - v;
                 T.lf_beg[lane] = w.begin;
@@ -356,7 +366,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                         e[3] = (R)p.m[j];
                         if (cls == 1) T.nearj[fill + lane] = j;
                     }
-                    fill += (total - base) < 64 ? (total - base) : 64;
+                    fill = uni(fill + ((total - base) < 64 ? (total - base) : 64));
                     if (fill >= 64) {
                         __syncthreads();
                         if (cls == 0) eval_far<R>(T, fill, px, py, pz, eps2, A);
@@ -381,9 +391,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
         if (nnear) eval_near<R>(T, nnear, px, py, pz, eps2, me, K, A);
         __syncthreads();
 
-        if (overflow) {
-            if (lane == 0) atomicOr(&p.cnt[kErr], kErrWalkStack);
-        }
+        if (overflow) atomicOr(&p.cnt[kErr], lane == 0 ? kErrWalkStack : 0ull);
         if (active) {
             const int orig = p.perm[gb + lane];
             p.acc[3 * (int64_t)orig] = A.gx();
@@ -391,11 +399,11 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
             p.acc[3 * (int64_t)orig + 2] = A.gz();
             p.pot[orig] = A.gp();
         }
-        if (lane == 0) {
-            atomicAdd(&p.cnt[kCntPN], c_pn * (unsigned long long)gcnt);
-            atomicAdd(&p.cnt[kCntFar], c_far * (unsigned long long)gcnt);
-            atomicAdd(&p.cnt[kCntNear], c_near * (unsigned long long)gcnt);
-        }
+        // interaction counters: one contribution per wave (lane 0), others add 0
+        const unsigned long long l0 = lane == 0 ? (unsigned long long)gcnt : 0ull;
+        atomicAdd(&p.cnt[kCntPN], c_pn * l0);
+        atomicAdd(&p.cnt[kCntFar], c_far * l0);
+        atomicAdd(&p.cnt[kCntNear], c_near * l0);
     }
 }
 
