@@ -61,7 +61,7 @@ typedef enum { PBH_FP64 = 0, PBH_MIXED = 1 } pbh_prec;
 /*
  * Tuning parameters; 0 selects the default.
  *   leaf_size  n_leaf: a node with more particles is split (default 16)
- *   n_crit     particles per walk group, 1..128 (default 64)
+ *   n_crit     particles per walk group, 1..64 (default 64; one wave lane each)
  *   key_bits   Morton bits per axis D, 1..21 (default 21 for one cluster;
  *              batched builds use min(21, (63 - cluster bits) / 3))
  *   prec       PBH_MIXED (FP32 interactions, FP64 positions and sums) or
@@ -87,6 +87,12 @@ typedef struct {
     int64_t n_pp_near;    /* pairs inside near leaves (changeover applied; self pairs counted) */
     int64_t nbr_total;    /* neighbour entries of the last force call */
     int64_t error_flags;  /* device-side guard bits; 0 when healthy */
+    /* Phase durations of the last build / force call in milliseconds, from
+       HIP events recorded on the call's stream; 0 unless timing is enabled
+       (pbh_set_timing). walk = the tree-walk kernel alone. */
+    double ms_build;
+    double ms_walk;
+    double ms_nbr;
 } pbh_stats;
 
 /* Create a context on HIP device `device`. params may be NULL (defaults). */
@@ -169,6 +175,10 @@ pbh_status pbh_kdk(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const doub
 pbh_status pbh_kdk_eager(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
                          double dt, int32_t steps, double r_in, double r_out, double theta,
                          double eps, double* energy_out, pbh_stream_t stream);
+
+/* Record HIP events around the build, walk and neighbour phases of later
+   eager calls (enable = 1) or stop (0). Costs a few microseconds per call. */
+pbh_status pbh_set_timing(pbh_ctx* ctx, int32_t enable);
 
 /* Waits for the stream of the last call, then fills *out. */
 pbh_status pbh_get_stats(pbh_ctx* ctx, pbh_stats* out);

@@ -25,7 +25,8 @@ PBH_MIXED = 1
 
 EXPORTS = ("pbh_create", "pbh_destroy", "pbh_set_params", "pbh_get_params", "pbh_build",
            "pbh_force", "pbh_build_batched", "pbh_force_batched", "pbh_kdk", "pbh_kdk_eager",
-           "pbh_get_stats", "pbh_debug_tree", "pbh_last_error", "pbh_status_string")
+           "pbh_get_stats", "pbh_set_timing", "pbh_debug_tree", "pbh_last_error",
+           "pbh_status_string")
 
 
 class pbh_params(C.Structure):
@@ -36,7 +37,8 @@ class pbh_params(C.Structure):
 class pbh_stats(C.Structure):
     _fields_ = [(name, C.c_int64) for name in (
         "n", "n_clusters", "n_nodes", "n_leaves", "n_groups", "max_level", "n_pn", "n_pp_far",
-        "n_pp_near", "nbr_total", "error_flags")]
+        "n_pp_near", "nbr_total", "error_flags")] + [
+        (name, C.c_double) for name in ("ms_build", "ms_walk", "ms_nbr")]
 
 
 class PbhError(RuntimeError):
@@ -71,6 +73,7 @@ def load(path: str = LIB_PATH):
         "pbh_kdk": (st, [vp, i64, vp, vp, vp, d, i32, d, d, d, d, vp, vp]),
         "pbh_kdk_eager": (st, [vp, i64, vp, vp, vp, d, i32, d, d, d, d, vp, vp]),
         "pbh_get_stats": (st, [vp, vp]),
+        "pbh_set_timing": (st, [vp, i32]),
         "pbh_debug_tree": (st, [vp, vp, vp, i64, vp, vp, vp]),
         "pbh_last_error": (C.c_char_p, [vp]),
         "pbh_status_string": (C.c_char_p, [C.c_int]),

@@ -168,10 +168,17 @@ class Pbh:
         return energy
 
     # -- stats / debug ----------------------------------------------------------
+    def set_timing(self, enable: bool = True):
+        check(self.ctx, self.L.pbh_set_timing(self.ctx, int(bool(enable))))
+
     def stats(self) -> dict:
         s = pbh_stats()
         check(self.ctx, self.L.pbh_get_stats(self.ctx, C.byref(s)))
-        return {name: int(getattr(s, name)) for name, _ in pbh_stats._fields_}
+        out = {}
+        for name, typ in pbh_stats._fields_:
+            v = getattr(s, name)
+            out[name] = float(v) if typ is C.c_double else int(v)
+        return out
 
     def debug_tree(self):
         """(order int32 [n], keys uint64 [n], nodes_i int64 [nodes,4], nodes_d f64 [nodes,16])."""

@@ -63,6 +63,11 @@ struct pbh_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<double> gkey;   // parameters the captured graph was made with
+
+    // phase timing: events 0/1 build, 2/3 walk, 4/5 neighbours
+    bool timing = false;
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool ev_build = false, ev_walk = false, ev_nbr = false;
 };
 
 namespace {
@@ -278,6 +283,10 @@ ClusterParams cluster_params(double r_in, double r_out) {
 
 bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 
+void mark(pbh_ctx* ctx, int k, hipStream_t s) {
+    if (ctx->timing) (void)hipEventRecord(ctx->ev[k], s);
+}
+
 constexpr int kParamsPerStore = 8;
 struct ParamPack {
     ClusterParams p[kParamsPerStore];
@@ -351,9 +360,14 @@ pbh_status do_force(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, double 
     const int gmax = w.mixed ? ctx->grid_mixed : ctx->grid_fp64;
     w.grid = (int)std::min<int64_t>(gmax, std::max<int64_t>(c.n_groups, 1));
     w.stack_cap = kStackCap;
+    mark(ctx, 2, s);
     launch_walk(d, c, w, acc, pot, s);
+    mark(ctx, 3, s);
+    ctx->ev_walk = ctx->timing;
+    ctx->ev_nbr = false;
     if (nbr_off) {
         const int grid = (int)std::min<int64_t>(ctx->grid_mixed, std::max<int64_t>(c.n_groups, 1));
+        mark(ctx, 4, s);
         launch_nbr_count(d, c, grid, kStackCap, s);
         exclusive_scan_i32_to_i64(d.nbr_cnt, nbr_off, c.n, d.scan_tmp, s);
         if (nbr_total) {
@@ -366,6 +380,8 @@ pbh_status do_force(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, double 
                                                          " < needed " + std::to_string(tot));
         }
         launch_nbr_fill(d, c, grid, kStackCap, nbr_off, nbr_idx, nbr_cap, s);
+        mark(ctx, 5, s);
+        ctx->ev_nbr = ctx->timing;
         if (nbr_total) {
             unsigned long long err = 0;
             HIP_TRY(hipMemcpyAsync(&err, d.cnt + kErr, sizeof(err), hipMemcpyDeviceToHost, s));
@@ -448,6 +464,8 @@ void pbh_destroy(pbh_ctx* ctx) {
     if (ctx->k_pot) (void)hipFree(ctx->k_pot);
     if (ctx->k_epart) (void)hipFree(ctx->k_epart);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -480,7 +498,10 @@ pbh_status pbh_build(pbh_ctx* ctx, int64_t n, const double* pos, const double* m
     const int64_t offs[2] = {0, n};
     pbh_status st = setup_build(ctx, n, 1, offs, s);
     if (st != PBH_OK) return st;
+    mark(ctx, 0, s);
     enqueue_build(ctx, pos, mass, s);
+    mark(ctx, 1, s);
+    ctx->ev_build = ctx->timing;
     return finish_build(ctx, s);
 }
 
@@ -501,7 +522,10 @@ pbh_status pbh_build_batched(pbh_ctx* ctx, int32_t n_clusters, const int64_t* of
     ctx->last = s;
     pbh_status st = setup_build(ctx, n, n_clusters, offsets, s);
     if (st != PBH_OK) return st;
+    mark(ctx, 0, s);
     enqueue_build(ctx, pos, mass, s);
+    mark(ctx, 1, s);
+    ctx->ev_build = ctx->timing;
     return finish_build(ctx, s);
 }
 
@@ -661,6 +685,21 @@ pbh_status pbh_kdk_eager(pbh_ctx* ctx, int64_t n, double* pos, double* vel, cons
                     (hipStream_t)stream, false);
 }
 
+pbh_status pbh_set_timing(pbh_ctx* ctx, int32_t enable) {
+    if (!ctx) return PBH_E_ARG;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (enable && !ctx->ev[0])
+        for (auto& e : ctx->ev) HIP_TRY(hipEventCreate(&e));
+    ctx->timing = enable != 0;
+    ctx->ev_build = ctx->ev_walk = ctx->ev_nbr = false;
+    return PBH_OK;
+}
+
+static double event_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.0f;
+    return hipEventElapsedTime(&ms, a, b) == hipSuccess ? (double)ms : 0.0;
+}
+
 pbh_status pbh_get_stats(pbh_ctx* ctx, pbh_stats* out) {
     if (!ctx || !out) return PBH_E_ARG;
     std::memset(out, 0, sizeof(*out));
@@ -679,6 +718,9 @@ pbh_status pbh_get_stats(pbh_ctx* ctx, pbh_stats* out) {
     out->n_pp_far = (int64_t)h[kCntFar];
     out->n_pp_near = (int64_t)h[kCntNear];
     out->error_flags = (int64_t)h[kErr];
+    if (ctx->ev_build) out->ms_build = event_ms(ctx->ev[0], ctx->ev[1]);
+    if (ctx->ev_walk) out->ms_walk = event_ms(ctx->ev[2], ctx->ev[3]);
+    if (ctx->ev_nbr) out->ms_nbr = event_ms(ctx->ev[4], ctx->ev[5]);
     return PBH_OK;
 }
 
