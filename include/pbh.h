@@ -195,6 +195,24 @@ pbh_status pbh_get_stats(pbh_ctx* ctx, pbh_stats* out);
 pbh_status pbh_debug_tree(pbh_ctx* ctx, int32_t* order, uint64_t* keys, int64_t cap,
                           int64_t* nodes_i, double* nodes_d, int64_t* n_nodes);
 
+/*
+ * Debug export of the walk groups of the last build (waits for the stream):
+ * first sorted particle and particle count of each group, in particle order,
+ * and its tight box (lo xyz, hi xyz). Host buffers of cap entries, or NULL.
+ * The group count is written to *n_groups; PBH_E_ARG if cap is too small.
+ */
+pbh_status pbh_debug_groups(pbh_ctx* ctx, int64_t cap, int32_t* begin, int32_t* count,
+                            double* box /* [cap][6] */, int64_t* n_groups);
+
+/*
+ * Debug export of the persistent launches of the last walk and neighbour
+ * count: for each workgroup, the number of groups it processed and its
+ * run time in ticks of the 100 MHz device wall clock. Host buffers of
+ * [cap][2] uint64; the workgroup counts go to *n_walk and *n_nbr.
+ */
+pbh_status pbh_debug_wave_log(pbh_ctx* ctx, uint64_t* walk, uint64_t* nbr, int64_t cap,
+                              int64_t* n_walk, int64_t* n_nbr);
+
 const char* pbh_last_error(const pbh_ctx* ctx);
 const char* pbh_status_string(pbh_status s);
 

@@ -58,6 +58,8 @@ def lib():
         L.orc_tree.argtypes = [_i64, _p, _p, _d, _d, _d, _d, C.c_int, C.c_int, C.c_int, _p, _p, _p]
         L.orc_tree_nodes.restype = _i64
         L.orc_tree_nodes.argtypes = [_i64, _p, _p, C.c_int, C.c_int, _i64, _p, _p, _p]
+        L.orc_groups.restype = _i64
+        L.orc_groups.argtypes = [_i64, _p, _p, C.c_int, C.c_int, C.c_int, _i64, _p, _p]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -180,6 +182,18 @@ def tree_nodes(pos, mass, n_leaf=16, D=21):
     db = np.zeros((nn, 16))
     lib().orc_tree_nodes(n, _ptr(pos), _ptr(mass), int(n_leaf), int(D), nn, _ptr(order), _ptr(ib), _ptr(db))
     return order, ib, db
+
+
+def groups(pos, mass, n_leaf=16, n_crit=64, D=21):
+    """Walk groups: (begin [G], count [G]) in sorted-particle positions."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    mass = _f64(mass, (n,))
+    ng = lib().orc_groups(n, _ptr(pos), _ptr(mass), int(n_leaf), int(n_crit), int(D), 0, None, None)
+    b = np.zeros(ng, dtype=np.int64)
+    c = np.zeros(ng, dtype=np.int64)
+    lib().orc_groups(n, _ptr(pos), _ptr(mass), int(n_leaf), int(n_crit), int(D), ng, _ptr(b), _ptr(c))
+    return b, c
 
 
 def num_threads() -> int:

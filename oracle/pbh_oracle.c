@@ -378,7 +378,13 @@ int64_t orc_nbr_cells(int64_t n, const double* pos, double r_out,
 /*         children, in order: M = sum m; COM = sum m x / M;                */
 /*         Q_ab = sum [Q_c,ab + m (3 d_a d_b - |d|^2 delta_ab)], d = x-COM; */
 /*         tight box lo/hi; l = max extent; delta = |COM - box centre|.     */
-/*  groups consecutive runs of n_crit sorted particles; tight group box.    */
+/*  groups every node holding more than n_crit particles splits into      */
+/*         groups: a leaf (only at level D) into runs of n_crit particles;  */
+/*         an inner node packs its consecutive children that hold at most  */
+/*         n_crit particles, greedily and in order, into groups of at most  */
+/*         n_crit particles (a child with more than n_crit interrupts the   */
+/*         run). A root with at most n_crit particles is one group. Groups  */
+/*         are ordered by their first particle; each has a tight box.       */
 /*  walk   per group and node: dbox2 = squared distance between the group   */
 /*         box and the node box; near if dbox2 < r_out^2 or dbox2 == 0;     */
 /*         accept (multipole) if not near, theta > 0 and the squared        */
@@ -604,6 +610,50 @@ static double box_pt_d2(const double* lo, const double* hi, const double* c)
     return g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
 }
 
+typedef struct { int64_t begin, count; } ogroup_t;
+
+static int group_cmp(const void* a, const void* b)
+{
+    int64_t x = ((const ogroup_t*)a)->begin, y = ((const ogroup_t*)b)->begin;
+    return (x > y) - (x < y);
+}
+
+/* Walk groups of the tree (rule in the comment above); returns the count. */
+static int64_t make_groups(const otree_t* t, int n_crit, ogroup_t** out)
+{
+    ogroup_t* g = (ogroup_t*)malloc(sizeof(ogroup_t) * (size_t)(t->n + 1));
+    int64_t ng = 0;
+    for (int64_t k = 0; k < t->n_nodes; ++k) {
+        const onode_t* nd = &t->nodes[k];
+        if (nd->level == 0 && nd->count <= n_crit) {
+            g[ng].begin = nd->begin; g[ng].count = nd->count; ++ng;
+        }
+        if (nd->count <= n_crit) continue;
+        if (nd->nchild == 0) {
+            for (int64_t s = nd->begin; s < nd->begin + nd->count; s += n_crit) {
+                int64_t e = s + n_crit < nd->begin + nd->count ? s + n_crit : nd->begin + nd->count;
+                g[ng].begin = s; g[ng].count = e - s; ++ng;
+            }
+            continue;
+        }
+        int64_t run_begin = 0, run_count = 0;
+        for (int32_t c = 0; c < nd->nchild; ++c) {
+            const onode_t* ch = &t->nodes[nd->first_child + c];
+            if (ch->count > n_crit || run_count + ch->count > n_crit) {
+                if (run_count > 0) { g[ng].begin = run_begin; g[ng].count = run_count; ++ng; }
+                run_count = 0;
+            }
+            if (ch->count > n_crit) continue;
+            if (run_count == 0) run_begin = ch->begin;
+            run_count += ch->count;
+        }
+        if (run_count > 0) { g[ng].begin = run_begin; g[ng].count = run_count; ++ng; }
+    }
+    qsort(g, (size_t)ng, sizeof(ogroup_t), group_cmp);
+    *out = g;
+    return ng;
+}
+
 typedef struct {
     const otree_t* t;
     const phir_t* p;
@@ -715,7 +765,8 @@ void orc_tree(int64_t n, const double* pos, const double* mass,
     }
     phir_t p;
     phir_init(&p, r_in, r_out);
-    int64_t ngroups = (n + n_crit - 1) / n_crit;
+    ogroup_t* groups = NULL;
+    int64_t ngroups = make_groups(&t, n_crit, &groups);
     int64_t s_pn = 0, s_far = 0, s_near = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : s_pn, s_far, s_near)
     for (int64_t g = 0; g < ngroups; ++g) {
@@ -726,8 +777,8 @@ void orc_tree(int64_t n, const double* pos, const double* mass,
         w.eps2 = eps * eps;
         w.rout2 = r_out * r_out;
         w.theta = theta;
-        w.gbeg = g * n_crit;
-        w.gcnt = (w.gbeg + n_crit <= n) ? n_crit : n - w.gbeg;
+        w.gbeg = groups[g].begin;
+        w.gcnt = groups[g].count;
         for (int64_t u = 0; u < w.gcnt; ++u) {
             int64_t i = w.gbeg + u;
             double v[3] = {t.x[i], t.y[i], t.z[i]};
@@ -755,7 +806,25 @@ void orc_tree(int64_t n, const double* pos, const double* mass,
         stats[0] = t.n_nodes; stats[1] = leaves; stats[2] = ngroups;
         stats[3] = s_pn; stats[4] = s_far; stats[5] = s_near;
     }
+    free(groups);
     tree_free(&t);
+}
+
+/* Walk groups of one cluster: writes up to cap (begin, count) pairs, returns the count. */
+int64_t orc_groups(int64_t n, const double* pos, const double* mass, int n_leaf, int n_crit, int D,
+                   int64_t cap, int64_t* begin, int64_t* count)
+{
+    otree_t t;
+    tree_build(&t, n, pos, mass, n_leaf, D);
+    ogroup_t* groups = NULL;
+    int64_t ng = make_groups(&t, n_crit, &groups);
+    for (int64_t g = 0; g < ng && g < cap; ++g) {
+        begin[g] = groups[g].begin;
+        count[g] = groups[g].count;
+    }
+    free(groups);
+    tree_free(&t);
+    return ng;
 }
 
 /*

@@ -25,8 +25,8 @@ PBH_MIXED = 1
 
 EXPORTS = ("pbh_create", "pbh_destroy", "pbh_set_params", "pbh_get_params", "pbh_build",
            "pbh_force", "pbh_build_batched", "pbh_force_batched", "pbh_kdk", "pbh_kdk_eager",
-           "pbh_get_stats", "pbh_set_timing", "pbh_debug_tree", "pbh_last_error",
-           "pbh_status_string")
+           "pbh_get_stats", "pbh_set_timing", "pbh_debug_tree", "pbh_debug_groups",
+           "pbh_debug_wave_log", "pbh_last_error", "pbh_status_string")
 
 
 class pbh_params(C.Structure):
@@ -75,6 +75,8 @@ def load(path: str = LIB_PATH):
         "pbh_get_stats": (st, [vp, vp]),
         "pbh_set_timing": (st, [vp, i32]),
         "pbh_debug_tree": (st, [vp, vp, vp, i64, vp, vp, vp]),
+        "pbh_debug_groups": (st, [vp, i64, vp, vp, vp, vp]),
+        "pbh_debug_wave_log": (st, [vp, vp, vp, i64, vp, vp]),
         "pbh_last_error": (C.c_char_p, [vp]),
         "pbh_status_string": (C.c_char_p, [C.c_int]),
     }

@@ -180,6 +180,29 @@ class Pbh:
             out[name] = float(v) if typ is C.c_double else int(v)
         return out
 
+    def debug_groups(self):
+        """(begin int32 [G], count int32 [G], box f64 [G,6]) of the last build."""
+        ng = C.c_int64(0)
+        check(self.ctx, self.L.pbh_debug_groups(self.ctx, 0, None, None, None, C.byref(ng)))
+        b = np.zeros(ng.value, dtype=np.int32)
+        c = np.zeros(ng.value, dtype=np.int32)
+        box = np.zeros((ng.value, 6))
+        check(self.ctx, self.L.pbh_debug_groups(self.ctx, ng.value, b.ctypes.data_as(C.c_void_p),
+                                                c.ctypes.data_as(C.c_void_p),
+                                                box.ctypes.data_as(C.c_void_p), C.byref(ng)))
+        return b, c, box
+
+    def debug_wave_log(self):
+        """(walk [workgroups,2], nbr [workgroups,2]) of (groups, ticks at 100 MHz)."""
+        nw, nn = C.c_int64(0), C.c_int64(0)
+        check(self.ctx, self.L.pbh_debug_wave_log(self.ctx, None, None, 0, C.byref(nw), C.byref(nn)))
+        cap = max(nw.value, nn.value)
+        a = np.zeros((cap, 2), dtype=np.uint64)
+        b = np.zeros((cap, 2), dtype=np.uint64)
+        check(self.ctx, self.L.pbh_debug_wave_log(self.ctx, a.ctypes.data_as(C.c_void_p),
+                                                  b.ctypes.data_as(C.c_void_p), cap, None, None))
+        return a[: nw.value], b[: nn.value]
+
     def debug_tree(self):
         """(order int32 [n], keys uint64 [n], nodes_i int64 [nodes,4], nodes_d f64 [nodes,16])."""
         nn = C.c_int64(0)

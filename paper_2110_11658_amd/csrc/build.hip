@@ -12,7 +12,7 @@
 //            breadth-first order in which every node's children are contiguous
 //   moments  bottom-up, one launch per level: M, centre of mass, traceless
 //            quadrupole about it (parallel-axis sums over children), tight box
-//   groups   runs of n_crit sorted particles per cluster with a tight box
+//   groups   tree-bounded runs of <= n_crit sorted particles (rule at k_group_mark)
 //
 // FP64 arithmetic that decides the tree (keys, moments) is evaluated without
 // fused multiply-add so it rounds exactly as written.
@@ -265,6 +265,12 @@ __global__ void k_topo_emit(const uint64_t* __restrict__ keys, const int64_t* __
     }
 }
 
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 __global__ void k_zero_i32(int32_t* __restrict__ p, const int32_t* __restrict__ n_dev, int64_t cap) {
     const int64_t n = min(cap, (int64_t)*n_dev);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -410,49 +416,98 @@ __global__ void k_moments_level(const int32_t* __restrict__ lvl_off, int level,
 }
 
 // ------------------------------------------------------------------ groups
-// One wave per group: particles [begin, begin+count) of one cluster.
-__global__ __launch_bounds__(64) void k_groups(const int32_t* __restrict__ grp_first, int nc,
-                                               const int64_t* __restrict__ cl_off, int n_crit,
-                                               int64_t G, const int32_t* __restrict__ p_base,
-                                               const int32_t* __restrict__ pre2bfs,
-                                               const double* __restrict__ x,
-                                               const double* __restrict__ y,
-                                               const double* __restrict__ z, GroupArrays g) {
-    const int64_t gi = blockIdx.x;
-    if (gi >= G) return;
-    // cluster: last c with grp_first[c] <= gi
-    int lo = 0, hi = nc;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) / 2;
-        if (grp_first[mid] <= gi) lo = mid; else hi = mid;
+// Every node with more than n_crit particles splits into walk groups: a leaf
+// (only at level D) into runs of n_crit particles; an inner node packs its
+// consecutive children of at most n_crit particles, greedily in order, into
+// groups of at most n_crit (a larger child interrupts the run). A root with
+// at most n_crit particles is one group. The first particle of each group is
+// flagged; a scan of the flags numbers the groups in particle order.
+__global__ void k_group_mark(const WNode* __restrict__ node, const uint64_t* __restrict__ lvl,
+                             const unsigned long long* __restrict__ n_dev, int n_crit,
+                             int32_t* __restrict__ flag, int32_t* __restrict__ len) {
+    const int64_t nn = (int64_t)*n_dev;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nn;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        const WNode w = node[b];
+        if (lvl[b] == 0 && w.count <= n_crit) {
+            flag[w.begin] = 1;
+            len[w.begin] = w.count;
+        }
+        if (w.count <= n_crit) continue;
+        if (w.nchild == 0) {
+            for (int s = w.begin; s < w.begin + w.count; s += n_crit) {
+                flag[s] = 1;
+                len[s] = min(n_crit, w.begin + w.count - s);
+            }
+            continue;
+        }
+        int run_begin = 0, run_count = 0;
+        for (int u = 0; u < w.nchild; ++u) {
+            const int cb = node[w.first_child + u].begin;
+            const int cc = node[w.first_child + u].count;
+            if (cc > n_crit || run_count + cc > n_crit) {
+                if (run_count > 0) {
+                    flag[run_begin] = 1;
+                    len[run_begin] = run_count;
+                }
+                run_count = 0;
+            }
+            if (cc > n_crit) continue;
+            if (run_count == 0) run_begin = cb;
+            run_count += cc;
+        }
+        if (run_count > 0) {
+            flag[run_begin] = 1;
+            len[run_begin] = run_count;
+        }
     }
-    const int c = lo;
-    const int64_t cs = cl_off[c], ce = cl_off[c + 1];
-    const int64_t b = cs + (gi - grp_first[c]) * (int64_t)n_crit;
-    const int cntg = (int)((ce - b) < n_crit ? (ce - b) : n_crit);
+}
+
+__global__ void k_group_fill(const int32_t* __restrict__ gid, const int32_t* __restrict__ len,
+                             const uint64_t* __restrict__ keys, const int64_t* __restrict__ cl_off,
+                             int64_t n, int D, const int32_t* __restrict__ p_base,
+                             const int32_t* __restrict__ pre2bfs, GroupArrays g,
+                             unsigned long long* __restrict__ cnt) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (gid[i + 1] == gid[i]) continue;   // not the first particle of a group
+        const int32_t k = gid[i];
+        const int c = cluster_of(keys[i], D);
+        g.begin[k] = (int32_t)i;
+        g.count[k] = len[i];
+        g.cluster[k] = c;
+        g.root[k] = pre2bfs[p_base[cl_off[c]]];   // level-0 node started by the cluster's first particle
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) cnt[kCntGroups] = (unsigned long long)gid[n];
+}
+
+// One wave per group (persistent over the device-side group count): tight box.
+__global__ __launch_bounds__(64) void k_group_box(const unsigned long long* __restrict__ g_dev,
+                                                  const double* __restrict__ x,
+                                                  const double* __restrict__ y,
+                                                  const double* __restrict__ z, GroupArrays g) {
+    const int64_t G = (int64_t)*g_dev;
     const int lane = threadIdx.x;
-    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    for (int k = lane; k < cntg; k += 64) {
-        const double p[3] = {x[b + k], y[b + k], z[b + k]};
-        for (int d = 0; d < 3; ++d) {
-            v[d] = fmin(v[d], p[d]);
-            v[3 + d] = fmax(v[3 + d], p[d]);
+    for (int64_t gi = blockIdx.x; gi < G; gi += gridDim.x) {
+        const int b = g.begin[gi];
+        const int cntg = g.count[gi];
+        double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        for (int k = lane; k < cntg; k += 64) {
+            const double p[3] = {x[b + k], y[b + k], z[b + k]};
+            for (int d = 0; d < 3; ++d) {
+                v[d] = fmin(v[d], p[d]);
+                v[3 + d] = fmax(v[3 + d], p[d]);
+            }
         }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        for (int d = 0; d < 3; ++d) {
-            v[d] = fmin(v[d], __shfl_xor(v[d], o, 64));
-            v[3 + d] = fmax(v[3 + d], __shfl_xor(v[3 + d], o, 64));
+        for (int o = 32; o > 0; o >>= 1) {
+            for (int d = 0; d < 3; ++d) {
+                v[d] = fmin(v[d], __shfl_xor(v[d], o, 64));
+                v[3 + d] = fmax(v[3 + d], __shfl_xor(v[3 + d], o, 64));
+            }
         }
-    }
-    if (lane == 0) {
-        g.begin[gi] = (int32_t)b;
-        g.count[gi] = cntg;
-        g.cluster[gi] = c;
-        g.root[gi] = pre2bfs[p_base[cs]];   // level-0 node started by the cluster's first particle
-        for (int d = 0; d < 3; ++d) {
-            g.lo[3 * gi + d] = v[d];
-            g.hi[3 * gi + d] = v[3 + d];
+        if (lane < 3) {
+            g.lo[3 * gi + lane] = lane == 0 ? v[0] : (lane == 1 ? v[1] : v[2]);
+            g.hi[3 * gi + lane] = lane == 0 ? v[3] : (lane == 1 ? v[4] : v[5]);
         }
     }
 }
@@ -522,11 +577,20 @@ void launch_moments(Dev& d, const BuildCfg& c, hipStream_t s) {
     }
 }
 
-void launch_groups(Dev& d, const BuildCfg& c, const int32_t* grp_first, hipStream_t s) {
-    hipLaunchKernelGGL(k_groups, dim3(c.n_groups), dim3(64), 0, s, grp_first, c.n_clusters,
-                       (const int64_t*)d.cl_off, c.n_crit, c.n_groups, (const int32_t*)d.p_nn,
-                       (const int32_t*)d.pre2bfs, (const double*)d.x, (const double*)d.y,
-                       (const double*)d.z, d.g);
+void launch_groups(Dev& d, const BuildCfg& c, hipStream_t s) {
+    const int64_t n = c.n;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, d.g_flag, n + 1, 0);
+    hipLaunchKernelGGL(k_group_mark, dim3(grid_for(c.node_cap, 256, 2048)), dim3(256), 0, s,
+                       (const WNode*)d.node, (const uint64_t*)d.lvl_key,
+                       (const unsigned long long*)(d.cnt + kCntNodes), c.n_crit, d.g_flag, d.g_len);
+    exclusive_scan_i32(d.g_flag, d.g_flag, n, d.scan_tmp, s);   // g_flag[n] = group count
+    hipLaunchKernelGGL(k_group_fill, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                       (const int32_t*)d.g_flag, (const int32_t*)d.g_len, (const uint64_t*)d.keys,
+                       (const int64_t*)d.cl_off, n, c.D, (const int32_t*)d.p_nn,
+                       (const int32_t*)d.pre2bfs, d.g, d.cnt);
+    hipLaunchKernelGGL(k_group_box, dim3(grid_for(n, 64, 8192)), dim3(64), 0, s,
+                       (const unsigned long long*)(d.cnt + kCntGroups), (const double*)d.x,
+                       (const double*)d.y, (const double*)d.z, d.g);
 }
 
 }  // namespace pbh

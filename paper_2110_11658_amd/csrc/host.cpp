@@ -46,8 +46,6 @@ struct pbh_ctx {
     Dev d;
     std::vector<Buf> bufs;
     std::vector<int64_t> cl_off_h;
-    std::vector<int32_t> grp_first_h;
-    int32_t* grp_first_d = nullptr;
     int nblk_box = 0;
     // allocation sizes
     int64_t a_n = -1, a_cap = -1, a_G = -1, a_C = -1, a_nblk = -1, a_stack = -1;
@@ -89,7 +87,6 @@ void free_all(pbh_ctx* ctx) {
         if (b.p) (void)hipFree(b.p);
     ctx->bufs.clear();
     ctx->d = Dev();
-    ctx->grp_first_d = nullptr;
     ctx->a_n = ctx->a_cap = ctx->a_G = ctx->a_C = ctx->a_nblk = ctx->a_stack = -1;
 }
 
@@ -141,12 +138,15 @@ pbh_status ensure_buffers(pbh_ctx* ctx) {
               dalloc(ctx, &d.bfs2pre, cap) && dalloc(ctx, &d.pre2bfs, cap) &&
               dalloc(ctx, &d.lvl_off, 32) && dalloc(ctx, &d.node, cap) &&
               dalloc(ctx, &d.q64, cap) && dalloc(ctx, &d.q32, cap) &&
+              dalloc(ctx, &d.g_flag, n + 1) && dalloc(ctx, &d.g_len, n) &&
               dalloc(ctx, &d.g.begin, G) && dalloc(ctx, &d.g.count, G) &&
               dalloc(ctx, &d.g.root, G) && dalloc(ctx, &d.g.cluster, G) &&
               dalloc(ctx, &d.g.lo, 3 * G) && dalloc(ctx, &d.g.hi, 3 * G) &&
-              dalloc(ctx, &ctx->grp_first_d, C + 1) && dalloc(ctx, &d.scan_tmp, scan_len) &&
+              dalloc(ctx, &d.scan_tmp, scan_len) &&
               dalloc(ctx, &d.rs_hist, radix_hist_need(big) + 1) && dalloc(ctx, &d.nbr_cnt, n) &&
-              dalloc(ctx, &d.stack, stack) && dalloc(ctx, &d.cnt, kNumCounters);
+              dalloc(ctx, &d.stack, stack) && dalloc(ctx, &d.cnt, kNumCounters) &&
+              dalloc(ctx, &d.wave_log, 2 * (stack / kStackCap)) &&
+              dalloc(ctx, &d.wave_log_nbr, 2 * (stack / kStackCap));
     if (!ok) {
         free_all(ctx);
         return fail(ctx, PBH_E_OOM, "device allocation failed");
@@ -174,15 +174,11 @@ pbh_status setup_build(pbh_ctx* ctx, int64_t n, int32_t C, const int64_t* offset
     c.node_cap = node_capacity(n, D, c.n_leaf, C);
     if (c.node_cap >= (1ll << 31)) return fail(ctx, PBH_E_ARG, "too many particles for int32 node indices");
     ctx->cl_off_h.assign(offsets, offsets + C + 1);
-    ctx->grp_first_h.assign(C + 1, 0);
     std::vector<int32_t> blk_cluster;
     std::vector<int64_t> blk_range;
     std::vector<int32_t> cblk(C + 1, 0);
-    int64_t G = 0;
     for (int k = 0; k < C; ++k) {
         const int64_t a = offsets[k], b = offsets[k + 1];
-        ctx->grp_first_h[k] = (int32_t)G;
-        G += (b - a + c.n_crit - 1) / c.n_crit;
         cblk[k] = (int32_t)blk_cluster.size();
         for (int64_t q = a; q < b; q += kBoxChunk) {
             blk_cluster.push_back(k);
@@ -190,9 +186,8 @@ pbh_status setup_build(pbh_ctx* ctx, int64_t n, int32_t C, const int64_t* offset
             blk_range.push_back(std::min(b, q + kBoxChunk));
         }
     }
-    ctx->grp_first_h[C] = (int32_t)G;
     cblk[C] = (int32_t)blk_cluster.size();
-    c.n_groups = G;
+    c.n_groups = n;   // capacity; the walk reads the actual count on the device
     ctx->nblk_box = (int)blk_cluster.size();
     if (ctx->grid_mixed == 0) {
         ctx->grid_mixed = walk_blocks_per_cu(1) * ctx->cus;
@@ -208,8 +203,6 @@ pbh_status setup_build(pbh_ctx* ctx, int64_t n, int32_t C, const int64_t* offset
     HIP_TRY(hipMemcpyAsync(ctx->d.blk_range, blk_range.data(), blk_range.size() * sizeof(int64_t),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(ctx->d.cl_off, ctx->cl_off_h.data(), (C + 1) * sizeof(int64_t),
-                           hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ctx->grp_first_d, ctx->grp_first_h.data(), (C + 1) * sizeof(int32_t),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));   // the host tables above are temporaries
     return PBH_OK;
@@ -227,7 +220,7 @@ void enqueue_build(pbh_ctx* ctx, const double* pos, const double* mass, hipStrea
     launch_gather(d, c, pos, mass, s);
     launch_topology(d, c, s);
     launch_moments(d, c, s);
-    launch_groups(d, c, ctx->grp_first_d, s);
+    launch_groups(d, c, s);
 }
 
 // Changeover constants of one cluster (see ClusterParams).
@@ -358,7 +351,7 @@ pbh_status do_force(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, double 
     w.eps = eps;
     w.mixed = ctx->params.prec == PBH_MIXED;
     const int gmax = w.mixed ? ctx->grid_mixed : ctx->grid_fp64;
-    w.grid = (int)std::min<int64_t>(gmax, std::max<int64_t>(c.n_groups, 1));
+    w.grid = gmax;   // persistent: workgroups leave when the group queue is empty
     w.stack_cap = kStackCap;
     mark(ctx, 2, s);
     launch_walk(d, c, w, acc, pot, s);
@@ -366,7 +359,7 @@ pbh_status do_force(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, double 
     ctx->ev_walk = ctx->timing;
     ctx->ev_nbr = false;
     if (nbr_off) {
-        const int grid = (int)std::min<int64_t>(ctx->grid_mixed, std::max<int64_t>(c.n_groups, 1));
+        const int grid = ctx->grid_mixed;
         mark(ctx, 4, s);
         launch_nbr_count(d, c, grid, kStackCap, s);
         exclusive_scan_i32_to_i64(d.nbr_cnt, nbr_off, c.n, d.scan_tmp, s);
@@ -599,7 +592,7 @@ static void kdk_force(pbh_ctx* ctx, const double* pos, const double* mass, doubl
     w.eps = eps;
     w.mixed = ctx->params.prec == PBH_MIXED;
     const int gmax = w.mixed ? ctx->grid_mixed : ctx->grid_fp64;
-    w.grid = (int)std::min<int64_t>(gmax, std::max<int64_t>(ctx->cfg.n_groups, 1));
+    w.grid = gmax;
     w.stack_cap = kStackCap;
     launch_walk(ctx->d, ctx->cfg, w, ctx->k_acc, ctx->k_pot, s);
 }
@@ -712,7 +705,7 @@ pbh_status pbh_get_stats(pbh_ctx* ctx, pbh_stats* out) {
     out->n_clusters = ctx->cfg.n_clusters;
     out->n_nodes = (int64_t)h[kCntNodes];
     out->n_leaves = (int64_t)h[kCntLeaves];
-    out->n_groups = ctx->cfg.n_groups;
+    out->n_groups = (int64_t)h[kCntGroups];
     out->max_level = (int64_t)h[kCntMaxLevel];
     out->n_pn = (int64_t)h[kCntPN];
     out->n_pp_far = (int64_t)h[kCntFar];
@@ -721,6 +714,48 @@ pbh_status pbh_get_stats(pbh_ctx* ctx, pbh_stats* out) {
     if (ctx->ev_build) out->ms_build = event_ms(ctx->ev[0], ctx->ev[1]);
     if (ctx->ev_walk) out->ms_walk = event_ms(ctx->ev[2], ctx->ev[3]);
     if (ctx->ev_nbr) out->ms_nbr = event_ms(ctx->ev[4], ctx->ev[5]);
+    return PBH_OK;
+}
+
+pbh_status pbh_debug_groups(pbh_ctx* ctx, int64_t cap, int32_t* begin, int32_t* count,
+                            double* box, int64_t* n_groups) {
+    if (!ctx) return PBH_E_ARG;
+    if (!ctx->built) return fail(ctx, PBH_E_STATE, "no successful build");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipStreamSynchronize(ctx->last));
+    unsigned long long G = 0;
+    HIP_TRY(hipMemcpy(&G, ctx->d.cnt + kCntGroups, sizeof(G), hipMemcpyDeviceToHost));
+    if (n_groups) *n_groups = (int64_t)G;
+    if (!begin && !count && !box) return PBH_OK;
+    if (cap < (int64_t)G) return fail(ctx, PBH_E_ARG, "group buffer too small");
+    if (begin) HIP_TRY(hipMemcpy(begin, ctx->d.g.begin, sizeof(int32_t) * G, hipMemcpyDeviceToHost));
+    if (count) HIP_TRY(hipMemcpy(count, ctx->d.g.count, sizeof(int32_t) * G, hipMemcpyDeviceToHost));
+    if (box) {
+        std::vector<double> lo(3 * G), hi(3 * G);
+        HIP_TRY(hipMemcpy(lo.data(), ctx->d.g.lo, sizeof(double) * 3 * G, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hi.data(), ctx->d.g.hi, sizeof(double) * 3 * G, hipMemcpyDeviceToHost));
+        for (unsigned long long g = 0; g < G; ++g)
+            for (int k = 0; k < 3; ++k) {
+                box[6 * g + k] = lo[3 * g + k];
+                box[6 * g + 3 + k] = hi[3 * g + k];
+            }
+    }
+    return PBH_OK;
+}
+
+pbh_status pbh_debug_wave_log(pbh_ctx* ctx, uint64_t* walk, uint64_t* nbr, int64_t cap,
+                                         int64_t* n_walk, int64_t* n_nbr) {
+    if (!ctx || !ctx->d.wave_log) return PBH_E_ARG;
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipStreamSynchronize(ctx->last));
+    const int64_t gw = ctx->params.prec == PBH_MIXED ? ctx->grid_mixed : ctx->grid_fp64;
+    const int64_t gn = ctx->grid_mixed;
+    if (n_walk) *n_walk = gw;
+    if (n_nbr) *n_nbr = gn;
+    if (walk && cap >= gw)
+        HIP_TRY(hipMemcpy(walk, ctx->d.wave_log, 16 * gw, hipMemcpyDeviceToHost));
+    if (nbr && cap >= gn)
+        HIP_TRY(hipMemcpy(nbr, ctx->d.wave_log_nbr, 16 * gn, hipMemcpyDeviceToHost));
     return PBH_OK;
 }
 

@@ -27,7 +27,7 @@ struct NbrParams {
     const double* g_lo;
     const double* g_hi;
     const ClusterParams* cp;
-    int64_t G;
+    const unsigned long long* G;   // device-side group count
     int32_t* counts;        // count pass: per caller index
     const int64_t* off;     // fill pass: CSR offsets (caller order)
     int32_t* idx;           // fill pass
@@ -36,6 +36,7 @@ struct NbrParams {
     int stack_cap;
     unsigned long long* cnt;
     int queue;
+    unsigned long long* wave_log;   // per workgroup: groups done, clock ticks (count pass)
 };
 
 // Wave-uniform helpers (see walk.hip): scalar copies of wave-uniform values
@@ -81,9 +82,13 @@ template <bool FILL>
 __global__ __launch_bounds__(64) void k_nbr(NbrParams p) {
     const int lane = threadIdx.x;
     int32_t* stack = p.stack + (int64_t)blockIdx.x * p.stack_cap;
+    const int64_t G = (int64_t)*p.G;
+    const unsigned long long t_start = wall_clock64();
+    int n_done = 0;
     for (;;) {
         const int g = wave_next(&p.cnt[p.queue], lane);
-        if (g >= p.G) break;
+        if (g >= G) break;
+        ++n_done;
         const int gb = uni(p.g_begin[g]), gcnt = uni(p.g_count[g]), root = uni(p.g_root[g]);
         const double rout2 = p.cp[p.g_cluster[g]].rout2;
         double glo[3], ghi[3];
@@ -145,6 +150,10 @@ __global__ __launch_bounds__(64) void k_nbr(NbrParams p) {
         const uint64_t ov = __ballot(overflow);
         if (ov) atomicOr(&p.cnt[kErr], lane == 0 ? (FILL ? kErrNbrOverflow : kErrNbrStack) : 0ull);
     }
+    if (!FILL && p.wave_log) {
+        p.wave_log[2 * blockIdx.x] = (unsigned long long)n_done;
+        p.wave_log[2 * blockIdx.x + 1] = wall_clock64() - t_start;
+    }
 }
 
 NbrParams make_params(Dev& d, const BuildCfg& c, int stack_cap) {
@@ -155,7 +164,7 @@ NbrParams make_params(Dev& d, const BuildCfg& c, int stack_cap) {
     p.g_begin = d.g.begin; p.g_count = d.g.count; p.g_root = d.g.root; p.g_cluster = d.g.cluster;
     p.g_lo = d.g.lo; p.g_hi = d.g.hi;
     p.cp = d.cparams;
-    p.G = c.n_groups;
+    p.G = d.cnt + kCntGroups;
     p.counts = d.nbr_cnt;
     p.off = nullptr;
     p.idx = nullptr;
@@ -164,6 +173,7 @@ NbrParams make_params(Dev& d, const BuildCfg& c, int stack_cap) {
     p.stack_cap = stack_cap;
     p.cnt = d.cnt;
     p.queue = kQueueNbrCount;
+    p.wave_log = d.wave_log_nbr;
     return p;
 }
 

@@ -36,7 +36,7 @@ enum : unsigned long long {
 // slots of the device counter array
 enum { kCntNodes = 0, kCntPN = 1, kCntFar = 2, kCntNear = 3, kCntNbrTotal = 4, kErr = 5,
        kQueueWalk = 6, kQueueNbrCount = 7, kQueueNbrFill = 8, kCntMaxLevel = 9,
-       kCntLeaves = 10, kNumCounters = 16 };
+       kCntLeaves = 10, kCntGroups = 12, kNumCounters = 16 };
 
 struct alignas(16) WNode {
     double lo[3];
@@ -120,8 +120,10 @@ struct Dev {
     WNode* node = nullptr;
     Mom64* q64 = nullptr;
     Mom32* q32 = nullptr;
-    // groups
+    // groups (capacity n: the count is data dependent, kept in cnt[kCntGroups])
     GroupArrays g;
+    int32_t* g_flag = nullptr;   // [n+1] 1 at the first particle of a group, then scanned
+    int32_t* g_len = nullptr;    // [n] group length at its first particle
     // generic scan scratch
     int64_t* scan_tmp = nullptr;
     int64_t scan_tmp_len = 0;
@@ -135,6 +137,9 @@ struct Dev {
     int64_t stack_len = 0;
     // counters
     unsigned long long* cnt = nullptr;
+    // per persistent workgroup of the last walk / neighbour count: groups, clock ticks
+    unsigned long long* wave_log = nullptr;
+    unsigned long long* wave_log_nbr = nullptr;
 };
 
 // ---- launchers (all enqueue on `s`, none waits) ----
@@ -158,7 +163,7 @@ void launch_keys(Dev& d, const BuildCfg& c, const double* pos, int nblk, hipStre
 void launch_gather(Dev& d, const BuildCfg& c, const double* pos, const double* mass, hipStream_t s);
 void launch_topology(Dev& d, const BuildCfg& c, hipStream_t s);
 void launch_moments(Dev& d, const BuildCfg& c, hipStream_t s);
-void launch_groups(Dev& d, const BuildCfg& c, const int32_t* grp_cluster_first, hipStream_t s);
+void launch_groups(Dev& d, const BuildCfg& c, hipStream_t s);
 
 // walk.hip
 struct WalkCfg {

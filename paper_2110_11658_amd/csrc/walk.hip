@@ -56,7 +56,7 @@ struct WalkParams {
     const double* g_lo;
     const double* g_hi;
     const ClusterParams* cp;
-    int64_t G;
+    const unsigned long long* G;   // device-side group count
     int use_theta;
     double eps2;
     double* acc;
@@ -64,6 +64,7 @@ struct WalkParams {
     int32_t* stack;
     int stack_cap;
     unsigned long long* cnt;
+    unsigned long long* wave_log;   // per workgroup: groups walked, clock ticks
 };
 
 __device__ inline int popc_below(uint64_t mask) {
@@ -250,10 +251,14 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
     const int lane = threadIdx.x;
     int32_t* stack = p.stack + (int64_t)blockIdx.x * p.stack_cap;
     const R eps2 = (R)p.eps2;
+    const int64_t G = (int64_t)*p.G;
+    const unsigned long long t_start = wall_clock64();
+    int n_walked = 0;
 
     for (;;) {
         const int g = wave_next(&p.cnt[kQueueWalk], lane);
-        if (g >= p.G) break;
+        if (g >= G) break;
+        ++n_walked;
 
         const int gb = uni(p.g_begin[g]), gcnt = uni(p.g_count[g]), root = uni(p.g_root[g]);
         const int cl = uni(p.g_cluster[g]);
@@ -405,6 +410,10 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
         atomicAdd(&p.cnt[kCntFar], c_far * l0);
         atomicAdd(&p.cnt[kCntNear], c_near * l0);
     }
+    if (p.wave_log) {
+        p.wave_log[2 * blockIdx.x] = (unsigned long long)n_walked;
+        p.wave_log[2 * blockIdx.x + 1] = wall_clock64() - t_start;
+    }
 }
 
 // rcrit^2 = (l/theta + delta)^2 per node, l = largest box extent, delta =
@@ -458,7 +467,7 @@ void launch_walk(Dev& d, const BuildCfg& c, const WalkCfg& w, double* acc, doubl
     p.g_begin = d.g.begin; p.g_count = d.g.count; p.g_root = d.g.root; p.g_cluster = d.g.cluster;
     p.g_lo = d.g.lo; p.g_hi = d.g.hi;
     p.cp = d.cparams;
-    p.G = c.n_groups;
+    p.G = d.cnt + kCntGroups;
     p.use_theta = w.theta > 0.0;
     p.eps2 = w.eps * w.eps;
     p.acc = acc;
@@ -466,6 +475,7 @@ void launch_walk(Dev& d, const BuildCfg& c, const WalkCfg& w, double* acc, doubl
     p.stack = d.stack;
     p.stack_cap = w.stack_cap;
     p.cnt = d.cnt;
+    p.wave_log = d.wave_log;
     if (w.mixed) hipLaunchKernelGGL(k_walk<true>, dim3(w.grid), dim3(64), 0, s, p);
     else hipLaunchKernelGGL(k_walk<false>, dim3(w.grid), dim3(64), 0, s, p);
 }

@@ -71,6 +71,14 @@ def test_tree_bit_exact(n, n_leaf, seed):
     st = p.stats()
     assert st["n_nodes"] == oi.shape[0] and st["n_leaves"] == int((oi[:, 2] == 0).sum())
     assert st["error_flags"] == 0
+    gb, gc, gbox = p.debug_groups()
+    ob, oc = oracle.groups(c.pos, c.mass, n_leaf=n_leaf, n_crit=64)
+    assert np.array_equal(gb.astype(np.int64), ob) and np.array_equal(gc.astype(np.int64), oc)
+    xs = c.pos[oorder]
+    for g in range(0, gb.size, 5):
+        pts = xs[gb[g]:gb[g] + gc[g]]
+        assert np.array_equal(gbox[g, :3], pts.min(0)) and np.array_equal(gbox[g, 3:], pts.max(0))
+    assert st["n_groups"] == gb.size
 
 
 def test_sort_ties_and_duplicates():

@@ -302,6 +302,33 @@ def test_node_moments_against_direct_sums():
         assert np.array_equal(db[k, 10:13], x.min(0)) and np.array_equal(db[k, 13:16], x.max(0))
 
 
+@pytest.mark.parametrize("n,n_leaf,n_crit", [(3000, 16, 64), (2000, 8, 32), (400, 4, 7), (50, 16, 64)])
+def test_walk_group_invariants(n, n_leaf, n_crit):
+    c = ic.plummer(n, seed=31, masses="kroupa")
+    order, ib, db = oracle.tree_nodes(c.pos, c.mass, n_leaf=n_leaf, D=21)
+    gb, gc = oracle.groups(c.pos, c.mass, n_leaf=n_leaf, n_crit=n_crit)
+    # a partition of the sorted particles into runs of at most n_crit
+    assert gb[0] == 0 and np.all(gb[1:] == gb[:-1] + gc[:-1]) and gb[-1] + gc[-1] == n
+    assert np.all(gc >= 1) and np.all(gc <= n_crit)
+    # every group lies inside one node whose parent (the smallest enclosing
+    # node holding more than n_crit) it cannot leave: find the smallest node
+    # containing each group and check that node is either a small node inside
+    # a large parent, the large node itself (a split leaf), or a small root
+    big = ib[ib[:, 1] > n_crit]
+    for b, k in zip(gb, gc):
+        host = big[(big[:, 0] <= b) & (big[:, 0] + big[:, 1] >= b + k)]
+        if host.size == 0:
+            assert ib[0, 1] <= n_crit and b == 0 and k == n      # the root is one group
+        else:
+            assert host[:, 1].min() > n_crit
+    # the walk through these groups still equals direct summation at theta = 0
+    r_out = 0.1
+    acc, pot = oracle.direct(c.pos, c.mass, 0.1 * r_out, r_out, 1e-4)
+    at, pt, st = oracle.tree(c.pos, c.mass, 0.1 * r_out, r_out, 0.0, 1e-4, n_leaf=n_leaf, n_crit=n_crit)
+    assert st["groups"] == gb.size
+    assert np.max(np.linalg.norm(at - acc, axis=1) / np.linalg.norm(acc, axis=1)) < 1e-12
+
+
 # --- P-8: theta = 0 tree equals direct summation (Section 2.4) ----------------
 
 @pytest.mark.parametrize("n_leaf,n_crit", [(16, 64), (1, 1), (8, 32)])
