@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--ncrit", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-neighbours", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the timed region, copy a buffer of this many MiB once "
+                         "(a plain copy kernel of known size, to scale HBM byte counters)")
     return ap.parse_args()
 
 
@@ -106,6 +109,14 @@ def main():
         check(ctx, L.pbh_force(ctx, w["r_in"], w["r_out"], theta, w["eps"], _ptr(acc), _ptr(pot),
                                _ptr(off) if neighbours else None, _ptr(idx) if neighbours else None,
                                cap if neighbours else 0, None, _stream()))
+
+    if args.calib_copy_mib:
+        src = torch.empty(args.calib_copy_mib << 17, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     p.set_timing(True)
     for _ in range(args.warmup):
