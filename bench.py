@@ -46,6 +46,24 @@ WORKLOADS = {
 }
 
 
+def walk_traffic(kernel: str):
+    """HBM bytes per walk launch from the committed rocprofv3 counter summary,
+    or None when the walk source has changed since the counters were taken."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2110_11658_amd", "csrc", "walk.hip")
+    prof = os.path.join(ROOT, "profiles", "k_walk_plummer1m_hbm_traffic.md")
+    if not os.path.exists(prof):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    text = open(prof).read()
+    m_sha = re.search(r"walk.hip sha256 prefix: ([0-9a-f]{16})", text)
+    m_val = re.search(r"traffic_bytes_per_launch " + re.escape(kernel) + r": ([0-9]+)", text)
+    if not m_sha or not m_val or m_sha.group(1) != sha:
+        return None
+    return float(m_val.group(1))
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,7 +188,9 @@ def main():
         "interactions_per_step": {"pn": s["n_pn"], "pp_far": s["n_pp_far"], "pp_near": s["n_pp_near"]},
         "nbr_total": int(off[-1].item()) if neighbours else None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": (walk_traffic("k_walk<true>") if args.prec == "mixed"
+                                 and wname == "plummer1m_kroupa" else None),
                      "kernel": "k_walk<mixed>" if args.prec == "mixed" else "k_walk<fp64>",
                      "flops_per_launch": flops},
     }
