@@ -21,7 +21,7 @@ using namespace pbh;
 namespace {
 
 constexpr int kBoxChunk = 16384;     // particles per bbox/key block
-constexpr int kStackCap = 16384;     // traversal stack entries per persistent wave
+constexpr int kStackCap = 16384;     // traversal stack entries per persistent wave (LDS + spill)
 constexpr int kCntKdkStep = 11;      // counter slot: KDK energy output index
 
 struct Buf {
@@ -145,6 +145,7 @@ pbh_status ensure_buffers(pbh_ctx* ctx) {
               dalloc(ctx, &d.scan_tmp, scan_len) &&
               dalloc(ctx, &d.rs_hist, radix_hist_need(big) + 1) && dalloc(ctx, &d.nbr_cnt, n) &&
               dalloc(ctx, &d.stack, stack) && dalloc(ctx, &d.cnt, kNumCounters) &&
+              dalloc(ctx, &d.queues, 32) &&
               dalloc(ctx, &d.wave_log, 2 * (stack / kStackCap)) &&
               dalloc(ctx, &d.wave_log_nbr, 2 * (stack / kStackCap));
     if (!ok) {

@@ -1,18 +1,24 @@
 // nbr.hip -- neighbour lists inside r_out (gfx950).
 //
 // The list of particle i is { j != i : r_ij^2 < r_out^2 } with unsoftened
-// FP64 distances evaluated without FMA as ((dx*dx + dy*dy) + dz*dz), the
+// FP64 distances evaluated without FMA as ((dx*dx + dy*dy) + dz*dz): the
 // constant neighbour radius of Section 2.3 of Arnold, Baumgardt & Wang (2021);
 // empty lists are legal. One wave per group walks only the nodes whose box
 // comes closer than r_out to the group box (box distances never exceed pair
-// distances, also after rounding, so no neighbour is missed). Two passes with
-// the same deterministic order: counts (in caller order, scanned on the host
-// side of the library into CSR offsets), then indices.
+// distances, also after rounding, so no neighbour is missed). The particles
+// of those leaves are staged 64 at a time in an LDS tile (FP64 position and
+// caller index, loaded lane-parallel) and every lane tests its own particle
+// against each tile entry by LDS broadcast. Two passes with the same
+// deterministic order: counts per caller index (scanned into CSR offsets by
+// the host library), then indices.
 #include "pbh_internal.hpp"
+#include "wave.hpp"
 
 namespace pbh {
 
 namespace {
+
+constexpr int NCAP = 128;   // candidate tile: < 64 left over + 64 new
 
 struct NbrParams {
     const WNode* node;
@@ -28,69 +34,60 @@ struct NbrParams {
     const double* g_hi;
     const ClusterParams* cp;
     const unsigned long long* G;   // device-side group count
-    int32_t* counts;        // count pass: per caller index
-    const int64_t* off;     // fill pass: CSR offsets (caller order)
-    int32_t* idx;           // fill pass
+    int32_t* counts;               // count pass: per caller index
+    const int64_t* off;            // fill pass: CSR offsets (caller order)
+    int32_t* idx;                  // fill pass
     int64_t cap;
     int32_t* stack;
     int stack_cap;
     unsigned long long* cnt;
-    int queue;
-    unsigned long long* wave_log;   // per workgroup: groups done, clock ticks (count pass)
+    unsigned long long* queues;    // [kQueues] of this pass
+    unsigned long long* wave_log;  // per workgroup: groups done, clock ticks (count pass)
 };
 
-// Wave-uniform helpers (see walk.hip): scalar copies of wave-uniform values
-// and a branch-free work-queue fetch.
-__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+struct NTile {
+    double x[NCAP], y[NCAP], z[NCAP];
+    int orig[NCAP];
+    int lf_ex[64];
+    int lf_beg[64];
+};
 
-__device__ inline int wave_next(unsigned long long* ctr, int lane) {
-    const unsigned long long r = atomicAdd(ctr, lane == 0 ? 1ull : 0ull);
-    return uni((int)r);
-}
-
-__device__ inline int wave_incl_scan(int v, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
-    return v;
-}
-
-__device__ inline double box_box_d2(const double* glo, const double* ghi, const double* lo,
-                                    const double* hi) {
+template <bool FILL>
+__device__ inline void test_tile(const NTile& T, int cnt, double xi, double yi, double zi, int me_orig,
+                                 bool active, double rout2, const NbrParams& p, int64_t wpos,
+                                 int& count, bool& overflow) {
 #pragma clang fp contract(off)
-    double g[3];
-    for (int k = 0; k < 3; ++k) {
-        const double a = lo[k] - ghi[k];
-        const double b = glo[k] - hi[k];
-        const double v = a > b ? a : b;
-        g[k] = v > 0.0 ? v : 0.0;
+    for (int e = 0; e < cnt; ++e) {
+        const double dx = T.x[e] - xi, dy = T.y[e] - yi, dz = T.z[e] - zi;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const int oj = T.orig[e];
+        if (active && r2 < rout2 && oj != me_orig) {
+            if (FILL) {
+                const int64_t at = wpos + count;
+                if (at < p.cap) p.idx[at] = oj;
+                else overflow = true;
+            }
+            ++count;
+        }
     }
-    return g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
-}
-
-__device__ inline bool within(double xi, double yi, double zi, double xj, double yj, double zj,
-                              double rout2) {
-#pragma clang fp contract(off)
-    const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    return r2 < rout2;
 }
 
 template <bool FILL>
 __global__ __launch_bounds__(64) void k_nbr(NbrParams p) {
+    __shared__ NTile T;
+    __shared__ int s_stack[kStackLds];
     const int lane = threadIdx.x;
-    int32_t* stack = p.stack + (int64_t)blockIdx.x * p.stack_cap;
+    const Stack stack{s_stack, p.stack + (int64_t)blockIdx.x * (p.stack_cap - kStackLds), p.stack_cap};
     const int64_t G = (int64_t)*p.G;
+    int home = blockIdx.x % kQueues;
     const unsigned long long t_start = wall_clock64();
     int n_done = 0;
     for (;;) {
-        const int g = wave_next(&p.cnt[p.queue], lane);
-        if (g >= G) break;
+        const int64_t g = queue_next(p.queues, G, home, lane);
+        if (g < 0) break;
         ++n_done;
         const int gb = uni(p.g_begin[g]), gcnt = uni(p.g_count[g]), root = uni(p.g_root[g]);
-        const double rout2 = p.cp[p.g_cluster[g]].rout2;
+        const double rout2 = p.cp[uni(p.g_cluster[g])].rout2;
         double glo[3], ghi[3];
         for (int k = 0; k < 3; ++k) {
             glo[k] = p.g_lo[3 * g + k];
@@ -105,14 +102,16 @@ __global__ __launch_bounds__(64) void k_nbr(NbrParams p) {
         int count = 0;
         bool overflow = false;
         if (rout2 > 0.0) {
-            stack[0] = root;   // every lane stores the same value
+            stack.put(0, root);
             int top = 1;
+            int fill = 0;
             while (top > 0) {
                 __threadfence_block();
                 const int npop = uni(top < 64 ? top : 64);
                 top -= npop;
                 const bool has = lane < npop;
-                const int nd = has ? stack[top + lane] : root;
+                const int nd = has ? stack.get(top + lane) : root;
+                __threadfence_block();
                 const WNode w = p.node[nd];
                 const bool near = has && box_box_d2(glo, ghi, w.lo, w.hi) < rout2;
                 const bool leaf = w.nchild == 0;
@@ -123,28 +122,44 @@ __global__ __launch_bounds__(64) void k_nbr(NbrParams p) {
                     overflow = true;
                     break;
                 }
-                for (int k = 0; k < nch; ++k) stack[top + incl - nch + k] = w.first_child + k;
+                for (int k = 0; k < nch; ++k) stack.put(top + incl - nch + k, w.first_child + k);
                 top = uni(top + tot);
-                uint64_t lm = __ballot(near && leaf);
-                while (lm) {
-                    const int k = __ffsll((long long)lm) - 1;
-                    lm &= lm - 1;
-                    const int lb = uni(__shfl(w.begin, k, 64));
-                    const int lc = uni(__shfl(w.count, k, 64));
-                    for (int j = lb; j < lb + lc; ++j) {
-                        const bool hit = active && j != me &&
-                                         within(xi, yi, zi, p.x[j], p.y[j], p.z[j], rout2);
-                        if (hit) {
-                            if (FILL) {
-                                const int64_t at = wpos + count;
-                                if (at < p.cap) p.idx[at] = p.perm[j];
-                                else overflow = true;
-                            }
-                            ++count;
-                        }
+                // particles of near leaves into the candidate tile
+                const bool flag = near && leaf;
+                if (!__ballot(flag)) continue;
+                const int v = flag ? w.count : 0;
+                const int li = wave_incl_scan(v, lane);
+                const int total = uni(__shfl(li, 63, 64));
+                __syncthreads();
+                T.lf_ex[lane] = li - v;
+                T.lf_beg[lane] = w.begin;
+                __syncthreads();
+                for (int base = 0; base < total; base += 64) {
+                    const int s = base + lane;
+                    int k = 0;
+#pragma unroll
+                    for (int st = 32; st > 0; st >>= 1)
+                        if (T.lf_ex[k + st] <= s) k += st;
+                    const int j = T.lf_beg[k] + (s - T.lf_ex[k]);
+                    if (s < total) {
+                        T.x[fill + lane] = p.x[j];
+                        T.y[fill + lane] = p.y[j];
+                        T.z[fill + lane] = p.z[j];
+                        T.orig[fill + lane] = p.perm[j];
+                    }
+                    fill = uni(fill + ((total - base) < 64 ? (total - base) : 64));
+                    if (fill >= 64) {
+                        __syncthreads();
+                        test_tile<FILL>(T, fill, xi, yi, zi, orig, active, rout2, p, wpos, count, overflow);
+                        fill = 0;
+                        __syncthreads();
                     }
                 }
+                __syncthreads();
             }
+            __syncthreads();
+            if (fill) test_tile<FILL>(T, fill, xi, yi, zi, orig, active, rout2, p, wpos, count, overflow);
+            __syncthreads();
         }
         if (!FILL && active) p.counts[orig] = count;
         const uint64_t ov = __ballot(overflow);
@@ -172,8 +187,9 @@ NbrParams make_params(Dev& d, const BuildCfg& c, int stack_cap) {
     p.stack = d.stack;
     p.stack_cap = stack_cap;
     p.cnt = d.cnt;
-    p.queue = kQueueNbrCount;
+    p.queues = d.queues + kQueues;
     p.wave_log = d.wave_log_nbr;
+    (void)c;
     return p;
 }
 
@@ -190,7 +206,7 @@ void launch_nbr_fill(Dev& d, const BuildCfg& c, int grid, int stack_cap, const i
     p.off = off;
     p.idx = idx;
     p.cap = cap;
-    p.queue = kQueueNbrFill;
+    p.queues = d.queues + 2 * kQueues;
     hipLaunchKernelGGL(k_nbr<true>, dim3(grid), dim3(64), 0, s, p);
 }
 

@@ -137,6 +137,8 @@ struct Dev {
     int64_t stack_len = 0;
     // counters
     unsigned long long* cnt = nullptr;
+    // group work queues: walk [0, 8), neighbour count [8, 16), neighbour fill [16, 24)
+    unsigned long long* queues = nullptr;
     // per persistent workgroup of the last walk / neighbour count: groups, clock ticks
     unsigned long long* wave_log = nullptr;
     unsigned long long* wave_log_nbr = nullptr;

@@ -23,6 +23,7 @@
 #include <type_traits>
 
 #include "pbh_internal.hpp"
+#include "wave.hpp"
 
 namespace pbh {
 
@@ -64,33 +65,9 @@ struct WalkParams {
     int32_t* stack;
     int stack_cap;
     unsigned long long* cnt;
+    unsigned long long* queues;     // [kQueues] group queue heads
     unsigned long long* wave_log;   // per workgroup: groups walked, clock ticks
 };
-
-__device__ inline int popc_below(uint64_t mask) {
-    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                          __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-}
-
-__device__ inline int wave_incl_scan(int v, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
-    return v;
-}
-
-// Wave-uniform helpers. A value that every lane holds equally is moved to a
-// scalar register, so loops and branches on it are wave-uniform in the
-// generated code. The work-queue fetch is issued by all lanes with lane 0
-// adding 1 and the rest 0, so no lane-0-only branch precedes the broadcast.
-__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ inline int wave_next(unsigned long long* ctr, int lane) {
-    const unsigned long long r = atomicAdd(ctr, lane == 0 ? 1ull : 0ull);
-    return uni((int)r);
-}
 
 __device__ inline void two_sum_acc(float& hi, float& lo, float v) {
     const float s = hi + v;
@@ -98,32 +75,6 @@ __device__ inline void two_sum_acc(float& hi, float& lo, float v) {
     const float e = (hi - (s - bp)) + (v - bp);
     hi = s;
     lo += e;
-}
-
-// squared distances used by the opening rules, in FP64 without contraction
-__device__ inline double box_box_d2(const double* glo, const double* ghi, const double* lo,
-                                    const double* hi) {
-#pragma clang fp contract(off)
-    double g[3];
-    for (int k = 0; k < 3; ++k) {
-        const double a = lo[k] - ghi[k];
-        const double b = glo[k] - hi[k];
-        const double v = a > b ? a : b;
-        g[k] = v > 0.0 ? v : 0.0;
-    }
-    return g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
-}
-
-__device__ inline double box_pt_d2(const double* glo, const double* ghi, const double* c) {
-#pragma clang fp contract(off)
-    double g[3];
-    for (int k = 0; k < 3; ++k) {
-        const double a = glo[k] - c[k];
-        const double b = c[k] - ghi[k];
-        const double v = a > b ? a : b;
-        g[k] = v > 0.0 ? v : 0.0;
-    }
-    return g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
 }
 
 template <typename R>
@@ -248,16 +199,18 @@ template <bool MIXED>
 __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
     using R = typename std::conditional<MIXED, float, double>::type;
     __shared__ Tiles<R> T;
+    __shared__ int s_stack[kStackLds];
     const int lane = threadIdx.x;
-    int32_t* stack = p.stack + (int64_t)blockIdx.x * p.stack_cap;
+    const Stack stack{s_stack, p.stack + (int64_t)blockIdx.x * (p.stack_cap - kStackLds), p.stack_cap};
+    int home = blockIdx.x % kQueues;
     const R eps2 = (R)p.eps2;
     const int64_t G = (int64_t)*p.G;
     const unsigned long long t_start = wall_clock64();
     int n_walked = 0;
 
     for (;;) {
-        const int g = wave_next(&p.cnt[kQueueWalk], lane);
-        if (g >= G) break;
+        const int64_t g = queue_next(p.queues, G, home, lane);
+        if (g < 0) break;
         ++n_walked;
 
         const int gb = uni(p.g_begin[g]), gcnt = uni(p.g_count[g]), root = uni(p.g_root[g]);
@@ -291,7 +244,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
 
         int npn = 0, nfar = 0, nnear = 0;
         unsigned long long c_pn = 0, c_far = 0, c_near = 0;
-        stack[0] = root;   // every lane stores the same value
+        stack.put(0, root);   // every lane stores the same value
         int top = 1;
         bool overflow = false;
 
@@ -300,7 +253,8 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
             const int npop = uni(top < 64 ? top : 64);
             top -= npop;
             const bool has = lane < npop;
-            const int nd = has ? stack[top + lane] : root;
+            const int nd = has ? stack.get(top + lane) : root;
+            __threadfence_block();
             const WNode w = p.node[nd];
             const double dbox2 = box_box_d2(glo, ghi, w.lo, w.hi);
             const bool near = (dbox2 < rout2) || (dbox2 == 0.0);
@@ -339,7 +293,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                 overflow = true;
                 break;
             }
-            for (int k = 0; k < nch; ++k) stack[top + incl - nch + k] = w.first_child + k;
+            for (int k = 0; k < nch; ++k) stack.put(top + incl - nch + k, w.first_child + k);
             top = uni(top + tot);
 
             // leaves: far ones (W = 1) and near ones (changeover)
@@ -419,12 +373,13 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
 // rcrit^2 = (l/theta + delta)^2 per node, l = largest box extent, delta =
 // |COM - box centre|; also clears the per-call counters and queues.
 __global__ void k_rcrit(WNode* __restrict__ node, const unsigned long long* __restrict__ n_dev,
-                        double theta, unsigned long long* __restrict__ cnt) {
+                        double theta, unsigned long long* __restrict__ cnt,
+                        unsigned long long* __restrict__ queues) {
 #pragma clang fp contract(off)
     const int64_t n = (int64_t)*n_dev;
+    if (blockIdx.x == 0 && threadIdx.x < 3 * kQueues) queues[threadIdx.x] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         cnt[kCntPN] = 0; cnt[kCntFar] = 0; cnt[kCntNear] = 0;
-        cnt[kQueueWalk] = 0; cnt[kQueueNbrCount] = 0; cnt[kQueueNbrFill] = 0;
     }
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n;
          b += (int64_t)gridDim.x * blockDim.x) {
@@ -446,7 +401,7 @@ void launch_rcrit(Dev& d, const BuildCfg& c, double theta, hipStream_t s) {
     int64_t nb = (c.node_cap + 255) / 256;
     if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL(k_rcrit, dim3(nb), dim3(256), 0, s, d.node,
-                       (const unsigned long long*)(d.cnt + kCntNodes), theta, d.cnt);
+                       (const unsigned long long*)(d.cnt + kCntNodes), theta, d.cnt, d.queues);
 }
 
 int walk_blocks_per_cu(int mixed) {
@@ -475,6 +430,7 @@ void launch_walk(Dev& d, const BuildCfg& c, const WalkCfg& w, double* acc, doubl
     p.stack = d.stack;
     p.stack_cap = w.stack_cap;
     p.cnt = d.cnt;
+    p.queues = d.queues;
     p.wave_log = d.wave_log;
     if (w.mixed) hipLaunchKernelGGL(k_walk<true>, dim3(w.grid), dim3(64), 0, s, p);
     else hipLaunchKernelGGL(k_walk<false>, dim3(w.grid), dim3(64), 0, s, p);

@@ -1,0 +1,93 @@
+// wave.hpp -- wavefront-level helpers shared by the walk and neighbour kernels.
+#pragma once
+
+#include "pbh_internal.hpp"
+
+namespace pbh {
+
+// A value every lane holds equally, moved to a scalar register so that loops
+// and branches on it are wave-uniform in the generated code.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ inline int popc_below(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+__device__ inline int wave_incl_scan(int v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Work queue of groups split into kQueues contiguous ranges, one per XCD:
+// workgroups are dispatched round-robin over the XCDs, so a workgroup takes
+// its XCD's range first (neighbouring groups share tree nodes in that XCD's
+// L2) and then helps the other ranges. All lanes issue the atomic (lane 0
+// adds 1, the others 0): no lane-0-only branch precedes the broadcast.
+constexpr int kQueues = 8;
+
+__device__ inline int64_t queue_next(unsigned long long* q /* [kQueues] */, int64_t G, int& home,
+                                     int lane) {
+    for (int k = 0; k < kQueues; ++k) {
+        const int qi = (home + k) % kQueues;
+        const int64_t lo = G * qi / kQueues, hi = G * (qi + 1) / kQueues;
+        if (k > 0 && (int64_t)__builtin_amdgcn_readfirstlane((int)(q[qi] < (unsigned long long)(hi - lo))) == 0)
+            continue;   // range already drained: skip the atomic
+        const unsigned long long r = atomicAdd(&q[qi], lane == 0 ? 1ull : 0ull);
+        const int64_t t = lo + (int64_t)uni((int)r);
+        if (t < hi) {
+            home = qi;
+            return t;
+        }
+    }
+    return -1;
+}
+
+// squared distance between two boxes (per-axis gap >= 0), FP64 without FMA
+__device__ inline double box_box_d2(const double* alo, const double* ahi, const double* blo,
+                                    const double* bhi) {
+#pragma clang fp contract(off)
+    double g[3];
+    for (int k = 0; k < 3; ++k) {
+        const double a = blo[k] - ahi[k];
+        const double b = alo[k] - bhi[k];
+        const double v = a > b ? a : b;
+        g[k] = v > 0.0 ? v : 0.0;
+    }
+    return g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+}
+
+// squared distance from point c to the box [lo, hi], FP64 without FMA
+__device__ inline double box_pt_d2(const double* lo, const double* hi, const double* c) {
+#pragma clang fp contract(off)
+    double g[3];
+    for (int k = 0; k < 3; ++k) {
+        const double a = lo[k] - c[k];
+        const double b = c[k] - hi[k];
+        const double v = a > b ? a : b;
+        g[k] = v > 0.0 ? v : 0.0;
+    }
+    return g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+}
+
+// Traversal stack: the first kStackLds entries live in LDS, deeper entries in
+// a per-wave spill region of global memory (rarely reached: the walk of a
+// 2^20-particle Plummer sphere needs < 900 entries).
+constexpr int kStackLds = 1024;
+
+struct Stack {
+    int* lds;        // [kStackLds]
+    int32_t* spill;  // [cap - kStackLds]
+    int cap;
+    __device__ int get(int i) const { return i < kStackLds ? lds[i] : spill[i - kStackLds]; }
+    __device__ void put(int i, int v) const {
+        if (i < kStackLds) lds[i] = v;
+        else spill[i - kStackLds] = v;
+    }
+};
+
+}  // namespace pbh
