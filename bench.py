@@ -1,21 +1,31 @@
 """Benchmark of the P3T distant-force path on one MI355X.
 
-One step = one pass of the whole path over a resident synthetic cluster:
+One step = one pass of the whole path over resident synthetic input:
 tree build (bounding box, Morton keys, radix sort, octree, FP64 moments,
-groups) + grouped mixed-precision walk (regular force and potential, written
-in caller order) + neighbour lists inside r_out (count, scan, fill).
+groups) + grouped walk (regular force and potential, written in caller order)
++ neighbour lists inside r_out (count, scan, fill).
 
-Default workload: Plummer sphere, N = 2^20, Kroupa masses, Henon units,
-eps = 1e-6, r_out for 64 mean neighbours (0.04077), r_in = 0.1 r_out,
-theta = 0.5, monopole + quadrupole nodes, FP32 interactions with FP64
-positions and sums.
+Workloads (--workload):
+  plummer1m    (default) Plummer sphere N = 2^20, Kroupa masses, Henon units,
+               eps = 1e-6, r_out for 64 mean neighbours (0.04077), r_in =
+               0.1 r_out, theta = 0.5, quadrupole nodes, FP32 interactions
+               with FP64 positions and sums, leaf/group sizes autotuned
+  plummer128k  N = 131072, eps = 1e-5 (run with --prec fp64 and mixed)
+  plummer4m    N = 2^22, eps = 1e-6
+  ensemble64   64 independent clusters, N log-uniform in [1e4, 2e5], each
+               with its own r_out for 64 neighbours; one batched build and one
+               persistent walk launch per step
+  kdk4m        N = 2^22: 32 kick-drift-kick steps of dt = 1/1024 with a full
+               rebuild each step, captured once in a hipGraph; reports the
+               relative energy drift (a step = one KDK step)
 
-Prints one JSON line. value = all interactions (particle-node + particle-
-particle) per second of whole step time. The roofline object covers the walk
-kernel, timed with HIP events on its own stream inside the timed region. The
-cpu_baseline leg times the CPU oracle (tree walk with the same tree, groups
-and opening rule, OpenMP over the host cores) on the full workload and
-compares the GPU result with FP64 direct sums on a sample of particles.
+Prints one JSON line. For the force workloads value = all interactions
+(particle-node + particle-particle) per second of whole step time. The
+roofline object covers the walk kernel, timed with HIP events on its stream
+inside the timed region. The cpu_baseline leg times the CPU oracle (tree walk
+with the same tree, groups and opening rule, OpenMP over the host cores) on
+the same workload and compares the GPU result with FP64 direct sums on a
+sample of particles.
 """
 from __future__ import annotations
 
@@ -31,19 +41,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic FP32 operations per interaction (add, sub, mul = 1, rsqrt = 1,
-# log = 1), counted from the formulas the walk evaluates:
+# Algorithmic operations per interaction (add, sub, mul = 1, FMA = 2,
+# rsqrt = 1, log = 1), counted from the formulas the walk evaluates:
 #   particle-node, monopole + traceless quadrupole: 55
 #   particle-particle outside r_out (W = 1): 20
 #   particle-particle in a near leaf (W(s) and the regular potential): 50
 FLOPS_PN, FLOPS_FAR, FLOPS_NEAR = 55, 20, 50
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (256 CU x 256 flop/clk x 2.4 GHz)
+PEAK_FP64_TFLOPS = 78.6
 
 WORKLOADS = {
-    "plummer1m": ("plummer1m_kroupa", 0.5),
-    "plummer128k": ("plummer128k_kroupa", 0.5),
-    "plummer4m": ("plummer4m_kroupa", 0.5),
+    "plummer1m": "plummer1m_kroupa",
+    "plummer128k": "plummer128k_kroupa",
+    "plummer4m": "plummer4m_kroupa",
+    "ensemble64": None,
+    "kdk4m": "plummer4m_kroupa",
 }
+METRIC = "particle-node interactions/s and force evals/s at N=1e6 vs FP32 VALU roofline"
 
 
 def walk_traffic(kernel: str):
@@ -70,10 +84,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plummer1m", choices=sorted(WORKLOADS))
-    ap.add_argument("--theta", type=float, default=None)
+    ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--leaf", type=int, default=16)
-    ap.add_argument("--ncrit", type=int, default=64)
+    ap.add_argument("--leaf", type=int, default=0, help="n_leaf (0 = autotune)")
+    ap.add_argument("--ncrit", type=int, default=0, help="n_crit (0 = autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-neighbours", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -82,51 +96,106 @@ def parse():
     return ap.parse_args()
 
 
+def q(e):
+    return {"median": float(np.median(e)), "p90": float(np.percentile(e, 90)),
+            "p99": float(np.percentile(e, 99)), "max": float(np.max(e))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the distant-force "
               "path is measured on a single MI355X.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "kdk4m":
+        return bench_kdk(args)
+    return bench_force(args)
 
+
+def _setup(args, torch):
+    from paper_2110_11658_amd import ic
+    dev = torch.device("cuda", 0)
+    if args.workload == "ensemble64":
+        e = ic.ensemble(n_clusters=64)
+        inp = {"pos": e.pos, "mass": e.mass, "offsets": e.offsets, "r_in": e.r_in, "r_out": e.r_out,
+               "eps": 1e-6, "name": "ensemble64_kroupa",
+               "desc": f"64 Plummer clusters, N log-uniform [1e4, 2e5] (total {e.offsets[-1]}), "
+                       f"Kroupa, eps=1e-6, per-cluster r_out for 64 neighbours, r_in=0.1 r_out"}
+    else:
+        wname = WORKLOADS[args.workload]
+        cl, w = ic.workload(wname)
+        inp = {"pos": cl.pos, "mass": cl.mass, "vel": cl.vel, "offsets": None, "r_in": w["r_in"],
+               "r_out": w["r_out"], "eps": w["eps"], "name": wname,
+               "desc": f"Plummer N={cl.n} Kroupa eps={w['eps']} r_out={w['r_out']:.5f} "
+                       f"r_in={w['r_in']:.6f}"}
+    inp["n"] = inp["mass"].size
+    inp["pos_d"] = torch.from_numpy(inp["pos"]).to(dev)
+    inp["mass_d"] = torch.from_numpy(inp["mass"]).to(dev)
+    return inp, dev
+
+
+def bench_force(args):
     import ctypes as C
 
     import torch
 
-    from paper_2110_11658_amd import ic
+    from paper_2110_11658_amd import autotune
     from paper_2110_11658_amd._lib import check
     from paper_2110_11658_amd.api import Pbh, _ptr, _stream
 
-    wname, theta = WORKLOADS[args.workload]
-    if args.theta is not None:
-        theta = args.theta
-    cl, w = ic.workload(wname)
-    n = cl.n
-    dev = torch.device("cuda", 0)
-    pos = torch.from_numpy(cl.pos).to(dev)
-    mass = torch.from_numpy(cl.mass).to(dev)
+    inp, dev = _setup(args, torch)
+    n, theta, eps = inp["n"], args.theta, inp["eps"]
+    pos, mass = inp["pos_d"], inp["mass_d"]
+    batched = inp["offsets"] is not None
+    neighbours = not args.no_neighbours
+    p = Pbh(0, prec=args.prec)
+    L, ctx = p.L, p.ctx
+
+    tuned = None
+    if args.leaf and args.ncrit:
+        p.set_params(leaf_size=args.leaf, n_crit=args.ncrit, prec=args.prec)
+    else:
+        tuned = autotune.tune(p, pos, mass, inp["r_in"], inp["r_out"], theta, eps, prec=args.prec,
+                              neighbours=neighbours, offsets=inp["offsets"])
+    prm = p.params()
+
     acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
     pot = torch.empty(n, dtype=torch.float64, device=dev)
     off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    if batched:
+        offs = np.ascontiguousarray(inp["offsets"], dtype=np.int64)
+        ri = np.ascontiguousarray(inp["r_in"], dtype=np.float64)
+        ro = np.ascontiguousarray(inp["r_out"], dtype=np.float64)
+        nc = offs.size - 1
 
-    p = Pbh(0, leaf_size=args.leaf, n_crit=args.ncrit, prec=args.prec)
-    L, ctx = p.L, p.ctx
-    neighbours = not args.no_neighbours
+        def build():
+            check(ctx, L.pbh_build_batched(ctx, nc, offs.ctypes.data_as(C.c_void_p), _ptr(pos),
+                                           _ptr(mass), _stream()))
+
+        def force(o, ix, cap, tot):
+            return L.pbh_force_batched(ctx, ri.ctypes.data_as(C.c_void_p),
+                                       ro.ctypes.data_as(C.c_void_p), theta, eps, _ptr(acc),
+                                       _ptr(pot), o, ix, cap, tot, _stream())
+    else:
+        def build():
+            check(ctx, L.pbh_build(ctx, n, _ptr(pos), _ptr(mass), _stream()))
+
+        def force(o, ix, cap, tot):
+            return L.pbh_force(ctx, inp["r_in"], inp["r_out"], theta, eps, _ptr(acc), _ptr(pot),
+                               o, ix, cap, tot, _stream())
 
     # size the neighbour buffer once (outside the timed region)
-    p.build(pos, mass)
+    build()
     total = C.c_int64(0)
     idx = torch.empty(1, dtype=torch.int32, device=dev)
-    st = L.pbh_force(ctx, w["r_in"], w["r_out"], theta, w["eps"], _ptr(acc), _ptr(pot), _ptr(off),
-                     _ptr(idx), 0, C.byref(total), _stream())
+    force(_ptr(off), _ptr(idx), 0, C.byref(total))
     cap = int(total.value * 1.05) + 1024
     idx = torch.empty(cap, dtype=torch.int32, device=dev)
 
     def step():
-        check(ctx, L.pbh_build(ctx, n, _ptr(pos), _ptr(mass), _stream()))
-        check(ctx, L.pbh_force(ctx, w["r_in"], w["r_out"], theta, w["eps"], _ptr(acc), _ptr(pot),
-                               _ptr(off) if neighbours else None, _ptr(idx) if neighbours else None,
-                               cap if neighbours else 0, None, _stream()))
+        build()
+        check(ctx, force(_ptr(off) if neighbours else None, _ptr(idx) if neighbours else None,
+                         cap if neighbours else 0, None))
 
     if args.calib_copy_mib:
         src = torch.empty(args.calib_copy_mib << 17, dtype=torch.float64, device=dev).fill_(1.0)
@@ -162,9 +231,11 @@ def main():
     walk_avg = float(np.mean(walk_ms))
     achieved = flops / (walk_avg * 1e-3) / 1e12
     per_step_inter = s["n_pn"] + s["n_pp_far"] + s["n_pp_near"]
+    peak = PEAK_FP32_TFLOPS if args.prec == "mixed" else PEAK_FP64_TFLOPS
+    kernel = "k_walk<true>" if args.prec == "mixed" else "k_walk<false>"
 
     rec = {
-        "metric": "particle-node interactions/s and force evals/s at N=1e6 vs FP32 VALU roofline",
+        "metric": METRIC,
         "value": inter / (t1 - t0),
         "unit": "interactions/s",
         "n_gpus": 1,
@@ -176,55 +247,120 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.prec == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{wname}: Plummer N={n} Kroupa eps={w['eps']} r_out={w['r_out']:.5f} "
-                               f"r_in={w['r_in']:.6f} theta={theta} quadrupole",
-                   "n": n, "theta": theta, "precision": args.prec, "leaf_size": args.leaf,
-                   "n_crit": args.ncrit, "neighbours": neighbours},
+        "config": {"workload": f"{inp['name']}: {inp['desc']} theta={theta} quadrupole",
+                   "n": n, "theta": theta, "precision": args.prec, "leaf_size": prm["leaf_size"],
+                   "n_crit": prm["n_crit"], "neighbours": neighbours,
+                   "autotuned": tuned is not None, "clusters": 64 if batched else 1},
         "force_evals_per_s": n / (ms_step * 1e-3),
         "force_evals_per_s_walk_only": n / (walk_avg * 1e-3),
         "interactions_per_s_walk_only": per_step_inter / (walk_avg * 1e-3),
         "phase_ms": {"build": float(np.mean(build_ms)), "walk": walk_avg,
                      "neighbours": float(np.mean(nbr_ms))},
         "interactions_per_step": {"pn": s["n_pn"], "pp_far": s["n_pp_far"], "pp_near": s["n_pp_near"]},
+        "groups": s["n_groups"],
         "nbr_total": int(off[-1].item()) if neighbours else None,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": (walk_traffic("k_walk<true>") if args.prec == "mixed"
-                                 and wname == "plummer1m_kroupa" else None),
-                     "kernel": "k_walk<mixed>" if args.prec == "mixed" else "k_walk<fp64>",
-                     "flops_per_launch": flops},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": (walk_traffic(kernel) if inp["name"] == "plummer1m_kroupa" else None),
+                     "kernel": kernel, "flops_per_launch": flops},
     }
+    if tuned is not None:
+        rec["autotune"] = {k: v for k, v in tuned.items() if k != "cached"}
+        rec["autotune"]["cached"] = tuned["cached"]
 
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"], rec["accuracy"] = cpu_baseline(cl, w, theta, args, acc, pot)
+        rec["cpu_baseline"], rec["accuracy"] = cpu_baseline(inp, theta, prm, acc, pot)
     p.close()
     print(json.dumps(rec))
 
 
-def cpu_baseline(cl, w, theta, args, acc, pot):
-    """CPU oracle on the same workload: tree walk over all particles (timed), plus
-    FP64 direct sums on 512 sampled particles for the GPU result's error."""
+def cpu_baseline(inp, theta, prm, acc, pot):
+    """CPU oracle on the same workload: tree walk over all particles (timed; for
+    the ensemble each cluster in turn), plus FP64 direct sums on 512 sampled
+    particles for the GPU result's error."""
     import oracle
     acc_h = acc.cpu().numpy()
     pot_h = pot.cpu().numpy()
+    pos, mass = inp["pos"], inp["mass"]
+    offsets = inp["offsets"] if inp["offsets"] is not None else np.array([0, inp["n"]])
+    nc = offsets.size - 1
+    r_in = np.broadcast_to(np.asarray(inp["r_in"], dtype=float), (nc,))
+    r_out = np.broadcast_to(np.asarray(inp["r_out"], dtype=float), (nc,))
     t = time.perf_counter()
-    _, _, st = oracle.tree(cl.pos, cl.mass, w["r_in"], w["r_out"], theta, w["eps"],
-                           n_leaf=args.leaf, n_crit=args.ncrit)
+    inter = 0
+    for k in range(nc):
+        s = slice(offsets[k], offsets[k + 1])
+        _, _, st = oracle.tree(pos[s], mass[s], r_in[k], r_out[k], theta, inp["eps"],
+                               n_leaf=prm["leaf_size"], n_crit=prm["n_crit"])
+        inter += st["pn"] + st["pp_far"] + st["pp_near"]
     dt = time.perf_counter() - t
-    inter = st["pn"] + st["pp_far"] + st["pp_near"]
     base = {"value": inter / dt, "unit": "interactions/s", "cores": oracle.num_threads(),
             "kind": "oracle", "seconds": dt,
-            "sample": f"full workload ({cl.n} particles) through the CPU FP64 tree walk "
-                      f"(tree build + walk), {oracle.num_threads()} OpenMP threads"}
-    tg = np.random.default_rng(12345).choice(cl.n, 512, replace=False)
-    ra, rp = oracle.direct(cl.pos, cl.mass, w["r_in"], w["r_out"], w["eps"], targets=tg)
-    ea = np.linalg.norm(acc_h[tg] - ra, axis=1) / np.linalg.norm(ra, axis=1)
-    ep = np.abs(pot_h[tg] - rp) / np.abs(rp)
-    q = lambda e: {"median": float(np.median(e)), "p90": float(np.percentile(e, 90)),
-                   "p99": float(np.percentile(e, 99)), "max": float(e.max())}
-    accuracy = {"vs": "FP64 direct summation on 512 sampled particles",
-                "force_rel": q(ea), "pot_rel": q(ep)}
+            "sample": f"full workload ({inp['n']} particles, {nc} cluster(s)) through the CPU FP64 "
+                      f"tree walk (tree build + walk), {oracle.num_threads()} OpenMP threads"}
+    rng = np.random.default_rng(12345)
+    ea, ep = [], []
+    per = max(1, 512 // nc)
+    for k in range(nc):
+        s = slice(offsets[k], offsets[k + 1])
+        nk = offsets[k + 1] - offsets[k]
+        tg = rng.choice(nk, min(per, nk), replace=False)
+        ra, rp = oracle.direct(pos[s], mass[s], r_in[k], r_out[k], inp["eps"], targets=tg)
+        ga = acc_h[s][tg]
+        gp = pot_h[s][tg]
+        ea.append(np.linalg.norm(ga - ra, axis=1) / np.linalg.norm(ra, axis=1))
+        ep.append(np.abs(gp - rp) / np.abs(rp))
+    accuracy = {"vs": f"FP64 direct summation on {sum(len(e) for e in ea)} sampled particles",
+                "force_rel": q(np.concatenate(ea)), "pot_rel": q(np.concatenate(ep))}
     return base, accuracy
+
+
+def bench_kdk(args):
+    import torch
+
+    from paper_2110_11658_amd.api import Pbh
+
+    inp, dev = _setup(args, torch)
+    n = inp["n"]
+    dt, steps = 1.0 / 1024.0, 32
+    leaf = args.leaf or 16
+    ncrit = args.ncrit or 64
+    out = {}
+    for prec in ("mixed", "fp64") if args.prec == "mixed" else ("fp64",):
+        p = Pbh(0, leaf_size=leaf, n_crit=ncrit, prec=prec)
+        pos = inp["pos_d"].clone()
+        vel = torch.from_numpy(inp["vel"]).to(dev)
+        # warm-up on copies: sizes the buffers and captures the one-step graph
+        p.kdk(pos.clone(), vel.clone(), inp["mass_d"], dt, 1, inp["r_in"], inp["r_out"], args.theta,
+              inp["eps"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e = p.kdk(pos, vel, inp["mass_d"], dt, steps, inp["r_in"], inp["r_out"], args.theta, inp["eps"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e = e.cpu().numpy()
+        out[prec] = {"seconds": t1 - t0, "energy": e,
+                     "drift": float(np.max(np.abs(e - e[0]) / abs(e[0])))}
+        p.close()
+    main_prec = args.prec
+    secs = out[main_prec]["seconds"]
+    rec = {
+        "metric": "KDK leapfrog steps with full tree rebuild (hipGraph) at N=2^22",
+        "value": n * steps / secs,
+        "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": 1e3 * secs / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if main_prec == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": f"{inp['name']}: {inp['desc']} theta={args.theta} dt=1/1024 32 KDK steps",
+                   "n": n, "leaf_size": leaf, "n_crit": ncrit},
+        "energy_drift": {k: v["drift"] for k, v in out.items()},
+        "energy_first_last": {k: [float(v["energy"][0]), float(v["energy"][-1])] for k, v in out.items()},
+        "ms_per_step_by_precision": {k: 1e3 * v["seconds"] / steps for k, v in out.items()},
+    }
+    if "fp64" in out and "mixed" in out:
+        rec["energy_diff_mixed_vs_fp64"] = float(np.max(np.abs(out["mixed"]["energy"] - out["fp64"]["energy"])
+                                                         / abs(out["fp64"]["energy"][0])))
+    print(json.dumps(rec))
 
 
 if __name__ == "__main__":

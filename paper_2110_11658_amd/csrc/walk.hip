@@ -16,9 +16,10 @@
 //   open   otherwise: a leaf becomes particle-particle work, an inner node
 //          pushes its children.
 // Accepted nodes and leaf particles are compacted with ballot + prefix sums
-// into LDS tiles (FP32 in the mixed path: positions relative to the group
-// centre, formed in FP64 first) and evaluated 64+ entries at a time with
-// every lane reading each entry by LDS broadcast. Tile partial sums are
+// into LDS tiles of up to 64 entries (FP32 in the mixed path: positions
+// relative to the group centre, formed in FP64 first); a tile is evaluated
+// just before it would overflow, every lane reading each entry by LDS
+// broadcast. Tile partial sums are
 // folded into FP32 (hi, lo) pairs with TwoSum and returned in FP64.
 #include <type_traits>
 
@@ -29,7 +30,7 @@ namespace pbh {
 
 namespace {
 
-constexpr int TCAP = 128;   // tile capacity: < 64 left over + 64 new entries
+constexpr int TCAP = 64;    // tile capacity; a tile is evaluated before it would overflow
 
 template <typename R>
 struct alignas(16) Tiles {
@@ -265,6 +266,13 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
             // multipole entries
             const uint64_t mk = __ballot(accept);
             if (mk) {
+                const int k = uni(__popcll(mk));
+                if (npn + k > TCAP) {
+                    __syncthreads();
+                    eval_pn<R>(T, npn, px, py, pz, eps2, A);
+                    npn = 0;
+                    __syncthreads();
+                }
                 if (accept) {
                     R* e = T.pn[npn + popc_below(mk)];
                     e[0] = (R)(w.com[0] - ctr[0]);
@@ -280,7 +288,6 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                         e[7] = q.qxy; e[8] = q.qxz; e[9] = q.qyz;
                     }
                 }
-                const int k = uni(__popcll(mk));
                 npn = uni(npn + k);
                 c_pn += k;
             }
@@ -317,6 +324,14 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                         if (T.lf_ex[k + st] <= s) k += st;
                     const int j = T.lf_beg[k] + (s - T.lf_ex[k]);
                     int& fill = cls == 0 ? nfar : nnear;
+                    const int add = (total - base) < 64 ? (total - base) : 64;
+                    if (fill + add > TCAP) {
+                        __syncthreads();
+                        if (cls == 0) eval_far<R>(T, fill, px, py, pz, eps2, A);
+                        else eval_near<R>(T, fill, px, py, pz, eps2, me, K, A);
+                        fill = 0;
+                        __syncthreads();
+                    }
                     if (s < total) {
                         R* e = cls == 0 ? T.far[fill + lane] : T.nearp[fill + lane];
                         e[0] = (R)(p.x[j] - ctr[0]);
@@ -325,22 +340,8 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                         e[3] = (R)p.m[j];
                         if (cls == 1) T.nearj[fill + lane] = j;
                     }
-                    fill = uni(fill + ((total - base) < 64 ? (total - base) : 64));
-                    if (fill >= 64) {
-                        __syncthreads();
-                        if (cls == 0) eval_far<R>(T, fill, px, py, pz, eps2, A);
-                        else eval_near<R>(T, fill, px, py, pz, eps2, me, K, A);
-                        fill = 0;
-                        __syncthreads();
-                    }
+                    fill = uni(fill + add);
                 }
-                __syncthreads();
-            }
-
-            if (npn >= 64) {
-                __syncthreads();
-                eval_pn<R>(T, npn, px, py, pz, eps2, A);
-                npn = 0;
                 __syncthreads();
             }
         }

@@ -335,3 +335,24 @@ def test_kdk_graph_equals_eager_and_oracle():
     gx, gv, ge = res["graph"]
     assert np.max(np.abs(gx - x)) < 1e-9
     assert np.allclose(ge, energies, rtol=1e-9)
+
+
+# ---------------------------------------------------------------- autotuner
+def test_autotune_choices_valid_and_cached(tmp_path, monkeypatch):
+    from paper_2110_11658_amd import autotune
+    monkeypatch.setenv("PBH_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    c = ic.plummer(20000, seed=21, masses="kroupa")
+    p = _pbh()
+    cands = ((8, 32), (16, 64))
+    r = autotune.tune(p, _t(c.pos), _t(c.mass), 0.01, 0.1, 0.5, 1e-5, candidates=cands, reps=1)
+    assert (r["leaf_size"], r["n_crit"]) in cands and not r["cached"]
+    assert len(r["table"]) == 2 and all(t["ms"] > 0 for t in r["table"])
+    assert (p.params()["leaf_size"], p.params()["n_crit"]) == (r["leaf_size"], r["n_crit"])
+    r2 = autotune.tune(p, _t(c.pos), _t(c.mass), 0.01, 0.1, 0.5, 1e-5, candidates=cands, reps=1)
+    assert r2["cached"] and (r2["leaf_size"], r2["n_crit"]) == (r["leaf_size"], r["n_crit"])
+    # every candidate gives the same neighbour sets
+    o_off, o_idx = oracle.nbr_cells(c.pos, 0.1)
+    for leaf, ncrit in cands:
+        p.set_params(leaf_size=leaf, n_crit=ncrit)
+        acc, pot, off, idx = _run(p, c, 0.01, 0.1, 0.5, 1e-5)
+        _sets_equal(off, idx, o_off, o_idx)
