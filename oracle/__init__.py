@@ -60,6 +60,8 @@ def lib():
         L.orc_tree_nodes.argtypes = [_i64, _p, _p, C.c_int, C.c_int, _i64, _p, _p, _p]
         L.orc_groups.restype = _i64
         L.orc_groups.argtypes = [_i64, _p, _p, C.c_int, C.c_int, C.c_int, _i64, _p, _p]
+        L.orc_group_limit.restype = _d
+        L.orc_group_limit.argtypes = [_i64, _p, _p, C.c_int, C.c_int, C.c_int]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -194,6 +196,14 @@ def groups(pos, mass, n_leaf=16, n_crit=64, D=21):
     c = np.zeros(ng, dtype=np.int64)
     lib().orc_groups(n, _ptr(pos), _ptr(mass), int(n_leaf), int(n_crit), int(D), ng, _ptr(b), _ptr(c))
     return b, c
+
+
+def group_limit(pos, mass, n_leaf=16, n_crit=64, D=21) -> float:
+    """Size limit (largest box side) of the walk groups of one cluster."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    mass = _f64(mass, (n,))
+    return float(lib().orc_group_limit(n, _ptr(pos), _ptr(mass), int(n_leaf), int(n_crit), int(D)))
 
 
 def num_threads() -> int:

@@ -378,13 +378,19 @@ int64_t orc_nbr_cells(int64_t n, const double* pos, double r_out,
 /*         children, in order: M = sum m; COM = sum m x / M;                */
 /*         Q_ab = sum [Q_c,ab + m (3 d_a d_b - |d|^2 delta_ab)], d = x-COM; */
 /*         tight box lo/hi; l = max extent; delta = |COM - box centre|.     */
-/*  groups every node holding more than n_crit particles splits into      */
-/*         groups: a leaf (only at level D) into runs of n_crit particles;  */
-/*         an inner node packs its consecutive children that hold at most  */
-/*         n_crit particles, greedily and in order, into groups of at most  */
-/*         n_crit particles (a child with more than n_crit interrupts the   */
-/*         run). A root with at most n_crit particles is one group. Groups  */
-/*         are ordered by their first particle; each has a tight box.       */
+/*  groups a node is "big" if it holds more than n_crit particles or its  */
+/*         tight box is larger (largest side) than the size limit S. Every  */
+/*         big node splits into groups: a big leaf into runs of n_crit      */
+/*         particles, or into single particles if its box exceeds S; an     */
+/*         inner node packs its consecutive children that are not big,      */
+/*         greedily and in order, into groups of at most n_crit particles   */
+/*         whose joint box stays within S (a big child interrupts the run). */
+/*         A root that is not big is one group. S is 2^7 x 2^e for the     */
+/*         octave e (2^e <= x < 2^(e+1)) holding the median box size of the */
+/*         groups this rule forms with S = infinity, per cluster; it keeps  */
+/*         a sparse-halo group from spanning the dense core. Groups are     */
+/*         ordered by their                                                 */
+/*         first particle; each has a tight box.                            */
 /*  walk   per group and node: dbox2 = squared distance between the group   */
 /*         box and the node box; near if dbox2 < r_out^2 or dbox2 == 0;     */
 /*         accept (multipole) if not near, theta > 0 and the squared        */
@@ -618,37 +624,126 @@ static int group_cmp(const void* a, const void* b)
     return (x > y) - (x < y);
 }
 
-/* Walk groups of the tree (rule in the comment above); returns the count. */
-static int64_t make_groups(const otree_t* t, int n_crit, ogroup_t** out)
+#ifndef GROUP_S_LOG2
+#define GROUP_S_LOG2 7
+#endif
+
+/* largest side of a box */
+static double box_extent(const double* lo, const double* hi)
 {
-    ogroup_t* g = (ogroup_t*)malloc(sizeof(ogroup_t) * (size_t)(t->n + 1));
+    double e = 0.0;
+    for (int d = 0; d < 3; ++d)
+        if (hi[d] - lo[d] > e) e = hi[d] - lo[d];
+    return e;
+}
+
+/* octave of a length: index e + 64 for 2^e <= x < 2^(e+1), e clamped to
+   [-64, 63]; index 0 for x = 0 */
+static int octave_index(double x)
+{
+    if (!(x > 0.0)) return 0;
+    int e;
+    frexp(x, &e);   /* x = m 2^e, 1/2 <= m < 1 */
+    e -= 1;
+    if (e < -64) e = -64;
+    if (e > 63) e = 63;
+    return e + 64;
+}
+
+static void emit_group(ogroup_t* g, int64_t* ng, int64_t begin, int64_t count, double ext,
+                       double* ext_out)
+{
+    g[*ng].begin = begin;
+    g[*ng].count = count;
+    if (ext_out) ext_out[*ng] = ext;
+    ++*ng;
+}
+
+/* One pass of the grouping rule with size limit S (see the tree comment). */
+static int64_t group_pass(const otree_t* t, int n_crit, double S, ogroup_t* g, double* ext_out)
+{
     int64_t ng = 0;
     for (int64_t k = 0; k < t->n_nodes; ++k) {
         const onode_t* nd = &t->nodes[k];
-        if (nd->level == 0 && nd->count <= n_crit) {
-            g[ng].begin = nd->begin; g[ng].count = nd->count; ++ng;
-        }
-        if (nd->count <= n_crit) continue;
+        double ext = box_extent(nd->lo, nd->hi);
+        int big = nd->count > n_crit || ext > S;
+        if (nd->level == 0 && !big) emit_group(g, &ng, nd->begin, nd->count, ext, ext_out);
+        if (!big) continue;
         if (nd->nchild == 0) {
-            for (int64_t s = nd->begin; s < nd->begin + nd->count; s += n_crit) {
-                int64_t e = s + n_crit < nd->begin + nd->count ? s + n_crit : nd->begin + nd->count;
-                g[ng].begin = s; g[ng].count = e - s; ++ng;
+            if (ext > S) {
+                for (int64_t j = nd->begin; j < nd->begin + nd->count; ++j)
+                    emit_group(g, &ng, j, 1, 0.0, ext_out);
+            } else {
+                for (int64_t s0 = nd->begin; s0 < nd->begin + nd->count; s0 += n_crit) {
+                    int64_t e0 = s0 + n_crit < nd->begin + nd->count ? s0 + n_crit : nd->begin + nd->count;
+                    double lo[3], hi[3];
+                    for (int64_t j = s0; j < e0; ++j) {
+                        double v[3] = {t->x[j], t->y[j], t->z[j]};
+                        for (int d = 0; d < 3; ++d) {
+                            if (j == s0 || v[d] < lo[d]) lo[d] = v[d];
+                            if (j == s0 || v[d] > hi[d]) hi[d] = v[d];
+                        }
+                    }
+                    emit_group(g, &ng, s0, e0 - s0, box_extent(lo, hi), ext_out);
+                }
             }
             continue;
         }
         int64_t run_begin = 0, run_count = 0;
+        double rlo[3] = {0, 0, 0}, rhi[3] = {0, 0, 0};
         for (int32_t c = 0; c < nd->nchild; ++c) {
             const onode_t* ch = &t->nodes[nd->first_child + c];
-            if (ch->count > n_crit || run_count + ch->count > n_crit) {
-                if (run_count > 0) { g[ng].begin = run_begin; g[ng].count = run_count; ++ng; }
+            int cbig = ch->count > n_crit || box_extent(ch->lo, ch->hi) > S;
+            if (cbig) {
+                if (run_count > 0) emit_group(g, &ng, run_begin, run_count, box_extent(rlo, rhi), ext_out);
                 run_count = 0;
+                continue;
             }
-            if (ch->count > n_crit) continue;
+            double ulo[3], uhi[3];
+            for (int d = 0; d < 3; ++d) {
+                ulo[d] = (run_count > 0 && rlo[d] < ch->lo[d]) ? rlo[d] : ch->lo[d];
+                uhi[d] = (run_count > 0 && rhi[d] > ch->hi[d]) ? rhi[d] : ch->hi[d];
+            }
+            if (run_count > 0 && (run_count + ch->count > n_crit || box_extent(ulo, uhi) > S)) {
+                emit_group(g, &ng, run_begin, run_count, box_extent(rlo, rhi), ext_out);
+                run_count = 0;
+                for (int d = 0; d < 3; ++d) { ulo[d] = ch->lo[d]; uhi[d] = ch->hi[d]; }
+            }
             if (run_count == 0) run_begin = ch->begin;
             run_count += ch->count;
+            for (int d = 0; d < 3; ++d) { rlo[d] = ulo[d]; rhi[d] = uhi[d]; }
         }
-        if (run_count > 0) { g[ng].begin = run_begin; g[ng].count = run_count; ++ng; }
+        if (run_count > 0) emit_group(g, &ng, run_begin, run_count, box_extent(rlo, rhi), ext_out);
     }
+    return ng;
+}
+
+/* Size limit of the walk groups of one cluster: 2^7 x 2^e for the octave e
+   holding the median extent of the groups the count rule alone would form. */
+static double group_size_limit(const otree_t* t, int n_crit)
+{
+    ogroup_t* g = (ogroup_t*)malloc(sizeof(ogroup_t) * (size_t)(t->n + 1));
+    double* ext = (double*)malloc(sizeof(double) * (size_t)(t->n + 1));
+    int64_t ng = group_pass(t, n_crit, INFINITY, g, ext);
+    int64_t hist[128] = {0};
+    for (int64_t k = 0; k < ng; ++k) hist[octave_index(ext[k])]++;
+    int64_t need = (ng + 1) / 2, cum = 0;
+    int b = 127;
+    for (int i = 0; i < 128; ++i) {
+        cum += hist[i];
+        if (cum >= need) { b = i; break; }
+    }
+    free(g);
+    free(ext);
+    return ldexp(1.0, b - 64 + GROUP_S_LOG2);
+}
+
+/* Walk groups of the tree (rule in the comment above); returns the count. */
+static int64_t make_groups(const otree_t* t, int n_crit, ogroup_t** out)
+{
+    double S = group_size_limit(t, n_crit);
+    ogroup_t* g = (ogroup_t*)malloc(sizeof(ogroup_t) * (size_t)(t->n + 1));
+    int64_t ng = group_pass(t, n_crit, S, g, NULL);
     qsort(g, (size_t)ng, sizeof(ogroup_t), group_cmp);
     *out = g;
     return ng;
@@ -808,6 +903,16 @@ void orc_tree(int64_t n, const double* pos, const double* mass,
     }
     free(groups);
     tree_free(&t);
+}
+
+/* Size limit S of the walk groups of one cluster. */
+double orc_group_limit(int64_t n, const double* pos, const double* mass, int n_leaf, int n_crit, int D)
+{
+    otree_t t;
+    tree_build(&t, n, pos, mass, n_leaf, D);
+    double S = group_size_limit(&t, n_crit);
+    tree_free(&t);
+    return S;
 }
 
 /* Walk groups of one cluster: writes up to cap (begin, count) pairs, returns the count. */

@@ -12,7 +12,7 @@
 //            breadth-first order in which every node's children are contiguous
 //   moments  bottom-up, one launch per level: M, centre of mass, traceless
 //            quadrupole about it (parallel-axis sums over children), tight box
-//   groups   tree-bounded runs of <= n_crit sorted particles (rule at k_group_mark)
+//   groups   tree-bounded runs of <= n_crit sorted particles (rule at k_group_pass)
 //
 // FP64 arithmetic that decides the tree (keys, moments) is evaluated without
 // fused multiply-add so it rounds exactly as written.
@@ -416,51 +416,138 @@ __global__ void k_moments_level(const int32_t* __restrict__ lvl_off, int level,
 }
 
 // ------------------------------------------------------------------ groups
-// Every node with more than n_crit particles splits into walk groups: a leaf
-// (only at level D) into runs of n_crit particles; an inner node packs its
-// consecutive children of at most n_crit particles, greedily in order, into
-// groups of at most n_crit (a larger child interrupts the run). A root with
-// at most n_crit particles is one group. The first particle of each group is
-// flagged; a scan of the flags numbers the groups in particle order.
-__global__ void k_group_mark(const WNode* __restrict__ node, const uint64_t* __restrict__ lvl,
-                             const unsigned long long* __restrict__ n_dev, int n_crit,
-                             int32_t* __restrict__ flag, int32_t* __restrict__ len) {
+// A node is "big" if it holds more than n_crit particles or its tight box is
+// larger (largest side) than the cluster's size limit S. Every big node splits
+// into walk groups: a big leaf into runs of n_crit particles, or into single
+// particles if its box exceeds S; an inner node packs its consecutive
+// children that are not big, greedily in order, into groups of at most
+// n_crit particles whose joint box stays within S (a big child interrupts the
+// run). A root that is not big is one group. S = 2^7 x 2^e for the octave e
+// (2^e <= x < 2^(e+1)) holding the median box size of the groups formed with
+// S = infinity (first pass, histogram only). The first particle of each group
+// is flagged; a scan of the flags numbers the groups in particle order.
+constexpr int kOctaves = 128;
+constexpr int kGroupLimitLog2 = 7;
+
+__device__ inline double box_extent(const double* lo, const double* hi) {
+    double e = 0.0;
+    for (int k = 0; k < 3; ++k)
+        if (hi[k] - lo[k] > e) e = hi[k] - lo[k];
+    return e;
+}
+
+__device__ inline int octave_index(double x) {
+    if (!(x > 0.0)) return 0;
+    int e = ilogb(x);   // 2^e <= x < 2^(e+1)
+    e = e < -64 ? -64 : (e > 63 ? 63 : e);
+    return e + 64;
+}
+
+// emit one group: first pass -> octave histogram of its box size; second
+// pass -> flag its first particle and store its length
+template <bool HIST>
+__device__ inline void emit_group(int begin, int count, double ext, unsigned* hist, int32_t* flag,
+                                  int32_t* len) {
+    if (HIST) {
+        atomicAdd(&hist[octave_index(ext)], 1u);
+    } else {
+        flag[begin] = 1;
+        len[begin] = count;
+    }
+}
+
+template <bool HIST>
+__global__ void k_group_pass(const WNode* __restrict__ node, const uint64_t* __restrict__ lvl,
+                             const unsigned long long* __restrict__ n_dev,
+                             const uint64_t* __restrict__ keys, int D, int n_crit,
+                             const double* __restrict__ x, const double* __restrict__ y,
+                             const double* __restrict__ z, const double* __restrict__ cl_S,
+                             unsigned* __restrict__ hist, int32_t* __restrict__ flag,
+                             int32_t* __restrict__ len) {
     const int64_t nn = (int64_t)*n_dev;
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nn;
          b += (int64_t)gridDim.x * blockDim.x) {
         const WNode w = node[b];
-        if (lvl[b] == 0 && w.count <= n_crit) {
-            flag[w.begin] = 1;
-            len[w.begin] = w.count;
-        }
-        if (w.count <= n_crit) continue;
+        const int c = cluster_of(keys[w.begin], D);
+        const double S = HIST ? INFINITY : cl_S[c];
+        unsigned* h = hist + (int64_t)c * kOctaves;
+        const double ext = box_extent(w.lo, w.hi);
+        const bool big = w.count > n_crit || ext > S;
+        if (lvl[b] == 0 && !big) emit_group<HIST>(w.begin, w.count, ext, h, flag, len);
+        if (!big) continue;
         if (w.nchild == 0) {
-            for (int s = w.begin; s < w.begin + w.count; s += n_crit) {
-                flag[s] = 1;
-                len[s] = min(n_crit, w.begin + w.count - s);
+            if (ext > S) {
+                for (int j = w.begin; j < w.begin + w.count; ++j) emit_group<HIST>(j, 1, 0.0, h, flag, len);
+            } else {
+                for (int s0 = w.begin; s0 < w.begin + w.count; s0 += n_crit) {
+                    const int e0 = min(s0 + n_crit, w.begin + w.count);
+                    double lo[3], hi[3];
+                    for (int j = s0; j < e0; ++j) {
+                        const double v[3] = {x[j], y[j], z[j]};
+                        for (int k = 0; k < 3; ++k) {
+                            if (j == s0 || v[k] < lo[k]) lo[k] = v[k];
+                            if (j == s0 || v[k] > hi[k]) hi[k] = v[k];
+                        }
+                    }
+                    emit_group<HIST>(s0, e0 - s0, box_extent(lo, hi), h, flag, len);
+                }
             }
             continue;
         }
         int run_begin = 0, run_count = 0;
+        double rlo[3] = {0, 0, 0}, rhi[3] = {0, 0, 0};
         for (int u = 0; u < w.nchild; ++u) {
-            const int cb = node[w.first_child + u].begin;
-            const int cc = node[w.first_child + u].count;
-            if (cc > n_crit || run_count + cc > n_crit) {
-                if (run_count > 0) {
-                    flag[run_begin] = 1;
-                    len[run_begin] = run_count;
-                }
+            const WNode& ch = node[w.first_child + u];
+            const double clo[3] = {ch.lo[0], ch.lo[1], ch.lo[2]};
+            const double chi[3] = {ch.hi[0], ch.hi[1], ch.hi[2]};
+            const int cc = ch.count;
+            if (cc > n_crit || box_extent(clo, chi) > S) {
+                if (run_count > 0) emit_group<HIST>(run_begin, run_count, box_extent(rlo, rhi), h, flag, len);
                 run_count = 0;
+                continue;
             }
-            if (cc > n_crit) continue;
-            if (run_count == 0) run_begin = cb;
+            double ulo[3], uhi[3];
+            for (int k = 0; k < 3; ++k) {
+                ulo[k] = (run_count > 0 && rlo[k] < clo[k]) ? rlo[k] : clo[k];
+                uhi[k] = (run_count > 0 && rhi[k] > chi[k]) ? rhi[k] : chi[k];
+            }
+            if (run_count > 0 && (run_count + cc > n_crit || box_extent(ulo, uhi) > S)) {
+                emit_group<HIST>(run_begin, run_count, box_extent(rlo, rhi), h, flag, len);
+                run_count = 0;
+                for (int k = 0; k < 3; ++k) { ulo[k] = clo[k]; uhi[k] = chi[k]; }
+            }
+            if (run_count == 0) run_begin = ch.begin;
             run_count += cc;
+            for (int k = 0; k < 3; ++k) { rlo[k] = ulo[k]; rhi[k] = uhi[k]; }
         }
-        if (run_count > 0) {
-            flag[run_begin] = 1;
-            len[run_begin] = run_count;
+        if (run_count > 0) emit_group<HIST>(run_begin, run_count, box_extent(rlo, rhi), h, flag, len);
+    }
+}
+
+// one thread per cluster: size limit from the median octave of the first pass
+__global__ void k_group_limit(const unsigned* __restrict__ hist, int nc, double* __restrict__ cl_S) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const unsigned* h = hist + (int64_t)c * kOctaves;
+    int64_t total = 0;
+    for (int i = 0; i < kOctaves; ++i) total += h[i];
+    const int64_t need = (total + 1) / 2;
+    int64_t cum = 0;
+    int b = kOctaves - 1;
+    for (int i = 0; i < kOctaves; ++i) {
+        cum += h[i];
+        if (cum >= need) {
+            b = i;
+            break;
         }
     }
+    cl_S[c] = ldexp(1.0, b - 64 + kGroupLimitLog2);
+}
+
+__global__ void k_fill_u32(unsigned* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
 }
 
 __global__ void k_group_fill(const int32_t* __restrict__ gid, const int32_t* __restrict__ len,
@@ -579,10 +666,21 @@ void launch_moments(Dev& d, const BuildCfg& c, hipStream_t s) {
 
 void launch_groups(Dev& d, const BuildCfg& c, hipStream_t s) {
     const int64_t n = c.n;
+    const unsigned long long* n_nodes = d.cnt + kCntNodes;
+    const int gb = grid_for(c.node_cap, 256, 2048);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((int64_t)c.n_clusters * kOctaves, 256)), dim3(256), 0, s,
+                       d.g_hist, (int64_t)c.n_clusters * kOctaves);
+    hipLaunchKernelGGL(k_group_pass<true>, dim3(gb), dim3(256), 0, s, (const WNode*)d.node,
+                       (const uint64_t*)d.lvl_key, n_nodes, (const uint64_t*)d.keys, c.D, c.n_crit,
+                       (const double*)d.x, (const double*)d.y, (const double*)d.z,
+                       (const double*)d.cl_S, d.g_hist, d.g_flag, d.g_len);
+    hipLaunchKernelGGL(k_group_limit, dim3((c.n_clusters + 63) / 64), dim3(64), 0, s,
+                       (const unsigned*)d.g_hist, c.n_clusters, d.cl_S);
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, d.g_flag, n + 1, 0);
-    hipLaunchKernelGGL(k_group_mark, dim3(grid_for(c.node_cap, 256, 2048)), dim3(256), 0, s,
-                       (const WNode*)d.node, (const uint64_t*)d.lvl_key,
-                       (const unsigned long long*)(d.cnt + kCntNodes), c.n_crit, d.g_flag, d.g_len);
+    hipLaunchKernelGGL(k_group_pass<false>, dim3(gb), dim3(256), 0, s, (const WNode*)d.node,
+                       (const uint64_t*)d.lvl_key, n_nodes, (const uint64_t*)d.keys, c.D, c.n_crit,
+                       (const double*)d.x, (const double*)d.y, (const double*)d.z,
+                       (const double*)d.cl_S, d.g_hist, d.g_flag, d.g_len);
     exclusive_scan_i32(d.g_flag, d.g_flag, n, d.scan_tmp, s);   // g_flag[n] = group count
     hipLaunchKernelGGL(k_group_fill, dim3(grid_for(n, 256)), dim3(256), 0, s,
                        (const int32_t*)d.g_flag, (const int32_t*)d.g_len, (const uint64_t*)d.keys,

@@ -139,6 +139,7 @@ pbh_status ensure_buffers(pbh_ctx* ctx) {
               dalloc(ctx, &d.lvl_off, 32) && dalloc(ctx, &d.node, cap) &&
               dalloc(ctx, &d.q64, cap) && dalloc(ctx, &d.q32, cap) &&
               dalloc(ctx, &d.g_flag, n + 1) && dalloc(ctx, &d.g_len, n) &&
+              dalloc(ctx, &d.g_hist, 128 * C) && dalloc(ctx, &d.cl_S, C) &&
               dalloc(ctx, &d.g.begin, G) && dalloc(ctx, &d.g.count, G) &&
               dalloc(ctx, &d.g.root, G) && dalloc(ctx, &d.g.cluster, G) &&
               dalloc(ctx, &d.g.lo, 3 * G) && dalloc(ctx, &d.g.hi, 3 * G) &&

@@ -124,6 +124,8 @@ struct Dev {
     GroupArrays g;
     int32_t* g_flag = nullptr;   // [n+1] 1 at the first particle of a group, then scanned
     int32_t* g_len = nullptr;    // [n] group length at its first particle
+    unsigned* g_hist = nullptr;  // [C][128] octave histogram of first-pass group sizes
+    double* cl_S = nullptr;      // [C] group size limit per cluster
     // generic scan scratch
     int64_t* scan_tmp = nullptr;
     int64_t scan_tmp_len = 0;

@@ -302,6 +302,24 @@ def test_node_moments_against_direct_sums():
         assert np.array_equal(db[k, 10:13], x.min(0)) and np.array_equal(db[k, 13:16], x.max(0))
 
 
+def test_group_size_limit_splits_halo_groups():
+    # a dense clump plus a sparse shell: without a size limit one shell group
+    # would span the clump; with it no multi-particle group is that large
+    rng = np.random.default_rng(3)
+    clump = rng.normal(size=(4000, 3)) * 0.01
+    shell = rng.normal(size=(60, 3))
+    shell = 10 * shell / np.linalg.norm(shell, axis=1)[:, None]
+    pos = np.concatenate([clump, shell])
+    mass = np.full(pos.shape[0], 1.0 / pos.shape[0])
+    order, ib, db = oracle.tree_nodes(pos, mass, n_leaf=16)
+    gb, gc = oracle.groups(pos, mass, n_leaf=16, n_crit=64)
+    S = oracle.group_limit(pos, mass, n_leaf=16, n_crit=64)
+    xs = pos[order]
+    ext = np.array([(xs[b:b + k].max(0) - xs[b:b + k].min(0)).max() for b, k in zip(gb, gc)])
+    assert S <= 2.0 and ext[gc > 1].max() <= S   # the shell spans ~20
+    assert (gc == 1).sum() >= 1      # isolated shell particles became their own groups
+
+
 @pytest.mark.parametrize("n,n_leaf,n_crit", [(3000, 16, 64), (2000, 8, 32), (400, 4, 7), (50, 16, 64)])
 def test_walk_group_invariants(n, n_leaf, n_crit):
     c = ic.plummer(n, seed=31, masses="kroupa")
@@ -310,17 +328,23 @@ def test_walk_group_invariants(n, n_leaf, n_crit):
     # a partition of the sorted particles into runs of at most n_crit
     assert gb[0] == 0 and np.all(gb[1:] == gb[:-1] + gc[:-1]) and gb[-1] + gc[-1] == n
     assert np.all(gc >= 1) and np.all(gc <= n_crit)
-    # every group lies inside one node whose parent (the smallest enclosing
-    # node holding more than n_crit) it cannot leave: find the smallest node
-    # containing each group and check that node is either a small node inside
-    # a large parent, the large node itself (a split leaf), or a small root
-    big = ib[ib[:, 1] > n_crit]
+    # groups never leave the box limit S (a power of two) unless they are single particles
+    S = oracle.group_limit(c.pos, c.mass, n_leaf=n_leaf, n_crit=n_crit)
+    assert S > 0 and np.frexp(S)[0] == 0.5
+    xs = c.pos[order]
     for b, k in zip(gb, gc):
-        host = big[(big[:, 0] <= b) & (big[:, 0] + big[:, 1] >= b + k)]
-        if host.size == 0:
-            assert ib[0, 1] <= n_crit and b == 0 and k == n      # the root is one group
-        else:
-            assert host[:, 1].min() > n_crit
+        if k > 1:
+            pts = xs[b:b + k]
+            assert (pts.max(0) - pts.min(0)).max() <= S
+    # groups are unions of whole tree nodes or runs inside one leaf: a group's
+    # first particle starts a node, or lies in a leaf holding the whole group
+    starts = set(ib[:, 0].tolist())
+    leaves = ib[ib[:, 2] == 0]
+    for b, k in zip(gb, gc):
+        if b in starts:
+            continue
+        lf = leaves[(leaves[:, 0] <= b) & (leaves[:, 0] + leaves[:, 1] >= b + k)]
+        assert lf.shape[0] == 1
     # the walk through these groups still equals direct summation at theta = 0
     r_out = 0.1
     acc, pot = oracle.direct(c.pos, c.mass, 0.1 * r_out, r_out, 1e-4)
