@@ -385,7 +385,7 @@ int64_t orc_nbr_cells(int64_t n, const double* pos, double r_out,
 /*         inner node packs its consecutive children that are not big,      */
 /*         greedily and in order, into groups of at most n_crit particles   */
 /*         whose joint box stays within S (a big child interrupts the run). */
-/*         A root that is not big is one group. S is 2^7 x 2^e for the     */
+/*         A root that is not big is one group. S is 2^5 x 2^e for the     */
 /*         octave e (2^e <= x < 2^(e+1)) holding the median box size of the */
 /*         groups this rule forms with S = infinity, per cluster; it keeps  */
 /*         a sparse-halo group from spanning the dense core. Groups are     */
@@ -625,7 +625,7 @@ static int group_cmp(const void* a, const void* b)
 }
 
 #ifndef GROUP_S_LOG2
-#define GROUP_S_LOG2 7
+#define GROUP_S_LOG2 5
 #endif
 
 /* largest side of a box */
@@ -718,7 +718,7 @@ static int64_t group_pass(const otree_t* t, int n_crit, double S, ogroup_t* g, d
     return ng;
 }
 
-/* Size limit of the walk groups of one cluster: 2^7 x 2^e for the octave e
+/* Size limit of the walk groups of one cluster: 2^5 x 2^e for the octave e
    holding the median extent of the groups the count rule alone would form. */
 static double group_size_limit(const otree_t* t, int n_crit)
 {

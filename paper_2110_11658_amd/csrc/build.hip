@@ -422,12 +422,12 @@ __global__ void k_moments_level(const int32_t* __restrict__ lvl_off, int level,
 // particles if its box exceeds S; an inner node packs its consecutive
 // children that are not big, greedily in order, into groups of at most
 // n_crit particles whose joint box stays within S (a big child interrupts the
-// run). A root that is not big is one group. S = 2^7 x 2^e for the octave e
+// run). A root that is not big is one group. S = 2^5 x 2^e for the octave e
 // (2^e <= x < 2^(e+1)) holding the median box size of the groups formed with
 // S = infinity (first pass, histogram only). The first particle of each group
 // is flagged; a scan of the flags numbers the groups in particle order.
 constexpr int kOctaves = 128;
-constexpr int kGroupLimitLog2 = 7;
+constexpr int kGroupLimitLog2 = 5;
 
 __device__ inline double box_extent(const double* lo, const double* hi) {
     double e = 0.0;
