@@ -355,6 +355,7 @@ pbh_status do_force(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, double 
     const int gmax = w.mixed ? ctx->grid_mixed : ctx->grid_fp64;
     w.grid = gmax;   // persistent: workgroups leave when the group queue is empty
     w.stack_cap = kStackCap;
+    w.count_nbr = nbr_off != nullptr;   // the walk counts the neighbours of every particle
     mark(ctx, 2, s);
     launch_walk(d, c, w, acc, pot, s);
     mark(ctx, 3, s);
@@ -363,7 +364,6 @@ pbh_status do_force(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, double 
     if (nbr_off) {
         const int grid = ctx->grid_mixed;
         mark(ctx, 4, s);
-        launch_nbr_count(d, c, grid, kStackCap, s);
         exclusive_scan_i32_to_i64(d.nbr_cnt, nbr_off, c.n, d.scan_tmp, s);
         if (nbr_total) {
             int64_t tot = 0;
@@ -596,6 +596,7 @@ static void kdk_force(pbh_ctx* ctx, const double* pos, const double* mass, doubl
     const int gmax = w.mixed ? ctx->grid_mixed : ctx->grid_fp64;
     w.grid = gmax;
     w.stack_cap = kStackCap;
+    w.count_nbr = 0;
     launch_walk(ctx->d, ctx->cfg, w, ctx->k_acc, ctx->k_pot, s);
 }
 

@@ -8,9 +8,10 @@
 // distances, also after rounding, so no neighbour is missed). The particles
 // of those leaves are staged 64 at a time in an LDS tile (FP64 position and
 // caller index, loaded lane-parallel) and every lane tests its own particle
-// against each tile entry by LDS broadcast. Two passes with the same
-// deterministic order: counts per caller index (scanned into CSR offsets by
-// the host library), then indices.
+// against each tile entry by LDS broadcast. The tree walk (walk.hip) counts
+// the neighbours while it evaluates the near pairs; the host library scans
+// the counts into CSR offsets; this pass then writes the indices, in its own
+// deterministic traversal order (the same set the walk counted).
 #include "pbh_internal.hpp"
 #include "wave.hpp"
 
@@ -34,15 +35,14 @@ struct NbrParams {
     const double* g_hi;
     const ClusterParams* cp;
     const unsigned long long* G;   // device-side group count
-    int32_t* counts;               // count pass: per caller index
-    const int64_t* off;            // fill pass: CSR offsets (caller order)
-    int32_t* idx;                  // fill pass
+    const int64_t* off;            // CSR offsets (caller order)
+    int32_t* idx;                  // CSR indices
     int64_t cap;
     int32_t* stack;
     int stack_cap;
     unsigned long long* cnt;
     unsigned long long* queues;    // [kQueues] of this pass
-    unsigned long long* wave_log;  // per workgroup: groups done, clock ticks (count pass)
+    unsigned long long* wave_log;  // per workgroup: groups done, clock ticks
 };
 
 struct NTile {
@@ -52,7 +52,6 @@ struct NTile {
     int lf_beg[64];
 };
 
-template <bool FILL>
 __device__ inline void test_tile(const NTile& T, int cnt, double xi, double yi, double zi, int me_orig,
                                  bool active, double rout2, const NbrParams& p, int64_t wpos,
                                  int& count, bool& overflow) {
@@ -62,18 +61,15 @@ __device__ inline void test_tile(const NTile& T, int cnt, double xi, double yi, 
         const double r2 = dx * dx + dy * dy + dz * dz;
         const int oj = T.orig[e];
         if (active && r2 < rout2 && oj != me_orig) {
-            if (FILL) {
-                const int64_t at = wpos + count;
-                if (at < p.cap) p.idx[at] = oj;
-                else overflow = true;
-            }
+            const int64_t at = wpos + count;
+            if (at < p.cap) p.idx[at] = oj;
+            else overflow = true;
             ++count;
         }
     }
 }
 
-template <bool FILL>
-__global__ __launch_bounds__(64) void k_nbr(NbrParams p) {
+__global__ __launch_bounds__(64) void k_nbr_fill(NbrParams p) {
     __shared__ NTile T;
     __shared__ int s_stack[kStackLds];
     const int lane = threadIdx.x;
@@ -98,7 +94,7 @@ __global__ __launch_bounds__(64) void k_nbr(NbrParams p) {
         const double xi = p.x[me], yi = p.y[me], zi = p.z[me];
         const int orig = p.perm[me];
         int64_t wpos = 0;
-        if (FILL && active) wpos = p.off[orig];
+        if (active) wpos = p.off[orig];
         int count = 0;
         bool overflow = false;
         if (rout2 > 0.0) {
@@ -150,7 +146,7 @@ __global__ __launch_bounds__(64) void k_nbr(NbrParams p) {
                     fill = uni(fill + ((total - base) < 64 ? (total - base) : 64));
                     if (fill >= 64) {
                         __syncthreads();
-                        test_tile<FILL>(T, fill, xi, yi, zi, orig, active, rout2, p, wpos, count, overflow);
+                        test_tile(T, fill, xi, yi, zi, orig, active, rout2, p, wpos, count, overflow);
                         fill = 0;
                         __syncthreads();
                     }
@@ -158,14 +154,13 @@ __global__ __launch_bounds__(64) void k_nbr(NbrParams p) {
                 __syncthreads();
             }
             __syncthreads();
-            if (fill) test_tile<FILL>(T, fill, xi, yi, zi, orig, active, rout2, p, wpos, count, overflow);
+            if (fill) test_tile(T, fill, xi, yi, zi, orig, active, rout2, p, wpos, count, overflow);
             __syncthreads();
         }
-        if (!FILL && active) p.counts[orig] = count;
         const uint64_t ov = __ballot(overflow);
-        if (ov) atomicOr(&p.cnt[kErr], lane == 0 ? (FILL ? kErrNbrOverflow : kErrNbrStack) : 0ull);
+        if (ov) atomicOr(&p.cnt[kErr], lane == 0 ? kErrNbrOverflow : 0ull);
     }
-    if (!FILL && p.wave_log) {
+    if (p.wave_log) {
         p.wave_log[2 * blockIdx.x] = (unsigned long long)n_done;
         p.wave_log[2 * blockIdx.x + 1] = wall_clock64() - t_start;
     }
@@ -180,7 +175,6 @@ NbrParams make_params(Dev& d, const BuildCfg& c, int stack_cap) {
     p.g_lo = d.g.lo; p.g_hi = d.g.hi;
     p.cp = d.cparams;
     p.G = d.cnt + kCntGroups;
-    p.counts = d.nbr_cnt;
     p.off = nullptr;
     p.idx = nullptr;
     p.cap = 0;
@@ -195,11 +189,6 @@ NbrParams make_params(Dev& d, const BuildCfg& c, int stack_cap) {
 
 }  // namespace
 
-void launch_nbr_count(Dev& d, const BuildCfg& c, int grid, int stack_cap, hipStream_t s) {
-    NbrParams p = make_params(d, c, stack_cap);
-    hipLaunchKernelGGL(k_nbr<false>, dim3(grid), dim3(64), 0, s, p);
-}
-
 void launch_nbr_fill(Dev& d, const BuildCfg& c, int grid, int stack_cap, const int64_t* off,
                      int32_t* idx, int64_t cap, hipStream_t s) {
     NbrParams p = make_params(d, c, stack_cap);
@@ -207,7 +196,7 @@ void launch_nbr_fill(Dev& d, const BuildCfg& c, int grid, int stack_cap, const i
     p.idx = idx;
     p.cap = cap;
     p.queues = d.queues + 2 * kQueues;
-    hipLaunchKernelGGL(k_nbr<true>, dim3(grid), dim3(64), 0, s, p);
+    hipLaunchKernelGGL(k_nbr_fill, dim3(grid), dim3(64), 0, s, p);
 }
 
 }  // namespace pbh

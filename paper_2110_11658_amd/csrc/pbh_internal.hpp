@@ -176,6 +176,7 @@ struct WalkCfg {
     int mixed;
     int grid;
     int stack_cap;
+    int count_nbr;   // also count neighbours per particle into Dev::nbr_cnt
 };
 void launch_rcrit(Dev& d, const BuildCfg& c, double theta, hipStream_t s);
 void launch_walk(Dev& d, const BuildCfg& c, const WalkCfg& w, double* acc, double* pot,
@@ -183,7 +184,6 @@ void launch_walk(Dev& d, const BuildCfg& c, const WalkCfg& w, double* acc, doubl
 int walk_blocks_per_cu(int mixed);
 
 // nbr.hip
-void launch_nbr_count(Dev& d, const BuildCfg& c, int grid, int stack_cap, hipStream_t s);
 void launch_nbr_fill(Dev& d, const BuildCfg& c, int grid, int stack_cap, const int64_t* off,
                      int32_t* idx, int64_t cap, hipStream_t s);
 

@@ -38,6 +38,7 @@ struct alignas(16) Tiles {
     R far[TCAP][4];      // x y z m (relative to the group centre)
     R nearp[TCAP][4];
     int nearj[TCAP];     // sorted index, to skip the self pair
+    double nx[TCAP], ny[TCAP], nz[TCAP];   // near entries in FP64 (neighbour test)
     int lf_ex[64];       // leaf expansion: exclusive prefix of particle counts
     int lf_beg[64];
 };
@@ -68,6 +69,7 @@ struct WalkParams {
     unsigned long long* cnt;
     unsigned long long* queues;     // [kQueues] group queue heads
     unsigned long long* wave_log;   // per workgroup: groups walked, clock ticks
+    int32_t* nbr_cnt;               // neighbour counts per caller index, or null
 };
 
 __device__ inline void two_sum_acc(float& hi, float& lo, float v) {
@@ -167,14 +169,28 @@ struct NearK {
     bool pole;   // r_in > 0: the -d0/s and log terms are present
 };
 
-// Pairs of near leaves: changeover weight W(s) and the regular potential.
+// Neighbour test of the CSR lists: r^2 < r_out^2 in FP64 from the original
+// coordinates, ((dx*dx + dy*dy) + dz*dz) without FMA.
+__device__ inline bool is_neighbour(double xj, double yj, double zj, double xi, double yi, double zi,
+                                    double rout2) {
+#pragma clang fp contract(off)
+    const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    return r2 < rout2;
+}
+
+// Pairs of near leaves: changeover weight W(s) and the regular potential;
+// optionally also counts the neighbours inside r_out (FP64 test).
 template <typename R>
 __device__ inline void eval_near(const Tiles<R>& T, int cnt, R px, R py, R pz, R eps2, int self,
-                                 const NearK<R>& K, Acc<R>& A) {
+                                 const NearK<R>& K, Acc<R>& A, bool count_nbr, double xi, double yi,
+                                 double zi, double rout2, int& nbr) {
     R ax = 0, ay = 0, az = 0, ph = 0;
     for (int e = 0; e < cnt; ++e) {
         const R* q = T.nearp[e];
         const bool is_self = T.nearj[e] == self;
+        if (count_nbr)
+            nbr += (!is_self && is_neighbour(T.nx[e], T.ny[e], T.nz[e], xi, yi, zi, rout2)) ? 1 : 0;
         const R dx = q[0] - px, dy = q[1] - py, dz = q[2] - pz;
         const R s2 = dx * dx + dy * dy + dz * dz + eps2;
         const R inv = rsq(s2);
@@ -238,9 +254,12 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
 
         const bool active = lane < gcnt;
         const int me = gb + (active ? lane : 0);
-        const R px = (R)(p.x[me] - ctr[0]);
-        const R py = (R)(p.y[me] - ctr[1]);
-        const R pz = (R)(p.z[me] - ctr[2]);
+        const double xi = p.x[me], yi = p.y[me], zi = p.z[me];
+        const R px = (R)(xi - ctr[0]);
+        const R py = (R)(yi - ctr[1]);
+        const R pz = (R)(zi - ctr[2]);
+        const bool count_nbr = p.nbr_cnt != nullptr;
+        int nbr = 0;
         Acc<R> A;
 
         int npn = 0, nfar = 0, nnear = 0;
@@ -328,7 +347,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                     if (fill + add > TCAP) {
                         __syncthreads();
                         if (cls == 0) eval_far<R>(T, fill, px, py, pz, eps2, A);
-                        else eval_near<R>(T, fill, px, py, pz, eps2, me, K, A);
+                        else eval_near<R>(T, fill, px, py, pz, eps2, me, K, A, count_nbr, xi, yi, zi, rout2, nbr);
                         fill = 0;
                         __syncthreads();
                     }
@@ -338,7 +357,12 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                         e[1] = (R)(p.y[j] - ctr[1]);
                         e[2] = (R)(p.z[j] - ctr[2]);
                         e[3] = (R)p.m[j];
-                        if (cls == 1) T.nearj[fill + lane] = j;
+                        if (cls == 1) {
+                            T.nearj[fill + lane] = j;
+                            T.nx[fill + lane] = p.x[j];
+                            T.ny[fill + lane] = p.y[j];
+                            T.nz[fill + lane] = p.z[j];
+                        }
                     }
                     fill = uni(fill + add);
                 }
@@ -348,12 +372,13 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
         __syncthreads();
         if (npn) eval_pn<R>(T, npn, px, py, pz, eps2, A);
         if (nfar) eval_far<R>(T, nfar, px, py, pz, eps2, A);
-        if (nnear) eval_near<R>(T, nnear, px, py, pz, eps2, me, K, A);
+        if (nnear) eval_near<R>(T, nnear, px, py, pz, eps2, me, K, A, count_nbr, xi, yi, zi, rout2, nbr);
         __syncthreads();
 
         if (overflow) atomicOr(&p.cnt[kErr], lane == 0 ? kErrWalkStack : 0ull);
         if (active) {
             const int orig = p.perm[gb + lane];
+            if (count_nbr) p.nbr_cnt[orig] = nbr;
             p.acc[3 * (int64_t)orig] = A.gx();
             p.acc[3 * (int64_t)orig + 1] = A.gy();
             p.acc[3 * (int64_t)orig + 2] = A.gz();
@@ -433,6 +458,7 @@ void launch_walk(Dev& d, const BuildCfg& c, const WalkCfg& w, double* acc, doubl
     p.cnt = d.cnt;
     p.queues = d.queues;
     p.wave_log = d.wave_log;
+    p.nbr_cnt = w.count_nbr ? d.nbr_cnt : nullptr;
     if (w.mixed) hipLaunchKernelGGL(k_walk<true>, dim3(w.grid), dim3(64), 0, s, p);
     else hipLaunchKernelGGL(k_walk<false>, dim3(w.grid), dim3(64), 0, s, p);
 }
