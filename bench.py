@@ -9,7 +9,8 @@ Workloads (--workload):
   plummer1m    (default) Plummer sphere N = 2^20, Kroupa masses, Henon units,
                eps = 1e-6, r_out for 64 mean neighbours (0.04077), r_in =
                0.1 r_out, theta = 0.5, quadrupole nodes, FP32 interactions
-               with FP64 positions and sums, leaf/group sizes autotuned
+               with FP64 positions and sums, n_leaf = 8, n_crit = 64 (the
+               autotuner's choice on MI355X; --autotune re-tunes)
   plummer128k  N = 131072, eps = 1e-5 (run with --prec fp64 and mixed)
   plummer4m    N = 2^22, eps = 1e-6
   ensemble64   64 independent clusters, N log-uniform in [1e4, 2e5], each
@@ -86,8 +87,11 @@ def parse():
     ap.add_argument("--workload", default="plummer1m", choices=sorted(WORKLOADS))
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--leaf", type=int, default=0, help="n_leaf (0 = autotune)")
-    ap.add_argument("--ncrit", type=int, default=0, help="n_crit (0 = autotune)")
+    ap.add_argument("--leaf", type=int, default=8, help="n_leaf (tree leaf size)")
+    ap.add_argument("--ncrit", type=int, default=64, help="n_crit (largest walk group)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick n_leaf and n_crit by timing candidates on this input first "
+                         "(on MI355X every workload here picks n_leaf=8, n_crit=64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-neighbours", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -152,7 +156,7 @@ def bench_force(args):
     L, ctx = p.L, p.ctx
 
     tuned = None
-    if args.leaf and args.ncrit:
+    if not args.autotune:
         p.set_params(leaf_size=args.leaf, n_crit=args.ncrit, prec=args.prec)
     else:
         tuned = autotune.tune(p, pos, mass, inp["r_in"], inp["r_out"], theta, eps, prec=args.prec,

@@ -34,7 +34,11 @@ def _cache_path() -> str:
 
 
 def _key(n: int, theta: float, prec: str, neighbours: bool, n_clusters: int) -> str:
-    dev = torch.cuda.get_device_name(torch.cuda.current_device()) if torch.cuda.is_available() else "cpu"
+    dev = "cpu"
+    if torch.cuda.is_available():
+        props = torch.cuda.get_device_properties(torch.cuda.current_device())
+        # the marketing name can read empty (e.g. under a profiler); the ISA name cannot
+        dev = f"{props.name}|{props.gcnArchName}"
     return f"{dev}|log2n={round(math.log2(max(n, 1)))}|theta={theta:.3f}|{prec}|nbr={int(neighbours)}|c={n_clusters}"
 
 

@@ -116,6 +116,7 @@ __device__ inline float lnr(float v) { return __logf(v); }
 __device__ inline double lnr(double v) { return log(v); }
 
 // Monopole + traceless quadrupole: phi = -M/s - (R^T Q R)/(2 s^5), a = -grad phi
+//   a = -(M/s^3 + (5/2) (R^T Q R)/s^7) R + Q R / s^5,   R = x_i - COM
 template <typename R>
 __device__ inline void eval_pn(const Tiles<R>& T, int cnt, R px, R py, R pz, R eps2, Acc<R>& A) {
     R ax = 0, ay = 0, az = 0, ph = 0;
@@ -142,6 +143,38 @@ __device__ inline void eval_pn(const Tiles<R>& T, int cnt, R px, R py, R pz, R e
     A.add(ax, ay, az, ph);
 }
 
+// FP32 form written as explicit FMA chains (34 VALU + 1 rsqrt per entry):
+//   t = R^T Q R / s^5,  cr = M/s^3 + 2.5 t / s^2,  a += Q R / s^5 - cr R,
+//   phi += -M/s - t/2.
+template <>
+__device__ inline void eval_pn<float>(const Tiles<float>& T, int cnt, float px, float py, float pz,
+                                      float eps2, Acc<float>& A) {
+    float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+#pragma unroll 4
+    for (int e = 0; e < cnt; ++e) {
+        const float4 a = *reinterpret_cast<const float4*>(&T.pn[e][0]);   // cx cy cz M
+        const float4 b = *reinterpret_cast<const float4*>(&T.pn[e][4]);   // qxx qyy qzz qxy
+        const float2 c = *reinterpret_cast<const float2*>(&T.pn[e][8]);   // qxz qyz
+        const float Rx = px - a.x, Ry = py - a.y, Rz = pz - a.z;
+        const float s2 = fmaf(Rz, Rz, fmaf(Ry, Ry, fmaf(Rx, Rx, eps2)));
+        const float inv = __builtin_amdgcn_rsqf(s2);
+        const float inv2 = inv * inv;
+        const float qx = fmaf(c.x, Rz, fmaf(b.w, Ry, b.x * Rx));
+        const float qy = fmaf(c.y, Rz, fmaf(b.y, Ry, b.w * Rx));
+        const float qz = fmaf(b.z, Rz, fmaf(c.y, Ry, c.x * Rx));
+        const float rqr = fmaf(Rz, qz, fmaf(Ry, qy, Rx * qx));
+        const float inv3 = inv * inv2;
+        const float inv5 = inv3 * inv2;
+        const float t = rqr * inv5;
+        const float cr = fmaf(2.5f * t, inv2, a.w * inv3);
+        ax = fmaf(-cr, Rx, fmaf(qx, inv5, ax));
+        ay = fmaf(-cr, Ry, fmaf(qy, inv5, ay));
+        az = fmaf(-cr, Rz, fmaf(qz, inv5, az));
+        ph = fmaf(-a.w, inv, fmaf(-0.5f, t, ph));
+    }
+    A.add(ax, ay, az, ph);
+}
+
 // Pairs of far leaves: every pair is at r >= r_out, where W = 1.
 template <typename R>
 __device__ inline void eval_far(const Tiles<R>& T, int cnt, R px, R py, R pz, R eps2, Acc<R>& A) {
@@ -157,6 +190,26 @@ __device__ inline void eval_far(const Tiles<R>& T, int cnt, R px, R py, R pz, R 
         ax += mi3 * dx;
         ay += mi3 * dy;
         az += mi3 * dz;
+        ph -= mi;
+    }
+    A.add(ax, ay, az, ph);
+}
+
+template <>
+__device__ inline void eval_far<float>(const Tiles<float>& T, int cnt, float px, float py, float pz,
+                                       float eps2, Acc<float>& A) {
+    float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+#pragma unroll 4
+    for (int e = 0; e < cnt; ++e) {
+        const float4 q = *reinterpret_cast<const float4*>(&T.far[e][0]);
+        const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+        const float s2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+        const float inv = __builtin_amdgcn_rsqf(s2);
+        const float mi = q.w * inv;
+        const float mi3 = mi * (inv * inv);
+        ax = fmaf(mi3, dx, ax);
+        ay = fmaf(mi3, dy, ay);
+        az = fmaf(mi3, dz, az);
         ph -= mi;
     }
     A.add(ax, ay, az, ph);
@@ -210,6 +263,59 @@ __device__ inline void eval_near(const Tiles<R>& T, int cnt, R px, R py, R pz, R
         ph += is_self ? R(0) : q[3] * phi;
     }
     A.add(ax, ay, az, ph);
+}
+
+// FP32 form without per-lane branches: the neighbour count and the pole
+// terms (-d0/s + l1 ln s, present when r_in > 0) are compile-time switches,
+// ln s = log2(s) ln 2, and the boundary cases of W and Phi_R are selects.
+template <bool CNT, bool POLE>
+__device__ inline void eval_near_f32(const Tiles<float>& T, int cnt, float px, float py, float pz,
+                                     float eps2, int self, const NearK<float>& K, Acc<float>& A,
+                                     double xi, double yi, double zi, double rout2, int& nbr) {
+    float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+    const float l1 = K.l1 * 0.693147180559945309f;
+#pragma unroll 2
+    for (int e = 0; e < cnt; ++e) {
+        const float4 q = *reinterpret_cast<const float4*>(&T.nearp[e][0]);
+        const bool other = T.nearj[e] != self;
+        if (CNT) nbr += (other & is_neighbour(T.nx[e], T.ny[e], T.nz[e], xi, yi, zi, rout2)) ? 1 : 0;
+        const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+        const float s2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+        const float inv = __builtin_amdgcn_rsqf(s2);
+        const float s = s2 > 0.f ? s2 * inv : 0.f;
+        const float xx = (s - K.r_in) * K.inv_delta;
+        const float x2 = xx * xx;
+        const float gp = x2 * x2 * fmaf(xx, fmaf(xx, fmaf(-20.f, xx, 70.f), -84.f), 35.f);
+        const bool outer = s >= K.r_out, inner = s < K.r_in;
+        const float W = outer ? 1.f : (inner ? 0.f : gp);
+        const float mi3 = q.w * (inv * inv) * inv;
+        const float f = (W > 0.f) & other ? W * mi3 : 0.f;
+        ax = fmaf(f, dx, ax);
+        ay = fmaf(f, dy, ay);
+        az = fmaf(f, dz, az);
+        const float t = s * K.inv_delta;
+        float mid = fmaf(t, fmaf(t, fmaf(t, fmaf(t, fmaf(t, K.e[5], K.e[4]), K.e[3]), K.e[2]), K.e[1]),
+                         K.e[0]);
+        mid = fmaf(t, mid, K.c0);
+        if (POLE) mid = fmaf(-K.d0, inv, fmaf(l1, __builtin_amdgcn_logf(s), mid));
+        const float phi = outer ? -inv : (inner ? K.inner : mid);
+        ph = other ? fmaf(q.w, phi, ph) : ph;
+    }
+    A.add(ax, ay, az, ph);
+}
+
+template <>
+__device__ inline void eval_near<float>(const Tiles<float>& T, int cnt, float px, float py, float pz,
+                                        float eps2, int self, const NearK<float>& K, Acc<float>& A,
+                                        bool count_nbr, double xi, double yi, double zi, double rout2,
+                                        int& nbr) {
+    if (count_nbr) {
+        if (K.pole) eval_near_f32<true, true>(T, cnt, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr);
+        else eval_near_f32<true, false>(T, cnt, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr);
+    } else {
+        if (K.pole) eval_near_f32<false, true>(T, cnt, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr);
+        else eval_near_f32<false, false>(T, cnt, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr);
+    }
 }
 
 template <bool MIXED>
