@@ -330,87 +330,182 @@ __global__ void k_nodes_init(const int32_t* __restrict__ bfs2pre, const int32_t*
 
 // ----------------------------------------------------------------- moments
 // One node per thread for the nodes of one level. Leaves sum their particles,
-// inner nodes their (contiguous) children, in order.
-__global__ void k_moments_level(const int32_t* __restrict__ lvl_off, int level,
+// inner nodes their (contiguous) children, in order: M, the mass-weighted
+// centre, the tight box, then the traceless quadrupole about the new centre
+// (children's own quadrupoles shifted by the parallel-axis terms).
+//
+// A node with at most 8 parts (every inner node; leaves up to n_leaf = 8)
+// loads all parts first, with indices clamped into the node so every load is
+// valid and can be issued at once; the sums then run over the parts in order,
+// exactly as in the general loop below, so both paths round alike.
+constexpr int kMomFast = 8;
+
+struct MomOut {
+    double M, com[3], lo[3], hi[3], q[6];
+};
+
+__device__ inline void moments_small(const WNode& w, bool leaf, int nsub, const double* __restrict__ x,
+                                     const double* __restrict__ y, const double* __restrict__ z,
+                                     const double* __restrict__ m, const WNode* __restrict__ node,
+                                     const Mom64* __restrict__ q64, MomOut& o) {
+#pragma clang fp contract(off)
+    double mu[kMomFast], cu[3][kMomFast], lu[3][kMomFast], hu[3][kMomFast];
+#pragma unroll
+    for (int k = 0; k < kMomFast; ++k) {
+        const int u = k < nsub ? k : nsub - 1;
+        if (leaf) {
+            const int j = w.begin + u;
+            mu[k] = m[j]; cu[0][k] = x[j]; cu[1][k] = y[j]; cu[2][k] = z[j];
+            for (int d = 0; d < 3; ++d) { lu[d][k] = cu[d][k]; hu[d][k] = cu[d][k]; }
+        } else {
+            const int c = w.first_child + u;
+            mu[k] = q64[c].M;
+            for (int d = 0; d < 3; ++d) {
+                cu[d][k] = node[c].com[d];
+                lu[d][k] = node[c].lo[d];
+                hu[d][k] = node[c].hi[d];
+            }
+        }
+    }
+    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMomFast; ++k) {
+        if (k < nsub) {
+            M = M + mu[k];
+            sx = sx + mu[k] * cu[0][k];
+            sy = sy + mu[k] * cu[1][k];
+            sz = sz + mu[k] * cu[2][k];
+            for (int d = 0; d < 3; ++d) {
+                if (k == 0 || lu[d][k] < o.lo[d]) o.lo[d] = lu[d][k];
+                if (k == 0 || hu[d][k] > o.hi[d]) o.hi[d] = hu[d][k];
+            }
+        }
+    }
+    if (M > 0.0) {
+        o.com[0] = sx / M; o.com[1] = sy / M; o.com[2] = sz / M;
+    } else {
+        for (int d = 0; d < 3; ++d) o.com[d] = (o.lo[d] + o.hi[d]) * 0.5;
+    }
+    o.M = M;
+    double qc[6][kMomFast];
+#pragma unroll
+    for (int k = 0; k < kMomFast; ++k) {
+        const int u = k < nsub ? k : nsub - 1;
+        if (leaf) {
+            for (int e = 0; e < 6; ++e) qc[e][k] = 0.0;
+        } else {
+            const Mom64 mc = q64[w.first_child + u];
+            qc[0][k] = mc.qxx; qc[1][k] = mc.qyy; qc[2][k] = mc.qzz;
+            qc[3][k] = mc.qxy; qc[4][k] = mc.qxz; qc[5][k] = mc.qyz;
+        }
+    }
+    double q[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < kMomFast; ++k) {
+        if (k < nsub) {
+            const double dx = cu[0][k] - o.com[0], dy = cu[1][k] - o.com[1], dz = cu[2][k] - o.com[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            q[0] = q[0] + (qc[0][k] + mu[k] * (3.0 * dx * dx - r2));
+            q[1] = q[1] + (qc[1][k] + mu[k] * (3.0 * dy * dy - r2));
+            q[2] = q[2] + (qc[2][k] + mu[k] * (3.0 * dz * dz - r2));
+            q[3] = q[3] + (qc[3][k] + mu[k] * (3.0 * dx * dy));
+            q[4] = q[4] + (qc[4][k] + mu[k] * (3.0 * dx * dz));
+            q[5] = q[5] + (qc[5][k] + mu[k] * (3.0 * dy * dz));
+        }
+    }
+    for (int e = 0; e < 6; ++e) o.q[e] = q[e];
+}
+
+__device__ inline void moments_loop(const WNode& w, bool leaf, int nsub, const double* __restrict__ x,
+                                    const double* __restrict__ y, const double* __restrict__ z,
+                                    const double* __restrict__ m, const WNode* __restrict__ node,
+                                    const Mom64* __restrict__ q64, MomOut& o) {
+#pragma clang fp contract(off)
+    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int u = 0; u < nsub; ++u) {
+        double mu, cu[3], lu[3], hu[3];
+        if (leaf) {
+            const int j = w.begin + u;
+            mu = m[j]; cu[0] = x[j]; cu[1] = y[j]; cu[2] = z[j];
+            for (int k = 0; k < 3; ++k) { lu[k] = cu[k]; hu[k] = cu[k]; }
+        } else {
+            const int c = w.first_child + u;
+            mu = q64[c].M;
+            for (int k = 0; k < 3; ++k) {
+                cu[k] = node[c].com[k];
+                lu[k] = node[c].lo[k];
+                hu[k] = node[c].hi[k];
+            }
+        }
+        M = M + mu;
+        sx = sx + mu * cu[0];
+        sy = sy + mu * cu[1];
+        sz = sz + mu * cu[2];
+        for (int k = 0; k < 3; ++k) {
+            if (u == 0 || lu[k] < o.lo[k]) o.lo[k] = lu[k];
+            if (u == 0 || hu[k] > o.hi[k]) o.hi[k] = hu[k];
+        }
+    }
+    if (M > 0.0) {
+        o.com[0] = sx / M; o.com[1] = sy / M; o.com[2] = sz / M;
+    } else {
+        for (int k = 0; k < 3; ++k) o.com[k] = (o.lo[k] + o.hi[k]) * 0.5;
+    }
+    o.M = M;
+    double q[6] = {0, 0, 0, 0, 0, 0};
+    for (int u = 0; u < nsub; ++u) {
+        double mu, cu[3], qc[6];
+        if (leaf) {
+            const int j = w.begin + u;
+            mu = m[j]; cu[0] = x[j]; cu[1] = y[j]; cu[2] = z[j];
+            for (int e = 0; e < 6; ++e) qc[e] = 0.0;
+        } else {
+            const int c = w.first_child + u;
+            const Mom64 mc = q64[c];
+            mu = mc.M;
+            for (int k = 0; k < 3; ++k) cu[k] = node[c].com[k];
+            qc[0] = mc.qxx; qc[1] = mc.qyy; qc[2] = mc.qzz;
+            qc[3] = mc.qxy; qc[4] = mc.qxz; qc[5] = mc.qyz;
+        }
+        const double dx = cu[0] - o.com[0], dy = cu[1] - o.com[1], dz = cu[2] - o.com[2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        q[0] = q[0] + (qc[0] + mu * (3.0 * dx * dx - r2));
+        q[1] = q[1] + (qc[1] + mu * (3.0 * dy * dy - r2));
+        q[2] = q[2] + (qc[2] + mu * (3.0 * dz * dz - r2));
+        q[3] = q[3] + (qc[3] + mu * (3.0 * dx * dy));
+        q[4] = q[4] + (qc[4] + mu * (3.0 * dx * dz));
+        q[5] = q[5] + (qc[5] + mu * (3.0 * dy * dz));
+    }
+    for (int e = 0; e < 6; ++e) o.q[e] = q[e];
+}
+
+__global__ __launch_bounds__(128) void k_moments_level(const int32_t* __restrict__ lvl_off, int level,
                                 const double* __restrict__ x, const double* __restrict__ y,
                                 const double* __restrict__ z, const double* __restrict__ m,
                                 WNode* __restrict__ node, Mom64* __restrict__ q64,
                                 Mom32* __restrict__ q32) {
-#pragma clang fp contract(off)
     const int64_t b0 = lvl_off[level], b1 = lvl_off[level + 1];
     for (int64_t b = b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < b1;
          b += (int64_t)gridDim.x * blockDim.x) {
-        WNode w = node[b];
+        const WNode w = node[b];
         const bool leaf = w.nchild == 0;
         const int nsub = leaf ? w.count : w.nchild;
-        double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-        double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-        for (int u = 0; u < nsub; ++u) {
-            double mu, cu[3], lu[3], hu[3];
-            if (leaf) {
-                const int j = w.begin + u;
-                mu = m[j]; cu[0] = x[j]; cu[1] = y[j]; cu[2] = z[j];
-                for (int k = 0; k < 3; ++k) { lu[k] = cu[k]; hu[k] = cu[k]; }
-            } else {
-                const int c = w.first_child + u;
-                mu = q64[c].M;
-                for (int k = 0; k < 3; ++k) {
-                    cu[k] = node[c].com[k];
-                    lu[k] = node[c].lo[k];
-                    hu[k] = node[c].hi[k];
-                }
-            }
-            M = M + mu;
-            sx = sx + mu * cu[0];
-            sy = sy + mu * cu[1];
-            sz = sz + mu * cu[2];
-            for (int k = 0; k < 3; ++k) {
-                if (u == 0 || lu[k] < lo[k]) lo[k] = lu[k];
-                if (u == 0 || hu[k] > hi[k]) hi[k] = hu[k];
-            }
-        }
-        double com[3];
-        if (M > 0.0) {
-            com[0] = sx / M; com[1] = sy / M; com[2] = sz / M;
-        } else {
-            for (int k = 0; k < 3; ++k) com[k] = (lo[k] + hi[k]) * 0.5;
-        }
-        double q[6] = {0, 0, 0, 0, 0, 0};
-        for (int u = 0; u < nsub; ++u) {
-            double mu, cu[3], qc[6];
-            if (leaf) {
-                const int j = w.begin + u;
-                mu = m[j]; cu[0] = x[j]; cu[1] = y[j]; cu[2] = z[j];
-                for (int e = 0; e < 6; ++e) qc[e] = 0.0;
-            } else {
-                const int c = w.first_child + u;
-                const Mom64 mc = q64[c];
-                mu = mc.M;
-                for (int k = 0; k < 3; ++k) cu[k] = node[c].com[k];
-                qc[0] = mc.qxx; qc[1] = mc.qyy; qc[2] = mc.qzz;
-                qc[3] = mc.qxy; qc[4] = mc.qxz; qc[5] = mc.qyz;
-            }
-            const double dx = cu[0] - com[0], dy = cu[1] - com[1], dz = cu[2] - com[2];
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            q[0] = q[0] + (qc[0] + mu * (3.0 * dx * dx - r2));
-            q[1] = q[1] + (qc[1] + mu * (3.0 * dy * dy - r2));
-            q[2] = q[2] + (qc[2] + mu * (3.0 * dz * dz - r2));
-            q[3] = q[3] + (qc[3] + mu * (3.0 * dx * dy));
-            q[4] = q[4] + (qc[4] + mu * (3.0 * dx * dz));
-            q[5] = q[5] + (qc[5] + mu * (3.0 * dy * dz));
-        }
+        MomOut o;
+        if (nsub <= kMomFast) moments_small(w, leaf, nsub, x, y, z, m, node, q64, o);
+        else moments_loop(w, leaf, nsub, x, y, z, m, node, q64, o);
         for (int k = 0; k < 3; ++k) {
-            node[b].lo[k] = lo[k];
-            node[b].hi[k] = hi[k];
-            node[b].com[k] = com[k];
+            node[b].lo[k] = o.lo[k];
+            node[b].hi[k] = o.hi[k];
+            node[b].com[k] = o.com[k];
         }
-        Mom64 o;
-        o.M = M; o.qxx = q[0]; o.qyy = q[1]; o.qzz = q[2]; o.qxy = q[3]; o.qxz = q[4]; o.qyz = q[5];
-        o.pad = 0.0;
-        q64[b] = o;
+        Mom64 r;
+        r.M = o.M; r.qxx = o.q[0]; r.qyy = o.q[1]; r.qzz = o.q[2]; r.qxy = o.q[3]; r.qxz = o.q[4];
+        r.qyz = o.q[5];
+        r.pad = 0.0;
+        q64[b] = r;
         Mom32 f;
-        f.M = (float)M; f.qxx = (float)q[0]; f.qyy = (float)q[1]; f.qzz = (float)q[2];
-        f.qxy = (float)q[3]; f.qxz = (float)q[4]; f.qyz = (float)q[5]; f.pad = 0.0f;
+        f.M = (float)o.M; f.qxx = (float)o.q[0]; f.qyy = (float)o.q[1]; f.qzz = (float)o.q[2];
+        f.qxy = (float)o.q[3]; f.qxz = (float)o.q[4]; f.qyz = (float)o.q[5]; f.pad = 0.0f;
         q32[b] = f;
     }
 }
@@ -462,7 +557,7 @@ __global__ void k_group_pass(const WNode* __restrict__ node, const uint64_t* __r
                              const uint64_t* __restrict__ keys, int D, int n_crit,
                              const double* __restrict__ x, const double* __restrict__ y,
                              const double* __restrict__ z, const double* __restrict__ cl_S,
-                             unsigned* __restrict__ hist, int32_t* __restrict__ flag,
+                             unsigned* __restrict__ hist, int nc, int reps, int32_t* __restrict__ flag,
                              int32_t* __restrict__ len) {
     const int64_t nn = (int64_t)*n_dev;
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nn;
@@ -470,7 +565,7 @@ __global__ void k_group_pass(const WNode* __restrict__ node, const uint64_t* __r
         const WNode w = node[b];
         const int c = cluster_of(keys[w.begin], D);
         const double S = HIST ? INFINITY : cl_S[c];
-        unsigned* h = hist + (int64_t)c * kOctaves;
+        unsigned* h = hist + ((int64_t)(b % reps) * nc + c) * kOctaves;
         const double ext = box_extent(w.lo, w.hi);
         const bool big = w.count > n_crit || ext > S;
         if (lvl[b] == 0 && !big) emit_group<HIST>(w.begin, w.count, ext, h, flag, len);
@@ -524,20 +619,26 @@ __global__ void k_group_pass(const WNode* __restrict__ node, const uint64_t* __r
     }
 }
 
-// one thread per cluster: size limit from the median octave of the first pass
-__global__ void k_group_limit(const unsigned* __restrict__ hist, int nc, double* __restrict__ cl_S) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
-    const unsigned* h = hist + (int64_t)c * kOctaves;
+// one block of kOctaves threads per cluster: sums the histogram copies, then
+// the size limit from the median octave of the first pass
+__global__ __launch_bounds__(kOctaves) void k_group_limit(const unsigned* __restrict__ hist, int nc,
+                                                          int reps, double* __restrict__ cl_S) {
+    __shared__ int64_t h[kOctaves];
+    const int c = blockIdx.x, i = threadIdx.x;
+    int64_t v = 0;
+    for (int r = 0; r < reps; ++r) v += hist[((int64_t)r * nc + c) * kOctaves + i];
+    h[i] = v;
+    __syncthreads();
+    if (i != 0) return;
     int64_t total = 0;
-    for (int i = 0; i < kOctaves; ++i) total += h[i];
+    for (int k = 0; k < kOctaves; ++k) total += h[k];
     const int64_t need = (total + 1) / 2;
     int64_t cum = 0;
     int b = kOctaves - 1;
-    for (int i = 0; i < kOctaves; ++i) {
-        cum += h[i];
+    for (int k = 0; k < kOctaves; ++k) {
+        cum += h[k];
         if (cum >= need) {
-            b = i;
+            b = k;
             break;
         }
     }
@@ -668,19 +769,20 @@ void launch_groups(Dev& d, const BuildCfg& c, hipStream_t s) {
     const int64_t n = c.n;
     const unsigned long long* n_nodes = d.cnt + kCntNodes;
     const int gb = grid_for(c.node_cap, 256, 2048);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((int64_t)c.n_clusters * kOctaves, 256)), dim3(256), 0, s,
-                       d.g_hist, (int64_t)c.n_clusters * kOctaves);
+    const int reps = group_hist_reps(c.n_clusters);
+    const int64_t hist_len = (int64_t)reps * c.n_clusters * kOctaves;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(hist_len, 256)), dim3(256), 0, s, d.g_hist, hist_len);
     hipLaunchKernelGGL(k_group_pass<true>, dim3(gb), dim3(256), 0, s, (const WNode*)d.node,
                        (const uint64_t*)d.lvl_key, n_nodes, (const uint64_t*)d.keys, c.D, c.n_crit,
                        (const double*)d.x, (const double*)d.y, (const double*)d.z,
-                       (const double*)d.cl_S, d.g_hist, d.g_flag, d.g_len);
-    hipLaunchKernelGGL(k_group_limit, dim3((c.n_clusters + 63) / 64), dim3(64), 0, s,
-                       (const unsigned*)d.g_hist, c.n_clusters, d.cl_S);
+                       (const double*)d.cl_S, d.g_hist, c.n_clusters, reps, d.g_flag, d.g_len);
+    hipLaunchKernelGGL(k_group_limit, dim3(c.n_clusters), dim3(kOctaves), 0, s,
+                       (const unsigned*)d.g_hist, c.n_clusters, reps, d.cl_S);
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, d.g_flag, n + 1, 0);
     hipLaunchKernelGGL(k_group_pass<false>, dim3(gb), dim3(256), 0, s, (const WNode*)d.node,
                        (const uint64_t*)d.lvl_key, n_nodes, (const uint64_t*)d.keys, c.D, c.n_crit,
                        (const double*)d.x, (const double*)d.y, (const double*)d.z,
-                       (const double*)d.cl_S, d.g_hist, d.g_flag, d.g_len);
+                       (const double*)d.cl_S, d.g_hist, c.n_clusters, reps, d.g_flag, d.g_len);
     exclusive_scan_i32(d.g_flag, d.g_flag, n, d.scan_tmp, s);   // g_flag[n] = group count
     hipLaunchKernelGGL(k_group_fill, dim3(grid_for(n, 256)), dim3(256), 0, s,
                        (const int32_t*)d.g_flag, (const int32_t*)d.g_len, (const uint64_t*)d.keys,

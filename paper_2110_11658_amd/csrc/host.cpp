@@ -139,10 +139,11 @@ pbh_status ensure_buffers(pbh_ctx* ctx) {
               dalloc(ctx, &d.lvl_off, 32) && dalloc(ctx, &d.node, cap) &&
               dalloc(ctx, &d.q64, cap) && dalloc(ctx, &d.q32, cap) &&
               dalloc(ctx, &d.g_flag, n + 1) && dalloc(ctx, &d.g_len, n) &&
-              dalloc(ctx, &d.g_hist, 128 * C) && dalloc(ctx, &d.cl_S, C) &&
+              dalloc(ctx, &d.g_hist, (int64_t)128 * C * group_hist_reps((int)C)) && dalloc(ctx, &d.cl_S, C) &&
               dalloc(ctx, &d.g.begin, G) && dalloc(ctx, &d.g.count, G) &&
               dalloc(ctx, &d.g.root, G) && dalloc(ctx, &d.g.cluster, G) &&
-              dalloc(ctx, &d.g.lo, 3 * G) && dalloc(ctx, &d.g.hi, 3 * G) &&
+              dalloc(ctx, &d.g.lo, 3 * G) && dalloc(ctx, &d.g.hi, 3 * G) && dalloc(ctx, &d.fill_list, G) &&
+              dalloc(ctx, &d.stage_k, n) &&
               dalloc(ctx, &d.scan_tmp, scan_len) &&
               dalloc(ctx, &d.rs_hist, radix_hist_need(big) + 1) && dalloc(ctx, &d.nbr_cnt, n) &&
               dalloc(ctx, &d.stack, stack) && dalloc(ctx, &d.cnt, kNumCounters) &&
@@ -159,6 +160,42 @@ pbh_status ensure_buffers(pbh_ctx* ctx) {
     ctx->a_n = n; ctx->a_cap = cap; ctx->a_G = G; ctx->a_C = C; ctx->a_nblk = nblk;
     ctx->a_stack = stack;
     return PBH_OK;
+}
+
+// Neighbour staging rows: `cap` entries per particle, within a fixed memory
+// budget (a particle of a Plummer core holds about 5.4x the mean count; 512
+// covers a mean of 64). Returns the row size in use, 0 when staging is off
+// (too little memory: every list then goes through the fill pass).
+constexpr int64_t kStageBudgetBytes = 8ll << 30;
+constexpr int kStageMaxCap = 512;
+constexpr int kStageMinCap = 32;
+
+int ensure_stage(pbh_ctx* ctx) {
+    Dev& d = ctx->d;
+    const int64_t n = std::max<int64_t>(ctx->cfg.n, 1);
+    int64_t cap = kStageBudgetBytes / (4 * n);
+    if (cap > kStageMaxCap) cap = kStageMaxCap;
+    cap &= ~(int64_t)31;
+    if (cap < kStageMinCap) return 0;
+    const int64_t need = ((n + kStageStride - 1) / kStageStride) * kStageStride * cap;
+    if (d.nbr_stage && d.nbr_stage_len >= need) return (int)cap;
+    if (d.nbr_stage) {
+        for (size_t k = 0; k < ctx->bufs.size(); ++k)
+            if (ctx->bufs[k].p == d.nbr_stage) {
+                (void)hipFree(ctx->bufs[k].p);
+                ctx->bufs.erase(ctx->bufs.begin() + (int64_t)k);
+                break;
+            }
+        d.nbr_stage = nullptr;
+        d.nbr_stage_len = 0;
+    }
+    if (!dalloc(ctx, &d.nbr_stage, need)) {
+        (void)hipGetLastError();   // a failed allocation is not a launch error
+        d.nbr_stage = nullptr;
+        return 0;
+    }
+    d.nbr_stage_len = need;
+    return (int)cap;
 }
 
 // Host part of a build: sizes, tables, uploads. No kernel runs here.
@@ -356,6 +393,7 @@ pbh_status do_force(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, double 
     w.grid = gmax;   // persistent: workgroups leave when the group queue is empty
     w.stack_cap = kStackCap;
     w.count_nbr = nbr_off != nullptr;   // the walk counts the neighbours of every particle
+    w.stage_cap = w.count_nbr ? ensure_stage(ctx) : 0;
     mark(ctx, 2, s);
     launch_walk(d, c, w, acc, pot, s);
     mark(ctx, 3, s);
@@ -374,6 +412,7 @@ pbh_status do_force(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, double 
                 return fail(ctx, PBH_E_NBR_OVERFLOW, "neighbour capacity " + std::to_string(nbr_cap) +
                                                          " < needed " + std::to_string(tot));
         }
+        if (w.stage_cap > 0) launch_nbr_copy(d, c, w.stage_cap, nbr_off, nbr_idx, nbr_cap, s);
         launch_nbr_fill(d, c, grid, kStackCap, nbr_off, nbr_idx, nbr_cap, s);
         mark(ctx, 5, s);
         ctx->ev_nbr = ctx->timing;
@@ -597,6 +636,7 @@ static void kdk_force(pbh_ctx* ctx, const double* pos, const double* mass, doubl
     w.grid = gmax;
     w.stack_cap = kStackCap;
     w.count_nbr = 0;
+    w.stage_cap = 0;
     launch_walk(ctx->d, ctx->cfg, w, ctx->k_acc, ctx->k_pot, s);
 }
 

@@ -9,9 +9,11 @@
 // of those leaves are staged 64 at a time in an LDS tile (FP64 position and
 // caller index, loaded lane-parallel) and every lane tests its own particle
 // against each tile entry by LDS broadcast. The tree walk (walk.hip) counts
-// the neighbours while it evaluates the near pairs; the host library scans
-// the counts into CSR offsets; this pass then writes the indices, in its own
-// deterministic traversal order (the same set the walk counted).
+// the neighbours while it evaluates the near pairs and writes them into
+// per-particle staging rows; the host library scans the counts into CSR
+// offsets. k_nbr_copy then moves the staged rows into the CSR, and
+// k_nbr_fill writes the lists of the groups whose rows overflowed, in its own
+// deterministic traversal order. Either route yields the set the walk counted.
 #include "pbh_internal.hpp"
 #include "wave.hpp"
 
@@ -31,6 +33,7 @@ struct NbrParams {
     const int32_t* g_count;
     const int32_t* g_root;
     const int32_t* g_cluster;
+    const int32_t* fill_list;      // the groups whose lists this pass writes
     const double* g_lo;
     const double* g_hi;
     const ClusterParams* cp;
@@ -79,9 +82,10 @@ __global__ __launch_bounds__(64) void k_nbr_fill(NbrParams p) {
     const unsigned long long t_start = wall_clock64();
     int n_done = 0;
     for (;;) {
-        const int64_t g = queue_next(p.queues, G, home, lane);
-        if (g < 0) break;
+        const int64_t q = queue_next(p.queues, G, home, lane);
+        if (q < 0) break;
         ++n_done;
+        const int64_t g = uni(p.fill_list[q]);
         const int gb = uni(p.g_begin[g]), gcnt = uni(p.g_count[g]), root = uni(p.g_root[g]);
         const double rout2 = p.cp[uni(p.g_cluster[g])].rout2;
         double glo[3], ghi[3];
@@ -166,15 +170,85 @@ __global__ __launch_bounds__(64) void k_nbr_fill(NbrParams p) {
     }
 }
 
+// Staged lists into the CSR. One wave per block of 64 consecutive sorted
+// particles (the interleaving unit of the staging rows); stage_k[p] = 1 if
+// the walk staged the list of p (0: the fill pass writes it). The block's
+// lists pass through an LDS tile of 32 entries per particle: entry t of all
+// 64 particles is one 256-byte load, and each store instruction writes 32
+// consecutive CSR entries of two particles (lists in caller order lie
+// scattered over the CSR; one lane per list would write 64 unrelated lines
+// per instruction). Entries beyond the caller's capacity are dropped and
+// flagged.
+constexpr int kCopyTile = 32;
+
+__global__ __launch_bounds__(64) void k_nbr_copy(int64_t n, const int8_t* __restrict__ stage_k,
+                                                 const int32_t* __restrict__ perm,
+                                                 const int32_t* __restrict__ stage, int scap,
+                                                 const int64_t* __restrict__ off,
+                                                 int32_t* __restrict__ idx, int64_t cap,
+                                                 unsigned long long* __restrict__ cnt) {
+    __shared__ int s_tile[kStageStride][kCopyTile + 1];
+    __shared__ int s_cnt[kStageStride];
+    __shared__ int64_t s_off[kStageStride];
+    const int lane = threadIdx.x;
+    const int64_t nblk = (n + kStageStride - 1) / kStageStride;
+    bool overflow = false;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int64_t i = blk * kStageStride + lane;
+        const bool staged = i < n && stage_k[i] != 0;
+        int c = 0;
+        int64_t at = 0;
+        if (staged) {
+            const int orig = perm[i];
+            at = off[orig];
+            c = (int)(off[orig + 1] - at);
+        }
+        const int32_t* row = stage + stage_index(i, 0, scap);   // inside the buffer for every lane
+        int maxc = c;
+        for (int o = 32; o > 0; o >>= 1) {
+            const int v = __shfl_xor(maxc, o, 64);
+            maxc = v > maxc ? v : maxc;
+        }
+        maxc = __builtin_amdgcn_readfirstlane(maxc);
+        __syncthreads();
+        s_cnt[lane] = c;
+        s_off[lane] = at;
+        for (int t0 = 0; t0 < maxc; t0 += kCopyTile) {
+            __syncthreads();
+            // unconditional loads (index clamped into the row) so that all of
+            // them are in flight together; unused tile entries are never read
+#pragma unroll
+            for (int u = 0; u < kCopyTile; ++u) {
+                const int t = t0 + u < c ? t0 + u : 0;
+                s_tile[lane][u] = row[(int64_t)t * kStageStride];
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int q = 0; q < kStageStride * kCopyTile / 64; ++q) {
+                const int slot = q * 64 + lane;
+                const int pp = slot / kCopyTile, u = slot % kCopyTile;
+                if (t0 + u < s_cnt[pp]) {
+                    const int64_t dst = s_off[pp] + t0 + u;
+                    if (dst < cap) idx[dst] = s_tile[pp][u];
+                    else overflow = true;
+                }
+            }
+        }
+    }
+    const uint64_t ov = __ballot(overflow);
+    if (ov) atomicOr(&cnt[kErr], lane == 0 ? kErrNbrOverflow : 0ull);
+}
+
 NbrParams make_params(Dev& d, const BuildCfg& c, int stack_cap) {
     NbrParams p;
     p.node = d.node;
     p.x = d.x; p.y = d.y; p.z = d.z;
     p.perm = d.perm;
     p.g_begin = d.g.begin; p.g_count = d.g.count; p.g_root = d.g.root; p.g_cluster = d.g.cluster;
+    p.fill_list = d.fill_list;
     p.g_lo = d.g.lo; p.g_hi = d.g.hi;
     p.cp = d.cparams;
-    p.G = d.cnt + kCntGroups;
+    p.G = d.cnt + kCntFill;
     p.off = nullptr;
     p.idx = nullptr;
     p.cap = 0;
@@ -188,6 +262,16 @@ NbrParams make_params(Dev& d, const BuildCfg& c, int stack_cap) {
 }
 
 }  // namespace
+
+void launch_nbr_copy(Dev& d, const BuildCfg& c, int stage_cap, const int64_t* off, int32_t* idx,
+                     int64_t cap, hipStream_t s) {
+    int64_t grid = (c.n + kStageStride - 1) / kStageStride;
+    if (grid > 16384) grid = 16384;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_nbr_copy, dim3((unsigned)grid), dim3(64), 0, s, c.n, (const int8_t*)d.stage_k,
+                       (const int32_t*)d.perm, (const int32_t*)d.nbr_stage, stage_cap, off, idx, cap,
+                       d.cnt);
+}
 
 void launch_nbr_fill(Dev& d, const BuildCfg& c, int grid, int stack_cap, const int64_t* off,
                      int32_t* idx, int64_t cap, hipStream_t s) {

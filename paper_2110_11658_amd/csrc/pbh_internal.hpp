@@ -35,8 +35,7 @@ enum : unsigned long long {
 
 // slots of the device counter array
 enum { kCntNodes = 0, kCntPN = 1, kCntFar = 2, kCntNear = 3, kCntNbrTotal = 4, kErr = 5,
-       kQueueWalk = 6, kQueueNbrCount = 7, kQueueNbrFill = 8, kCntMaxLevel = 9,
-       kCntLeaves = 10, kCntGroups = 12, kNumCounters = 16 };
+       kCntMaxLevel = 9, kCntLeaves = 10, kCntGroups = 12, kCntFill = 13, kNumCounters = 16 };
 
 struct alignas(16) WNode {
     double lo[3];
@@ -88,6 +87,23 @@ struct BuildCfg {
 };
 
 // Scratch and arrays of one built forest.
+// The first group pass counts groups per box-size octave with global atomics.
+// A single cluster puts all of them on a few bins; spreading them over
+// `reps` copies of the histogram (summed afterwards) removes the contention.
+inline int group_hist_reps(int n_clusters) {
+    return n_clusters >= 256 ? 1 : (n_clusters > 4 ? 256 / n_clusters : 64);
+}
+
+// Staging rows are interleaved by 64 particles: entry t of sorted particle i
+// sits at stage_index(i, t, cap). The walk's lanes append entries with
+// similar t at the same time, and the copy kernel's wave reads entry t of 64
+// consecutive particles from one 256-byte segment; rows laid end to end
+// would put every lane of a wave on its own 2 KB-strided line.
+constexpr int kStageStride = 64;
+__host__ __device__ inline int64_t stage_index(int64_t i, int t, int cap) {
+    return (i / kStageStride) * kStageStride * cap + (int64_t)t * kStageStride + (i % kStageStride);
+}
+
 struct Dev {
     // particles
     double *x = nullptr, *y = nullptr, *z = nullptr, *m = nullptr;
@@ -124,7 +140,7 @@ struct Dev {
     GroupArrays g;
     int32_t* g_flag = nullptr;   // [n+1] 1 at the first particle of a group, then scanned
     int32_t* g_len = nullptr;    // [n] group length at its first particle
-    unsigned* g_hist = nullptr;  // [C][128] octave histogram of first-pass group sizes
+    unsigned* g_hist = nullptr;  // [reps][C][128] octave histograms of first-pass group sizes
     double* cl_S = nullptr;      // [C] group size limit per cluster
     // generic scan scratch
     int64_t* scan_tmp = nullptr;
@@ -134,6 +150,14 @@ struct Dev {
     int64_t rs_hist_len = 0;
     // neighbour counts
     int32_t* nbr_cnt = nullptr;
+    // neighbour staging: the walk writes every particle's list into a row of
+    // stage_cap entries (per-copy sub-rows in split groups); stage_k[p] is the
+    // group's copy count, or 0 when the group's lists are left to the fill pass,
+    // whose groups are listed in fill_list[0 .. cnt[kCntFill])
+    int32_t* nbr_stage = nullptr;   // layout: stage_index()
+    int64_t nbr_stage_len = 0;
+    int8_t* stage_k = nullptr;     // [n]
+    int32_t* fill_list = nullptr;  // [G]
     // walk stacks
     int32_t* stack = nullptr;
     int64_t stack_len = 0;
@@ -177,6 +201,7 @@ struct WalkCfg {
     int grid;
     int stack_cap;
     int count_nbr;   // also count neighbours per particle into Dev::nbr_cnt
+    int stage_cap;   // > 0: stage neighbour indices in Dev::nbr_stage rows of this size
 };
 void launch_rcrit(Dev& d, const BuildCfg& c, double theta, hipStream_t s);
 void launch_walk(Dev& d, const BuildCfg& c, const WalkCfg& w, double* acc, double* pot,
@@ -184,6 +209,8 @@ void launch_walk(Dev& d, const BuildCfg& c, const WalkCfg& w, double* acc, doubl
 int walk_blocks_per_cu(int mixed);
 
 // nbr.hip
+void launch_nbr_copy(Dev& d, const BuildCfg& c, int stage_cap, const int64_t* off, int32_t* idx,
+                     int64_t cap, hipStream_t s);
 void launch_nbr_fill(Dev& d, const BuildCfg& c, int grid, int stack_cap, const int64_t* off,
                      int32_t* idx, int64_t cap, hipStream_t s);
 

@@ -37,7 +37,7 @@ struct alignas(16) Tiles {
     R pn[TCAP][12];      // cx cy cz M | qxx qyy qzz qxy | qxz qyz - -
     R far[TCAP][4];      // x y z m (relative to the group centre)
     R nearp[TCAP][4];
-    int nearj[TCAP];     // sorted index, to skip the self pair
+    int nearj[TCAP];     // caller index: skips the self pair, and is the neighbour index
     double nx[TCAP], ny[TCAP], nz[TCAP];   // near entries in FP64 (neighbour test)
     int lf_ex[64];       // leaf expansion: exclusive prefix of particle counts
     int lf_beg[64];
@@ -70,6 +70,10 @@ struct WalkParams {
     unsigned long long* queues;     // [kQueues] group queue heads
     unsigned long long* wave_log;   // per workgroup: groups walked, clock ticks
     int32_t* nbr_cnt;               // neighbour counts per caller index, or null
+    int32_t* stage;                 // neighbour staging rows per sorted particle, or null
+    int scap;                       // entries per staging row
+    int8_t* stage_k;                // per sorted particle: 1 = list staged, 0 = left to the fill pass
+    int32_t* fill_list;             // groups left to the fill pass
 };
 
 __device__ inline void two_sum_acc(float& hi, float& lo, float v) {
@@ -86,11 +90,22 @@ struct Acc;
 template <>
 struct Acc<float> {
     float hx = 0, hy = 0, hz = 0, hp = 0, lx = 0, ly = 0, lz = 0, lp = 0;
+    static constexpr int kWords = 8;
     __device__ void add(float ax, float ay, float az, float ph) {
         two_sum_acc(hx, lx, ax);
         two_sum_acc(hy, ly, ay);
         two_sum_acc(hz, lz, az);
         two_sum_acc(hp, lp, ph);
+    }
+    __device__ void store(float* w) const {
+        w[0] = hx; w[1] = lx; w[2] = hy; w[3] = ly; w[4] = hz; w[5] = lz; w[6] = hp; w[7] = lp;
+    }
+    // adds another (hi, lo) set: TwoSum of the high parts, plain sum of the low parts
+    __device__ void merge(const float* w) {
+        two_sum_acc(hx, lx, w[0]); lx += w[1];
+        two_sum_acc(hy, ly, w[2]); ly += w[3];
+        two_sum_acc(hz, lz, w[4]); lz += w[5];
+        two_sum_acc(hp, lp, w[6]); lp += w[7];
     }
     __device__ double gx() const { return (double)hx + (double)lx; }
     __device__ double gy() const { return (double)hy + (double)ly; }
@@ -101,9 +116,12 @@ struct Acc<float> {
 template <>
 struct Acc<double> {
     double x = 0, y = 0, z = 0, p = 0;
+    static constexpr int kWords = 4;
     __device__ void add(double ax, double ay, double az, double ph) {
         x += ax; y += ay; z += az; p += ph;
     }
+    __device__ void store(double* w) const { w[0] = x; w[1] = y; w[2] = z; w[3] = p; }
+    __device__ void merge(const double* w) { x += w[0]; y += w[1]; z += w[2]; p += w[3]; }
     __device__ double gx() const { return x; }
     __device__ double gy() const { return y; }
     __device__ double gz() const { return z; }
@@ -115,13 +133,31 @@ __device__ inline double rsq(double v) { return rsqrt(v); }
 __device__ inline float lnr(float v) { return __logf(v); }
 __device__ inline double lnr(double v) { return log(v); }
 
+// Sub-wave split of the tile entries. A group of g <= 32 particles occupies
+// ksub = 64 / g copies of itself in the wave (lane = sub * g + particle); the
+// copy `sub` evaluates tile entries sub, sub + ksub, sub + 2 ksub, ... and the
+// copies' partial sums are merged once per group. ksub = 1 is the plain
+// one-particle-per-lane walk. `body(e)` evaluates entry e for this lane.
+template <int U, typename F>
+__device__ inline void for_entries(int cnt, int ksub, int sub, F&& body) {
+    if (ksub == 1) {
+#pragma unroll U
+        for (int e = 0; e < cnt; ++e) body(e);
+    } else {
+        const int nfull = cnt - cnt % ksub;
+#pragma unroll 1
+        for (int e2 = 0; e2 < nfull; e2 += ksub) body(e2 + sub);
+        if (nfull + sub < cnt) body(nfull + sub);
+    }
+}
+
 // Monopole + traceless quadrupole: phi = -M/s - (R^T Q R)/(2 s^5), a = -grad phi
 //   a = -(M/s^3 + (5/2) (R^T Q R)/s^7) R + Q R / s^5,   R = x_i - COM
 template <typename R>
-__device__ inline void eval_pn(const Tiles<R>& T, int cnt, R px, R py, R pz, R eps2, Acc<R>& A) {
+__device__ inline void eval_pn(const Tiles<R>& T, int cnt, int ksub, int sub, R px, R py, R pz, R eps2,
+                               Acc<R>& A) {
     R ax = 0, ay = 0, az = 0, ph = 0;
-#pragma unroll 2
-    for (int e = 0; e < cnt; ++e) {
+    for_entries<2>(cnt, ksub, sub, [&](int e) {
         const R* q = T.pn[e];
         const R Rx = px - q[0], Ry = py - q[1], Rz = pz - q[2];
         const R s2 = Rx * Rx + Ry * Ry + Rz * Rz + eps2;
@@ -139,7 +175,7 @@ __device__ inline void eval_pn(const Tiles<R>& T, int cnt, R px, R py, R pz, R e
         ay += cr * Ry + qy * inv5;
         az += cr * Rz + qz * inv5;
         ph += -q[3] * inv - R(0.5) * rqr * inv5;
-    }
+    });
     A.add(ax, ay, az, ph);
 }
 
@@ -147,11 +183,10 @@ __device__ inline void eval_pn(const Tiles<R>& T, int cnt, R px, R py, R pz, R e
 //   t = R^T Q R / s^5,  cr = M/s^3 + 2.5 t / s^2,  a += Q R / s^5 - cr R,
 //   phi += -M/s - t/2.
 template <>
-__device__ inline void eval_pn<float>(const Tiles<float>& T, int cnt, float px, float py, float pz,
-                                      float eps2, Acc<float>& A) {
+__device__ inline void eval_pn<float>(const Tiles<float>& T, int cnt, int ksub, int sub, float px,
+                                      float py, float pz, float eps2, Acc<float>& A) {
     float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
-#pragma unroll 4
-    for (int e = 0; e < cnt; ++e) {
+    for_entries<4>(cnt, ksub, sub, [&](int e) {
         const float4 a = *reinterpret_cast<const float4*>(&T.pn[e][0]);   // cx cy cz M
         const float4 b = *reinterpret_cast<const float4*>(&T.pn[e][4]);   // qxx qyy qzz qxy
         const float2 c = *reinterpret_cast<const float2*>(&T.pn[e][8]);   // qxz qyz
@@ -171,16 +206,16 @@ __device__ inline void eval_pn<float>(const Tiles<float>& T, int cnt, float px, 
         ay = fmaf(-cr, Ry, fmaf(qy, inv5, ay));
         az = fmaf(-cr, Rz, fmaf(qz, inv5, az));
         ph = fmaf(-a.w, inv, fmaf(-0.5f, t, ph));
-    }
+    });
     A.add(ax, ay, az, ph);
 }
 
 // Pairs of far leaves: every pair is at r >= r_out, where W = 1.
 template <typename R>
-__device__ inline void eval_far(const Tiles<R>& T, int cnt, R px, R py, R pz, R eps2, Acc<R>& A) {
+__device__ inline void eval_far(const Tiles<R>& T, int cnt, int ksub, int sub, R px, R py, R pz, R eps2,
+                                Acc<R>& A) {
     R ax = 0, ay = 0, az = 0, ph = 0;
-#pragma unroll 4
-    for (int e = 0; e < cnt; ++e) {
+    for_entries<4>(cnt, ksub, sub, [&](int e) {
         const R* q = T.far[e];
         const R dx = q[0] - px, dy = q[1] - py, dz = q[2] - pz;
         const R s2 = dx * dx + dy * dy + dz * dz + eps2;
@@ -191,16 +226,15 @@ __device__ inline void eval_far(const Tiles<R>& T, int cnt, R px, R py, R pz, R 
         ay += mi3 * dy;
         az += mi3 * dz;
         ph -= mi;
-    }
+    });
     A.add(ax, ay, az, ph);
 }
 
 template <>
-__device__ inline void eval_far<float>(const Tiles<float>& T, int cnt, float px, float py, float pz,
-                                       float eps2, Acc<float>& A) {
+__device__ inline void eval_far<float>(const Tiles<float>& T, int cnt, int ksub, int sub, float px,
+                                       float py, float pz, float eps2, Acc<float>& A) {
     float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
-#pragma unroll 4
-    for (int e = 0; e < cnt; ++e) {
+    for_entries<4>(cnt, ksub, sub, [&](int e) {
         const float4 q = *reinterpret_cast<const float4*>(&T.far[e][0]);
         const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
         const float s2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
@@ -211,7 +245,7 @@ __device__ inline void eval_far<float>(const Tiles<float>& T, int cnt, float px,
         ay = fmaf(mi3, dy, ay);
         az = fmaf(mi3, dz, az);
         ph -= mi;
-    }
+    });
     A.add(ax, ay, az, ph);
 }
 
@@ -234,16 +268,22 @@ __device__ inline bool is_neighbour(double xj, double yj, double zj, double xi, 
 
 // Pairs of near leaves: changeover weight W(s) and the regular potential;
 // optionally also counts the neighbours inside r_out (FP64 test).
+// optionally also stores them in the lane's staging row (`srow`, at most
+// `scap` entries, kStageStride apart).
 template <typename R>
-__device__ inline void eval_near(const Tiles<R>& T, int cnt, R px, R py, R pz, R eps2, int self,
-                                 const NearK<R>& K, Acc<R>& A, bool count_nbr, double xi, double yi,
-                                 double zi, double rout2, int& nbr) {
+__device__ inline void eval_near(const Tiles<R>& T, int cnt, int ksub, int sub, R px, R py, R pz, R eps2,
+                                 int self, const NearK<R>& K, Acc<R>& A, bool count_nbr, double xi,
+                                 double yi, double zi, double rout2, int& nbr, int32_t* srow, int scap) {
     R ax = 0, ay = 0, az = 0, ph = 0;
-    for (int e = 0; e < cnt; ++e) {
+    for_entries<1>(cnt, ksub, sub, [&](int e) {
         const R* q = T.nearp[e];
-        const bool is_self = T.nearj[e] == self;
-        if (count_nbr)
-            nbr += (!is_self && is_neighbour(T.nx[e], T.ny[e], T.nz[e], xi, yi, zi, rout2)) ? 1 : 0;
+        const int oj = T.nearj[e];
+        const bool is_self = oj == self;
+        if (count_nbr) {
+            const bool nb = !is_self && is_neighbour(T.nx[e], T.ny[e], T.nz[e], xi, yi, zi, rout2);
+            if (nb && nbr < scap) srow[nbr * kStageStride] = oj;
+            nbr += nb ? 1 : 0;
+        }
         const R dx = q[0] - px, dy = q[1] - py, dz = q[2] - pz;
         const R s2 = dx * dx + dy * dy + dz * dz + eps2;
         const R inv = rsq(s2);
@@ -261,7 +301,7 @@ __device__ inline void eval_near(const Tiles<R>& T, int cnt, R px, R py, R pz, R
         if (K.pole) mid += -K.d0 * inv + K.l1 * lnr(s);
         const R phi = s >= K.r_out ? -inv : (s < K.r_in ? K.inner : mid);
         ph += is_self ? R(0) : q[3] * phi;
-    }
+    });
     A.add(ax, ay, az, ph);
 }
 
@@ -269,16 +309,21 @@ __device__ inline void eval_near(const Tiles<R>& T, int cnt, R px, R py, R pz, R
 // terms (-d0/s + l1 ln s, present when r_in > 0) are compile-time switches,
 // ln s = log2(s) ln 2, and the boundary cases of W and Phi_R are selects.
 template <bool CNT, bool POLE>
-__device__ inline void eval_near_f32(const Tiles<float>& T, int cnt, float px, float py, float pz,
-                                     float eps2, int self, const NearK<float>& K, Acc<float>& A,
-                                     double xi, double yi, double zi, double rout2, int& nbr) {
+__device__ inline void eval_near_f32(const Tiles<float>& T, int cnt, int ksub, int sub, float px,
+                                     float py, float pz, float eps2, int self, const NearK<float>& K,
+                                     Acc<float>& A, double xi, double yi, double zi, double rout2,
+                                     int& nbr, int32_t* srow, int scap) {
     float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
     const float l1 = K.l1 * 0.693147180559945309f;
-#pragma unroll 2
-    for (int e = 0; e < cnt; ++e) {
+    for_entries<2>(cnt, ksub, sub, [&](int e) {
         const float4 q = *reinterpret_cast<const float4*>(&T.nearp[e][0]);
-        const bool other = T.nearj[e] != self;
-        if (CNT) nbr += (other & is_neighbour(T.nx[e], T.ny[e], T.nz[e], xi, yi, zi, rout2)) ? 1 : 0;
+        const int oj = T.nearj[e];
+        const bool other = oj != self;
+        if (CNT) {
+            const bool nb = other & is_neighbour(T.nx[e], T.ny[e], T.nz[e], xi, yi, zi, rout2);
+            if (nb & (nbr < scap)) srow[nbr * kStageStride] = oj;
+            nbr += nb ? 1 : 0;
+        }
         const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
         const float s2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
         const float inv = __builtin_amdgcn_rsqf(s2);
@@ -300,21 +345,25 @@ __device__ inline void eval_near_f32(const Tiles<float>& T, int cnt, float px, f
         if (POLE) mid = fmaf(-K.d0, inv, fmaf(l1, __builtin_amdgcn_logf(s), mid));
         const float phi = outer ? -inv : (inner ? K.inner : mid);
         ph = other ? fmaf(q.w, phi, ph) : ph;
-    }
+    });
     A.add(ax, ay, az, ph);
 }
 
 template <>
-__device__ inline void eval_near<float>(const Tiles<float>& T, int cnt, float px, float py, float pz,
-                                        float eps2, int self, const NearK<float>& K, Acc<float>& A,
-                                        bool count_nbr, double xi, double yi, double zi, double rout2,
-                                        int& nbr) {
+__device__ inline void eval_near<float>(const Tiles<float>& T, int cnt, int ksub, int sub, float px,
+                                        float py, float pz, float eps2, int self, const NearK<float>& K,
+                                        Acc<float>& A, bool count_nbr, double xi, double yi, double zi,
+                                        double rout2, int& nbr, int32_t* srow, int scap) {
     if (count_nbr) {
-        if (K.pole) eval_near_f32<true, true>(T, cnt, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr);
-        else eval_near_f32<true, false>(T, cnt, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr);
+        if (K.pole)
+            eval_near_f32<true, true>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr, srow, scap);
+        else
+            eval_near_f32<true, false>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr, srow, scap);
     } else {
-        if (K.pole) eval_near_f32<false, true>(T, cnt, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr);
-        else eval_near_f32<false, false>(T, cnt, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr);
+        if (K.pole)
+            eval_near_f32<false, true>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr, srow, scap);
+        else
+            eval_near_f32<false, false>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr, srow, scap);
     }
 }
 
@@ -358,9 +407,26 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
         }
         K.pole = cp.d0 != 0.0;
 
+        // sub-wave copies of a small group (see for_entries); lanes beyond
+        // ksub * gcnt duplicate copy 0 and are ignored at the merge
+        const int ksub = 64 / gcnt;
+        const int copy = lane / gcnt;
+        const int pl = lane - copy * gcnt;
+        const int sub = copy < ksub ? copy : 0;
         const bool active = lane < gcnt;
-        const int me = gb + (active ? lane : 0);
+        const int me = gb + pl;
         const double xi = p.x[me], yi = p.y[me], zi = p.z[me];
+        const int orig_me = p.perm[me];
+        // Neighbour staging. A particle's row holds p.scap entries; an unsplit
+        // group uses it whole, a split group gives each copy a sub-row of
+        // wrow = p.scap / ksub entries (joined into one list after the walk).
+        // Lanes that repeat copy 0 store nothing (scap = 0).
+        const bool real = copy < ksub;
+        const int wrow = p.scap / ksub;
+        const int scap = (p.stage == nullptr || !real) ? 0 : (ksub == 1 ? p.scap : wrow);
+        int32_t* srow = p.stage != nullptr
+                            ? p.stage + stage_index(me, (ksub == 1 ? 0 : sub * wrow), p.scap)
+                            : nullptr;
         const R px = (R)(xi - ctr[0]);
         const R py = (R)(yi - ctr[1]);
         const R pz = (R)(zi - ctr[2]);
@@ -394,7 +460,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                 const int k = uni(__popcll(mk));
                 if (npn + k > TCAP) {
                     __syncthreads();
-                    eval_pn<R>(T, npn, px, py, pz, eps2, A);
+                    eval_pn<R>(T, npn, ksub, sub, px, py, pz, eps2, A);
                     npn = 0;
                     __syncthreads();
                 }
@@ -452,8 +518,8 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                     const int add = (total - base) < 64 ? (total - base) : 64;
                     if (fill + add > TCAP) {
                         __syncthreads();
-                        if (cls == 0) eval_far<R>(T, fill, px, py, pz, eps2, A);
-                        else eval_near<R>(T, fill, px, py, pz, eps2, me, K, A, count_nbr, xi, yi, zi, rout2, nbr);
+                        if (cls == 0) eval_far<R>(T, fill, ksub, sub, px, py, pz, eps2, A);
+                        else eval_near<R>(T, fill, ksub, sub, px, py, pz, eps2, orig_me, K, A, count_nbr, xi, yi, zi, rout2, nbr, srow, scap);
                         fill = 0;
                         __syncthreads();
                     }
@@ -464,7 +530,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                         e[2] = (R)(p.z[j] - ctr[2]);
                         e[3] = (R)p.m[j];
                         if (cls == 1) {
-                            T.nearj[fill + lane] = j;
+                            T.nearj[fill + lane] = p.perm[j];
                             T.nx[fill + lane] = p.x[j];
                             T.ny[fill + lane] = p.y[j];
                             T.nz[fill + lane] = p.z[j];
@@ -476,14 +542,61 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
             }
         }
         __syncthreads();
-        if (npn) eval_pn<R>(T, npn, px, py, pz, eps2, A);
-        if (nfar) eval_far<R>(T, nfar, px, py, pz, eps2, A);
-        if (nnear) eval_near<R>(T, nnear, px, py, pz, eps2, me, K, A, count_nbr, xi, yi, zi, rout2, nbr);
+        if (npn) eval_pn<R>(T, npn, ksub, sub, px, py, pz, eps2, A);
+        if (nfar) eval_far<R>(T, nfar, ksub, sub, px, py, pz, eps2, A);
+        if (nnear) eval_near<R>(T, nnear, ksub, sub, px, py, pz, eps2, orig_me, K, A, count_nbr, xi, yi, zi, rout2, nbr, srow, scap);
         __syncthreads();
 
+        // a row that overflowed sends the group's lists to the fill pass
+        const bool row_full = count_nbr && real && nbr > scap;
+        const bool need_fill = count_nbr && (p.stage == nullptr || __ballot(row_full) != 0);
+        if (ksub > 1) {
+            // merge the copies' partial sums in copy order, into copy 0
+            R* red = &T.pn[0][0];
+            constexpr int W = Acc<R>::kWords + 1;   // odd stride: no LDS bank conflicts
+            A.store(red + W * lane);
+            T.nearj[lane] = nbr;
+            __syncthreads();
+            // (the barrier also makes the copies' staged entries visible)
+            if (active) {
+                const bool join = count_nbr && !need_fill;
+                int32_t* base = join ? p.stage + stage_index(me, 0, p.scap) : nullptr;
+                for (int c = 1; c < ksub; ++c) {
+                    A.merge(red + W * (c * gcnt + lane));
+                    const int nc = T.nearj[c * gcnt + lane];
+                    // move copy c's sub-row down to follow the list so far;
+                    // targets lie below sources, loads of a batch precede its stores
+                    if (join) {
+                        for (int t0 = 0; t0 < nc; t0 += 8) {
+                            int v[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const int t = t0 + u < nc ? t0 + u : nc - 1;
+                                v[u] = base[(int64_t)(c * wrow + t) * kStageStride];
+                            }
+#pragma unroll
+                            for (int u = 0; u < 8; ++u)
+                                if (t0 + u < nc) base[(int64_t)(nbr + t0 + u) * kStageStride] = v[u];
+                        }
+                    }
+                    nbr += nc;
+                }
+            }
+            __syncthreads();
+        }
         if (overflow) atomicOr(&p.cnt[kErr], lane == 0 ? kErrWalkStack : 0ull);
+        if (count_nbr) {
+            // lists this walk did not stage completely go to the fill pass
+            if (need_fill) {
+                // all lanes issue the atomic (lane 0 adds 1): no lane-0-only branch
+                const unsigned long long slot =
+                    atomicAdd(&p.cnt[kCntFill], lane == 0 ? 1ull : 0ull);
+                if (lane == 0) p.fill_list[slot] = (int32_t)g;
+            }
+            if (active) p.stage_k[me] = (int8_t)(need_fill ? 0 : 1);
+        }
         if (active) {
-            const int orig = p.perm[gb + lane];
+            const int orig = orig_me;
             if (count_nbr) p.nbr_cnt[orig] = nbr;
             p.acc[3 * (int64_t)orig] = A.gx();
             p.acc[3 * (int64_t)orig + 1] = A.gy();
@@ -511,7 +624,7 @@ __global__ void k_rcrit(WNode* __restrict__ node, const unsigned long long* __re
     const int64_t n = (int64_t)*n_dev;
     if (blockIdx.x == 0 && threadIdx.x < 3 * kQueues) queues[threadIdx.x] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        cnt[kCntPN] = 0; cnt[kCntFar] = 0; cnt[kCntNear] = 0;
+        cnt[kCntPN] = 0; cnt[kCntFar] = 0; cnt[kCntNear] = 0; cnt[kCntFill] = 0;
     }
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n;
          b += (int64_t)gridDim.x * blockDim.x) {
@@ -565,6 +678,10 @@ void launch_walk(Dev& d, const BuildCfg& c, const WalkCfg& w, double* acc, doubl
     p.queues = d.queues;
     p.wave_log = d.wave_log;
     p.nbr_cnt = w.count_nbr ? d.nbr_cnt : nullptr;
+    p.stage = (w.count_nbr && w.stage_cap > 0) ? d.nbr_stage : nullptr;
+    p.scap = w.stage_cap;
+    p.stage_k = d.stage_k;
+    p.fill_list = d.fill_list;
     if (w.mixed) hipLaunchKernelGGL(k_walk<true>, dim3(w.grid), dim3(64), 0, s, p);
     else hipLaunchKernelGGL(k_walk<false>, dim3(w.grid), dim3(64), 0, s, p);
 }

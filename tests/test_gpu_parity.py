@@ -224,6 +224,31 @@ def test_lattice_ties():
         _sets_equal(off.cpu().numpy(), idx.cpu().numpy(), o_off, o_idx)
 
 
+def test_neighbour_routes():
+    # Lists reach the CSR by two routes: rows the walk staged (whole rows, or
+    # per-copy sub-rows of split groups) and the fill traversal (groups with a
+    # list longer than its row). A clump where every member has ~1500
+    # neighbours overflows the rows, a sparse halo gives split groups, and the
+    # Plummer body is staged; every route must give the oracle's sets.
+    rng = np.random.default_rng(11)
+    r_out = 0.05
+    body = ic.plummer(6000, seed=12).pos
+    clump = rng.uniform(-1.0, 1.0, size=(1500, 3)) * (r_out / 4) + 0.3
+    halo = rng.normal(size=(300, 3)) * 5.0
+    pos = np.ascontiguousarray(np.concatenate([body, clump, halo]))
+    mass = np.full(pos.shape[0], 1.0 / pos.shape[0])
+    print(f"routes n={pos.shape[0]}", flush=True)
+    p = _pbh(leaf_size=8, n_crit=64)
+    _, _, off, idx = _run(p, type("C", (), {"pos": pos, "mass": mass})(), 0.1 * r_out, r_out, 0.5, 0.0)
+    o_off, o_idx = oracle.nbr_brute(pos, r_out)
+    assert o_off[-1] > 1500 * 1499
+    _sets_equal(off, idx, o_off, o_idx)
+    _, nb = p.debug_wave_log()
+    filled = int(nb[:, 0].sum())
+    n_groups = p.stats()["n_groups"]
+    assert 0 < filled < n_groups, (filled, n_groups)
+
+
 # ---------------------------------------------------------------- error paths
 def test_error_paths():
     from paper_2110_11658_amd._lib import (PBH_E_ARG, PBH_E_NBR_OVERFLOW, PBH_E_NONFINITE,
