@@ -254,6 +254,10 @@ struct NearK {
     R r_in, r_out, inv_delta, c0, d0, l1, inner;
     R e[6];
     bool pole;   // r_in > 0: the -d0/s and log terms are present
+    // FP32 neighbour pre-test (mixed path): r_out^2 in FP32 and the half-width
+    // of the band around it inside which the FP64 test decides (infinite:
+    // always FP64)
+    float rout2f, band;
 };
 
 // Neighbour test of the CSR lists: r^2 < r_out^2 in FP64 from the original
@@ -319,13 +323,22 @@ __device__ inline void eval_near_f32(const Tiles<float>& T, int cnt, int ksub, i
         const float4 q = *reinterpret_cast<const float4*>(&T.nearp[e][0]);
         const int oj = T.nearj[e];
         const bool other = oj != self;
+        const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const float s2 = r2 + eps2;
         if (CNT) {
-            const bool nb = other & is_neighbour(T.nx[e], T.ny[e], T.nz[e], xi, yi, zi, rout2);
+            // FP32 decides outside the band (where it provably agrees with the
+            // FP64 definition), the FP64 test inside it
+            const float dr = r2 - K.rout2f;
+            const bool band = fabsf(dr) <= K.band;
+            bool nb = dr < 0.f;
+            if (__ballot(band)) {
+                if (band) nb = is_neighbour(T.nx[e], T.ny[e], T.nz[e], xi, yi, zi, rout2);
+            }
+            nb = nb & other;
             if (nb & (nbr < scap)) srow[nbr * kStageStride] = oj;
             nbr += nb ? 1 : 0;
         }
-        const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
-        const float s2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
         const float inv = __builtin_amdgcn_rsqf(s2);
         const float s = s2 > 0.f ? s2 * inv : 0.f;
         const float xx = (s - K.r_in) * K.inv_delta;
@@ -406,6 +419,19 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
             for (int k = 0; k < 6; ++k) K.e[k] = cp.e[k];
         }
         K.pole = cp.d0 != 0.0;
+        {
+            // Band of the FP32 neighbour pre-test. Relative coordinates are FP64
+            // differences rounded once to FP32, so with |p| <= h (group box half
+            // side) and a pair at r <= 2 r_out each component of d errs by at most
+            // 2^-24 (2h + 2.01 r); with h <= 64 r_out the error of r^2 (squares,
+            // FMA rounding, r_out^2 in FP32) stays below 928 * 2^-24 r_out^2, and
+            // for r > 2 r_out far below r^2 - r_out^2. The band is 2048 * 2^-24
+            // r_out^2; larger groups always take the FP64 test.
+            double h = 0.0;
+            for (int k = 0; k < 3; ++k) h = fmax(h, (ghi[k] - glo[k]) * 0.5);
+            K.rout2f = (float)rout2;
+            K.band = (h <= 64.0 * cp.r_out) ? (float)(2048.0 * 0x1p-24 * rout2) : INFINITY;
+        }
 
         // sub-wave copies of a small group (see for_entries); lanes beyond
         // ksub * gcnt duplicate copy 0 and are ignored at the merge

@@ -249,6 +249,29 @@ def test_neighbour_routes():
     assert 0 < filled < n_groups, (filled, n_groups)
 
 
+@pytest.mark.parametrize("spread", [1.0, 300.0])
+def test_neighbour_boundary_pairs(spread):
+    # Pairs separated by r_out (1 + u 1e-6): the mixed walk decides most pairs
+    # in FP32 and those within a rounding band of r_out in FP64; the sets must
+    # equal the FP64 definition's. spread = 300 puts the pairs in sparse,
+    # large groups (box half-side > 64 r_out), which always take the FP64 test.
+    rng = np.random.default_rng(21)
+    r_out = 0.01
+    m = 1500
+    centres = rng.uniform(-1.0, 1.0, size=(m, 3)) * spread * r_out * 20
+    d = rng.normal(size=(m, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    sep = r_out * (1.0 + rng.uniform(-1.0, 1.0, size=m) * 1e-6)
+    pos = np.ascontiguousarray(np.concatenate([centres, centres + d * sep[:, None]]))
+    mass = np.full(pos.shape[0], 1.0 / pos.shape[0])
+    print(f"boundary pairs spread={spread}", flush=True)
+    p = _pbh(prec="mixed", leaf_size=8, n_crit=64)
+    _, _, off, idx = _run(p, type("C", (), {"pos": pos, "mass": mass})(), 0.1 * r_out, r_out, 0.5, 0.0)
+    o_off, o_idx = oracle.nbr_brute(pos, r_out)
+    assert o_off[-1] > 0
+    _sets_equal(off, idx, o_off, o_idx)
+
+
 # ---------------------------------------------------------------- error paths
 def test_error_paths():
     from paper_2110_11658_amd._lib import (PBH_E_ARG, PBH_E_NBR_OVERFLOW, PBH_E_NONFINITE,
