@@ -326,10 +326,22 @@ __device__ inline void eval_near_f32(const Tiles<float>& T, int cnt, int ksub, i
         const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         const float s2 = r2 + eps2;
+        const float dr = r2 - K.rout2f;
+        if (__ballot(dr <= K.band) == 0) {
+            // every lane's pair lies beyond r_out by more than the rounding band:
+            // no neighbour, W = 1 and Phi_R = -1/s (the far-pair formula)
+            const float inv = __builtin_amdgcn_rsqf(s2);
+            const float mi = q.w * inv;
+            const float mi3 = mi * (inv * inv);
+            ax = fmaf(mi3, dx, ax);
+            ay = fmaf(mi3, dy, ay);
+            az = fmaf(mi3, dz, az);
+            ph -= mi;
+            return;
+        }
         if (CNT) {
             // FP32 decides outside the band (where it provably agrees with the
             // FP64 definition), the FP64 test inside it
-            const float dr = r2 - K.rout2f;
             const bool band = fabsf(dr) <= K.band;
             bool nb = dr < 0.f;
             if (__ballot(band)) {
