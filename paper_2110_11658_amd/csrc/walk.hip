@@ -32,13 +32,25 @@ namespace {
 
 constexpr int TCAP = 64;    // tile capacity; a tile is evaluated before it would overflow
 
+// Near entries of the FP64 walk keep their original coordinates for the
+// neighbour test; the mixed walk keeps the sorted index instead and reads the
+// coordinates from global memory in the rare case the FP64 test is needed
+// (10 KB of LDS per wave: 16 waves per CU).
 template <typename R>
-struct alignas(16) Tiles {
+struct NearExtra {
+    double nx[TCAP], ny[TCAP], nz[TCAP];
+};
+template <>
+struct NearExtra<float> {
+    int nears[TCAP];     // sorted index
+};
+
+template <typename R>
+struct alignas(16) Tiles : NearExtra<R> {
     R pn[TCAP][12];      // cx cy cz M | qxx qyy qzz qxy | qxz qyz - -
     R far[TCAP][4];      // x y z m (relative to the group centre)
     R nearp[TCAP][4];
     int nearj[TCAP];     // caller index: skips the self pair, and is the neighbour index
-    double nx[TCAP], ny[TCAP], nz[TCAP];   // near entries in FP64 (neighbour test)
     int lf_ex[64];       // leaf expansion: exclusive prefix of particle counts
     int lf_beg[64];
 };
@@ -258,6 +270,9 @@ struct NearK {
     // of the band around it inside which the FP64 test decides (infinite:
     // always FP64)
     float rout2f, band;
+    const double* x;   // sorted FP64 coordinates (the FP64 neighbour test of the mixed walk)
+    const double* y;
+    const double* z;
 };
 
 // Neighbour test of the CSR lists: r^2 < r_out^2 in FP64 from the original
@@ -317,6 +332,9 @@ __device__ inline void eval_near_f32(const Tiles<float>& T, int cnt, int ksub, i
                                      float py, float pz, float eps2, int self, const NearK<float>& K,
                                      Acc<float>& A, double xi, double yi, double zi, double rout2,
                                      int& nbr, int32_t* srow, int scap) {
+    const double* __restrict__ gx = K.x;
+    const double* __restrict__ gy = K.y;
+    const double* __restrict__ gz = K.z;
     float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
     const float l1 = K.l1 * 0.693147180559945309f;
     for_entries<2>(cnt, ksub, sub, [&](int e) {
@@ -345,7 +363,10 @@ __device__ inline void eval_near_f32(const Tiles<float>& T, int cnt, int ksub, i
             const bool band = fabsf(dr) <= K.band;
             bool nb = dr < 0.f;
             if (__ballot(band)) {
-                if (band) nb = is_neighbour(T.nx[e], T.ny[e], T.nz[e], xi, yi, zi, rout2);
+                if (band) {
+                    const int js = T.nears[e];
+                    nb = is_neighbour(gx[js], gy[js], gz[js], xi, yi, zi, rout2);
+                }
             }
             nb = nb & other;
             if (nb & (nbr < scap)) srow[nbr * kStageStride] = oj;
@@ -442,6 +463,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
             double h = 0.0;
             for (int k = 0; k < 3; ++k) h = fmax(h, (ghi[k] - glo[k]) * 0.5);
             K.rout2f = (float)rout2;
+            K.x = p.x; K.y = p.y; K.z = p.z;
             K.band = (h <= 64.0 * cp.r_out) ? (float)(2048.0 * 0x1p-24 * rout2) : INFINITY;
         }
 
@@ -569,9 +591,13 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                         e[3] = (R)p.m[j];
                         if (cls == 1) {
                             T.nearj[fill + lane] = p.perm[j];
-                            T.nx[fill + lane] = p.x[j];
-                            T.ny[fill + lane] = p.y[j];
-                            T.nz[fill + lane] = p.z[j];
+                            if constexpr (MIXED) {
+                                T.nears[fill + lane] = j;
+                            } else {
+                                T.nx[fill + lane] = p.x[j];
+                                T.ny[fill + lane] = p.y[j];
+                                T.nz[fill + lane] = p.z[j];
+                            }
                         }
                     }
                     fill = uni(fill + add);
