@@ -117,7 +117,7 @@ __global__ __launch_bounds__(64) void k_nbr_fill(NbrParams p) {
                 const bool leaf = w.nchild == 0;
                 const int nch = (near && !leaf) ? w.nchild : 0;
                 const int incl = wave_incl_scan(nch, lane);
-                const int tot = uni(__shfl(incl, 63, 64));
+                const int tot = last_lane(incl);
                 if (top + tot > p.stack_cap) {
                     overflow = true;
                     break;
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(64) void k_nbr_fill(NbrParams p) {
                 if (!__ballot(flag)) continue;
                 const int v = flag ? w.count : 0;
                 const int li = wave_incl_scan(v, lane);
-                const int total = uni(__shfl(li, 63, 64));
+                const int total = last_lane(li);
                 __syncthreads();
                 T.lf_ex[lane] = li - v;
                 T.lf_beg[lane] = w.begin;

@@ -546,7 +546,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
             // children of opened inner nodes
             const int nch = (open && !leaf) ? w.nchild : 0;
             const int incl = wave_incl_scan(nch, lane);
-            const int tot = uni(__shfl(incl, 63, 64));
+            const int tot = last_lane(incl);
             if (top + tot > p.stack_cap) {
                 overflow = true;
                 break;
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                 if (!lm) continue;
                 const int v = flag ? w.count : 0;
                 const int li = wave_incl_scan(v, lane);
-                const int total = uni(__shfl(li, 63, 64));
+                const int total = last_lane(li);
                 __syncthreads();
                 T.lf_ex[lane] = li - v;
                 T.lf_beg[lane] = w.begin;

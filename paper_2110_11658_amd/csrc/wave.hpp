@@ -14,14 +14,23 @@ __device__ inline int popc_below(uint64_t mask) {
                                           __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
-__device__ inline int wave_incl_scan(int v, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
+// Inclusive prefix sum over the 64 lanes (all lanes active) with DPP moves:
+// shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the last lane of row
+// 0 is added into row 1 and row 3 (row_bcast:15, row mask 0b1010) and the last
+// lane of row 1 into rows 2 and 3 (row_bcast:31, row mask 0b1100). Lanes whose
+// source lies outside the row, and rows outside the mask, add 0.
+__device__ inline int wave_incl_scan(int v, int /*lane*/) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31
     return v;
 }
+
+// value of lane 63, in a scalar register
+__device__ inline int last_lane(int v) { return __builtin_amdgcn_readlane(v, 63); }
 
 // Work queue of groups split into kQueues contiguous ranges, one per XCD:
 // workgroups are dispatched round-robin over the XCDs, so a workgroup takes
