@@ -59,21 +59,36 @@ __global__ __launch_bounds__(BB_T) void k_bbox_part(const double* __restrict__ p
     if (t == 0) bad[blockIdx.x] = s_bad;
 }
 
-// one thread per cluster; blocks of cluster c are [cblk[c], cblk[c+1])
-__global__ void k_bbox_final(const double* __restrict__ part, const int32_t* __restrict__ bad,
-                             const int32_t* __restrict__ cblk, int nc, double* __restrict__ box,
-                             unsigned long long* __restrict__ cnt) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
+// one block per cluster; blocks of cluster c are [cblk[c], cblk[c+1]). min and
+// max are exact, so the reduction order does not matter.
+__global__ __launch_bounds__(BB_T) void k_bbox_final(const double* __restrict__ part,
+                                                     const int32_t* __restrict__ bad,
+                                                     const int32_t* __restrict__ cblk, int nc,
+                                                     double* __restrict__ box,
+                                                     unsigned long long* __restrict__ cnt) {
+    __shared__ double s_v[6][BB_T];
+    __shared__ int s_bad;
+    const int c = blockIdx.x, t = threadIdx.x;
+    if (t == 0) s_bad = 0;
     double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     int nf = 0;
-    for (int b = cblk[c]; b < cblk[c + 1]; ++b) {
+    for (int b = cblk[c] + t; b < cblk[c + 1]; b += BB_T) {
         for (int k = 0; k < 3; ++k) v[k] = fmin(v[k], part[6 * b + k]);
         for (int k = 3; k < 6; ++k) v[k] = fmax(v[k], part[6 * b + k]);
         nf |= bad[b];
     }
-    for (int k = 0; k < 6; ++k) box[6 * c + k] = v[k];
-    if (nf) atomicOr(&cnt[kErr], kErrNonFinite);
+    for (int k = 0; k < 6; ++k) s_v[k][t] = v[k];
+    __syncthreads();
+    if (nf) atomicOr(&s_bad, 1);
+    for (int o = BB_T / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            for (int k = 0; k < 3; ++k) s_v[k][t] = fmin(s_v[k][t], s_v[k][t + o]);
+            for (int k = 3; k < 6; ++k) s_v[k][t] = fmax(s_v[k][t], s_v[k][t + o]);
+        }
+        __syncthreads();
+    }
+    if (t < 6) box[6 * c + t] = s_v[t][0];
+    if (t == 0 && s_bad) atomicOr(&cnt[kErr], kErrNonFinite);
 }
 
 // ------------------------------------------------------------------ keys
@@ -325,7 +340,14 @@ __global__ void k_nodes_init(const int32_t* __restrict__ bfs2pre, const int32_t*
         w.first_child = nc ? pre2bfs[p + 1] : -1;
         leaves += (nc == 0);
     }
-    if (leaves) atomicAdd(&cnt[kCntLeaves], leaves);
+    // one atomic per block: a single counter serialises same-address atomics
+    __shared__ unsigned long long s_leaves;
+    if (threadIdx.x == 0) s_leaves = 0;
+    __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) leaves += __shfl_xor(leaves, o, 64);
+    if ((threadIdx.x & 63) == 0 && leaves) atomicAdd(&s_leaves, leaves);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_leaves) atomicAdd(&cnt[kCntLeaves], s_leaves);
 }
 
 // ----------------------------------------------------------------- moments
@@ -479,6 +501,32 @@ __device__ inline void moments_loop(const WNode& w, bool leaf, int nsub, const d
     for (int e = 0; e < 6; ++e) o.q[e] = q[e];
 }
 
+__device__ inline void moments_node(int64_t b, const double* __restrict__ x, const double* __restrict__ y,
+                                    const double* __restrict__ z, const double* __restrict__ m,
+                                    WNode* __restrict__ node, Mom64* __restrict__ q64,
+                                    Mom32* __restrict__ q32) {
+    const WNode w = node[b];
+    const bool leaf = w.nchild == 0;
+    const int nsub = leaf ? w.count : w.nchild;
+    MomOut o;
+    if (nsub <= kMomFast) moments_small(w, leaf, nsub, x, y, z, m, node, q64, o);
+    else moments_loop(w, leaf, nsub, x, y, z, m, node, q64, o);
+    for (int k = 0; k < 3; ++k) {
+        node[b].lo[k] = o.lo[k];
+        node[b].hi[k] = o.hi[k];
+        node[b].com[k] = o.com[k];
+    }
+    Mom64 r;
+    r.M = o.M; r.qxx = o.q[0]; r.qyy = o.q[1]; r.qzz = o.q[2]; r.qxy = o.q[3]; r.qxz = o.q[4];
+    r.qyz = o.q[5];
+    r.pad = 0.0;
+    q64[b] = r;
+    Mom32 f;
+    f.M = (float)o.M; f.qxx = (float)o.q[0]; f.qyy = (float)o.q[1]; f.qzz = (float)o.q[2];
+    f.qxy = (float)o.q[3]; f.qxz = (float)o.q[4]; f.qyz = (float)o.q[5]; f.pad = 0.0f;
+    q32[b] = f;
+}
+
 __global__ __launch_bounds__(128) void k_moments_level(const int32_t* __restrict__ lvl_off, int level,
                                 const double* __restrict__ x, const double* __restrict__ y,
                                 const double* __restrict__ z, const double* __restrict__ m,
@@ -486,27 +534,21 @@ __global__ __launch_bounds__(128) void k_moments_level(const int32_t* __restrict
                                 Mom32* __restrict__ q32) {
     const int64_t b0 = lvl_off[level], b1 = lvl_off[level + 1];
     for (int64_t b = b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < b1;
-         b += (int64_t)gridDim.x * blockDim.x) {
-        const WNode w = node[b];
-        const bool leaf = w.nchild == 0;
-        const int nsub = leaf ? w.count : w.nchild;
-        MomOut o;
-        if (nsub <= kMomFast) moments_small(w, leaf, nsub, x, y, z, m, node, q64, o);
-        else moments_loop(w, leaf, nsub, x, y, z, m, node, q64, o);
-        for (int k = 0; k < 3; ++k) {
-            node[b].lo[k] = o.lo[k];
-            node[b].hi[k] = o.hi[k];
-            node[b].com[k] = o.com[k];
-        }
-        Mom64 r;
-        r.M = o.M; r.qxx = o.q[0]; r.qyy = o.q[1]; r.qzz = o.q[2]; r.qxy = o.q[3]; r.qxz = o.q[4];
-        r.qyz = o.q[5];
-        r.pad = 0.0;
-        q64[b] = r;
-        Mom32 f;
-        f.M = (float)o.M; f.qxx = (float)o.q[0]; f.qyy = (float)o.q[1]; f.qzz = (float)o.q[2];
-        f.qxy = (float)o.q[3]; f.qxz = (float)o.q[4]; f.qyz = (float)o.q[5]; f.pad = 0.0f;
-        q32[b] = f;
+         b += (int64_t)gridDim.x * blockDim.x)
+        moments_node(b, x, y, z, m, node, q64, q32);
+}
+
+// one workgroup, levels l_hi down to l_lo in order (a barrier between levels)
+__global__ __launch_bounds__(128) void k_moments_levels(const int32_t* __restrict__ lvl_off, int l_hi,
+                                 int l_lo, const double* __restrict__ x,
+                                 const double* __restrict__ y, const double* __restrict__ z,
+                                 const double* __restrict__ m, WNode* __restrict__ node,
+                                 Mom64* __restrict__ q64, Mom32* __restrict__ q32) {
+    for (int l = l_hi; l >= l_lo; --l) {
+        const int64_t b0 = lvl_off[l], b1 = lvl_off[l + 1];
+        for (int64_t b = b0 + threadIdx.x; b < b1; b += blockDim.x)
+            moments_node(b, x, y, z, m, node, q64, q32);
+        __syncthreads();
     }
 }
 
@@ -715,7 +757,7 @@ void launch_bbox(Dev& d, const BuildCfg& c, const double* pos, const double* mas
                        (const int64_t*)d.blk_range, d.blk_part, d.blk_bad);
     // d.blk_cluster is followed by the per-cluster block offsets (see host setup)
     const int32_t* cblk = d.blk_cluster + nblk;
-    hipLaunchKernelGGL(k_bbox_final, dim3((c.n_clusters + 63) / 64), dim3(64), 0, s,
+    hipLaunchKernelGGL(k_bbox_final, dim3(c.n_clusters), dim3(BB_T), 0, s,
                        (const double*)d.blk_part, (const int32_t*)d.blk_bad, cblk, c.n_clusters,
                        d.cl_box, d.cnt);
 }
@@ -751,18 +793,29 @@ void launch_topology(Dev& d, const BuildCfg& c, hipStream_t s) {
                        n_nodes, cap, d.lvl_off, d.cnt);
     hipLaunchKernelGGL(k_invert, dim3(grid_for(cap, 256)), dim3(256), 0, s,
                        (const int32_t*)d.bfs2pre, n_nodes, cap, d.pre2bfs);
-    hipLaunchKernelGGL(k_nodes_init, dim3(grid_for(cap, 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_nodes_init, dim3(grid_for(cap, 256, 1024)), dim3(256), 0, s,
                        (const int32_t*)d.bfs2pre, (const int32_t*)d.pre2bfs, n_nodes, cap,
                        (const int32_t*)d.pre_begin, (const int32_t*)d.pre_count,
                        (const int32_t*)d.pre_nchild, d.node, d.cnt);
 }
 
 void launch_moments(Dev& d, const BuildCfg& c, hipStream_t s) {
-    for (int l = c.D; l >= 0; --l) {
-        hipLaunchKernelGGL(k_moments_level, dim3(grid_for(c.node_cap, 128, 2048)), dim3(128), 0, s,
+    const int hi = c.mom_hi < c.D ? c.mom_hi : c.D;
+    const int lo = c.mom_lo;
+    if (hi < c.D)
+        hipLaunchKernelGGL(k_moments_levels, dim3(1), dim3(128), 0, s, (const int32_t*)d.lvl_off, c.D,
+                           hi + 1, (const double*)d.x, (const double*)d.y, (const double*)d.z,
+                           (const double*)d.m, d.node, d.q64, d.q32);
+    for (int l = hi; l > lo; --l) {
+        const int grid = c.mom_grid[l] > 0 ? c.mom_grid[l] : grid_for(c.node_cap, 128, 2048);
+        hipLaunchKernelGGL(k_moments_level, dim3(grid), dim3(128), 0, s,
                            (const int32_t*)d.lvl_off, l, (const double*)d.x, (const double*)d.y,
                            (const double*)d.z, (const double*)d.m, d.node, d.q64, d.q32);
     }
+    if (lo >= 0)
+        hipLaunchKernelGGL(k_moments_levels, dim3(1), dim3(128), 0, s, (const int32_t*)d.lvl_off, lo, 0,
+                           (const double*)d.x, (const double*)d.y, (const double*)d.z,
+                           (const double*)d.m, d.node, d.q64, d.q32);
 }
 
 void launch_groups(Dev& d, const BuildCfg& c, hipStream_t s) {

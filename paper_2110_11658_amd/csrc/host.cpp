@@ -20,7 +20,7 @@ using namespace pbh;
 
 namespace {
 
-constexpr int kBoxChunk = 16384;     // particles per bbox/key block
+constexpr int kBoxChunk = 2048;      // particles per bbox/key block (512 blocks per 2^20)
 constexpr int kStackCap = 16384;     // traversal stack entries per persistent wave (LDS + spill)
 constexpr int kCntKdkStep = 11;      // counter slot: KDK energy output index
 
@@ -60,6 +60,11 @@ struct pbh_ctx {
     int64_t k_n = -1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // the build's kernel sequence, captured once per (buffers, sizes, parameters)
+    std::vector<int32_t> lvl_count;   // nodes per level of the last build (moment grids)
+    hipGraph_t bgraph = nullptr;
+    hipGraphExec_t bexec = nullptr;
+    std::vector<double> bkey;
     std::vector<double> gkey;   // parameters the captured graph was made with
 
     // phase timing: events 0/1 build, 2/3 walk, 4/5 neighbours
@@ -211,6 +216,29 @@ pbh_status setup_build(pbh_ctx* ctx, int64_t n, int32_t C, const int64_t* offset
     c.n_leaf = ctx->params.leaf_size;
     c.n_crit = ctx->params.n_crit;
     c.node_cap = node_capacity(n, D, c.n_leaf, C);
+    for (int l = 0; l < 32; ++l) {
+        c.mom_grid[l] = 0;
+        if (l < (int)ctx->lvl_count.size()) {
+            // power-of-two bucket of 1.5x the last count (few distinct graphs)
+            const int64_t want = (ctx->lvl_count[l] * 3 / 2 + 127) / 128;
+            int g = 1;
+            while (g < want && g < 2048) g <<= 1;
+            c.mom_grid[l] = g;
+        }
+    }
+    c.mom_hi = D;
+    c.mom_lo = -1;
+    if (!ctx->lvl_count.empty()) {
+        // deepest level that held nodes, and the top levels that held few
+        int hi = 0;
+        for (int l = 0; l < (int)ctx->lvl_count.size() && l <= D; ++l)
+            if (ctx->lvl_count[l] > 0) hi = l;
+        int lo = -1;
+        while (lo + 1 <= hi && ctx->lvl_count[lo + 1] <= 128) ++lo;   // one node per thread
+        if (lo >= hi) lo = hi - 1;   // at least the deepest non-empty level runs on its own
+        c.mom_hi = hi;
+        c.mom_lo = lo;
+    }
     if (c.node_cap >= (1ll << 31)) return fail(ctx, PBH_E_ARG, "too many particles for int32 node indices");
     ctx->cl_off_h.assign(offsets, offsets + C + 1);
     std::vector<int32_t> blk_cluster;
@@ -244,6 +272,40 @@ pbh_status setup_build(pbh_ctx* ctx, int64_t n, int32_t C, const int64_t* offset
     HIP_TRY(hipMemcpyAsync(ctx->d.cl_off, ctx->cl_off_h.data(), (C + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));   // the host tables above are temporaries
+    return PBH_OK;
+}
+
+void enqueue_build(pbh_ctx* ctx, const double* pos, const double* mass, hipStream_t s);
+
+// The build issues about 90 small kernels; launched one by one, the host's
+// launch rate rather than the GPU sets the build time. The sequence is captured
+// into a graph once per set of buffers, sizes and parameters (the block tables
+// it reads are uploaded before each launch) and replayed.
+pbh_status launch_build(pbh_ctx* ctx, const double* pos, const double* mass, hipStream_t s) {
+    const BuildCfg& c = ctx->cfg;
+    const std::vector<double> key = {(double)(uintptr_t)pos, (double)(uintptr_t)mass, (double)c.n,
+                                     (double)c.n_clusters, (double)c.D, (double)c.cbits,
+                                     (double)c.n_leaf, (double)c.n_crit, (double)c.node_cap,
+                                     (double)ctx->nblk_box, (double)ctx->alloc_gen,
+                                     (double)c.mom_grid[0], (double)c.mom_grid[1], (double)c.mom_grid[2],
+                                     (double)c.mom_grid[3], (double)c.mom_grid[4], (double)c.mom_grid[5],
+                                     (double)c.mom_grid[6], (double)c.mom_grid[7], (double)c.mom_grid[8],
+                                     (double)c.mom_grid[9], (double)c.mom_grid[10], (double)c.mom_grid[11],
+                                     (double)c.mom_grid[12], (double)c.mom_grid[13], (double)c.mom_grid[14],
+                                     (double)c.mom_grid[15], (double)c.mom_grid[16], (double)c.mom_grid[17],
+                                     (double)c.mom_grid[18], (double)c.mom_grid[19], (double)c.mom_grid[20],
+                                     (double)c.mom_grid[21], (double)c.mom_hi, (double)c.mom_lo};
+    if (!ctx->bexec || ctx->bkey != key) {
+        if (ctx->bexec) { (void)hipGraphExecDestroy(ctx->bexec); ctx->bexec = nullptr; }
+        if (ctx->bgraph) { (void)hipGraphDestroy(ctx->bgraph); ctx->bgraph = nullptr; }
+        hipStream_t cs = ctx->cap_stream;
+        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        enqueue_build(ctx, pos, mass, cs);
+        HIP_TRY(hipStreamEndCapture(cs, &ctx->bgraph));
+        HIP_TRY(hipGraphInstantiate(&ctx->bexec, ctx->bgraph, nullptr, nullptr, 0));
+        ctx->bkey = key;
+    }
+    HIP_TRY(hipGraphLaunch(ctx->bexec, s));
     return PBH_OK;
 }
 
@@ -359,8 +421,13 @@ pbh_status check_radii(pbh_ctx* ctx, double r_in, double r_out) {
 
 pbh_status finish_build(pbh_ctx* ctx, hipStream_t s) {
     unsigned long long h[kNumCounters];
+    int32_t lo[32];
     HIP_TRY(hipMemcpyAsync(h, ctx->d.cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(lo, ctx->d.lvl_off, sizeof(lo), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    const int D = ctx->cfg.D;
+    ctx->lvl_count.assign(D + 1, 0);
+    for (int l = 0; l <= D; ++l) ctx->lvl_count[l] = lo[l + 1] - lo[l];
     if (h[kErr] & kErrNonFinite) {
         ctx->built = false;
         return fail(ctx, PBH_E_NONFINITE, "non-finite position or mass");
@@ -493,6 +560,8 @@ void pbh_destroy(pbh_ctx* ctx) {
     (void)hipDeviceSynchronize();
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->bexec) (void)hipGraphExecDestroy(ctx->bexec);
+    if (ctx->bgraph) (void)hipGraphDestroy(ctx->bgraph);
     free_all(ctx);
     if (ctx->k_acc) (void)hipFree(ctx->k_acc);
     if (ctx->k_pot) (void)hipFree(ctx->k_pot);
@@ -533,7 +602,8 @@ pbh_status pbh_build(pbh_ctx* ctx, int64_t n, const double* pos, const double* m
     pbh_status st = setup_build(ctx, n, 1, offs, s);
     if (st != PBH_OK) return st;
     mark(ctx, 0, s);
-    enqueue_build(ctx, pos, mass, s);
+    st = launch_build(ctx, pos, mass, s);
+    if (st != PBH_OK) return st;
     mark(ctx, 1, s);
     ctx->ev_build = ctx->timing;
     return finish_build(ctx, s);
@@ -557,7 +627,8 @@ pbh_status pbh_build_batched(pbh_ctx* ctx, int32_t n_clusters, const int64_t* of
     pbh_status st = setup_build(ctx, n, n_clusters, offsets, s);
     if (st != PBH_OK) return st;
     mark(ctx, 0, s);
-    enqueue_build(ctx, pos, mass, s);
+    st = launch_build(ctx, pos, mass, s);
+    if (st != PBH_OK) return st;
     mark(ctx, 1, s);
     ctx->ev_build = ctx->timing;
     return finish_build(ctx, s);

@@ -84,6 +84,14 @@ struct BuildCfg {
     int32_t n_crit = 64;
     int64_t node_cap = 0;
     int64_t n_groups = 0;
+    // workgroups of the moment pass per level (0: sized for the node capacity).
+    // Taken from the previous build's level sizes; any size is correct (the
+    // kernel strides), a good guess avoids dispatching thousands of idle groups.
+    int32_t mom_grid[32] = {0};
+    // levels [mom_hi+1, D] and [0, mom_lo] are each done by one workgroup that
+    // walks its levels in order (they held few or no nodes last time);
+    // mom_hi = D and mom_lo = -1 launch every level on its own
+    int32_t mom_hi = 21, mom_lo = -1;
 };
 
 // Scratch and arrays of one built forest.
