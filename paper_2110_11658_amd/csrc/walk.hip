@@ -191,13 +191,15 @@ __device__ inline void eval_pn(const Tiles<R>& T, int cnt, int ksub, int sub, R 
     A.add(ax, ay, az, ph);
 }
 
-// FP32 form written as explicit FMA chains (34 VALU + 1 rsqrt per entry):
-//   t = R^T Q R / s^5,  cr = M/s^3 + 2.5 t / s^2,  a += Q R / s^5 - cr R,
-//   phi += -M/s - t/2.
+// FP32 form written as explicit FMA chains (33 VALU + 1 rsqrt per entry). The
+// tile holds Q' = 2.5 Q, so with q' = Q' R and t' = R.q' / s^5 (= 2.5 t):
+//   cr = M/s^3 + t'/s^2,  a += 0.4 q'/s^5 - cr R,  phi += -M/s - 0.2 t'.
+// The q'/s^5 terms are summed apart and scaled by 0.4 once per tile.
 template <>
 __device__ inline void eval_pn<float>(const Tiles<float>& T, int cnt, int ksub, int sub, float px,
                                       float py, float pz, float eps2, Acc<float>& A) {
     float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+    float bx = 0.f, by = 0.f, bz = 0.f;
     for_entries<4>(cnt, ksub, sub, [&](int e) {
         const float4 a = *reinterpret_cast<const float4*>(&T.pn[e][0]);   // cx cy cz M
         const float4 b = *reinterpret_cast<const float4*>(&T.pn[e][4]);   // qxx qyy qzz qxy
@@ -213,13 +215,16 @@ __device__ inline void eval_pn<float>(const Tiles<float>& T, int cnt, int ksub, 
         const float inv3 = inv * inv2;
         const float inv5 = inv3 * inv2;
         const float t = rqr * inv5;
-        const float cr = fmaf(2.5f * t, inv2, a.w * inv3);
-        ax = fmaf(-cr, Rx, fmaf(qx, inv5, ax));
-        ay = fmaf(-cr, Ry, fmaf(qy, inv5, ay));
-        az = fmaf(-cr, Rz, fmaf(qz, inv5, az));
-        ph = fmaf(-a.w, inv, fmaf(-0.5f, t, ph));
+        const float cr = fmaf(t, inv2, a.w * inv3);
+        bx = fmaf(qx, inv5, bx);
+        by = fmaf(qy, inv5, by);
+        bz = fmaf(qz, inv5, bz);
+        ax = fmaf(-cr, Rx, ax);
+        ay = fmaf(-cr, Ry, ay);
+        az = fmaf(-cr, Rz, az);
+        ph = fmaf(-a.w, inv, fmaf(-0.2f, t, ph));
     });
-    A.add(ax, ay, az, ph);
+    A.add(fmaf(0.4f, bx, ax), fmaf(0.4f, by, ay), fmaf(0.4f, bz, az), ph);
 }
 
 // Pairs of far leaves: every pair is at r >= r_out, where W = 1.
@@ -530,9 +535,10 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                     e[1] = (R)(w.com[1] - ctr[1]);
                     e[2] = (R)(w.com[2] - ctr[2]);
                     if (MIXED) {
+                        // quadrupole scaled by 2.5 (see eval_pn<float>)
                         const Mom32 q = p.q32[nd];
-                        e[3] = q.M; e[4] = q.qxx; e[5] = q.qyy; e[6] = q.qzz;
-                        e[7] = q.qxy; e[8] = q.qxz; e[9] = q.qyz;
+                        e[3] = q.M; e[4] = 2.5f * q.qxx; e[5] = 2.5f * q.qyy; e[6] = 2.5f * q.qzz;
+                        e[7] = 2.5f * q.qxy; e[8] = 2.5f * q.qxz; e[9] = 2.5f * q.qyz;
                     } else {
                         const Mom64 q = p.q64[nd];
                         e[3] = q.M; e[4] = q.qxx; e[5] = q.qyy; e[6] = q.qzz;
