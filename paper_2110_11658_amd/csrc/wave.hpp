@@ -44,6 +44,7 @@ __device__ inline int64_t queue_next(unsigned long long* q /* [kQueues] */, int6
     for (int k = 0; k < kQueues; ++k) {
         const int qi = (home + k) % kQueues;
         const int64_t lo = G * qi / kQueues, hi = G * (qi + 1) / kQueues;
+        if (hi <= lo) continue;   // empty range (G < kQueues, or nothing queued)
         if (k > 0 && (int64_t)__builtin_amdgcn_readfirstlane((int)(q[qi] < (unsigned long long)(hi - lo))) == 0)
             continue;   // range already drained: skip the atomic
         const unsigned long long r = atomicAdd(&q[qi], lane == 0 ? 1ull : 0ull);
