@@ -224,7 +224,8 @@ def test_lattice_ties():
         _sets_equal(off.cpu().numpy(), idx.cpu().numpy(), o_off, o_idx)
 
 
-def test_neighbour_routes():
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_neighbour_routes(prec):
     # Lists reach the CSR by two routes: rows the walk staged (whole rows, or
     # per-copy sub-rows of split groups) and the fill traversal (groups with a
     # list longer than its row). A clump where every member has ~1500
@@ -237,8 +238,8 @@ def test_neighbour_routes():
     halo = rng.normal(size=(300, 3)) * 5.0
     pos = np.ascontiguousarray(np.concatenate([body, clump, halo]))
     mass = np.full(pos.shape[0], 1.0 / pos.shape[0])
-    print(f"routes n={pos.shape[0]}", flush=True)
-    p = _pbh(leaf_size=8, n_crit=64)
+    print(f"routes n={pos.shape[0]} {prec}", flush=True)
+    p = _pbh(leaf_size=8, n_crit=64, prec=prec)
     _, _, off, idx = _run(p, type("C", (), {"pos": pos, "mass": mass})(), 0.1 * r_out, r_out, 0.5, 0.0)
     o_off, o_idx = oracle.nbr_brute(pos, r_out)
     assert o_off[-1] > 1500 * 1499
@@ -329,6 +330,22 @@ def test_deterministic_repeat():
     r2 = _run(p, c, 0.01, 0.1, 0.5, 1e-5)
     for a, b in zip(r1, r2):
         assert np.array_equal(a, b)
+
+
+def test_context_reuse_across_inputs():
+    # One context serves inputs of different sizes and different buffers of
+    # the same size (its captured build sequence and level-sized launches are
+    # keyed on them): every result equals that of a fresh context.
+    cs = [ic.plummer(20000, seed=31, masses="kroupa"), ic.plummer(3000, seed=32),
+          ic.plummer(20000, seed=33, masses="kroupa"), ic.plummer(20000, seed=31, masses="kroupa")]
+    args = (0.005, 0.05, 0.5, 1e-5)
+    p = _pbh()
+    for k, c in enumerate(cs):
+        print(f"reuse input {k} n={c.mass.size}", flush=True)
+        got = _run(p, c, *args)
+        ref = _run(_pbh(), c, *args)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b)
 
 
 # ---------------------------------------------------------------- batched
