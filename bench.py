@@ -61,6 +61,19 @@ WORKLOADS = {
 METRIC = "particle-node interactions/s and force evals/s at N=1e6 vs FP32 VALU roofline"
 
 
+def clock_mhz(torch):
+    """Peak engine clock the runtime reports for device 0 (MHz), or None."""
+    try:
+        props = torch.cuda.get_device_properties(0)
+        for name in ("clock_rate", "clockRate"):
+            v = getattr(props, name, None)
+            if v:
+                return float(v) / 1000.0
+    except Exception:
+        pass
+    return None
+
+
 def walk_traffic(kernel: str):
     """HBM bytes per walk launch from the committed rocprofv3 counter summary,
     or None when the walk source has changed since the counters were taken."""
@@ -266,7 +279,11 @@ def bench_force(args):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": (walk_traffic(kernel) if inp["name"] == "plummer1m_kroupa" else None),
-                     "kernel": kernel, "flops_per_launch": flops},
+                     "kernel": kernel, "flops_per_launch": flops,
+                     # the same rate against the FP32 vector peak without packed
+                     # instructions (4 SIMD16 x 2 flop x 256 CUs x 2.4 GHz)
+                     "peak_unpacked": 78.6, "frac_unpacked": achieved / 78.6,
+                     "clock_mhz": clock_mhz(torch)},
     }
     if tuned is not None:
         rec["autotune"] = {k: v for k, v in tuned.items() if k != "cached"}
