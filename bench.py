@@ -11,7 +11,7 @@ Workloads (--workload):
                0.1 r_out, theta = 0.5, quadrupole nodes, FP32 interactions
                with FP64 positions and sums, n_leaf = 8, n_crit = 64 (the
                autotuner's choice on MI355X; --autotune re-tunes)
-  plummer128k  N = 131072, eps = 1e-5 (run with --prec fp64 and mixed)
+  plummer128k  N = 131072, eps = 1e-5, n_crit = 32 (run with --prec fp64 and mixed)
   plummer4m    N = 2^22, eps = 1e-6
   ensemble64   64 independent clusters, N log-uniform in [1e4, 2e5], each
                with its own r_out for 64 neighbours; one batched build and one
@@ -101,7 +101,9 @@ def parse():
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--leaf", type=int, default=8, help="n_leaf (tree leaf size)")
-    ap.add_argument("--ncrit", type=int, default=64, help="n_crit (largest walk group)")
+    ap.add_argument("--ncrit", type=int, default=0,
+                    help="n_crit (largest walk group); 0 = the library's choice by size "
+                         "(32 below 2^18 particles, else 64)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick n_leaf and n_crit by timing candidates on this input first "
                          "(on MI355X every workload here picks n_leaf=8, n_crit=64)")
@@ -170,7 +172,8 @@ def bench_force(args):
 
     tuned = None
     if not args.autotune:
-        p.set_params(leaf_size=args.leaf, n_crit=args.ncrit, prec=args.prec)
+        ncrit = args.ncrit or (32 if n < (1 << 18) else 64)   # the library's rule for n_crit = 0
+        p.set_params(leaf_size=args.leaf, n_crit=ncrit, prec=args.prec)
     else:
         tuned = autotune.tune(p, pos, mass, inp["r_in"], inp["r_out"], theta, eps, prec=args.prec,
                               neighbours=neighbours, offsets=inp["offsets"])

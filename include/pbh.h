@@ -60,8 +60,9 @@ typedef enum { PBH_FP64 = 0, PBH_MIXED = 1 } pbh_prec;
 
 /*
  * Tuning parameters; 0 selects the default.
- *   leaf_size  n_leaf: a node with more particles is split (default 16)
- *   n_crit     particles per walk group, 1..64 (default 64; one wave lane each)
+ *   leaf_size  n_leaf: a node with more particles is split (default 8)
+ *   n_crit     particles per walk group, 1..64 (0: chosen per build, 32 below
+ *              2^18 particles and 64 from there; one wave lane each)
  *   key_bits   Morton bits per axis D, 1..21 (default 21 for one cluster;
  *              batched builds use min(21, (63 - cluster bits) / 3))
  *   prec       PBH_MIXED (FP32 interactions, FP64 positions and sums) or

@@ -36,7 +36,7 @@ def _need(t: torch.Tensor, shape, name: str, dtype=torch.float64):
 class Pbh:
     """One libpbh context (tree scratch lives on the GPU between calls)."""
 
-    def __init__(self, device: int = 0, leaf_size: int = 16, n_crit: int = 64, key_bits: int = 0,
+    def __init__(self, device: int = 0, leaf_size: int = 8, n_crit: int = 0, key_bits: int = 0,
                  prec: str = "mixed"):
         self.L = _lib.load()
         self.device = device
@@ -54,7 +54,7 @@ class Pbh:
         pr = {"mixed": PBH_MIXED, "fp64": PBH_FP64}[prec]
         return pbh_params(int(leaf_size), int(n_crit), int(key_bits), pr)
 
-    def set_params(self, leaf_size=16, n_crit=64, key_bits=0, prec="mixed"):
+    def set_params(self, leaf_size=8, n_crit=0, key_bits=0, prec="mixed"):
         p = self._params(leaf_size, n_crit, key_bits, prec)
         check(self.ctx, self.L.pbh_set_params(self.ctx, C.byref(p)))
 

@@ -214,7 +214,8 @@ pbh_status setup_build(pbh_ctx* ctx, int64_t n, int32_t C, const int64_t* offset
     if (ctx->params.key_bits > 0 && ctx->params.key_bits < D) D = ctx->params.key_bits;
     c.D = D;
     c.n_leaf = ctx->params.leaf_size;
-    c.n_crit = ctx->params.n_crit;
+    // n_crit 0: 32 below 2^18 particles (more, smaller groups keep all CUs busy), else 64
+    c.n_crit = ctx->params.n_crit ? ctx->params.n_crit : (n < (1 << 18) ? 32 : 64);
     c.node_cap = node_capacity(n, D, c.n_leaf, C);
     for (int l = 0; l < 32; ++l) {
         c.mom_grid[l] = 0;
@@ -515,7 +516,7 @@ const char* pbh_status_string(pbh_status s) {
 const char* pbh_last_error(const pbh_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 static pbh_status resolve_params(pbh_ctx* ctx, const pbh_params* in, pbh_params* out) {
-    pbh_params p{16, 64, 0, PBH_MIXED};
+    pbh_params p{8, 0, 0, PBH_MIXED};   // n_crit 0: chosen per build from N
     if (in) {
         if (in->leaf_size < 0 || in->n_crit < 0 || in->n_crit > 64 || in->key_bits < 0 ||
             in->key_bits > 21 || (in->prec != PBH_FP64 && in->prec != PBH_MIXED))

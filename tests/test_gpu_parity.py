@@ -58,7 +58,7 @@ def _run(p, c, r_in, r_out, theta, eps, nbr=True):
 def test_tree_bit_exact(n, n_leaf, seed):
     print(f"tree n={n} n_leaf={n_leaf}", flush=True)
     c = ic.plummer(n, seed=seed, masses="kroupa")
-    p = _pbh(leaf_size=n_leaf)
+    p = _pbh(leaf_size=n_leaf, n_crit=64)
     p.build(_t(c.pos), _t(c.mass))
     order, keys, ni, nd = p.debug_tree()
     okeys = oracle.keys(c.pos, 21)
@@ -353,13 +353,13 @@ def test_batched_equals_per_cluster():
     e = ic.ensemble(n_clusters=5, nmin=300, nmax=5000, nbar=16)
     theta, eps = 0.5, 1e-5
     from paper_2110_11658_amd.api import Pbh
-    pb = Pbh(0, key_bits=19)
+    pb = Pbh(0, key_bits=19, n_crit=64)   # same groups in both builds whatever the total size
     pb.build_batched(e.offsets, _t(e.pos), _t(e.mass))
     acc, pot, off, idx = pb.force_batched(e.r_in, e.r_out, theta, eps)
     torch.cuda.synchronize()
     acc, pot, off, idx = (t.cpu().numpy() for t in (acc, pot, off, idx))
     assert pb.stats()["n_clusters"] == 5
-    ps = Pbh(0, key_bits=19)
+    ps = Pbh(0, key_bits=19, n_crit=64)
     for k in range(5):
         s = slice(e.offsets[k], e.offsets[k + 1])
         ps.build(_t(e.pos[s]), _t(e.mass[s]))
@@ -380,7 +380,7 @@ def test_kdk_graph_equals_eager_and_oracle():
     r_in, theta, eps, dt, steps = 0.1 * r_out, 0.5, 1e-4, 1.0 / 256, 6
     res = {}
     for mode in ("graph", "eager"):
-        p = _pbh(prec="fp64")
+        p = _pbh(prec="fp64", leaf_size=16, n_crit=64)   # the oracle walk's defaults
         pos, vel, mass = _t(c.pos), _t(c.vel), _t(c.mass)
         en = p.kdk(pos, vel, mass, dt, steps, r_in, r_out, theta, eps, graph=(mode == "graph"))
         torch.cuda.synchronize()
