@@ -62,14 +62,17 @@ METRIC = "particle-node interactions/s and force evals/s at N=1e6 vs FP32 VALU r
 
 
 def clock_mhz(torch):
-    """Peak engine clock the runtime reports for device 0 (MHz), or None."""
+    """Peak engine clock the HIP runtime reports for device 0 (MHz), or None.
+
+    hipDeviceGetAttribute(hipDeviceAttributeClockRate = 5, in kHz) from the HIP
+    runtime library torch has loaded."""
+    import ctypes
     try:
-        props = torch.cuda.get_device_properties(0)
-        for name in ("clock_rate", "clockRate"):
-            v = getattr(props, name, None)
-            if v:
-                return float(v) / 1000.0
-    except Exception:
+        hip = ctypes.CDLL("libamdhip64.so")
+        v = ctypes.c_int(0)
+        if hip.hipDeviceGetAttribute(ctypes.byref(v), 5, 0) == 0 and v.value > 0:
+            return v.value / 1000.0
+    except OSError:
         pass
     return None
 
