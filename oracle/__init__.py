@@ -50,6 +50,7 @@ def lib():
         L.orc_phiR_coeffs.argtypes = [_d, _d, _p, _p]
         L.orc_direct.argtypes = [_i64, _p, _p, _d, _d, _d, _i64, _p, _p, _p]
         L.orc_full_direct.argtypes = [_i64, _p, _p, _d, _p, _p]
+        L.orc_irregular.argtypes = [_i64, _p, _p, _p, _d, _d, _d, _i64, _p, _p, _p, _p, _p]
         L.orc_nbr_brute.restype = _i64
         L.orc_nbr_brute.argtypes = [_i64, _p, _d, _p, _p, _i64]
         L.orc_nbr_cells.restype = _i64
@@ -125,6 +126,35 @@ def full_direct(pos, mass, eps):
     pot = np.zeros(n)
     lib().orc_full_direct(n, _ptr(pos), _ptr(mass), float(eps), _ptr(acc), _ptr(pot))
     return acc, pot
+
+
+def irregular(pos, vel, mass, r_in, r_out, eps, targets=None):
+    """O(N^2) irregular force F_I (eq. fi), its time derivative (eq. fidot,
+    read as the term-by-term derivative of eq. fi) and the irregular
+    potential Phi_I = -1/s - Phi_R(s), summed over every j != i.
+
+    Returns (acc [n_t,3], jerk [n_t,3], pot [n_t], scale [n_t,3]); scale holds
+    per-target magnitude sums (acceleration, jerk, potential) over the pairs
+    inside r_out, for error bounds.
+    """
+    pos = _f64(pos)
+    n = pos.shape[0]
+    vel = _f64(vel, (n, 3))
+    mass = _f64(mass, (n,))
+    if targets is None:
+        nt = n
+        tgt = None
+    else:
+        tgt = np.ascontiguousarray(targets, dtype=np.int64)
+        nt = tgt.size
+    acc = np.zeros((nt, 3))
+    jerk = np.zeros((nt, 3))
+    pot = np.zeros(nt)
+    scale = np.zeros((nt, 3))
+    lib().orc_irregular(n, _ptr(pos), _ptr(vel), _ptr(mass), float(r_in), float(r_out), float(eps),
+                        nt, None if tgt is None else _ptr(tgt), _ptr(acc), _ptr(jerk), _ptr(pot),
+                        _ptr(scale))
+    return acc, jerk, pot, scale
 
 
 def _nbr(fn, pos, r_out):

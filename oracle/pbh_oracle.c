@@ -26,6 +26,8 @@
  *   orc_W, orc_phiR           the changeover weight and regular potential
  *   orc_direct                O(N^2) direct sum (all or a subset of targets)
  *   orc_full_direct           plain softened gravity (no split)
+ *   orc_irregular             O(N^2) irregular force F_I, its time
+ *                             derivative and the irregular potential
  *   orc_nbr_brute/orc_nbr_cells neighbour sets, brute force and cell list
  *   orc_keys                  Morton keys of the octree
  *   orc_tree                  Barnes-Hut octree walk with the same tree,
@@ -227,6 +229,100 @@ void orc_full_direct(int64_t n, const double* pos, const double* mass, double ep
         acc[3 * i + 1] = ay;
         acc[3 * i + 2] = az;
         pot[i] = ph;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Irregular force, its time derivative and potential                        */
+/* (Section 2.1: eq. fi, eq. fidot, eq. duncan, eq. duncan2)                 */
+/*                                                                          */
+/* With d = x_j - x_i, u = v_j - v_i and s^2 = |d|^2 + eps^2:                */
+/*   F_I      = sum_{j != i} m_j K(s) d / s^3                                */
+/*   dF_I/dt  = sum_{j != i} m_j { K(s) [u / s^3 - 3 (d.u) d / s^5]          */
+/*                                 + (dK/dt) d / s^3 }                       */
+/*   dK/dt    = -g'(x) (d.u) / (s (r_out - r_in)) for r_in <= s < r_out,     */
+/*              0 elsewhere; g'(x) = 140 x^3 (1 - x)^3                       */
+/*   Phi_I(s) = -1/s - Phi_R(s) (so Phi_I + Phi_R is plain softened gravity) */
+/* The jerk is the time derivative of eq. fi taken term by term along the    */
+/* particles' velocities (ds/dt = d.u / s). As printed, eq. fidot drops m_j  */
+/* and K from its second term, and eq. duncan2 gives dK/dt the sign of       */
+/* +g'(x) although K = 1 - g(x) decreases with x; this follows the           */
+/* derivative. A step changeover (r_in = r_out) has K = 1 below r_out and    */
+/* dK/dt = 0 (the jump carries no smooth derivative); r_out = 0 gives K = 0. */
+/* ------------------------------------------------------------------------ */
+
+/* K(s) and g'(x)/(r_out - r_in) for one pair (the latter 0 off the band). */
+static void k_and_slope(const phir_t* p, double s, double* K, double* slope)
+{
+    *slope = 0.0;
+    if (p->mode == 0 || s >= p->r_out) { *K = 0.0; return; }
+    if (p->mode == 1 || s < p->r_in) { *K = 1.0; return; }
+    double x = (s - p->r_in) / p->D;
+    double omx = 1.0 - x;
+    *K = 1.0 - g_poly(x);
+    *slope = 140.0 * x * x * x * omx * omx * omx / p->D;
+}
+
+/*
+ * pos, vel: [n][3]; mass: [n]. If tgt != NULL only the n_tgt listed targets
+ * are computed and the outputs are [n_tgt][3] / [n_tgt]; otherwise all n.
+ * jerk, pot and scale may be NULL. scale [n_tgt][3], if given, receives
+ * per-target magnitude sums over the pairs with s < r_out, for error bounds:
+ *   sum m_j / s^2,  sum m_j |u| (4/s^3 + max g' / (s^2 (r_out - r_in))),
+ *   sum m_j (1/s + |Phi_R(s)|)
+ * (max g' = 140/64; the second sum drops that term for a step changeover).
+ */
+void orc_irregular(int64_t n, const double* pos, const double* vel, const double* mass,
+                   double r_in, double r_out, double eps,
+                   int64_t n_tgt, const int64_t* tgt,
+                   double* acc, double* jerk, double* pot, double* scale)
+{
+    phir_t p;
+    phir_init(&p, r_in, r_out);
+    double eps2 = eps * eps;
+    int64_t nt = tgt ? n_tgt : n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t i = tgt ? tgt[t] : t;
+        double a[3] = {0, 0, 0}, jk[3] = {0, 0, 0}, ph = 0;
+        double sa = 0, sj = 0, sp = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3], u[3];
+            for (int k = 0; k < 3; ++k) {
+                d[k] = pos[3 * j + k] - pos[3 * i + k];
+                u[k] = vel[3 * j + k] - vel[3 * i + k];
+            }
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            double s2 = r2 + eps2;
+            double s = sqrt(s2);
+            double K, slope;
+            k_and_slope(&p, s, &K, &slope);
+            if (p.mode == 0 || s >= p.r_out) continue;   /* K = 0 and Phi_I = 0 */
+            double du = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+            double s3 = s2 * s;
+            double Kdot = -slope * du / s;
+            for (int k = 0; k < 3; ++k) {
+                a[k] += mass[j] * K * d[k] / s3;
+                jk[k] += mass[j] * (K * (u[k] / s3 - 3.0 * du * d[k] / (s3 * s2)) + Kdot * d[k] / s3);
+            }
+            double phiR = phir_eval(&p, s);
+            ph += mass[j] * (-1.0 / s - phiR);
+            double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            sa += mass[j] / s2;
+            sj += mass[j] * un * (4.0 / s3 + (p.mode == 2 ? (140.0 / 64.0) / (s2 * p.D) : 0.0));
+            sp += mass[j] * (1.0 / s + fabs(phiR));
+        }
+        for (int k = 0; k < 3; ++k) {
+            acc[3 * t + k] = a[k];
+            if (jerk) jerk[3 * t + k] = jk[k];
+        }
+        if (pot) pot[t] = ph;
+        if (scale) {
+            scale[3 * t] = sa;
+            scale[3 * t + 1] = sj;
+            scale[3 * t + 2] = sp;
+        }
     }
 }
 

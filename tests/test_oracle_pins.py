@@ -195,6 +195,135 @@ def test_split_identity_and_newton3():
     assert np.linalg.norm(mom) <= 1e-12 * (c.mass * np.linalg.norm(acc, axis=1)).sum()
 
 
+# --- Irregular force F_I, its time derivative and potential (Section 2.1) ----
+
+def _ball(n, seed, radius=0.1):
+    """n particles in a ball with random velocities and masses (not Plummer:
+    dense enough that most pairs fall in the changeover band)."""
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(-radius, radius, size=(n, 3))
+    vel = rng.normal(size=(n, 3))
+    mass = rng.uniform(0.5, 1.5, size=n) / n
+    return pos, vel, mass
+
+
+def test_irregular_split_identity_and_newton3():
+    # F_R + F_I is plain softened gravity, and so is Phi_R + Phi_I (eq. fi and
+    # the definition F_R = total - F_I)
+    c = ic.plummer(2048, seed=12, masses="kroupa")
+    r_out = 0.12
+    r_in = 0.1 * r_out
+    eps = 1e-4
+    acc_r, pot_r = oracle.direct(c.pos, c.mass, r_in, r_out, eps)
+    acc_i, jerk_i, pot_i, scale = oracle.irregular(c.pos, c.vel, c.mass, r_in, r_out, eps)
+    full, full_pot = oracle.full_direct(c.pos, c.mass, eps)
+    err = np.linalg.norm(acc_r + acc_i - full, axis=1) / np.linalg.norm(full, axis=1)
+    assert err.max() < 1e-12
+    assert np.abs(pot_r + pot_i - full_pot).max() < 1e-12 * np.abs(full_pot).max()
+    assert (scale[:, 0] > 0).sum() > 1000   # many particles have pairs inside r_out
+    # antisymmetric pair sums: total momentum change vanishes, also for the jerk
+    mom = (c.mass[:, None] * acc_i).sum(0)
+    assert np.linalg.norm(mom) <= 1e-13 * (c.mass * scale[:, 0]).sum()
+    mdot = (c.mass[:, None] * jerk_i).sum(0)
+    assert np.linalg.norm(mdot) <= 1e-13 * (c.mass * scale[:, 1]).sum()
+
+
+@pytest.mark.parametrize("r_in,r_out,eps", [(0.005, 0.05, 0.0), (0.01, 0.08, 0.004),
+                                            (0.0, 0.06, 0.0)])
+def test_irregular_jerk_is_time_derivative(r_in, r_out, eps):
+    # the jerk is dF_I/dt along straight-line motion x(t) = x + v t: a central
+    # difference of F_I pins every term (K, the -3 (d.u) d / s^5 term, m_j and
+    # the sign of dK/dt)
+    pos, vel, mass = _ball(160, seed=21)
+    acc, jerk, _, scale = oracle.irregular(pos, vel, mass, r_in, r_out, eps)
+    h = 2e-6
+    ap, _, _, _ = oracle.irregular(pos + h * vel, vel, mass, r_in, r_out, eps)
+    am, _, _, _ = oracle.irregular(pos - h * vel, vel, mass, r_in, r_out, eps)
+    fd = (ap - am) / (2 * h)
+    err = np.linalg.norm(fd - jerk, axis=1)
+    live = scale[:, 1] > 0
+    assert live.sum() > 100
+    assert np.all(err[live] <= 1e-6 * scale[live, 1])
+    assert np.all(jerk[~live] == 0) and np.all(acc[~live] == 0)
+    # the changeover slope term is a sizeable part of the jerk here
+    if r_out > r_in:
+        acc_step, jerk_step, _, _ = oracle.irregular(pos, vel, mass, r_out, r_out, eps)
+        assert np.linalg.norm(jerk - jerk_step) > 0.1 * np.linalg.norm(jerk)
+
+
+def test_irregular_potential_gradient():
+    # -grad_i Phi_I,i = F_I,i, moving particle i alone
+    pos, vel, mass = _ball(120, seed=22)
+    r_in, r_out, eps = 0.006, 0.06, 0.002
+    tg = np.array([0, 7, 33, 90])
+    acc, _, _, scale = oracle.irregular(pos, vel, mass, r_in, r_out, eps, targets=tg)
+    # F_I is a cancelling sum: bound against its magnitude sum sum m_j / s^2
+    # (difference truncation ~ h^2 m / s^5, rounding ~ 1e-16 |Phi| / h)
+    h = 1e-6
+    for t, i in enumerate(tg):
+        g = np.zeros(3)
+        for k in range(3):
+            pp = pos.copy()
+            pp[i, k] += h
+            pm = pos.copy()
+            pm[i, k] -= h
+            _, _, php, _ = oracle.irregular(pp, vel, mass, r_in, r_out, eps, targets=[i])
+            _, _, phm, _ = oracle.irregular(pm, vel, mass, r_in, r_out, eps, targets=[i])
+            g[k] = (php[0] - phm[0]) / (2 * h)
+        assert np.linalg.norm(-g - acc[t]) <= 1e-8 * scale[t, 0]
+        assert np.linalg.norm(acc[t]) > 1e-4 * scale[t, 0]
+
+
+def test_irregular_two_body_closed_forms():
+    r_in, r_out = 0.01, 0.1
+    dl = r_out - r_in
+    s = r_in + 0.5 * dl            # x = 1/2: K = 1/2, g'(1/2) = 140/64
+    m1 = 0.7
+    pos = np.array([[0.0, 0.0, 0.0], [s, 0.0, 0.0]])
+    mass = np.array([0.3, m1])
+    w = 2.0
+    # radial approach of particle 1 (u = v_1 - v_0 along d)
+    vel = np.array([[0.0, 0.0, 0.0], [w, 0.0, 0.0]])
+    acc, jerk, pot, _ = oracle.irregular(pos, vel, mass, r_in, r_out, 0.0)
+    assert acc[0, 0] == pytest.approx(m1 * 0.5 / s**2, rel=1e-14)
+    # K [u/s^3 - 3 (d.u) d/s^5] = -2 K w / s^3 ; dK/dt d/s^3 = -(140/64)(w/dl)/s^2
+    assert jerk[0, 0] == pytest.approx(m1 * (-w / s**3 - (140 / 64) * w / (dl * s**2)), rel=1e-13)
+    assert np.all(jerk[:, 1:] == 0)
+    assert pot[0] == pytest.approx(m1 * (-1.0 / s - oracle.phiR(s, r_in, r_out)), rel=1e-14)
+    # tangential motion: d.u = 0, only the K u / s^3 term
+    vel = np.array([[0.0, 0.0, 0.0], [0.0, w, 0.0]])
+    _, jerk, _, _ = oracle.irregular(pos, vel, mass, r_in, r_out, 0.0)
+    assert jerk[0, 1] == pytest.approx(m1 * 0.5 * w / s**3, rel=1e-14)
+    assert jerk[0, 0] == 0 and jerk[0, 2] == 0
+    # inside r_in the pair is wholly irregular: Newtonian force and jerk
+    pos[1, 0] = 0.5 * r_in
+    vel = np.array([[0.0, 0.0, 0.0], [w, w, 0.0]])
+    acc, jerk, pot, _ = oracle.irregular(pos, vel, mass, r_in, r_out, 0.0)
+    r = 0.5 * r_in
+    assert acc[0, 0] == pytest.approx(m1 / r**2, rel=1e-14)
+    assert jerk[0, 0] == pytest.approx(m1 * (w / r**3 - 3 * w / r**3), rel=1e-14)
+    assert jerk[0, 1] == pytest.approx(m1 * w / r**3, rel=1e-14)
+    assert pot[0] == pytest.approx(m1 * (-1.0 / r - oracle.phiR(0.0, r_in, r_out)), rel=1e-14)
+    # beyond r_out nothing is irregular
+    pos[1, 0] = 1.5 * r_out
+    acc, jerk, pot, scale = oracle.irregular(pos, vel, mass, r_in, r_out, 0.0)
+    assert np.all(acc == 0) and np.all(jerk == 0) and np.all(pot == 0) and np.all(scale == 0)
+
+
+def test_irregular_degenerate_radii():
+    pos, vel, mass = _ball(60, seed=23)
+    # r_out = 0: everything is regular
+    acc, jerk, pot, _ = oracle.irregular(pos, vel, mass, 0.0, 0.0, 1e-3)
+    assert np.all(acc == 0) and np.all(jerk == 0) and np.all(pot == 0)
+    # r_in = r_out larger than the ball: every pair wholly irregular, so F_I is
+    # plain softened gravity and Phi_I = -1/s + 1/r_out (Phi_R = -1/r_out)
+    R, eps = 10.0, 1e-3
+    acc, jerk, pot, _ = oracle.irregular(pos, vel, mass, R, R, eps)
+    full, full_pot = oracle.full_direct(pos, mass, eps)
+    assert np.abs(acc - full).max() <= 1e-13 * np.abs(full).max()
+    assert np.abs(pot - (full_pot + (mass.sum() - mass) / R)).max() <= 1e-13 * np.abs(full_pot).max()
+
+
 # --- P-7: Plummer potential, inward field, virial energy ---------------------
 
 def test_plummer_field_henon_units():
