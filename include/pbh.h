@@ -87,7 +87,8 @@ typedef struct {
     int64_t n_pp_far;     /* particle-particle pairs outside r_out (W = 1) */
     int64_t n_pp_near;    /* pairs inside near leaves (changeover applied; self pairs counted) */
     int64_t nbr_total;    /* neighbour entries of the last force call */
-    int64_t error_flags;  /* device-side guard bits; 0 when healthy */
+    int64_t error_flags;  /* device-side guard bits; 0 when healthy (bits 8-10:
+                             malformed input of the last pbh_irregular call) */
     /* Phase durations of the last build / force call in milliseconds, from
        HIP events recorded on the call's stream; 0 unless timing is enabled
        (pbh_set_timing). walk = the tree-walk kernel alone. */
@@ -157,6 +158,63 @@ pbh_status pbh_force_batched(pbh_ctx* ctx, const double* r_in, const double* r_o
                              double theta, double eps, double* acc, double* pot,
                              int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap,
                              int64_t* nbr_total, pbh_stream_t stream);
+
+/*
+ * Irregular (neighbour) force, its time derivative and the irregular
+ * potential from neighbour lists, in FP64 (Section 2.1, eq. fi, eq. fidot,
+ * eq. duncan, eq. duncan2). With d = x_j - x_i, u = v_j - v_i,
+ * s^2 = |d|^2 + eps^2, K = 1 - W and x = (s - r_in)/(r_out - r_in):
+ *   acc_i  = sum_{j in list(i), j != i} m_j K(s) d / s^3
+ *   jerk_i = sum m_j { K(s) [u / s^3 - 3 (d.u) d / s^5] + (dK/dt) d / s^3 },
+ *            dK/dt = -140 x^3 (1-x)^3 (d.u) / (s (r_out - r_in)) on
+ *            r_in <= s < r_out and 0 elsewhere (the term-by-term time
+ *            derivative of eq. fi; eq. fidot as printed drops m_j and K from
+ *            its second term, and eq. duncan2 has the opposite sign)
+ *   pot_i  = sum m_j (-1/s - Phi_R(s)), so pot_i plus the regular potential
+ *            of pbh_force is plain softened gravity.
+ * Pairs with s >= r_out contribute nothing, so lists holding every j with
+ * r_ij < r_out (the lists of pbh_force with the same r_out) give the whole
+ * irregular force; lists of a larger radius give the same sums. A coincident
+ * pair (s = 0) has no finite irregular force.
+ *   n            particles, 1 <= n < 2^31
+ *   pos, vel     [n][3] FP64 (vel may be NULL when jerk is NULL); mass [n]
+ *   r_in, r_out  changeover radii as in pbh_force
+ *   eps          Plummer softening >= 0
+ *   nbr_off      [n+1] CSR offsets, nbr_idx [nbr_cap] caller-order indices
+ *                (a list entry equal to i is skipped)
+ *   targets      NULL: all n particles, outputs [n] in caller order; else a
+ *                device int32 array of n_targets caller indices whose
+ *                results go to outputs [n_targets] in that order (e.g. the
+ *                active particles of a block time step); a non-NULL list
+ *                with n_targets = 0 does nothing
+ *   acc          output [.][3]; jerk [.][3] and pot [.] outputs or NULL
+ *   check        1: wait for the stream and return PBH_E_ARG if a target,
+ *                offset or list entry was out of range (it is skipped, never
+ *                read); 0: do not wait, report such input in
+ *                pbh_stats.error_flags bits 8 (list entry), 9 (offsets) and
+ *                10 (target)
+ * The call needs no build. When the context holds a build of n particles
+ * and targets is NULL the particles are processed in its key order (faster;
+ * the results are identical).
+ */
+pbh_status pbh_irregular(pbh_ctx* ctx, int64_t n, const double* pos, const double* vel,
+                         const double* mass, double r_in, double r_out, double eps,
+                         const int64_t* nbr_off, const int32_t* nbr_idx, int64_t nbr_cap,
+                         int64_t n_targets, const int32_t* targets,
+                         double* acc, double* jerk, double* pot, int32_t check,
+                         pbh_stream_t stream);
+
+/*
+ * pbh_irregular over the clusters of the last batched build: n and the
+ * cluster ranges are the build's; r_in/r_out are host arrays [n_clusters]
+ * and particle i takes the radii of its own cluster.
+ */
+pbh_status pbh_irregular_batched(pbh_ctx* ctx, const double* pos, const double* vel,
+                                 const double* mass, const double* r_in, const double* r_out,
+                                 double eps, const int64_t* nbr_off, const int32_t* nbr_idx,
+                                 int64_t nbr_cap, int64_t n_targets, const int32_t* targets,
+                                 double* acc, double* jerk, double* pot, int32_t check,
+                                 pbh_stream_t stream);
 
 /*
  * Kick-drift-kick leapfrog under the regular force (Section 2.2, eq. kick and

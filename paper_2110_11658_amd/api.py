@@ -149,6 +149,53 @@ class Pbh:
                                          _stream()))
 
     # -- pbh_kdk --------------------------------------------------------------
+    # -- pbh_irregular / pbh_irregular_batched -------------------------------
+    def irregular(self, pos: torch.Tensor, vel: Optional[torch.Tensor], mass: torch.Tensor,
+                  r_in, r_out, eps: float, nbr_off: torch.Tensor, nbr_idx: torch.Tensor,
+                  targets: Optional[torch.Tensor] = None, jerk: bool = True, pot: bool = True,
+                  validate: bool = True, batched: bool = False):
+        """Irregular force, its time derivative and potential from neighbour
+        lists (eq. fi, fidot, duncan). Returns (acc, jerk or None, pot or None),
+        [n] rows in caller order, or one row per entry of ``targets``.
+        ``validate`` waits and raises on out-of-range targets or list entries.
+        With ``batched`` the radii are per-cluster sequences of the last
+        batched build."""
+        n = pos.shape[0]
+        _need(pos, (n, 3), "pos")
+        _need(mass, (n,), "mass")
+        if jerk:
+            _need(vel, (n, 3), "vel")
+        _need(nbr_off, (n + 1,), "nbr_off", torch.int64)
+        _need(nbr_idx, (nbr_idx.shape[0],), "nbr_idx", torch.int32)
+        rows = n
+        if targets is not None:
+            _need(targets, (targets.shape[0],), "targets", torch.int32)
+            rows = targets.shape[0]
+        opts = dict(dtype=torch.float64, device=pos.device)
+        acc = torch.empty((rows, 3), **opts)
+        jk = torch.empty((rows, 3), **opts) if jerk else None
+        ph = torch.empty((rows,), **opts) if pot else None
+        if rows == 0:   # an empty target list (its data pointer would read as "all")
+            return acc, jk, ph
+        common = (float(eps), _ptr(nbr_off), _ptr(nbr_idx), int(nbr_idx.shape[0]),
+                  int(rows if targets is not None else 0), _ptr(targets), _ptr(acc), _ptr(jk),
+                  _ptr(ph), int(bool(validate)), _stream())
+        if batched:
+            if n != self.n:
+                raise ValueError("batched irregular force needs the particles of the last build")
+            ri = np.ascontiguousarray(r_in, dtype=np.float64)
+            ro = np.ascontiguousarray(r_out, dtype=np.float64)
+            if ri.shape != (self.n_clusters,) or ro.shape != (self.n_clusters,):
+                raise ValueError("need one r_in and r_out per cluster")
+            st = self.L.pbh_irregular_batched(self.ctx, _ptr(pos), _ptr(vel), _ptr(mass),
+                                              ri.ctypes.data_as(C.c_void_p),
+                                              ro.ctypes.data_as(C.c_void_p), *common)
+        else:
+            st = self.L.pbh_irregular(self.ctx, n, _ptr(pos), _ptr(vel), _ptr(mass), float(r_in),
+                                      float(r_out), *common)
+        check(self.ctx, st)
+        return acc, jk, ph
+
     def kdk(self, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor, dt: float, steps: int,
             r_in: float, r_out: float, theta: float, eps: float, graph: bool = True,
             energy: Optional[torch.Tensor] = None) -> torch.Tensor:

@@ -67,6 +67,9 @@ struct pbh_ctx {
     std::vector<double> bkey;
     std::vector<double> gkey;   // parameters the captured graph was made with
 
+    // irregular-force calls: device flag word of the last call (kIrr* bits)
+    unsigned long long* irr_err = nullptr;
+
     // phase timing: events 0/1 build, 2/3 walk, 4/5 neighbours
     bool timing = false;
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -495,6 +498,57 @@ pbh_status do_force(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, double 
     return PBH_OK;
 }
 
+// Shared part of pbh_irregular and pbh_irregular_batched: p already holds the
+// cluster constants (C, cl_off, cps or cp0).
+pbh_status do_irregular(pbh_ctx* ctx, IrrParams& p, int64_t n, const double* pos, const double* vel,
+                        const double* mass, double eps, const int64_t* nbr_off,
+                        const int32_t* nbr_idx, int64_t nbr_cap, int64_t n_targets,
+                        const int32_t* targets, double* acc, double* jerk, double* pot,
+                        int32_t check, hipStream_t s) {
+    if (n < 1 || n >= (1ll << 31) - 1) return fail(ctx, PBH_E_ARG, "need 1 <= n < 2^31");
+    if (targets && n_targets < 0) return fail(ctx, PBH_E_ARG, "n_targets must be >= 0");
+    if (targets && n_targets == 0) return PBH_OK;   // an empty target list: nothing to do
+    if (!pos || !mass || !acc || !nbr_off) return fail(ctx, PBH_E_ARG, "pos, mass, acc and nbr_off are required");
+    if (jerk && !vel) return fail(ctx, PBH_E_ARG, "the jerk needs vel");
+    if (nbr_cap < 0 || (nbr_cap > 0 && !nbr_idx)) return fail(ctx, PBH_E_ARG, "bad neighbour buffer");
+    if (!finite_nonneg(eps)) return fail(ctx, PBH_E_ARG, "eps must be finite and >= 0");
+    if (!ctx->irr_err) {
+        void* q = nullptr;
+        if (hipMalloc(&q, sizeof(unsigned long long)) != hipSuccess)
+            return fail(ctx, PBH_E_OOM, "irregular-force flag word");
+        ctx->irr_err = (unsigned long long*)q;
+    }
+    launch_zero_u64(ctx->irr_err, 1, s);
+    p.n = n;
+    p.n_tgt = targets ? n_targets : n;
+    p.tgt = targets;
+    // all targets: walk them in the key order of a build of the same particle
+    // count when there is one (gathers hit cache; the sums do not depend on it)
+    p.order = (!targets && ctx->built && ctx->cfg.n == n) ? ctx->d.perm : nullptr;
+    p.pos = pos;
+    p.vel = vel;
+    p.mass = mass;
+    p.off = nbr_off;
+    p.idx = nbr_idx;
+    p.cap = nbr_cap;
+    p.eps2 = eps * eps;
+    p.acc = acc;
+    p.jerk = jerk;
+    p.pot = pot;
+    p.err = ctx->irr_err;
+    launch_irregular(p, s);
+    HIP_TRY(hipGetLastError());
+    if (check) {
+        unsigned long long err = 0;
+        HIP_TRY(hipMemcpyAsync(&err, ctx->irr_err, sizeof(err), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (err & kIrrBadTarget) return fail(ctx, PBH_E_ARG, "a target index is outside [0, n)");
+        if (err & kIrrBadOffsets) return fail(ctx, PBH_E_ARG, "neighbour offsets decrease or pass nbr_cap");
+        if (err & kIrrBadIndex) return fail(ctx, PBH_E_ARG, "a neighbour index is outside [0, n)");
+    }
+    return PBH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -567,6 +621,7 @@ void pbh_destroy(pbh_ctx* ctx) {
     if (ctx->k_acc) (void)hipFree(ctx->k_acc);
     if (ctx->k_pot) (void)hipFree(ctx->k_pot);
     if (ctx->k_epart) (void)hipFree(ctx->k_epart);
+    if (ctx->irr_err) (void)hipFree(ctx->irr_err);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
@@ -669,6 +724,56 @@ pbh_status pbh_force_batched(pbh_ctx* ctx, const double* r_in, const double* r_o
     return do_force(ctx, cps, theta, eps, acc, pot, nbr_off, nbr_idx, nbr_cap, nbr_total, s);
 }
 
+pbh_status pbh_irregular(pbh_ctx* ctx, int64_t n, const double* pos, const double* vel,
+                         const double* mass, double r_in, double r_out, double eps,
+                         const int64_t* nbr_off, const int32_t* nbr_idx, int64_t nbr_cap,
+                         int64_t n_targets, const int32_t* targets, double* acc, double* jerk,
+                         double* pot, int32_t check, pbh_stream_t stream) {
+    if (!ctx) return PBH_E_ARG;
+    pbh_status st = check_radii(ctx, r_in, r_out);
+    if (st != PBH_OK) return st;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    IrrParams p;
+    p.C = 1;
+    p.cp0 = cluster_params(r_in, r_out);
+    return do_irregular(ctx, p, n, pos, vel, mass, eps, nbr_off, nbr_idx, nbr_cap, n_targets,
+                        targets, acc, jerk, pot, check, s);
+}
+
+pbh_status pbh_irregular_batched(pbh_ctx* ctx, const double* pos, const double* vel,
+                                 const double* mass, const double* r_in, const double* r_out,
+                                 double eps, const int64_t* nbr_off, const int32_t* nbr_idx,
+                                 int64_t nbr_cap, int64_t n_targets, const int32_t* targets,
+                                 double* acc, double* jerk, double* pot, int32_t check,
+                                 pbh_stream_t stream) {
+    if (!ctx) return PBH_E_ARG;
+    if (!ctx->built) return fail(ctx, PBH_E_STATE, "no successful build");
+    if (!r_in || !r_out) return fail(ctx, PBH_E_ARG, "r_in and r_out arrays are required");
+    const int C = ctx->cfg.n_clusters;
+    std::vector<ClusterParams> cps;
+    for (int k = 0; k < C; ++k) {
+        pbh_status st = check_radii(ctx, r_in[k], r_out[k]);
+        if (st != PBH_OK) return st;
+        cps.push_back(cluster_params(r_in[k], r_out[k]));
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    IrrParams p;
+    p.C = C;
+    p.cp0 = cps[0];
+    if (C > 1) {
+        pbh_status up = upload_cparams(ctx, cps, s);
+        if (up != PBH_OK) return up;
+        p.cl_off = ctx->d.cl_off;
+        p.cps = ctx->d.cparams;
+    }
+    return do_irregular(ctx, p, ctx->cfg.n, pos, vel, mass, eps, nbr_off, nbr_idx, nbr_cap,
+                        n_targets, targets, acc, jerk, pot, check, s);
+}
+
 static pbh_status kdk_prepare(pbh_ctx* ctx, int64_t n, double r_in, double r_out, double theta,
                               double eps, hipStream_t s) {
     if (n < 1 || n >= (1ll << 31) - 1) return fail(ctx, PBH_E_ARG, "bad n");
@@ -682,6 +787,7 @@ static pbh_status kdk_prepare(pbh_ctx* ctx, int64_t n, double r_in, double r_out
         if (ctx->k_acc) (void)hipFree(ctx->k_acc);
         if (ctx->k_pot) (void)hipFree(ctx->k_pot);
         if (ctx->k_epart) (void)hipFree(ctx->k_epart);
+    if (ctx->irr_err) (void)hipFree(ctx->irr_err);
         ctx->k_acc = ctx->k_pot = ctx->k_epart = nullptr;
         ctx->k_n = -1;
         ctx->k_nblk = (int)std::min<int64_t>(1024, (n + 255) / 256) + 1;
@@ -811,9 +917,14 @@ static double event_ms(hipEvent_t a, hipEvent_t b) {
 pbh_status pbh_get_stats(pbh_ctx* ctx, pbh_stats* out) {
     if (!ctx || !out) return PBH_E_ARG;
     std::memset(out, 0, sizeof(*out));
-    if (!ctx->d.cnt) return PBH_OK;
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(hipStreamSynchronize(ctx->last));
+    if (ctx->irr_err) {
+        unsigned long long f = 0;
+        HIP_TRY(hipMemcpy(&f, ctx->irr_err, sizeof(f), hipMemcpyDeviceToHost));
+        out->error_flags = (int64_t)(f << 8);
+    }
+    if (!ctx->d.cnt) return PBH_OK;
     unsigned long long h[kNumCounters];
     HIP_TRY(hipMemcpy(h, ctx->d.cnt, sizeof(h), hipMemcpyDeviceToHost));
     out->n = ctx->cfg.n;
@@ -825,7 +936,7 @@ pbh_status pbh_get_stats(pbh_ctx* ctx, pbh_stats* out) {
     out->n_pn = (int64_t)h[kCntPN];
     out->n_pp_far = (int64_t)h[kCntFar];
     out->n_pp_near = (int64_t)h[kCntNear];
-    out->error_flags = (int64_t)h[kErr];
+    out->error_flags |= (int64_t)h[kErr];
     if (ctx->ev_build) out->ms_build = event_ms(ctx->ev[0], ctx->ev[1]);
     if (ctx->ev_walk) out->ms_walk = event_ms(ctx->ev[2], ctx->ev[3]);
     if (ctx->ev_nbr) out->ms_nbr = event_ms(ctx->ev[4], ctx->ev[5]);

@@ -222,6 +222,35 @@ void launch_nbr_copy(Dev& d, const BuildCfg& c, int stage_cap, const int64_t* of
 void launch_nbr_fill(Dev& d, const BuildCfg& c, int grid, int stack_cap, const int64_t* off,
                      int32_t* idx, int64_t cap, hipStream_t s);
 
+// irr.hip: irregular force, jerk and potential from neighbour lists
+enum : unsigned long long {
+    kIrrBadIndex = 1ull,     // a list entry outside [0, n)
+    kIrrBadOffsets = 2ull,   // off[i] < 0, off[i+1] < off[i] or off[i+1] > cap
+    kIrrBadTarget = 4ull,    // a target index outside [0, n)
+};
+struct IrrParams {
+    int64_t n = 0;              // particles (caller order)
+    int64_t n_tgt = 0;          // targets of this launch
+    const int32_t* tgt = nullptr;    // target caller indices (outputs compact), or null = all
+    const int32_t* order = nullptr;  // processing order of all targets (outputs by index), or null
+    const double* pos = nullptr;     // [n][3]
+    const double* vel = nullptr;     // [n][3] (jerk only)
+    const double* mass = nullptr;    // [n]
+    const int64_t* off = nullptr;    // [n+1]
+    const int32_t* idx = nullptr;    // [cap]
+    int64_t cap = 0;
+    int C = 1;                        // clusters; > 1: cluster of i from cl_off, constants from cps
+    const int64_t* cl_off = nullptr;  // [C+1] caller-order cluster offsets
+    const ClusterParams* cps = nullptr;
+    ClusterParams cp0;                // constants when C == 1
+    double eps2 = 0.0;
+    double* acc = nullptr;            // outputs ([n_tgt] or [n] slots)
+    double* jerk = nullptr;           // may be null
+    double* pot = nullptr;            // may be null
+    unsigned long long* err = nullptr;   // kIrr* flag bits (OR)
+};
+void launch_irregular(const IrrParams& p, hipStream_t s);
+
 // kdk.hip
 void launch_kick(double* vel, const double* acc, double h, int64_t n, hipStream_t s);
 void launch_drift(double* pos, const double* vel, double dt, int64_t n, hipStream_t s);

@@ -1,0 +1,225 @@
+"""GPU parity of the irregular force, its time derivative and the irregular
+potential (pbh_irregular, through the C ABI) against the CPU oracle.
+
+The oracle sums over every j != i with the changeover function K (Section 2.1,
+eq. fi, eq. fidot, eq. duncan, eq. duncan2); the GPU sums over the neighbour
+lists that pbh_force wrote, so each comparison also checks that the lists hold
+every pair with K != 0.
+
+Tolerance: per particle and component group, |GPU - oracle| <= 1e-12 times
+the oracle's magnitude sum over the pairs inside r_out (sum m/s^2 for the
+force, sum m|u|(4/s^3 + max g'/(s^2 (r_out - r_in))) for the jerk,
+sum m (1/s + |Phi_R|) for the potential). Both sides are FP64; each pair term
+carries a few hundred ulp at most (the closed-form Phi_R cancels about two
+decimal digits) and the sums differ only in order, so the bound holds with a
+margin of about ten.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2110_11658_amd import ic
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0) if torch.cuda.is_available() else None
+TOL = 1e-12
+
+
+def _pbh(**kw):
+    from paper_2110_11658_amd.api import Pbh
+    return Pbh(0, **kw)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _np(t):
+    return None if t is None else t.cpu().numpy()
+
+
+def _lists(p, pos, mass, r_in, r_out, eps, theta=0.5):
+    p.build(_t(pos), _t(mass))
+    _, _, off, idx = p.force(r_in, r_out, theta, eps)
+    return off, idx
+
+
+def _compare(got, ref, rows=None):
+    acc, jerk, pot = got
+    oacc, ojerk, opot, scale = ref
+    if rows is not None:
+        oacc, ojerk, opot, scale = oacc[rows], ojerk[rows], opot[rows], scale[rows]
+    ea = np.linalg.norm(acc - oacc, axis=1)
+    assert np.all(ea <= TOL * scale[:, 0]), f"acc: worst {np.max(ea / np.maximum(scale[:, 0], 1e-300))}"
+    if jerk is not None:
+        ej = np.linalg.norm(jerk - ojerk, axis=1)
+        assert np.all(ej <= TOL * scale[:, 1]), f"jerk: worst {np.max(ej / np.maximum(scale[:, 1], 1e-300))}"
+    if pot is not None:
+        ep = np.abs(pot - opot)
+        assert np.all(ep <= TOL * scale[:, 2]), f"pot: worst {np.max(ep / np.maximum(scale[:, 2], 1e-300))}"
+    # particles without pairs inside r_out are exactly zero
+    empty = scale[:, 0] == 0
+    assert np.all(acc[empty] == 0)
+
+
+@pytest.mark.parametrize("n,nbar,eps,gamma,seed", [
+    (4096, 64.0, 1e-4, 0.1, 31),     # dense lists, many pairs in the changeover band
+    (3001, 0.46, 1e-4, 0.1, 32),     # the paper's regime: lists mostly empty
+    (2000, 30.0, 0.0, 0.0, 33),      # r_in = 0 (no pole terms), no softening
+    (1500, 40.0, 2e-3, 1.0, 34),     # step changeover r_in = r_out
+])
+def test_irregular_matches_oracle(n, nbar, eps, gamma, seed):
+    print(f"irregular n={n} nbar={nbar} eps={eps} gamma={gamma}", flush=True)
+    c = ic.plummer(n, seed=seed, masses="kroupa")
+    r_out = ic.r_out_for_nbar(n, nbar)
+    r_in = gamma * r_out
+    p = _pbh()
+    off, idx = _lists(p, c.pos, c.mass, r_in, r_out, eps)
+    got = p.irregular(_t(c.pos), _t(c.vel), _t(c.mass), r_in, r_out, eps, off, idx)
+    torch.cuda.synchronize()
+    ref = oracle.irregular(c.pos, c.vel, c.mass, r_in, r_out, eps)
+    _compare([_np(g) for g in got], ref)
+    if nbar > 10:
+        assert (ref[3][:, 0] > 0).mean() > 0.8   # halo particles have none
+    assert p.stats()["error_flags"] == 0
+
+
+def test_irregular_split_identity_on_gpu():
+    # F_R (pbh_force, FP64, theta = 0) + F_I (pbh_irregular) = plain softened
+    # gravity, and the same for the potentials (eq. fi: F_R = total - F_I)
+    n = 3000
+    c = ic.plummer(n, seed=35, masses="kroupa")
+    r_out = ic.r_out_for_nbar(n, 64.0)
+    r_in, eps = 0.1 * r_out, 1e-4
+    p = _pbh(prec="fp64")
+    p.build(_t(c.pos), _t(c.mass))
+    acc_r, pot_r, off, idx = p.force(r_in, r_out, 0.0, eps)
+    acc_i, _, pot_i = p.irregular(_t(c.pos), _t(c.vel), _t(c.mass), r_in, r_out, eps, off, idx,
+                                  jerk=False)
+    full, full_pot = oracle.full_direct(c.pos, c.mass, eps)
+    tot = _np(acc_r) + _np(acc_i)
+    err = np.linalg.norm(tot - full, axis=1) / np.linalg.norm(full, axis=1)
+    assert err.max() < 1e-11
+    assert np.abs(_np(pot_r) + _np(pot_i) - full_pot).max() < 1e-11 * np.abs(full_pot).max()
+
+
+def test_irregular_targets_and_order_do_not_change_results():
+    n = 5000
+    c = ic.plummer(n, seed=36, masses="kroupa")
+    r_out = ic.r_out_for_nbar(n, 64.0)
+    r_in, eps = 0.1 * r_out, 1e-4
+    p = _pbh()
+    off, idx = _lists(p, c.pos, c.mass, r_in, r_out, eps)
+    pos, vel, mass = _t(c.pos), _t(c.vel), _t(c.mass)
+    full = [_np(g) for g in p.irregular(pos, vel, mass, r_in, r_out, eps, off, idx)]
+    # a context without a build processes in caller order: identical sums
+    q = _pbh()
+    plain = [_np(g) for g in q.irregular(pos, vel, mass, r_in, r_out, eps, off, idx)]
+    for a, b in zip(full, plain):
+        assert np.array_equal(a, b)
+    # a target subset (with a repeat) returns the same rows, compact
+    rng = np.random.default_rng(7)
+    tg = rng.choice(n, size=333, replace=False).astype(np.int32)
+    tg[5] = tg[4]
+    sub = [_np(g) for g in p.irregular(pos, vel, mass, r_in, r_out, eps, off, idx,
+                                       targets=_t(tg))]
+    for a, b in zip(sub, full):
+        assert np.array_equal(a, b[tg])
+    ref = oracle.irregular(c.pos, c.vel, c.mass, r_in, r_out, eps, targets=tg.astype(np.int64))
+    _compare(sub, ref)
+    # empty target list
+    e = p.irregular(pos, vel, mass, r_in, r_out, eps, off, idx, targets=_t(np.zeros(0, np.int32)))
+    assert e[0].shape == (0, 3)
+    # optional outputs off
+    a, j, ph = p.irregular(pos, None, mass, r_in, r_out, eps, off, idx, jerk=False, pot=False)
+    assert j is None and ph is None and np.array_equal(_np(a), full[0])
+
+
+def test_irregular_batched_per_cluster():
+    ens = ic.ensemble(n_clusters=6, seed0=4100, nmin=500, nmax=4000)
+    eps = 1e-4
+    p = _pbh()
+    p.build_batched(ens.offsets, _t(ens.pos), _t(ens.mass))
+    _, _, off, idx = p.force_batched(ens.r_in, ens.r_out, 0.5, eps)
+    got = [_np(g) for g in p.irregular(_t(ens.pos), _t(ens.vel), _t(ens.mass), ens.r_in,
+                                       ens.r_out, eps, off, idx, batched=True)]
+    for k in range(ens.n_clusters):
+        a, b = ens.offsets[k], ens.offsets[k + 1]
+        ref = oracle.irregular(ens.pos[a:b], ens.vel[a:b], ens.mass[a:b], ens.r_in[k],
+                               ens.r_out[k], eps)
+        _compare([g[a:b] for g in got], ref)
+
+
+def test_irregular_degenerate_inputs():
+    p = _pbh()
+    # one particle: nothing irregular
+    pos = np.zeros((1, 3))
+    one = p.irregular(_t(pos), _t(pos), _t(np.ones(1)), 0.01, 0.1, 0.0,
+                      _t(np.zeros(2, np.int64)), _t(np.zeros(0, np.int32)))
+    assert all(np.all(_np(g) == 0) for g in one)
+    # r_out = 0: every pair regular, even with lists present
+    c = ic.plummer(500, seed=37)
+    r_out = ic.r_out_for_nbar(500, 30.0)
+    off, idx = _lists(p, c.pos, c.mass, 0.1 * r_out, r_out, 1e-4)
+    z = p.irregular(_t(c.pos), _t(c.vel), _t(c.mass), 0.0, 0.0, 1e-4, off, idx)
+    assert all(np.all(_np(g) == 0) for g in z)
+    # lists of a larger radius give the same sums (pairs beyond r_out add 0)
+    off2, idx2 = _lists(p, c.pos, c.mass, 0.05 * r_out, 2.0 * r_out, 1e-4)
+    a = [_np(g) for g in p.irregular(_t(c.pos), _t(c.vel), _t(c.mass), 0.1 * r_out, r_out, 1e-4,
+                                     off, idx)]
+    b = [_np(g) for g in p.irregular(_t(c.pos), _t(c.vel), _t(c.mass), 0.1 * r_out, r_out, 1e-4,
+                                     off2, idx2)]
+    ref = oracle.irregular(c.pos, c.vel, c.mass, 0.1 * r_out, r_out, 1e-4)
+    _compare(a, ref)
+    _compare(b, ref)
+
+
+def test_irregular_rejects_malformed_lists():
+    from paper_2110_11658_amd._lib import PBH_E_ARG, PbhError
+    n = 64
+    c = ic.plummer(n, seed=38)
+    pos, vel, mass = _t(c.pos), _t(c.vel), _t(c.mass)
+    p = _pbh()
+    off = np.arange(n + 1, dtype=np.int64)          # one entry per particle
+    good = ((np.arange(n) + 1) % n).astype(np.int32)
+    p.irregular(pos, vel, mass, 0.01, 10.0, 1e-3, _t(off), _t(good))
+    bad_idx = good.copy()
+    bad_idx[10] = n + 5
+    with pytest.raises(PbhError) as e:
+        p.irregular(pos, vel, mass, 0.01, 10.0, 1e-3, _t(off), _t(bad_idx))
+    assert e.value.status == PBH_E_ARG and "neighbour index" in str(e.value)
+    bad_off = off.copy()
+    bad_off[n] = n + 100                            # passes the index capacity
+    with pytest.raises(PbhError) as e:
+        p.irregular(pos, vel, mass, 0.01, 10.0, 1e-3, _t(bad_off), _t(good))
+    assert "offsets" in str(e.value)
+    with pytest.raises(PbhError) as e:
+        p.irregular(pos, vel, mass, 0.01, 10.0, 1e-3, _t(off), _t(good),
+                    targets=_t(np.array([3, -1], np.int32)))
+    assert "target" in str(e.value)
+    # without validation nothing waits; the bits appear in the stats
+    p.irregular(pos, vel, mass, 0.01, 10.0, 1e-3, _t(off), _t(bad_idx), validate=False)
+    assert p.stats()["error_flags"] & (1 << 8)
+    # the bad entry was skipped: the other particles are exact
+    a, _, _ = p.irregular(pos, vel, mass, 0.01, 10.0, 1e-3, _t(off), _t(bad_idx), validate=False)
+    ref = p.irregular(pos, vel, mass, 0.01, 10.0, 1e-3, _t(off), _t(good))
+    rows = np.arange(n) != 10
+    assert np.array_equal(_np(a)[rows], _np(ref[0])[rows]) and np.all(_np(a)[10] == 0)
+
+
+def test_irregular_full_size_sampled():
+    # the 2^20-particle Plummer/Kroupa workload with 64 neighbours on average:
+    # all particles on the GPU, 384 sampled targets by the oracle's O(S N) sum
+    c, w = ic.workload("plummer1m_kroupa")
+    print(f"irregular full size n={c.n}", flush=True)
+    p = _pbh()
+    off, idx = _lists(p, c.pos, c.mass, w["r_in"], w["r_out"], w["eps"], w["theta"])
+    got = [_np(g) for g in p.irregular(_t(c.pos), _t(c.vel), _t(c.mass), w["r_in"], w["r_out"],
+                                       w["eps"], off, idx)]
+    rng = np.random.default_rng(8)
+    tg = np.sort(rng.choice(c.n, size=384, replace=False))
+    ref = oracle.irregular(c.pos, c.vel, c.mass, w["r_in"], w["r_out"], w["eps"], targets=tg)
+    _compare([g[tg] for g in got], ref)
+    assert (ref[3][:, 0] > 0).mean() > 0.8
