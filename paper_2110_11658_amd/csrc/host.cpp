@@ -23,6 +23,7 @@ namespace {
 constexpr int kBoxChunk = 2048;      // particles per bbox/key block (512 blocks per 2^20)
 constexpr int kStackCap = 16384;     // traversal stack entries per persistent wave (LDS + spill)
 constexpr int kCntKdkStep = 11;      // counter slot: KDK energy output index
+constexpr int64_t kIrrPackRatio = 32;  // target lists of >= n/32 use the key-order records
 
 struct Buf {
     void* p = nullptr;
@@ -522,9 +523,25 @@ pbh_status do_irregular(pbh_ctx* ctx, IrrParams& p, int64_t n, const double* pos
     p.n = n;
     p.n_tgt = targets ? n_targets : n;
     p.tgt = targets;
-    // all targets: walk them in the key order of a build of the same particle
-    // count when there is one (gathers hit cache; the sums do not depend on it)
-    p.order = (!targets && ctx->built && ctx->cfg.n == n) ? ctx->d.perm : nullptr;
+    // With a build of the same particle count, all targets or a long target
+    // list: pack the particles into key-order records and take the targets in
+    // key order (a wave's gathers then stay in a compact, cached range; the
+    // sums do not depend on it). Otherwise gather from the caller's arrays
+    // (a short list does not pay for a pass over every particle).
+    Dev& d = ctx->d;
+    if (ctx->built && ctx->cfg.n == n && (!targets || n_targets * kIrrPackRatio >= n)) {
+        if (d.irr_len < n) {
+            if (!dalloc(ctx, &d.irr_rank, n) || !dalloc(ctx, &d.irr_rec, n)) {
+                (void)hipGetLastError();
+                return fail(ctx, PBH_E_OOM, "irregular-force records");
+            }
+            d.irr_len = n;
+        }
+        p.perm = d.perm;
+        p.rank = d.irr_rank;
+        p.rec = d.irr_rec;
+        p.order = targets ? nullptr : d.perm;
+    }
     p.pos = pos;
     p.vel = vel;
     p.mass = mass;

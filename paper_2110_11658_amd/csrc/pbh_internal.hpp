@@ -112,6 +112,11 @@ __host__ __device__ inline int64_t stage_index(int64_t i, int t, int cap) {
     return (i / kStageStride) * kStageStride * cap + (int64_t)t * kStageStride + (i % kStageStride);
 }
 
+// One particle of the irregular-force pass, packed in key order (64 B).
+struct alignas(64) IrrRec {
+    double x, y, z, m, vx, vy, vz, pad;
+};
+
 struct Dev {
     // particles
     double *x = nullptr, *y = nullptr, *z = nullptr, *m = nullptr;
@@ -166,6 +171,10 @@ struct Dev {
     int64_t nbr_stage_len = 0;
     int8_t* stage_k = nullptr;     // [n]
     int32_t* fill_list = nullptr;  // [G]
+    // irregular force: caller index -> key position, key-order particle records
+    int32_t* irr_rank = nullptr;
+    IrrRec* irr_rec = nullptr;
+    int64_t irr_len = 0;
     // walk stacks
     int32_t* stack = nullptr;
     int64_t stack_len = 0;
@@ -232,7 +241,13 @@ struct IrrParams {
     int64_t n = 0;              // particles (caller order)
     int64_t n_tgt = 0;          // targets of this launch
     const int32_t* tgt = nullptr;    // target caller indices (outputs compact), or null = all
-    const int32_t* order = nullptr;  // processing order of all targets (outputs by index), or null
+    const int32_t* order = nullptr;  // processing order of all targets (key order), or null
+    // key-order records: perm [n] (key position -> caller index), rank [n]
+    // (caller index -> key position) and rec [n], the last two written by the
+    // pre-pass; null rec: gather from pos/vel/mass directly
+    const int32_t* perm = nullptr;
+    int32_t* rank = nullptr;
+    IrrRec* rec = nullptr;
     const double* pos = nullptr;     // [n][3]
     const double* vel = nullptr;     // [n][3] (jerk only)
     const double* mass = nullptr;    // [n]

@@ -129,6 +129,11 @@ def test_irregular_targets_and_order_do_not_change_results():
         assert np.array_equal(a, b[tg])
     ref = oracle.irregular(c.pos, c.vel, c.mass, r_in, r_out, eps, targets=tg.astype(np.int64))
     _compare(sub, ref)
+    # a short list (gathered from the caller's arrays, not the key-order records)
+    few = [_np(g) for g in p.irregular(pos, vel, mass, r_in, r_out, eps, off, idx,
+                                       targets=_t(tg[:20]))]
+    for a, b in zip(few, full):
+        assert np.array_equal(a, b[tg[:20]])
     # empty target list
     e = p.irregular(pos, vel, mass, r_in, r_out, eps, off, idx, targets=_t(np.zeros(0, np.int32)))
     assert e[0].shape == (0, 3)
@@ -177,13 +182,20 @@ def test_irregular_degenerate_inputs():
 
 
 def test_irregular_rejects_malformed_lists():
-    from paper_2110_11658_amd._lib import PBH_E_ARG, PbhError
     n = 64
     c = ic.plummer(n, seed=38)
     pos, vel, mass = _t(c.pos), _t(c.vel), _t(c.mass)
-    p = _pbh()
     off = np.arange(n + 1, dtype=np.int64)          # one entry per particle
     good = ((np.arange(n) + 1) % n).astype(np.int32)
+    for built in (False, True):   # caller-array gathers, then key-order records
+        p = _pbh()
+        if built:
+            p.build(pos, mass)
+        _malformed_cases(p, n, pos, vel, mass, off, good)
+
+
+def _malformed_cases(p, n, pos, vel, mass, off, good):
+    from paper_2110_11658_amd._lib import PBH_E_ARG, PbhError
     p.irregular(pos, vel, mass, 0.01, 10.0, 1e-3, _t(off), _t(good))
     bad_idx = good.copy()
     bad_idx[10] = n + 5
