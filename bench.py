@@ -48,6 +48,11 @@ if ROOT not in sys.path:
 #   particle-particle outside r_out (W = 1): 20
 #   particle-particle in a near leaf (W(s) and the regular potential): 50
 FLOPS_PN, FLOPS_FAR, FLOPS_NEAR = 55, 20, 50
+# Irregular force + jerk + potential per neighbour pair (FP64): separation 3,
+# s^2 6, rsqrt and powers 4, changeover K and its slope 19, force 8, jerk 33,
+# irregular potential (closed-form Phi_R with log) 22.
+FLOPS_IRR = 95
+HBM_PEAK_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (256 CU x 256 flop/clk x 2.4 GHz)
 PEAK_FP64_TFLOPS = 78.6
 
@@ -295,10 +300,78 @@ def bench_force(args):
         rec["autotune"] = {k: v for k, v in tuned.items() if k != "cached"}
         rec["autotune"]["cached"] = tuned["cached"]
 
+    if neighbours and not batched:
+        total = int(off[-1].item())
+        rec["irregular"] = bench_irregular(p, inp, off, idx[:total], dev, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"], rec["accuracy"] = cpu_baseline(inp, theta, prm, acc, pot)
     p.close()
     print(json.dumps(rec))
+
+
+def bench_irregular(p, inp, off, idx, dev, with_oracle, calls=10):
+    """Irregular force, jerk and potential of every particle from the step's
+    neighbour lists (pbh_irregular), timed with HIP events on its stream after
+    the timed step region; sampled parity and the oracle's per-target cost."""
+    import torch
+
+    from paper_2110_11658_amd._lib import check
+    from paper_2110_11658_amd.api import _ptr, _stream
+    n = inp["n"]
+    vel = torch.from_numpy(np.ascontiguousarray(inp["vel"])).to(dev)
+    a = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    j = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    ph = torch.empty(n, dtype=torch.float64, device=dev)
+    pairs = int(idx.shape[0])
+
+    def call():
+        check(p.ctx, p.L.pbh_irregular(p.ctx, n, _ptr(inp["pos_d"]), _ptr(vel), _ptr(inp["mass_d"]),
+                                       inp["r_in"], inp["r_out"], inp["eps"], _ptr(off), _ptr(idx),
+                                       pairs, 0, None, _ptr(a), _ptr(j), _ptr(ph), 0, _stream()))
+    for _ in range(2):
+        call()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(calls):
+        call()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / calls
+    flops = FLOPS_IRR * pairs
+    tflops = flops / (ms * 1e-3) / 1e12
+    # algorithmic bytes: lists and offsets once, positions/velocities/masses
+    # read once, records and ranks written once, outputs written once
+    nbytes = 4 * pairs + 8 * (n + 1) + 56 * n + (64 + 4) * n + 56 * n
+    out = {"ms": ms, "pairs": pairs, "pairs_per_s": pairs / (ms * 1e-3),
+           "targets_per_s": n / (ms * 1e-3), "calls": calls,
+           "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": tflops / PEAK_FP64_TFLOPS,
+                        "flops_per_launch": flops, "kernel": "k_irregular (+ k_irr_pack)",
+                        "hbm_bytes": nbytes,
+                        "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    if with_oracle:
+        import oracle
+        rng = np.random.default_rng(4321)
+        tg = np.sort(rng.choice(n, size=64, replace=False))
+        t = time.perf_counter()
+        ra, rj, rp, sc = oracle.irregular(inp["pos"], inp["vel"], inp["mass"], inp["r_in"],
+                                          inp["r_out"], inp["eps"], targets=tg)
+        dt = time.perf_counter() - t
+        ga, gj, gp = a.cpu().numpy()[tg], j.cpu().numpy()[tg], ph.cpu().numpy()[tg]
+        live = sc[:, 0] > 0
+
+        def worst(g, r, scale):
+            d = np.linalg.norm((g - r).reshape(len(tg), -1), axis=1)
+            return float(np.max(d[live] / scale[live])) if live.any() else 0.0
+        out["cpu_baseline"] = {"value": len(tg) / dt, "unit": "targets/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"{len(tg)} sampled targets, each summed over all {n} "
+                                         f"particles (the O(N) definition)"}
+        out["accuracy"] = {"vs": f"oracle on {len(tg)} sampled targets, error / magnitude sum",
+                           "acc": worst(ga, ra, sc[:, 0]), "jerk": worst(gj, rj, sc[:, 1]),
+                           "pot": worst(gp, rp, sc[:, 2])}
+    return out
 
 
 def cpu_baseline(inp, theta, prm, acc, pot):
