@@ -27,6 +27,7 @@
 // sums do not depend on the route or the order. Lists, targets and offsets are
 // range-checked: a bad entry is skipped and flagged, never dereferenced.
 #include "pbh_internal.hpp"
+#include "wave.hpp"
 
 namespace pbh {
 
@@ -208,12 +209,16 @@ __device__ inline void store_sums(const IrrParams& p, int64_t slot, const IrrSum
 // List entries per batch: their list, rank and particle loads are independent
 // and issue together (one dependent chain per batch instead of per entry).
 constexpr int kIrrBatch = 8;
+// Blocks (of 256 key-order targets) per XCD chunk.
+constexpr unsigned kIrrChunk = 16;
 
 // MULTI: clusters with their own constants (per lane); otherwise one set, read
 // from the kernel arguments (wave-uniform, so it stays in scalar registers).
 template <bool JERK, bool POT, bool SORTED, bool MULTI>
 __global__ __launch_bounds__(256) void k_irregular(IrrParams p) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // key-order targets in chunks per XCD (cache locality and load balance)
+    const unsigned blk = SORTED ? xcd_chunk_block(blockIdx.x, kIrrChunk) : blockIdx.x;
+    const int64_t k = (int64_t)blk * blockDim.x + threadIdx.x;
     if (k >= p.n_tgt) return;
     unsigned long long bad = 0;
     const int64_t i = p.tgt ? (int64_t)p.tgt[k] : (p.order ? (int64_t)p.order[k] : k);
@@ -260,9 +265,15 @@ __global__ __launch_bounds__(256) void k_irregular(IrrParams p) {
 
 template <bool JERK, bool POT, bool MULTI>
 void launch_route(const IrrParams& p, hipStream_t s) {
-    const dim3 grid((unsigned)((p.n_tgt + 255) / 256)), block(256);
-    if (p.rec) hipLaunchKernelGGL((k_irregular<JERK, POT, true, MULTI>), grid, block, 0, s, p);
-    else hipLaunchKernelGGL((k_irregular<JERK, POT, false, MULTI>), grid, block, 0, s, p);
+    const int64_t nb = (p.n_tgt + 255) / 256;
+    const dim3 block(256);
+    if (p.rec) {   // grid padded to whole rounds of chunks over the XCDs
+        const int64_t round = (int64_t)kQueues * kIrrChunk;
+        const dim3 grid((unsigned)((nb + round - 1) / round * round));
+        hipLaunchKernelGGL((k_irregular<JERK, POT, true, MULTI>), grid, block, 0, s, p);
+    } else {
+        hipLaunchKernelGGL((k_irregular<JERK, POT, false, MULTI>), dim3((unsigned)nb), block, 0, s, p);
+    }
 }
 
 template <bool JERK, bool POT>

@@ -39,6 +39,17 @@ __device__ inline int last_lane(int v) { return __builtin_amdgcn_readlane(v, 63)
 // adds 1, the others 0): no lane-0-only branch precedes the broadcast.
 constexpr int kQueues = 8;
 
+// Workgroup id -> logical block in chunks of `chunk` consecutive blocks:
+// workgroups go to XCDs round-robin by id, and XCD x runs the chunks
+// x, x + 8, x + 16, ... in order, so every XCD's L2 serves a few compact
+// stretches at a time while dense and sparse stretches spread over all XCDs.
+// A bijection on [0, nb) when nb is a multiple of 8 * chunk (pad the grid;
+// blocks mapped past the real count have no work).
+__device__ inline unsigned xcd_chunk_block(unsigned b, unsigned chunk) {
+    const unsigned x = b % kQueues, j = b / kQueues;
+    return ((j / chunk) * kQueues + x) * chunk + j % chunk;
+}
+
 __device__ inline int64_t queue_next(unsigned long long* q /* [kQueues] */, int64_t G, int& home,
                                      int lane) {
     for (int k = 0; k < kQueues; ++k) {
