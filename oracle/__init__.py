@@ -56,7 +56,7 @@ def lib():
         L.orc_nbr_cells.restype = _i64
         L.orc_nbr_cells.argtypes = [_i64, _p, _d, _p, _p, _i64]
         L.orc_keys.argtypes = [_i64, _p, C.c_int, _p]
-        L.orc_tree.argtypes = [_i64, _p, _p, _d, _d, _d, _d, C.c_int, C.c_int, C.c_int, _p, _p, _p]
+        L.orc_tree.argtypes = [_i64, _p, _p, _d, _d, _d, _d, _d, C.c_int, C.c_int, C.c_int, _p, _p, _p]
         L.orc_tree_nodes.restype = _i64
         L.orc_tree_nodes.argtypes = [_i64, _p, _p, C.c_int, C.c_int, _i64, _p, _p, _p]
         L.orc_groups.restype = _i64
@@ -185,10 +185,12 @@ def keys(pos, D: int = 21) -> np.ndarray:
     return k
 
 
-def tree(pos, mass, r_in, r_out, theta, eps, n_leaf=16, n_crit=64, D=21):
+def tree(pos, mass, r_in, r_out, theta, eps, n_leaf=16, n_crit=64, D=21, r_buff=0.0):
     """CPU Barnes-Hut walk with the same tree, group and opening rules as the GPU.
 
-    Returns (acc, pot, stats) with stats = dict(nodes, leaves, groups, pn, pp_far, pp_near).
+    Nodes closer than the list radius r_out + r_buff to a group are opened to
+    particle pairs. Returns (acc, pot, stats) with stats = dict(nodes, leaves,
+    groups, pn, pp_far, pp_near).
     """
     pos = _f64(pos)
     n = pos.shape[0]
@@ -196,8 +198,8 @@ def tree(pos, mass, r_in, r_out, theta, eps, n_leaf=16, n_crit=64, D=21):
     acc = np.zeros((n, 3))
     pot = np.zeros(n)
     st = np.zeros(6, dtype=np.int64)
-    lib().orc_tree(n, _ptr(pos), _ptr(mass), float(r_in), float(r_out), float(theta), float(eps),
-                   int(n_leaf), int(n_crit), int(D), _ptr(acc), _ptr(pot), _ptr(st))
+    lib().orc_tree(n, _ptr(pos), _ptr(mass), float(r_in), float(r_out), float(r_buff), float(theta),
+                   float(eps), int(n_leaf), int(n_crit), int(D), _ptr(acc), _ptr(pot), _ptr(st))
     names = ("nodes", "leaves", "groups", "pn", "pp_far", "pp_near")
     return acc, pot, dict(zip(names, (int(v) for v in st)))
 

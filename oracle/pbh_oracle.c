@@ -848,7 +848,7 @@ static int64_t make_groups(const otree_t* t, int n_crit, ogroup_t** out)
 typedef struct {
     const otree_t* t;
     const phir_t* p;
-    double eps2, rout2, theta;
+    double eps2, rlist2, theta;   /* rlist2: square of the list radius r_out + r_buff */
     int64_t gbeg, gcnt;
     double glo[3], ghi[3];
     double* ax; double* ay; double* az; double* ph; /* per group member */
@@ -896,7 +896,7 @@ static void eval_pp(walkctx* w, const onode_t* nd, int near)
                 pair_regular(w->p, w->eps2, t->x[i], t->y[i], t->z[i], t->x[j], t->y[j], t->z[j],
                              t->m[j], &w->ax[u], &w->ay[u], &w->az[u], &w->ph[u]);
             } else {
-                /* every pair of a far leaf is at r >= r_out, where W = 1 */
+                /* every pair of a far leaf is at r >= r_out + r_buff >= r_out, where W = 1 */
                 double dx = t->x[j] - t->x[i], dy = t->y[j] - t->y[i], dz = t->z[j] - t->z[i];
                 double s2 = dx * dx + dy * dy + dz * dz + w->eps2;
                 double s = sqrt(s2);
@@ -915,7 +915,7 @@ static void visit(walkctx* w, int64_t k)
 {
     const onode_t* nd = &w->t->nodes[k];
     double dbox2 = box_box_d2(w->glo, w->ghi, nd->lo, nd->hi);
-    int near = (dbox2 < w->rout2) || (dbox2 == 0.0);
+    int near = (dbox2 < w->rlist2) || (dbox2 == 0.0);
     if (!near && w->theta > 0.0 && box_pt_d2(w->glo, w->ghi, nd->com) > nd->rcrit2) {
         eval_pn(w, nd);
         return;
@@ -929,12 +929,18 @@ static void visit(walkctx* w, int64_t k)
 
 /*
  * Tree walk of one cluster. Outputs acc [n][3], pot [n] in the caller's order.
+ * A node is near when its box comes closer than the neighbour-list radius
+ * r_out + r_buff to the group box (or touches it); near nodes are opened and
+ * their leaf pairs take W(s), which is 1 beyond r_out. With r_buff > 0 the
+ * lists hold a buffer beyond the changeover radius (Section 2.3, R_buff, and
+ * the rule r_buff = 3 tau sigma of the run parameters), so every list member
+ * is found as a particle pair.
  * stats (optional, int64[6]): n_nodes, n_leaves, n_groups, PN, PP-far, PP-near
  * interaction counts (PN counted once per group member, PP once per pair
  * evaluated, the excluded self pair included in PP-near).
  */
 void orc_tree(int64_t n, const double* pos, const double* mass,
-              double r_in, double r_out, double theta, double eps,
+              double r_in, double r_out, double r_buff, double theta, double eps,
               int n_leaf, int n_crit, int D,
               double* acc, double* pot, int64_t* stats)
 {
@@ -966,7 +972,7 @@ void orc_tree(int64_t n, const double* pos, const double* mass,
         w.t = &t;
         w.p = &p;
         w.eps2 = eps * eps;
-        w.rout2 = r_out * r_out;
+        w.rlist2 = (r_out + r_buff) * (r_out + r_buff);
         w.theta = theta;
         w.gbeg = groups[g].begin;
         w.gcnt = groups[g].count;

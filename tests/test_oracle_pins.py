@@ -490,10 +490,41 @@ def test_tree_theta0_equals_direct(n_leaf, n_crit):
     r_out = 0.1
     args = (c.pos, c.mass, 0.1 * r_out, r_out)
     acc, pot = oracle.direct(*args, 1e-4)
-    at, pt, st = oracle.tree(*args, 0.0, 1e-4, n_leaf=n_leaf, n_crit=n_crit)
-    assert st["pn"] == 0 and st["pp_far"] + st["pp_near"] == c.n * c.n
-    assert np.max(np.linalg.norm(at - acc, axis=1) / np.linalg.norm(acc, axis=1)) < 1e-12
-    assert np.max(np.abs(pt - pot) / np.abs(pot)) < 1e-12
+    for r_buff in (0.0, 0.05):
+        at, pt, st = oracle.tree(*args, 0.0, 1e-4, n_leaf=n_leaf, n_crit=n_crit, r_buff=r_buff)
+        assert st["pn"] == 0 and st["pp_far"] + st["pp_near"] == c.n * c.n
+        assert np.max(np.linalg.norm(at - acc, axis=1) / np.linalg.norm(acc, axis=1)) < 1e-12
+        assert np.max(np.abs(pt - pot) / np.abs(pot)) < 1e-12
+
+
+def test_buffered_list_radius_opens_every_node_within_it():
+    # neighbour lists of radius r_out + r_buff (Section 2.3, R_buff): the walk
+    # opens every node closer than that radius, so every list pair is summed
+    # exactly; beyond r_out such pairs take W = 1
+    c = ic.plummer(4000, seed=22, masses="kroupa")
+    r_out = 0.08
+    r_in = 0.1 * r_out
+    r_buff = 0.06
+    eps = 1e-4
+    a0, _, s0 = oracle.tree(c.pos, c.mass, r_in, r_out, 0.5, eps, n_leaf=8, n_crit=32)
+    a1, _, s1 = oracle.tree(c.pos, c.mass, r_in, r_out, 0.5, eps, n_leaf=8, n_crit=32, r_buff=r_buff)
+    off, _ = oracle.nbr_brute(c.pos, r_out + r_buff)
+    # near-leaf pairs (self pairs included) cover every pair inside the list radius
+    assert s1["pp_near"] >= off[-1] + c.n
+    assert s1["pp_near"] > s0["pp_near"] and s1["pn"] < s0["pn"]
+    # more exact pairs: the tree error against direct summation does not grow
+    ref, _ = oracle.direct(c.pos, c.mass, r_in, r_out, eps)
+    e0 = np.linalg.norm(a0 - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    e1 = np.linalg.norm(a1 - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert np.median(e1) <= np.median(e0)
+    # a list radius wider than the cluster makes every node near: any theta
+    # then reduces to direct summation
+    big = 2.0 * np.ptp(c.pos, axis=0).max()
+    a2, p2, s2 = oracle.tree(c.pos, c.mass, r_in, r_out, 0.5, eps, n_leaf=8, n_crit=32, r_buff=big)
+    _, pref = oracle.direct(c.pos, c.mass, r_in, r_out, eps)
+    assert s2["pn"] == 0
+    assert np.max(np.linalg.norm(a2 - ref, axis=1) / np.linalg.norm(ref, axis=1)) < 1e-12
+    assert np.max(np.abs(p2 - pref) / np.abs(pref)) < 1e-12
 
 
 # --- P-9 / P-10: neighbour sets ----------------------------------------------
