@@ -139,6 +139,21 @@ pbh_status pbh_force(pbh_ctx* ctx, double r_in, double r_out, double theta, doub
                      pbh_stream_t stream);
 
 /*
+ * pbh_force with a buffered neighbour radius (Section 2.3: R_cut = R_s +
+ * R_buff; the run-parameter rule r_buff = 3 tau sigma): the lists hold every
+ * j != i with r_ij^2 < (r_out + r_buff)^2, so they stay complete while the
+ * particles move for a regular step. The changeover W still uses r_in and
+ * r_out; nodes closer than r_out + r_buff to a walk group are opened to
+ * particle pairs (W = 1 beyond r_out). r_buff finite and >= 0; r_buff = 0 is
+ * pbh_force. The lists feed pbh_irregular unchanged (pairs beyond r_out add
+ * nothing there).
+ */
+pbh_status pbh_force_buffered(pbh_ctx* ctx, double r_in, double r_out, double r_buff,
+                              double theta, double eps, double* acc, double* pot,
+                              int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap,
+                              int64_t* nbr_total, pbh_stream_t stream);
+
+/*
  * Ensemble of independent clusters built as one forest: cluster k holds
  * particles [offsets[k], offsets[k+1]) (host array, n_clusters + 1 entries,
  * offsets[0] = 0, each cluster non-empty). Keys carry the cluster id above
@@ -158,6 +173,14 @@ pbh_status pbh_force_batched(pbh_ctx* ctx, const double* r_in, const double* r_o
                              double theta, double eps, double* acc, double* pot,
                              int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap,
                              int64_t* nbr_total, pbh_stream_t stream);
+
+/* pbh_force_batched with per-cluster buffers r_buff (host array [n_clusters],
+   or NULL for none), as pbh_force_buffered. */
+pbh_status pbh_force_batched_buffered(pbh_ctx* ctx, const double* r_in, const double* r_out,
+                                      const double* r_buff, double theta, double eps,
+                                      double* acc, double* pot, int64_t* nbr_off,
+                                      int32_t* nbr_idx, int64_t nbr_cap, int64_t* nbr_total,
+                                      pbh_stream_t stream);
 
 /*
  * Irregular (neighbour) force, its time derivative and the irregular

@@ -24,7 +24,8 @@ PBH_FP64 = 0
 PBH_MIXED = 1
 
 EXPORTS = ("pbh_create", "pbh_destroy", "pbh_set_params", "pbh_get_params", "pbh_build",
-           "pbh_force", "pbh_build_batched", "pbh_force_batched", "pbh_irregular",
+           "pbh_force", "pbh_force_buffered", "pbh_build_batched", "pbh_force_batched",
+           "pbh_force_batched_buffered", "pbh_irregular",
            "pbh_irregular_batched", "pbh_kdk", "pbh_kdk_eager",
            "pbh_get_stats", "pbh_set_timing", "pbh_debug_tree", "pbh_debug_groups",
            "pbh_debug_wave_log", "pbh_last_error", "pbh_status_string")
@@ -71,6 +72,8 @@ def load(path: str = LIB_PATH):
         "pbh_force": (st, [vp, d, d, d, d, vp, vp, vp, vp, i64, vp, vp]),
         "pbh_build_batched": (st, [vp, i32, vp, vp, vp, vp]),
         "pbh_force_batched": (st, [vp, vp, vp, d, d, vp, vp, vp, vp, i64, vp, vp]),
+        "pbh_force_buffered": (st, [vp, d, d, d, d, d, vp, vp, vp, vp, i64, vp, vp]),
+        "pbh_force_batched_buffered": (st, [vp, vp, vp, vp, d, d, vp, vp, vp, vp, i64, vp, vp]),
         "pbh_irregular": (st, [vp, i64, vp, vp, vp, d, d, d, vp, vp, i64, i64, vp, vp, vp, vp,
                                i32, vp]),
         "pbh_irregular_batched": (st, [vp, vp, vp, vp, vp, vp, d, vp, vp, i64, i64, vp, vp, vp,

@@ -118,26 +118,34 @@ class Pbh:
         raise PbhError(PBH_E_NBR_OVERFLOW, "neighbour capacity still too small")
 
     def force(self, r_in: float, r_out: float, theta: float, eps: float, neighbours: bool = True,
-              nbr_cap: Optional[int] = None):
-        """(acc [n,3], pot [n], nbr_off [n+1] | None, nbr_idx [total] | None)."""
+              nbr_cap: Optional[int] = None, r_buff: float = 0.0):
+        """(acc [n,3], pot [n], nbr_off [n+1] | None, nbr_idx [total] | None).
+
+        The lists hold every j with r_ij < r_out + r_buff (r_buff = 0: r_out)."""
         def call(acc, pot, off, idx, cap, total):
-            return self.L.pbh_force(self.ctx, float(r_in), float(r_out), float(theta), float(eps),
-                                    _ptr(acc), _ptr(pot), _ptr(off), _ptr(idx), int(cap), total,
-                                    _stream())
+            return self.L.pbh_force_buffered(self.ctx, float(r_in), float(r_out), float(r_buff),
+                                             float(theta), float(eps), _ptr(acc), _ptr(pot),
+                                             _ptr(off), _ptr(idx), int(cap), total, _stream())
         return self._force(call, neighbours, nbr_cap)
 
     def force_batched(self, r_in: Sequence[float], r_out: Sequence[float], theta: float, eps: float,
-                      neighbours: bool = True, nbr_cap: Optional[int] = None):
+                      neighbours: bool = True, nbr_cap: Optional[int] = None,
+                      r_buff: Optional[Sequence[float]] = None):
         ri = np.ascontiguousarray(np.asarray(r_in, dtype=np.float64))
         ro = np.ascontiguousarray(np.asarray(r_out, dtype=np.float64))
         if ri.size != self.n_clusters or ro.size != self.n_clusters:
             raise ValueError("need one r_in and r_out per cluster")
+        rb = None
+        if r_buff is not None:
+            rb = np.ascontiguousarray(np.asarray(r_buff, dtype=np.float64))
+            if rb.size != self.n_clusters:
+                raise ValueError("need one r_buff per cluster")
 
         def call(acc, pot, off, idx, cap, total):
-            return self.L.pbh_force_batched(self.ctx, ri.ctypes.data_as(C.c_void_p),
-                                            ro.ctypes.data_as(C.c_void_p), float(theta), float(eps),
-                                            _ptr(acc), _ptr(pot), _ptr(off), _ptr(idx), int(cap),
-                                            total, _stream())
+            return self.L.pbh_force_batched_buffered(
+                self.ctx, ri.ctypes.data_as(C.c_void_p), ro.ctypes.data_as(C.c_void_p),
+                None if rb is None else rb.ctypes.data_as(C.c_void_p), float(theta), float(eps),
+                _ptr(acc), _ptr(pot), _ptr(off), _ptr(idx), int(cap), total, _stream())
         return self._force(call, neighbours, nbr_cap)
 
     def force_into(self, r_in, r_out, theta, eps, acc: torch.Tensor, pot: torch.Tensor):

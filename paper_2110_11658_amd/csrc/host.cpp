@@ -329,13 +329,15 @@ void enqueue_build(pbh_ctx* ctx, const double* pos, const double* mass, hipStrea
     launch_groups(d, c, s);
 }
 
-// Changeover constants of one cluster (see ClusterParams).
-ClusterParams cluster_params(double r_in, double r_out) {
+// Changeover constants of one cluster (see ClusterParams); lists reach r_out + r_buff.
+ClusterParams cluster_params(double r_in, double r_out, double r_buff = 0.0) {
     ClusterParams p;
     std::memset(&p, 0, sizeof(p));
     p.r_in = r_in;
     p.r_out = r_out;
     p.rout2 = r_out * r_out;
+    p.rlist = r_out + r_buff;
+    p.rlist2 = p.rlist * p.rlist;
     const double delta = r_out - r_in;
     if (r_out > 0.0 && delta > 0.0) {
         // g(t - a) = sum_k dk t^k with g(x) = 35x^4 - 84x^5 + 70x^6 - 20x^7
@@ -707,25 +709,34 @@ pbh_status pbh_build_batched(pbh_ctx* ctx, int32_t n_clusters, const int64_t* of
     return finish_build(ctx, s);
 }
 
-pbh_status pbh_force(pbh_ctx* ctx, double r_in, double r_out, double theta, double eps,
-                     double* acc, double* pot, int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap,
-                     int64_t* nbr_total, pbh_stream_t stream) {
+pbh_status pbh_force_buffered(pbh_ctx* ctx, double r_in, double r_out, double r_buff, double theta,
+                              double eps, double* acc, double* pot, int64_t* nbr_off,
+                              int32_t* nbr_idx, int64_t nbr_cap, int64_t* nbr_total,
+                              pbh_stream_t stream) {
     if (!ctx) return PBH_E_ARG;
     pbh_status st = check_radii(ctx, r_in, r_out);
     if (st != PBH_OK) return st;
+    if (!finite_nonneg(r_buff)) return fail(ctx, PBH_E_ARG, "r_buff must be finite and >= 0");
     if (ctx->built && ctx->cfg.n_clusters != 1)
         return fail(ctx, PBH_E_STATE, "last build was batched: use pbh_force_batched");
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     ctx->last = s;
-    std::vector<ClusterParams> cps(1, cluster_params(r_in, r_out));
+    std::vector<ClusterParams> cps(1, cluster_params(r_in, r_out, r_buff));
     return do_force(ctx, cps, theta, eps, acc, pot, nbr_off, nbr_idx, nbr_cap, nbr_total, s);
 }
 
-pbh_status pbh_force_batched(pbh_ctx* ctx, const double* r_in, const double* r_out, double theta,
-                             double eps, double* acc, double* pot, int64_t* nbr_off,
-                             int32_t* nbr_idx, int64_t nbr_cap, int64_t* nbr_total,
-                             pbh_stream_t stream) {
+pbh_status pbh_force(pbh_ctx* ctx, double r_in, double r_out, double theta, double eps,
+                     double* acc, double* pot, int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap,
+                     int64_t* nbr_total, pbh_stream_t stream) {
+    return pbh_force_buffered(ctx, r_in, r_out, 0.0, theta, eps, acc, pot, nbr_off, nbr_idx,
+                              nbr_cap, nbr_total, stream);
+}
+
+pbh_status pbh_force_batched_buffered(pbh_ctx* ctx, const double* r_in, const double* r_out,
+                                      const double* r_buff, double theta, double eps, double* acc,
+                                      double* pot, int64_t* nbr_off, int32_t* nbr_idx,
+                                      int64_t nbr_cap, int64_t* nbr_total, pbh_stream_t stream) {
     if (!ctx) return PBH_E_ARG;
     if (!ctx->built) return fail(ctx, PBH_E_STATE, "no successful build");
     if (!r_in || !r_out) return fail(ctx, PBH_E_ARG, "r_in and r_out arrays are required");
@@ -733,12 +744,22 @@ pbh_status pbh_force_batched(pbh_ctx* ctx, const double* r_in, const double* r_o
     for (int k = 0; k < ctx->cfg.n_clusters; ++k) {
         pbh_status st = check_radii(ctx, r_in[k], r_out[k]);
         if (st != PBH_OK) return st;
-        cps.push_back(cluster_params(r_in[k], r_out[k]));
+        const double rb = r_buff ? r_buff[k] : 0.0;
+        if (!finite_nonneg(rb)) return fail(ctx, PBH_E_ARG, "r_buff must be finite and >= 0");
+        cps.push_back(cluster_params(r_in[k], r_out[k], rb));
     }
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     ctx->last = s;
     return do_force(ctx, cps, theta, eps, acc, pot, nbr_off, nbr_idx, nbr_cap, nbr_total, s);
+}
+
+pbh_status pbh_force_batched(pbh_ctx* ctx, const double* r_in, const double* r_out, double theta,
+                             double eps, double* acc, double* pot, int64_t* nbr_off,
+                             int32_t* nbr_idx, int64_t nbr_cap, int64_t* nbr_total,
+                             pbh_stream_t stream) {
+    return pbh_force_batched_buffered(ctx, r_in, r_out, nullptr, theta, eps, acc, pot, nbr_off,
+                                      nbr_idx, nbr_cap, nbr_total, stream);
 }
 
 pbh_status pbh_irregular(pbh_ctx* ctx, int64_t n, const double* pos, const double* vel,

@@ -1,10 +1,11 @@
-// nbr.hip -- neighbour lists inside r_out (gfx950).
+// nbr.hip -- neighbour lists inside the list radius R (gfx950).
 //
-// The list of particle i is { j != i : r_ij^2 < r_out^2 } with unsoftened
-// FP64 distances evaluated without FMA as ((dx*dx + dy*dy) + dz*dz): the
-// constant neighbour radius of Section 2.3 of Arnold, Baumgardt & Wang (2021);
-// empty lists are legal. One wave per group walks only the nodes whose box
-// comes closer than r_out to the group box (box distances never exceed pair
+// The list of particle i is { j != i : r_ij^2 < R^2 } with unsoftened FP64
+// distances evaluated without FMA as ((dx*dx + dy*dy) + dz*dz): the constant
+// neighbour radius of Section 2.3 of Arnold, Baumgardt & Wang (2021), R =
+// r_out + r_buff (r_buff = 0: R = r_out); empty lists are legal. One wave per
+// group walks only the nodes whose box comes closer than R to the group box
+// (box distances never exceed pair
 // distances, also after rounding, so no neighbour is missed). The particles
 // of those leaves are staged 64 at a time in an LDS tile (FP64 position and
 // caller index, loaded lane-parallel) and every lane tests its own particle
@@ -56,14 +57,14 @@ struct NTile {
 };
 
 __device__ inline void test_tile(const NTile& T, int cnt, double xi, double yi, double zi, int me_orig,
-                                 bool active, double rout2, const NbrParams& p, int64_t wpos,
+                                 bool active, double rlist2, const NbrParams& p, int64_t wpos,
                                  int& count, bool& overflow) {
 #pragma clang fp contract(off)
     for (int e = 0; e < cnt; ++e) {
         const double dx = T.x[e] - xi, dy = T.y[e] - yi, dz = T.z[e] - zi;
         const double r2 = dx * dx + dy * dy + dz * dz;
         const int oj = T.orig[e];
-        if (active && r2 < rout2 && oj != me_orig) {
+        if (active && r2 < rlist2 && oj != me_orig) {
             const int64_t at = wpos + count;
             if (at < p.cap) p.idx[at] = oj;
             else overflow = true;
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(64) void k_nbr_fill(NbrParams p) {
         ++n_done;
         const int64_t g = uni(p.fill_list[q]);
         const int gb = uni(p.g_begin[g]), gcnt = uni(p.g_count[g]), root = uni(p.g_root[g]);
-        const double rout2 = p.cp[uni(p.g_cluster[g])].rout2;
+        const double rlist2 = p.cp[uni(p.g_cluster[g])].rlist2;   // list radius R^2
         double glo[3], ghi[3];
         for (int k = 0; k < 3; ++k) {
             glo[k] = p.g_lo[3 * g + k];
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(64) void k_nbr_fill(NbrParams p) {
         if (active) wpos = p.off[orig];
         int count = 0;
         bool overflow = false;
-        if (rout2 > 0.0) {
+        if (rlist2 > 0.0) {
             stack.put(0, root);
             int top = 1;
             int fill = 0;
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(64) void k_nbr_fill(NbrParams p) {
                 const int nd = has ? stack.get(top + lane) : root;
                 __threadfence_block();
                 const WNode w = p.node[nd];
-                const bool near = has && box_box_d2(glo, ghi, w.lo, w.hi) < rout2;
+                const bool near = has && box_box_d2(glo, ghi, w.lo, w.hi) < rlist2;
                 const bool leaf = w.nchild == 0;
                 const int nch = (near && !leaf) ? w.nchild : 0;
                 const int incl = wave_incl_scan(nch, lane);
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(64) void k_nbr_fill(NbrParams p) {
                     fill = uni(fill + ((total - base) < 64 ? (total - base) : 64));
                     if (fill >= 64) {
                         __syncthreads();
-                        test_tile(T, fill, xi, yi, zi, orig, active, rout2, p, wpos, count, overflow);
+                        test_tile(T, fill, xi, yi, zi, orig, active, rlist2, p, wpos, count, overflow);
                         fill = 0;
                         __syncthreads();
                     }
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(64) void k_nbr_fill(NbrParams p) {
                 __syncthreads();
             }
             __syncthreads();
-            if (fill) test_tile(T, fill, xi, yi, zi, orig, active, rout2, p, wpos, count, overflow);
+            if (fill) test_tile(T, fill, xi, yi, zi, orig, active, rlist2, p, wpos, count, overflow);
             __syncthreads();
         }
         const uint64_t ov = __ballot(overflow);

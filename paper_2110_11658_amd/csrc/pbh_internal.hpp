@@ -60,6 +60,7 @@ struct alignas(16) ClusterParams {
     double r_in, r_out, rout2, inv_delta;
     double c0, d0, l1, inner;
     double e[6];   // e2..e7
+    double rlist, rlist2;   // neighbour-list radius R = r_out + r_buff and R^2
     float f_r_in, f_r_out, f_inv_delta, f_c0;
     float f_d0, f_l1, f_inner, f_pad;
     float f_e[6];

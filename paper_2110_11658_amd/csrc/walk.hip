@@ -11,7 +11,8 @@
 // lane). Persistent workgroups of one wave pull groups from a global counter.
 // Per step the wave pops up to 64 nodes from its stack (one per lane) and
 // classifies them in FP64 without FMA, exactly like the definition:
-//   near   box-box distance^2 < r_out^2, or the boxes touch
+//   near   box-box distance^2 < R^2, or the boxes touch (R = r_out + r_buff,
+//          the neighbour-list radius; R = r_out without a buffer)
 //   accept not near, theta > 0, distance^2(group box, COM) > rcrit^2
 //   open   otherwise: a leaf becomes particle-particle work, an inner node
 //          pushes its children.
@@ -227,7 +228,7 @@ __device__ inline void eval_pn<float>(const Tiles<float>& T, int cnt, int ksub, 
     A.add(fmaf(0.4f, bx, ax), fmaf(0.4f, by, ay), fmaf(0.4f, bz, az), ph);
 }
 
-// Pairs of far leaves: every pair is at r >= r_out, where W = 1.
+// Pairs of far leaves: every pair is at r >= R >= r_out, where W = 1.
 template <typename R>
 __device__ inline void eval_far(const Tiles<R>& T, int cnt, int ksub, int sub, R px, R py, R pz, R eps2,
                                 Acc<R>& A) {
@@ -271,40 +272,40 @@ struct NearK {
     R r_in, r_out, inv_delta, c0, d0, l1, inner;
     R e[6];
     bool pole;   // r_in > 0: the -d0/s and log terms are present
-    // FP32 neighbour pre-test (mixed path): r_out^2 in FP32 and the half-width
+    // FP32 neighbour pre-test (mixed path): R^2 (list radius) in FP32 and the half-width
     // of the band around it inside which the FP64 test decides (infinite:
     // always FP64)
-    float rout2f, band;
+    float rlist2f, band;
     const double* x;   // sorted FP64 coordinates (the FP64 neighbour test of the mixed walk)
     const double* y;
     const double* z;
 };
 
-// Neighbour test of the CSR lists: r^2 < r_out^2 in FP64 from the original
+// Neighbour test of the CSR lists: r^2 < R^2 (list radius) in FP64 from the original
 // coordinates, ((dx*dx + dy*dy) + dz*dz) without FMA.
 __device__ inline bool is_neighbour(double xj, double yj, double zj, double xi, double yi, double zi,
-                                    double rout2) {
+                                    double rlist2) {
 #pragma clang fp contract(off)
     const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
     const double r2 = dx * dx + dy * dy + dz * dz;
-    return r2 < rout2;
+    return r2 < rlist2;
 }
 
 // Pairs of near leaves: changeover weight W(s) and the regular potential;
-// optionally also counts the neighbours inside r_out (FP64 test).
+// optionally also counts the neighbours inside the list radius R (FP64 test).
 // optionally also stores them in the lane's staging row (`srow`, at most
 // `scap` entries, kStageStride apart).
 template <typename R>
 __device__ inline void eval_near(const Tiles<R>& T, int cnt, int ksub, int sub, R px, R py, R pz, R eps2,
                                  int self, const NearK<R>& K, Acc<R>& A, bool count_nbr, double xi,
-                                 double yi, double zi, double rout2, int& nbr, int32_t* srow, int scap) {
+                                 double yi, double zi, double rlist2, int& nbr, int32_t* srow, int scap) {
     R ax = 0, ay = 0, az = 0, ph = 0;
     for_entries<1>(cnt, ksub, sub, [&](int e) {
         const R* q = T.nearp[e];
         const int oj = T.nearj[e];
         const bool is_self = oj == self;
         if (count_nbr) {
-            const bool nb = !is_self && is_neighbour(T.nx[e], T.ny[e], T.nz[e], xi, yi, zi, rout2);
+            const bool nb = !is_self && is_neighbour(T.nx[e], T.ny[e], T.nz[e], xi, yi, zi, rlist2);
             if (nb && nbr < scap) srow[nbr * kStageStride] = oj;
             nbr += nb ? 1 : 0;
         }
@@ -335,7 +336,7 @@ __device__ inline void eval_near(const Tiles<R>& T, int cnt, int ksub, int sub, 
 template <bool CNT, bool POLE>
 __device__ inline void eval_near_f32(const Tiles<float>& T, int cnt, int ksub, int sub, float px,
                                      float py, float pz, float eps2, int self, const NearK<float>& K,
-                                     Acc<float>& A, double xi, double yi, double zi, double rout2,
+                                     Acc<float>& A, double xi, double yi, double zi, double rlist2,
                                      int& nbr, int32_t* srow, int scap) {
     const double* __restrict__ gx = K.x;
     const double* __restrict__ gy = K.y;
@@ -349,9 +350,9 @@ __device__ inline void eval_near_f32(const Tiles<float>& T, int cnt, int ksub, i
         const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         const float s2 = r2 + eps2;
-        const float dr = r2 - K.rout2f;
+        const float dr = r2 - K.rlist2f;
         if (__ballot(dr <= K.band) == 0) {
-            // every lane's pair lies beyond r_out by more than the rounding band:
+            // every lane's pair lies beyond R >= r_out by more than the rounding band:
             // no neighbour, W = 1 and Phi_R = -1/s (the far-pair formula)
             const float inv = __builtin_amdgcn_rsqf(s2);
             const float mi = q.w * inv;
@@ -370,7 +371,7 @@ __device__ inline void eval_near_f32(const Tiles<float>& T, int cnt, int ksub, i
             if (__ballot(band)) {
                 if (band) {
                     const int js = T.nears[e];
-                    nb = is_neighbour(gx[js], gy[js], gz[js], xi, yi, zi, rout2);
+                    nb = is_neighbour(gx[js], gy[js], gz[js], xi, yi, zi, rlist2);
                 }
             }
             nb = nb & other;
@@ -404,17 +405,17 @@ template <>
 __device__ inline void eval_near<float>(const Tiles<float>& T, int cnt, int ksub, int sub, float px,
                                         float py, float pz, float eps2, int self, const NearK<float>& K,
                                         Acc<float>& A, bool count_nbr, double xi, double yi, double zi,
-                                        double rout2, int& nbr, int32_t* srow, int scap) {
+                                        double rlist2, int& nbr, int32_t* srow, int scap) {
     if (count_nbr) {
         if (K.pole)
-            eval_near_f32<true, true>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr, srow, scap);
+            eval_near_f32<true, true>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
         else
-            eval_near_f32<true, false>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr, srow, scap);
+            eval_near_f32<true, false>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
     } else {
         if (K.pole)
-            eval_near_f32<false, true>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr, srow, scap);
+            eval_near_f32<false, true>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
         else
-            eval_near_f32<false, false>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rout2, nbr, srow, scap);
+            eval_near_f32<false, false>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
     }
 }
 
@@ -445,7 +446,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
             ctr[k] = (glo[k] + ghi[k]) * 0.5;
         }
         const ClusterParams& cp = p.cp[cl];
-        const double rout2 = cp.rout2;
+        const double rlist2 = cp.rlist2;   // neighbour-list radius R = r_out + r_buff, squared
         NearK<R> K;
         if (MIXED) {
             K.r_in = cp.f_r_in; K.r_out = cp.f_r_out; K.inv_delta = cp.f_inv_delta;
@@ -458,18 +459,18 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
         }
         K.pole = cp.d0 != 0.0;
         {
-            // Band of the FP32 neighbour pre-test. Relative coordinates are FP64
-            // differences rounded once to FP32, so with |p| <= h (group box half
-            // side) and a pair at r <= 2 r_out each component of d errs by at most
-            // 2^-24 (2h + 2.01 r); with h <= 64 r_out the error of r^2 (squares,
-            // FMA rounding, r_out^2 in FP32) stays below 928 * 2^-24 r_out^2, and
-            // for r > 2 r_out far below r^2 - r_out^2. The band is 2048 * 2^-24
-            // r_out^2; larger groups always take the FP64 test.
+            // Band of the FP32 neighbour pre-test against the list radius R.
+            // Relative coordinates are FP64 differences rounded once to FP32, so
+            // with |p| <= h (group box half side) and a pair at r <= 2 R each
+            // component of d errs by at most 2^-24 (2h + 2.01 r); with h <= 64 R
+            // the error of r^2 (squares, FMA rounding, R^2 in FP32) stays below
+            // 928 * 2^-24 R^2, and for r > 2 R far below r^2 - R^2. The band is
+            // 2048 * 2^-24 R^2; larger groups always take the FP64 test.
             double h = 0.0;
             for (int k = 0; k < 3; ++k) h = fmax(h, (ghi[k] - glo[k]) * 0.5);
-            K.rout2f = (float)rout2;
+            K.rlist2f = (float)rlist2;
             K.x = p.x; K.y = p.y; K.z = p.z;
-            K.band = (h <= 64.0 * cp.r_out) ? (float)(2048.0 * 0x1p-24 * rout2) : INFINITY;
+            K.band = (h <= 64.0 * cp.rlist) ? (float)(2048.0 * 0x1p-24 * rlist2) : INFINITY;
         }
 
         // sub-wave copies of a small group (see for_entries); lanes beyond
@@ -514,7 +515,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
             __threadfence_block();
             const WNode w = p.node[nd];
             const double dbox2 = box_box_d2(glo, ghi, w.lo, w.hi);
-            const bool near = (dbox2 < rout2) || (dbox2 == 0.0);
+            const bool near = (dbox2 < rlist2) || (dbox2 == 0.0);
             const bool accept = has && !near && p.use_theta && (box_pt_d2(glo, ghi, w.com) > w.rcrit2);
             const bool open = has && !accept;
             const bool leaf = w.nchild == 0;
@@ -585,7 +586,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                     if (fill + add > TCAP) {
                         __syncthreads();
                         if (cls == 0) eval_far<R>(T, fill, ksub, sub, px, py, pz, eps2, A);
-                        else eval_near<R>(T, fill, ksub, sub, px, py, pz, eps2, orig_me, K, A, count_nbr, xi, yi, zi, rout2, nbr, srow, scap);
+                        else eval_near<R>(T, fill, ksub, sub, px, py, pz, eps2, orig_me, K, A, count_nbr, xi, yi, zi, rlist2, nbr, srow, scap);
                         fill = 0;
                         __syncthreads();
                     }
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
         __syncthreads();
         if (npn) eval_pn<R>(T, npn, ksub, sub, px, py, pz, eps2, A);
         if (nfar) eval_far<R>(T, nfar, ksub, sub, px, py, pz, eps2, A);
-        if (nnear) eval_near<R>(T, nnear, ksub, sub, px, py, pz, eps2, orig_me, K, A, count_nbr, xi, yi, zi, rout2, nbr, srow, scap);
+        if (nnear) eval_near<R>(T, nnear, ksub, sub, px, py, pz, eps2, orig_me, K, A, count_nbr, xi, yi, zi, rlist2, nbr, srow, scap);
         __syncthreads();
 
         // a row that overflowed sends the group's lists to the fill pass
