@@ -51,6 +51,8 @@ def lib():
         L.orc_direct.argtypes = [_i64, _p, _p, _d, _d, _d, _i64, _p, _p, _p]
         L.orc_full_direct.argtypes = [_i64, _p, _p, _d, _p, _p]
         L.orc_irregular.argtypes = [_i64, _p, _p, _p, _d, _d, _d, _i64, _p, _p, _p, _p, _p]
+        L.orc_core.argtypes = [_i64, _p, _p, _i64, _p, _d, _p, _p]
+        L.orc_knn6.argtypes = [_i64, _p, _i64, _p, _p, _p]
         L.orc_nbr_brute.restype = _i64
         L.orc_nbr_brute.argtypes = [_i64, _p, _d, _p, _p, _i64]
         L.orc_nbr_cells.restype = _i64
@@ -155,6 +157,36 @@ def irregular(pos, vel, mass, r_in, r_out, eps, targets=None):
                         nt, None if tgt is None else _ptr(tgt), _ptr(acc), _ptr(jerk), _ptr(pot),
                         _ptr(scale))
     return acc, jerk, pot, scale
+
+
+CORE_KEYS = ("center", "rho_core", "r_core", "n_core", "r_half", "r_min", "dt_min")
+
+
+def core(pos, mass, sample, eta=0.02):
+    """Core quantities from the 6 nearest neighbours of a particle sample
+    (brute force): per-sample densities rho [n_s] and a dict with the density
+    centre, core density, core radius, core count, half-mass radius about the
+    density centre, and the regularisation parameters R_min, dT_min."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    mass = _f64(mass, (n,))
+    smp = np.ascontiguousarray(sample, dtype=np.int64)
+    rho = np.zeros(smp.size)
+    out = np.zeros(9)
+    lib().orc_core(n, _ptr(pos), _ptr(mass), smp.size, _ptr(smp), float(eta), _ptr(rho), _ptr(out))
+    res = {"center": out[:3].copy(), "rho_core": out[3], "r_core": out[4], "n_core": int(out[5]),
+           "r_half": out[6], "r_min": out[7], "dt_min": out[8]}
+    return rho, res
+
+
+def knn6(pos, sample):
+    """(d2 [n_s,6] ascending, idx [n_s,6]): 6 nearest neighbours by brute force."""
+    pos = _f64(pos)
+    smp = np.ascontiguousarray(sample, dtype=np.int64)
+    d2 = np.zeros((smp.size, 6))
+    idx = np.zeros((smp.size, 6), dtype=np.int64)
+    lib().orc_knn6(pos.shape[0], _ptr(pos), smp.size, _ptr(smp), _ptr(d2), _ptr(idx))
+    return d2, idx
 
 
 def _nbr(fn, pos, r_out):

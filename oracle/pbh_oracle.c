@@ -28,11 +28,14 @@
  *   orc_full_direct           plain softened gravity (no split)
  *   orc_irregular             O(N^2) irregular force F_I, its time
  *                             derivative and the irregular potential
+ *   orc_core                  core quantities from the 6 nearest neighbours
+ *                             of a particle sample, by brute force
  *   orc_nbr_brute/orc_nbr_cells neighbour sets, brute force and cell list
  *   orc_keys                  Morton keys of the octree
  *   orc_tree                  Barnes-Hut octree walk with the same tree,
  *                             group and opening rules as the GPU path
  */
+#define _DEFAULT_SOURCE
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -324,6 +327,141 @@ void orc_irregular(int64_t n, const double* pos, const double* vel, const double
             scale[3 * t + 2] = sp;
         }
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Core quantities (the core-radius algorithm of the paper's Other            */
+/* Modifications, with the density estimator of Casertano & Hut 1985, and    */
+/* the regularisation parameters R_min, dT_min of the paper's Regularisation  */
+/* section)                                                                   */
+/*                                                                            */
+/* For each sampled particle i: its 6 nearest neighbours among all n (j != i, */
+/* unsoftened ((dx*dx + dy*dy) + dz*dz), ties to the lower index), and        */
+/*   rho_i = (sum of the masses of the 5 nearest) / ((4 pi / 3) r_6^3)        */
+/* the order-6 estimator with masses. Over the sample:                        */
+/*   x_d = sum rho x / sum rho          density centre                        */
+/*   r_c = sqrt(sum rho^2 |x - x_d|^2 / sum rho^2)   core radius              */
+/*   rho_core = sum rho^2 / sum rho                  core density             */
+/* Over all particles: N_core = #{ |x - x_d|^2 < r_c^2 }, and the half-mass   */
+/* radius r_h = the smallest |x_k - x_d| whose sphere (inclusive) holds at    */
+/* least half the total mass. R_min = 4 r_h / (n rho_core^(1/3)) and          */
+/* dT_min = 0.01 sqrt(eta / 0.02) sqrt(R_min^3).                              */
+/* ------------------------------------------------------------------------ */
+
+/* 6 nearest neighbours of particle i by brute force; d2[6] ascending, idx[6]. */
+static void knn6(int64_t n, const double* pos, int64_t i, double* d2, int64_t* idx)
+{
+    int cnt = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        double dx = pos[3 * j] - pos[3 * i];
+        double dy = pos[3 * j + 1] - pos[3 * i + 1];
+        double dz = pos[3 * j + 2] - pos[3 * i + 2];
+        double r2 = dx * dx + dy * dy + dz * dz;
+        if (cnt == 6 && !(r2 < d2[5])) continue;   /* equal distance: the lower index stays */
+        int k = cnt < 6 ? cnt++ : 5;
+        while (k > 0 && r2 < d2[k - 1]) {
+            d2[k] = d2[k - 1];
+            idx[k] = idx[k - 1];
+            --k;
+        }
+        d2[k] = r2;
+        idx[k] = j;
+    }
+}
+
+static int cmp_dist(const void* a, const void* b)
+{
+    const double* x = (const double*)a;
+    const double* y = (const double*)b;
+    if (x[0] < y[0]) return -1;
+    if (x[0] > y[0]) return 1;
+    return (x[1] < y[1]) ? -1 : (x[1] > y[1]);
+}
+
+/*
+ * pos [n][3], mass [n], n >= 7; sample [n_s] distinct particle indices.
+ * rho [n_s] receives the per-sample densities (may be NULL); out[9] =
+ * x_d (3), rho_core, r_c, N_core, r_h, R_min, dT_min.
+ */
+void orc_core(int64_t n, const double* pos, const double* mass, int64_t n_s, const int64_t* sample,
+              double eta, double* rho, double* out)
+{
+    double* r = (double*)malloc(sizeof(double) * (size_t)n_s);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t s = 0; s < n_s; ++s) {
+        double d2[6];
+        int64_t idx[6];
+        knn6(n, pos, sample[s], d2, idx);
+        double m5 = 0.0;
+        for (int k = 0; k < 5; ++k) m5 += mass[idx[k]];
+        double r6 = sqrt(d2[5]);
+        r[s] = m5 / (4.0 / 3.0 * M_PI * (d2[5] * r6));
+    }
+    double sr = 0.0, srx[3] = {0, 0, 0};
+    for (int64_t s = 0; s < n_s; ++s) {
+        sr += r[s];
+        for (int d = 0; d < 3; ++d) srx[d] += r[s] * pos[3 * sample[s] + d];
+    }
+    double xd[3];
+    for (int d = 0; d < 3; ++d) xd[d] = srx[d] / sr;
+    double sr2 = 0.0, sr2d2 = 0.0;
+    for (int64_t s = 0; s < n_s; ++s) {
+        double dd = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            double v = pos[3 * sample[s] + d] - xd[d];
+            dd += v * v;
+        }
+        sr2 += r[s] * r[s];
+        sr2d2 += r[s] * r[s] * dd;
+    }
+    double rc = sqrt(sr2d2 / sr2);
+    double rho_core = sr2 / sr;
+    /* core membership and half-mass radius over all particles */
+    double* dm = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    int64_t ncore = 0;
+    double mtot = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double dd = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            double v = pos[3 * i + d] - xd[d];
+            dd += v * v;
+        }
+        if (dd < rc * rc) ++ncore;
+        dm[2 * i] = dd;
+        dm[2 * i + 1] = (double)i;
+        mtot += mass[i];
+    }
+    qsort(dm, (size_t)n, 2 * sizeof(double), cmp_dist);
+    double cum = 0.0, rh = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        cum += mass[(int64_t)dm[2 * k + 1]];
+        if (cum >= 0.5 * mtot) {
+            rh = sqrt(dm[2 * k]);
+            break;
+        }
+    }
+    double rmin = 4.0 * rh / ((double)n * cbrt(rho_core));
+    double dtmin = 0.01 * sqrt(eta / 0.02) * sqrt(rmin * rmin * rmin);
+    for (int d = 0; d < 3; ++d) out[d] = xd[d];
+    out[3] = rho_core;
+    out[4] = rc;
+    out[5] = (double)ncore;
+    out[6] = rh;
+    out[7] = rmin;
+    out[8] = dtmin;
+    if (rho)
+        for (int64_t s = 0; s < n_s; ++s) rho[s] = r[s];
+    free(dm);
+    free(r);
+}
+
+/* 6 nearest neighbours of the listed particles (for tests): d2 [n_s][6], idx [n_s][6]. */
+void orc_knn6(int64_t n, const double* pos, int64_t n_s, const int64_t* sample, double* d2,
+              int64_t* idx)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t s = 0; s < n_s; ++s) knn6(n, pos, sample[s], d2 + 6 * s, idx + 6 * s);
 }
 
 /* ------------------------------------------------------------------------ */

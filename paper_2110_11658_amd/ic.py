@@ -213,6 +213,18 @@ def ensemble(n_clusters: int = 64, seed0: int = 4000, nmin: float = 1e4, nmax: f
     return Ensemble(pos, vel, mass, offsets, r_out, gamma * r_out)
 
 
+def core_sample_size(n: int) -> int:
+    """Sample size of the paper's core-radius algorithm: min(N, sqrt(5000 N))."""
+    return int(min(n, math.floor(math.sqrt(5000.0 * n))))
+
+
+def core_sample(n: int, seed: int) -> np.ndarray:
+    """Distinct particle indices (int32, ascending) drawn uniformly for the
+    core-radius algorithm; the draw is an input, made here with PCG64."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, core_sample_size(n), replace=False)).astype(np.int32)
+
+
 # Workloads named in the measurement plan: (seed, N, mass spectrum, eps, r_out, theta)
 WORKLOADS = {
     "plummer4k_equal": dict(seed=1, n=4096, masses="equal", eps=1e-4, r_out=0.05, theta=0.5),

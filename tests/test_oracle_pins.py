@@ -324,6 +324,90 @@ def test_irregular_degenerate_radii():
     assert np.abs(pot - (full_pot + (mass.sum() - mass) / R)).max() <= 1e-13 * np.abs(full_pot).max()
 
 
+# --- Core quantities: 6 nearest neighbours of a sample (Casertano & Hut) -----
+
+def test_knn6_against_numpy_with_ties():
+    rng = np.random.default_rng(61)
+    # random points and a lattice with exact distance ties (ties: lower index first)
+    pts = [rng.normal(size=(300, 3)),
+           np.array(np.meshgrid(*[np.arange(5.0)] * 3, indexing="ij")).reshape(3, -1).T.copy()]
+    for pos in pts:
+        smp = np.arange(0, pos.shape[0], 7)
+        d2, idx = oracle.knn6(pos, smp)
+        for s, i in enumerate(smp):
+            d = ((pos - pos[i]) ** 2).sum(1)
+            d[i] = np.inf
+            order = np.lexsort((np.arange(pos.shape[0]), d))[:6]
+            assert np.array_equal(idx[s], order)
+            assert np.array_equal(d2[s], d[order])
+
+
+def test_density_estimator_moments_uniform():
+    # Poisson field of density 1: the volume to the 6th neighbour is
+    # Gamma(6, 1) distributed, so rho = 5 m / V_6 has E[rho] = 1 and
+    # E[rho^2] / E[rho] = 5/4 (interior targets, away from the faces)
+    rng = np.random.default_rng(62)
+    n = 100000
+    pos = rng.uniform(0.0, 1.0, size=(n, 3))
+    m = np.full(n, 1.0 / n)
+    inner = np.where(np.all((pos > 0.15) & (pos < 0.85), axis=1))[0][:15000]
+    rho, _ = oracle.core(pos, m, inner)
+    assert abs(rho.mean() - 1.0) < 0.03
+    assert abs((rho ** 2).mean() / rho.mean() - 1.25) < 0.06
+
+
+def test_core_quantities_plummer_closed_forms():
+    # Plummer sphere (M = 1, a = 3 pi / 16, truncated at mass fraction 0.999),
+    # sample of min(N, sqrt(5000 N)) particles. With rho_i = rho(x_i) e_i,
+    # E[e] = 1, E[e^2] = 5/4: rho_core -> (5/4) int rho^3 / int rho^2 and
+    # r_c^2 -> int rho^3 r^2 / int rho^3 = 0.3 a^2; r_h at mass fraction 0.4995
+    # of the untruncated profile. Bounds are about four times the scatter over
+    # seeds (3.5 % for rho_core, 1.6 % for r_c).
+    a = ic.PLUMMER_A_HENON
+    c = ic.plummer(60000, seed=63)
+    rng = np.random.default_rng(64)
+    S = ic.core_sample_size(c.n)
+    smp = np.sort(rng.choice(c.n, S, replace=False))
+    _, res = oracle.core(c.pos, c.mass, smp)
+
+    def I(p):   # int_0^inf x^2 (1 + x^2)^(-p) dx
+        return math.sqrt(math.pi) * math.gamma(p - 1.5) / (4.0 * math.gamma(p))
+    rho0 = 3.0 / (4.0 * math.pi * a ** 3)
+    assert res["rho_core"] == pytest.approx(1.25 * rho0 * I(7.5) / I(5.0), rel=0.15)
+    assert res["r_core"] == pytest.approx(math.sqrt(0.3) * a, rel=0.07)
+    assert res["r_half"] == pytest.approx(a / math.sqrt(0.4995 ** (-2.0 / 3.0) - 1.0), rel=0.015)
+    assert np.linalg.norm(res["center"]) < 0.06 * a
+    # the particles inside r_c about the density centre, counted directly
+    d2 = ((c.pos - res["center"]) ** 2).sum(1)
+    assert res["n_core"] == int((d2 < res["r_core"] ** 2).sum())
+
+
+def test_core_quantities_covariance():
+    c = ic.plummer(8000, seed=65, masses="kroupa")
+    smp = np.arange(0, c.n, 3)
+    rho, res = oracle.core(c.pos, c.mass, smp, eta=0.02)
+    shift = np.array([0.3, -1.2, 2.5])
+    _, rs = oracle.core(c.pos + shift, c.mass, smp, eta=0.02)
+    assert np.allclose(rs["center"], res["center"] + shift, rtol=0, atol=1e-12)
+    for k in ("rho_core", "r_core", "r_half", "r_min"):
+        assert rs[k] == pytest.approx(res[k], rel=1e-10)
+    assert rs["n_core"] == res["n_core"]
+    lam = 1.7   # lengths x lam: rho x lam^-3, radii x lam, R_min x lam^2
+    rl, rls = oracle.core(c.pos * lam, c.mass, smp, eta=0.02)
+    assert np.allclose(rl, rho * lam ** -3, rtol=1e-12)
+    assert rls["r_core"] == pytest.approx(lam * res["r_core"], rel=1e-12)
+    assert rls["r_half"] == pytest.approx(lam * res["r_half"], rel=1e-12)
+    assert rls["r_min"] == pytest.approx(lam ** 2 * res["r_min"], rel=1e-12)
+    mu = 3.0    # masses x mu: rho and rho_core x mu, R_min x mu^(-1/3)
+    _, rms = oracle.core(c.pos, c.mass * mu, smp, eta=0.02)
+    assert rms["rho_core"] == pytest.approx(mu * res["rho_core"], rel=1e-12)
+    assert rms["r_core"] == pytest.approx(res["r_core"], rel=1e-12)
+    assert rms["r_min"] == pytest.approx(mu ** (-1.0 / 3.0) * res["r_min"], rel=1e-12)
+    # dT_min grows as sqrt(eta)
+    _, re4 = oracle.core(c.pos, c.mass, smp, eta=0.08)
+    assert re4["dt_min"] == pytest.approx(2.0 * res["dt_min"], rel=1e-14)
+
+
 # --- P-7: Plummer potential, inward field, virial energy ---------------------
 
 def test_plummer_field_henon_units():
