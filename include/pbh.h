@@ -97,6 +97,17 @@ typedef struct {
     double ms_nbr;
 } pbh_stats;
 
+/* Core quantities of pbh_core (Casertano & Hut 1985 estimator, see there). */
+typedef struct {
+    double center[3];   /* density centre x_d */
+    double rho_core;    /* sum rho^2 / sum rho over the sample */
+    double r_core;      /* sqrt(sum rho^2 |x - x_d|^2 / sum rho^2) */
+    int64_t n_core;     /* particles with |x - x_d| < r_core (all n) */
+    double r_half;      /* half-mass radius about x_d */
+    double r_min;       /* 4 r_half / (n rho_core^(1/3)) */
+    double dt_min;      /* 0.01 sqrt(eta / 0.02) sqrt(r_min^3) */
+} pbh_core_info;
+
 /* Create a context on HIP device `device`. params may be NULL (defaults). */
 pbh_status pbh_create(int device, const pbh_params* params, pbh_ctx** out);
 void pbh_destroy(pbh_ctx* ctx);
@@ -238,6 +249,31 @@ pbh_status pbh_irregular_batched(pbh_ctx* ctx, const double* pos, const double* 
                                  int64_t nbr_cap, int64_t n_targets, const int32_t* targets,
                                  double* acc, double* jerk, double* pot, int32_t check,
                                  pbh_stream_t stream);
+
+/*
+ * Core quantities and regularisation parameters from the 6 nearest
+ * neighbours of a particle sample (Section 3.2: a uniform sample of
+ * min(N, sqrt(5000 N)) particles whose 6 nearest neighbours are searched
+ * directly; Section 2.5: the regularisation parameters R_min and dT_min).
+ * For each sampled particle i, with its 6 nearest neighbours among all n
+ * particles (j != i, r^2 = (dx*dx + dy*dy) + dz*dz in FP64 without FMA, ties to
+ * the lower index):
+ *   rho_i = (sum of the masses of the 5 nearest) / ((4 pi / 3) r_6^3)
+ * and the quantities of pbh_core_info over the sample (N_core and r_half over
+ * all particles). The search runs through the octree of the last build and
+ * returns the exact neighbours.
+ *   pos, mass    the arrays of the last build (one cluster), n >= 7
+ *   sample       device int32 [n_sample] distinct caller indices drawn by
+ *                the caller (uniformly, without replacement), 1 <= n_sample <= n
+ *   eta          accuracy parameter of the dT_min rule (the paper uses 0.02)
+ *   rho          device FP64 [n_sample] out (per-sample densities), or NULL
+ *   out          host struct, filled when the call returns (it waits)
+ * PBH_E_ARG for a sample index outside [0, n); PBH_E_STATE without a
+ * single-cluster build.
+ */
+pbh_status pbh_core(pbh_ctx* ctx, const double* pos, const double* mass, int64_t n_sample,
+                    const int32_t* sample, double eta, double* rho, pbh_core_info* out,
+                    pbh_stream_t stream);
 
 /*
  * Kick-drift-kick leapfrog under the regular force (Section 2.2, eq. kick and

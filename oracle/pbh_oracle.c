@@ -330,10 +330,9 @@ void orc_irregular(int64_t n, const double* pos, const double* vel, const double
 }
 
 /* ------------------------------------------------------------------------ */
-/* Core quantities (the core-radius algorithm of the paper's Other            */
-/* Modifications, with the density estimator of Casertano & Hut 1985, and    */
-/* the regularisation parameters R_min, dT_min of the paper's Regularisation  */
-/* section)                                                                   */
+/* Core quantities: the sampled core algorithm of Section 3.2 with the       */
+/* density estimator of Casertano & Hut (1985), and the regularisation       */
+/* parameters R_min, dT_min of Section 2.5                                   */
 /*                                                                            */
 /* For each sampled particle i: its 6 nearest neighbours among all n (j != i, */
 /* unsoftened ((dx*dx + dy*dy) + dz*dz), ties to the lower index), and        */

@@ -26,7 +26,7 @@ PBH_MIXED = 1
 EXPORTS = ("pbh_create", "pbh_destroy", "pbh_set_params", "pbh_get_params", "pbh_build",
            "pbh_force", "pbh_force_buffered", "pbh_build_batched", "pbh_force_batched",
            "pbh_force_batched_buffered", "pbh_irregular",
-           "pbh_irregular_batched", "pbh_kdk", "pbh_kdk_eager",
+           "pbh_irregular_batched", "pbh_core", "pbh_kdk", "pbh_kdk_eager",
            "pbh_get_stats", "pbh_set_timing", "pbh_debug_tree", "pbh_debug_groups",
            "pbh_debug_wave_log", "pbh_last_error", "pbh_status_string")
 
@@ -41,6 +41,12 @@ class pbh_stats(C.Structure):
         "n", "n_clusters", "n_nodes", "n_leaves", "n_groups", "max_level", "n_pn", "n_pp_far",
         "n_pp_near", "nbr_total", "error_flags")] + [
         (name, C.c_double) for name in ("ms_build", "ms_walk", "ms_nbr")]
+
+
+class pbh_core_info(C.Structure):
+    _fields_ = [("center", C.c_double * 3), ("rho_core", C.c_double), ("r_core", C.c_double),
+                ("n_core", C.c_int64), ("r_half", C.c_double), ("r_min", C.c_double),
+                ("dt_min", C.c_double)]
 
 
 class PbhError(RuntimeError):
@@ -78,6 +84,7 @@ def load(path: str = LIB_PATH):
                                i32, vp]),
         "pbh_irregular_batched": (st, [vp, vp, vp, vp, vp, vp, d, vp, vp, i64, i64, vp, vp, vp,
                                        vp, i32, vp]),
+        "pbh_core": (st, [vp, vp, vp, i64, vp, d, vp, vp, vp]),
         "pbh_kdk": (st, [vp, i64, vp, vp, vp, d, i32, d, d, d, d, vp, vp]),
         "pbh_kdk_eager": (st, [vp, i64, vp, vp, vp, d, i32, d, d, d, d, vp, vp]),
         "pbh_get_stats": (st, [vp, vp]),

@@ -14,7 +14,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import PBH_E_NBR_OVERFLOW, PBH_FP64, PBH_MIXED, PbhError, check, pbh_params, pbh_stats
+from ._lib import (PBH_E_NBR_OVERFLOW, PBH_FP64, PBH_MIXED, PbhError, check, pbh_core_info, pbh_params,
+                   pbh_stats)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -203,6 +204,24 @@ class Pbh:
                                       float(r_out), *common)
         check(self.ctx, st)
         return acc, jk, ph
+
+    # -- pbh_core -----------------------------------------------------------------
+    def core(self, pos: torch.Tensor, mass: torch.Tensor, sample: torch.Tensor, eta: float = 0.02,
+             densities: bool = True):
+        """Core quantities from the 6 nearest neighbours of the sampled particles
+        (int32 caller indices) of the last build: (rho [n_sample] or None, dict)."""
+        n = pos.shape[0]
+        _need(pos, (n, 3), "pos")
+        _need(mass, (n,), "mass")
+        _need(sample, (sample.shape[0],), "sample", torch.int32)
+        rho = torch.empty(sample.shape[0], dtype=torch.float64, device=pos.device) if densities else None
+        info = pbh_core_info()
+        check(self.ctx, self.L.pbh_core(self.ctx, _ptr(pos), _ptr(mass), int(sample.shape[0]),
+                                        _ptr(sample), float(eta), _ptr(rho), C.byref(info), _stream()))
+        res = {"center": np.array(info.center[:]), "rho_core": info.rho_core, "r_core": info.r_core,
+               "n_core": int(info.n_core), "r_half": info.r_half, "r_min": info.r_min,
+               "dt_min": info.dt_min}
+        return rho, res
 
     def kdk(self, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor, dt: float, steps: int,
             r_in: float, r_out: float, theta: float, eps: float, graph: bool = True,

@@ -812,6 +812,91 @@ pbh_status pbh_irregular_batched(pbh_ctx* ctx, const double* pos, const double* 
                         n_targets, targets, acc, jerk, pot, check, s);
 }
 
+pbh_status pbh_core(pbh_ctx* ctx, const double* pos, const double* mass, int64_t n_sample,
+                    const int32_t* sample, double eta, double* rho, pbh_core_info* out,
+                    pbh_stream_t stream) {
+    if (!ctx) return PBH_E_ARG;
+    if (!ctx->built) return fail(ctx, PBH_E_STATE, "pbh_core needs a build of these particles");
+    if (ctx->cfg.n_clusters != 1) return fail(ctx, PBH_E_STATE, "pbh_core works on a single-cluster build");
+    const int64_t n = ctx->cfg.n;
+    if (n < 7) return fail(ctx, PBH_E_ARG, "need at least 7 particles (6 neighbours each)");
+    if (!pos || !mass || !sample || !out) return fail(ctx, PBH_E_ARG, "pos, mass, sample and out are required");
+    if (n_sample < 1 || n_sample > n) return fail(ctx, PBH_E_ARG, "need 1 <= n_sample <= n");
+    if (!(std::isfinite(eta) && eta > 0.0)) return fail(ctx, PBH_E_ARG, "eta must be finite and > 0");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    Dev& d = ctx->d;
+    if (d.irr_len < n) {   // the rank array is shared with the irregular-force records
+        if (!dalloc(ctx, &d.irr_rank, n) || !dalloc(ctx, &d.irr_rec, n)) {
+            (void)hipGetLastError();
+            return fail(ctx, PBH_E_OOM, "rank array");
+        }
+        d.irr_len = n;
+    }
+    if (d.core_len < n) {
+        if (!dalloc(ctx, &d.core_keys, n) || !dalloc(ctx, &d.core_keys_alt, n) ||
+            !dalloc(ctx, &d.core_vals, n) || !dalloc(ctx, &d.core_vals_alt, n) ||
+            !dalloc(ctx, &d.core_bsum, core_bsum_len(n)) || !dalloc(ctx, &d.core_stats, 16) ||
+            !dalloc(ctx, &d.core_cnt, 2)) {
+            (void)hipGetLastError();
+            return fail(ctx, PBH_E_OOM, "core-quantity scratch");
+        }
+        d.core_len = n;
+    }
+    double* rho_d = rho;
+    if (!rho_d) {
+        if (d.core_rho_len < n_sample) {
+            if (!dalloc(ctx, &d.core_rho, n_sample)) {
+                (void)hipGetLastError();
+                return fail(ctx, PBH_E_OOM, "sample densities");
+            }
+            d.core_rho_len = n_sample;
+        }
+        rho_d = d.core_rho;
+    }
+    launch_zero_u64(d.core_cnt, 2, s);
+    CoreLaunch c;
+    c.n = n;
+    c.ns = n_sample;
+    c.sample = sample;
+    c.node = d.node;
+    c.x = d.x; c.y = d.y; c.z = d.z;
+    c.perm = d.perm;
+    c.rank = d.irr_rank;
+    c.pos = pos;
+    c.mass = mass;
+    c.rho = rho_d;
+    c.stats = d.core_stats;
+    c.keys = d.core_keys;
+    c.keys_alt = d.core_keys_alt;
+    c.vals = d.core_vals;
+    c.vals_alt = d.core_vals_alt;
+    c.hist = d.rs_hist;
+    c.scan_tmp = d.scan_tmp;
+    c.bsum = d.core_bsum;
+    c.ncore = d.core_cnt;
+    c.err = d.core_cnt + 1;
+    c.eta = eta;
+    launch_core(c, s);
+    HIP_TRY(hipGetLastError());
+    double st[9];
+    unsigned long long err = 0;
+    HIP_TRY(hipMemcpyAsync(st, d.core_stats, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&err, d.core_cnt + 1, sizeof(err), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (err & kCoreBadSample) return fail(ctx, PBH_E_ARG, "a sample index is outside [0, n)");
+    if (err & kCoreStackFull) return fail(ctx, PBH_E_INTERNAL, "nearest-neighbour traversal stack full");
+    for (int k = 0; k < 3; ++k) out->center[k] = st[k];
+    out->rho_core = st[3];
+    out->r_core = st[4];
+    out->n_core = (int64_t)st[5];
+    out->r_half = st[6];
+    out->r_min = st[7];
+    out->dt_min = st[8];
+    return PBH_OK;
+}
+
 static pbh_status kdk_prepare(pbh_ctx* ctx, int64_t n, double r_in, double r_out, double theta,
                               double eps, hipStream_t s) {
     if (n < 1 || n >= (1ll << 31) - 1) return fail(ctx, PBH_E_ARG, "bad n");

@@ -176,6 +176,17 @@ struct Dev {
     int32_t* irr_rank = nullptr;
     IrrRec* irr_rec = nullptr;
     int64_t irr_len = 0;
+    // core quantities: distance keys and their sort scratch, block sums, results
+    uint64_t* core_keys = nullptr;
+    uint64_t* core_keys_alt = nullptr;
+    int32_t* core_vals = nullptr;
+    int32_t* core_vals_alt = nullptr;
+    double* core_bsum = nullptr;
+    double* core_stats = nullptr;          // [16]
+    unsigned long long* core_cnt = nullptr; // [2]: N_core, error flags
+    int64_t core_len = 0;
+    double* core_rho = nullptr;            // [core_rho_len] when the caller passes none
+    int64_t core_rho_len = 0;
     // walk stacks
     int32_t* stack = nullptr;
     int64_t stack_len = 0;
@@ -266,6 +277,36 @@ struct IrrParams {
     unsigned long long* err = nullptr;   // kIrr* flag bits (OR)
 };
 void launch_irregular(const IrrParams& p, hipStream_t s);
+
+// core.hip: core quantities from the 6 nearest neighbours of a sample
+enum : unsigned long long {
+    kCoreBadSample = 1ull,   // a sample index outside [0, n)
+    kCoreStackFull = 2ull,   // traversal stack of a nearest-neighbour search full
+};
+struct CoreLaunch {
+    int64_t n = 0, ns = 0;
+    const int32_t* sample = nullptr;   // [ns] caller indices
+    const WNode* node = nullptr;
+    const double *x = nullptr, *y = nullptr, *z = nullptr;   // sorted coordinates
+    const int32_t* perm = nullptr;
+    int32_t* rank = nullptr;           // [n] written here
+    const double* pos = nullptr;       // [n][3] caller order
+    const double* mass = nullptr;      // [n] caller order
+    double* rho = nullptr;             // [ns] out
+    double* stats = nullptr;           // [9] x_d, rho_core, r_c, N_core, r_h, R_min, dT_min
+    uint64_t* keys = nullptr;          // [n] scratch
+    uint64_t* keys_alt = nullptr;
+    int32_t* vals = nullptr;
+    int32_t* vals_alt = nullptr;
+    int64_t* hist = nullptr;           // radix-sort scratch of the build
+    int64_t* scan_tmp = nullptr;
+    double* bsum = nullptr;            // [core_bsum_len(n)]
+    unsigned long long* ncore = nullptr;
+    unsigned long long* err = nullptr;
+    double eta = 0.02;
+};
+void launch_core(const CoreLaunch& c, hipStream_t s);
+int64_t core_bsum_len(int64_t n);
 
 // kdk.hip
 void launch_kick(double* vel, const double* acc, double h, int64_t n, hipStream_t s);
