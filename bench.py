@@ -303,6 +303,8 @@ def bench_force(args):
     if neighbours and not batched:
         total = int(off[-1].item())
         rec["irregular"] = bench_irregular(p, inp, off, idx[:total], dev, not args.no_cpu_baseline)
+    if not batched:
+        rec["core"] = bench_core(p, inp, dev, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"], rec["accuracy"] = cpu_baseline(inp, theta, prm, acc, pot)
     p.close()
@@ -371,6 +373,39 @@ def bench_irregular(p, inp, off, idx, dev, with_oracle, calls=10):
         out["accuracy"] = {"vs": f"oracle on {len(tg)} sampled targets, error / magnitude sum",
                            "acc": worst(ga, ra, sc[:, 0]), "jerk": worst(gj, rj, sc[:, 1]),
                            "pot": worst(gp, rp, sc[:, 2])}
+    return out
+
+
+def bench_core(p, inp, dev, with_oracle, calls=5):
+    """Core quantities (pbh_core) on the step's tree with the paper's sample
+    size min(N, sqrt(5000 N)); each call waits for its result. The oracle's
+    brute-force search is timed on a few targets and checks their densities."""
+    import torch
+
+    from paper_2110_11658_amd import ic
+    n = inp["n"]
+    smp = ic.core_sample(n, 2021)
+    smp_d = torch.from_numpy(smp).to(dev)
+    p.core(inp["pos_d"], inp["mass_d"], smp_d)
+    t = time.perf_counter()
+    for _ in range(calls):
+        rho, res = p.core(inp["pos_d"], inp["mass_d"], smp_d)
+    ms = 1e3 * (time.perf_counter() - t) / calls
+    out = {"ms": ms, "samples": int(smp.size), "samples_per_s": smp.size / (ms * 1e-3),
+           "brute_force_pairs_per_s": smp.size * n / (ms * 1e-3),
+           "r_core": res["r_core"], "rho_core": res["rho_core"], "n_core": res["n_core"],
+           "r_half": res["r_half"], "r_min": res["r_min"], "dt_min": res["dt_min"]}
+    if with_oracle:
+        import oracle
+        sel = np.random.default_rng(5).choice(smp.size, 64, replace=False)
+        t = time.perf_counter()
+        ro, _ = oracle.core(inp["pos"], inp["mass"], smp[sel].astype(np.int64))
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": len(sel) / dt, "unit": "samples/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"{len(sel)} of the sampled particles, 6 nearest neighbours by "
+                                         f"brute force over all {n} (the paper's search)"}
+        out["densities_bit_exact"] = bool(np.array_equal(rho.cpu().numpy()[sel], ro))
     return out
 
 
