@@ -52,6 +52,8 @@ def lib():
         L.orc_full_direct.argtypes = [_i64, _p, _p, _d, _p, _p]
         L.orc_irregular.argtypes = [_i64, _p, _p, _p, _d, _d, _d, _i64, _p, _p, _p, _p, _p]
         L.orc_core.argtypes = [_i64, _p, _p, _i64, _p, _d, _p, _p]
+        L.orc_hermite.argtypes = [_i64, _p, _p, _p, _p, _d, _d, _d, _d, _d, _p]
+        L.orc_p3t.argtypes = [_i64, _p, _p, _p, _d, _d, _d, _d, _d, C.c_int, _p]
         L.orc_knn6.argtypes = [_i64, _p, _i64, _p, _p, _p]
         L.orc_nbr_brute.restype = _i64
         L.orc_nbr_brute.argtypes = [_i64, _p, _d, _p, _p, _i64]
@@ -187,6 +189,33 @@ def knn6(pos, sample):
     idx = np.zeros((smp.size, 6), dtype=np.int64)
     lib().orc_knn6(pos.shape[0], _ptr(pos), smp.size, _ptr(smp), _ptr(d2), _ptr(idx))
     return d2, idx
+
+
+def hermite(pos, vel, mass, r_in, r_out, eps, T, eta=0.02, fr=None):
+    """Hermite integration of F_I with block time steps over one regular step
+    T (Section 2.2). Returns (x, v, stats) with stats = dict(blocks, steps, kmax)."""
+    x = _f64(pos).copy()
+    n = x.shape[0]
+    v = _f64(vel, (n, 3)).copy()
+    mass = _f64(mass, (n,))
+    f = None if fr is None else _f64(fr, (n, 3))
+    st = np.zeros(3, dtype=np.int64)
+    lib().orc_hermite(n, _ptr(x), _ptr(v), _ptr(mass), None if f is None else _ptr(f), float(r_in),
+                      float(r_out), float(eps), float(T), float(eta), _ptr(st))
+    return x, v, {"blocks": int(st[0]), "steps": int(st[1]), "kmax": int(st[2])}
+
+
+def p3t(pos, vel, mass, r_in, r_out, eps, T, eta=0.02, steps=1):
+    """P3T loop (Section 2.2): kick, Hermite F_I over T, kick, with the direct
+    regular force. Returns (x, v, energy [steps+1])."""
+    x = _f64(pos).copy()
+    n = x.shape[0]
+    v = _f64(vel, (n, 3)).copy()
+    mass = _f64(mass, (n,))
+    e = np.zeros(steps + 1)
+    lib().orc_p3t(n, _ptr(x), _ptr(v), _ptr(mass), float(r_in), float(r_out), float(eps), float(T),
+                  float(eta), int(steps), _ptr(e))
+    return x, v, e
 
 
 def _nbr(fn, pos, r_out):

@@ -30,6 +30,8 @@
  *                             derivative and the irregular potential
  *   orc_core                  core quantities from the 6 nearest neighbours
  *                             of a particle sample, by brute force
+ *   orc_hermite, orc_p3t      Hermite integration of F_I with block time
+ *                             steps over one regular step, and the P3T loop
  *   orc_nbr_brute/orc_nbr_cells neighbour sets, brute force and cell list
  *   orc_keys                  Morton keys of the octree
  *   orc_tree                  Barnes-Hut octree walk with the same tree,
@@ -461,6 +463,192 @@ void orc_knn6(int64_t n, const double* pos, int64_t n_s, const int64_t* sample, 
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t s = 0; s < n_s; ++s) knn6(n, pos, sample[s], d2 + 6 * s, idx + 6 * s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hermite integration of the irregular force with block time steps, and the */
+/* P3T loop (Section 2.2: the integration algorithm and eq. p3t-jpred-x,      */
+/* p3t-jpred-dx; eq. dt with eta; eq. dtmax: dt_max = dt_reg / 4)             */
+/*                                                                            */
+/* Over one regular step of length T every particle carries x, v, a = F_I,    */
+/* j = dF_I/dt, its time tau_i and block step dt_i = dt_max / 2^k.            */
+/*   start: tau = 0, a and j from the state; dt from eta_s |a + F_R| / |j|    */
+/*          (eta_s = 0.01; dt_max when j = 0)                                 */
+/*   block: tau' = min(tau_i + dt_i); the active particles have              */
+/*          tau_i + dt_i = tau'. All particles are predicted to tau' (d =     */
+/*          tau' - tau_i):  x_p = x + d v + d^2/2 a + d^3/6 j,               */
+/*          v_p = v + d a + d^2/2 j  (no regular force: the kicks carry it).  */
+/*          Active particles get a1, j1 at the predicted state and the        */
+/*          4th-order Hermite correction (d = dt_i, da = a - a1):            */
+/*            a2 = (-6 da - d (4 j + 2 j1)) / d^2                             */
+/*            a3 = (12 da + 6 d (j + j1)) / d^3                               */
+/*            x = x_p + d^4/24 a2 + d^5/120 a3,  v = v_p + d^3/6 a2 + d^4/24 a3 */
+/*          new step: eq. dt with a^(0) = a1 + F_R, a^(1) = j1,               */
+/*          a^(2) = a2 + d a3, a^(3) = a3, at most twice the old step and     */
+/*          dt_max, rounded down to dt_max / 2^k and to a divisor of tau'.    */
+/*   until every particle is at tau = T (steps divide T, so they all meet).   */
+/* Reading: eq. dt and the P3T predictor are the paper's; the corrector is   */
+/* the standard 4th-order Hermite one (Makino & Aarseth 1992) and the start   */
+/* step eta_s |a| / |j| the usual one, since the paper defers both to NBODY6. */
+/* ------------------------------------------------------------------------ */
+
+/* Times are counted in integer ticks of dt_max / 2^HERM_KMAX (a regular step
+   is 4 * 2^HERM_KMAX ticks), so block times add exactly; a time length in
+   FP64 is ticks * (T / 2^(HERM_KMAX + 2)). */
+#define HERM_KMAX 40
+
+static double hnorm(const double* v) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+/* block step in ticks: dt_max / 2^k not above `want`, dividing tau */
+static int64_t block_step(double want, double dtmax, int64_t tau)
+{
+    double d = dtmax;
+    int k = 0;
+    while (d > want && k < HERM_KMAX) { d *= 0.5; ++k; }
+    int64_t t = (int64_t)1 << (HERM_KMAX - k);
+    while (tau % t != 0) t >>= 1;
+    return t;
+}
+
+/* F_I and its derivative at particle i from all others (the definition) */
+static void irr_at(const phir_t* p, double eps2, int64_t n, const double* xs, const double* vs,
+                   const double* mass, int64_t i, double* a, double* jk)
+{
+    for (int k = 0; k < 3; ++k) a[k] = jk[k] = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        double d[3], u[3];
+        for (int k = 0; k < 3; ++k) {
+            d[k] = xs[3 * j + k] - xs[3 * i + k];
+            u[k] = vs[3 * j + k] - vs[3 * i + k];
+        }
+        double s2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
+        double s = sqrt(s2);
+        double K, slope;
+        k_and_slope(p, s, &K, &slope);
+        if (p->mode == 0 || s >= p->r_out) continue;
+        double du = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+        double s3 = s2 * s;
+        double Kdot = -slope * du / s;
+        for (int k = 0; k < 3; ++k) {
+            a[k] += mass[j] * K * d[k] / s3;
+            jk[k] += mass[j] * (K * (u[k] / s3 - 3.0 * du * d[k] / (s3 * s2)) + Kdot * d[k] / s3);
+        }
+    }
+}
+
+/*
+ * Integrate F_I over one regular step T in place (x, v [n][3]). fr [n][3] is
+ * the regular force for the step criterion (may be NULL). stats (optional,
+ * int64[3]): block steps, particle steps, smallest k.
+ */
+void orc_hermite(int64_t n, double* x, double* v, const double* mass, const double* fr,
+                 double r_in, double r_out, double eps, double T, double eta, int64_t* stats)
+{
+    phir_t p;
+    phir_init(&p, r_in, r_out);
+    const double eps2 = eps * eps, dtmax = T / 4.0;
+    const double unit = T / (double)((int64_t)1 << (HERM_KMAX + 2));
+    const int64_t tend = (int64_t)1 << (HERM_KMAX + 2);
+    double* a = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    double* jk = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    int64_t* tau = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t* dt = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    double* xp = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    double* vp = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    double* a1 = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    double* j1 = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    char* act = (char*)malloc((size_t)n);
+    int64_t nblock = 0, nsteps = 0, kmin = 0;
+#pragma omp parallel for
+    for (int64_t i = 0; i < n; ++i) irr_at(&p, eps2, n, x, v, mass, i, a + 3 * i, jk + 3 * i);
+    for (int64_t i = 0; i < n; ++i) {
+        double at[3];
+        for (int k = 0; k < 3; ++k) at[k] = a[3 * i + k] + (fr ? fr[3 * i + k] : 0.0);
+        double jn = hnorm(jk + 3 * i);
+        double want = jn > 0.0 ? 0.01 * hnorm(at) / jn : dtmax;
+        tau[i] = 0;
+        dt[i] = block_step(want, dtmax, 0);
+    }
+    for (;;) {
+        int64_t tn = tau[0] + dt[0];
+        for (int64_t i = 1; i < n; ++i)
+            if (tau[i] + dt[i] < tn) tn = tau[i] + dt[i];
+        for (int64_t i = 0; i < n; ++i) {
+            double d = (double)(tn - tau[i]) * unit;
+            double d2 = d * d, d3 = d2 * d;
+            for (int k = 0; k < 3; ++k) {
+                xp[3 * i + k] = x[3 * i + k] + d * v[3 * i + k] + 0.5 * d2 * a[3 * i + k] + d3 / 6.0 * jk[3 * i + k];
+                vp[3 * i + k] = v[3 * i + k] + d * a[3 * i + k] + 0.5 * d2 * jk[3 * i + k];
+            }
+            act[i] = (tau[i] + dt[i] == tn);
+        }
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; ++i)
+            if (act[i]) irr_at(&p, eps2, n, xp, vp, mass, i, a1 + 3 * i, j1 + 3 * i);
+        for (int64_t i = 0; i < n; ++i) {
+            if (!act[i]) continue;
+            double d = (double)dt[i] * unit, d2 = d * d, d3 = d2 * d, d4 = d3 * d, d5 = d4 * d;
+            double a2[3], a3[3], a2e[3], at[3];
+            for (int k = 0; k < 3; ++k) {
+                double da = a[3 * i + k] - a1[3 * i + k];
+                a2[k] = (-6.0 * da - d * (4.0 * jk[3 * i + k] + 2.0 * j1[3 * i + k])) / d2;
+                a3[k] = (12.0 * da + 6.0 * d * (jk[3 * i + k] + j1[3 * i + k])) / d3;
+                x[3 * i + k] = xp[3 * i + k] + d4 / 24.0 * a2[k] + d5 / 120.0 * a3[k];
+                v[3 * i + k] = vp[3 * i + k] + d3 / 6.0 * a2[k] + d4 / 24.0 * a3[k];
+                a[3 * i + k] = a1[3 * i + k];
+                jk[3 * i + k] = j1[3 * i + k];
+                a2e[k] = a2[k] + d * a3[k];
+                at[k] = a1[3 * i + k] + (fr ? fr[3 * i + k] : 0.0);
+            }
+            double n0 = hnorm(at), n1 = hnorm(jk + 3 * i), n2 = hnorm(a2e), n3 = hnorm(a3);
+            double num = n0 * n2 + n1 * n1, den = n1 * n3 + n2 * n2;
+            double want = den > 0.0 ? sqrt(eta * num / den) : dtmax;
+            if (want > 2.0 * d) want = 2.0 * d;
+            tau[i] = tn;
+            dt[i] = block_step(want, dtmax, tn);
+            ++nsteps;
+            int64_t k = 0;
+            for (int64_t q = (int64_t)1 << HERM_KMAX; q > dt[i]; q >>= 1) ++k;
+            if (k > kmin) kmin = k;
+        }
+        ++nblock;
+        if (tn == tend) break;
+    }
+    if (stats) { stats[0] = nblock; stats[1] = nsteps; stats[2] = kmin; }
+    free(a); free(jk); free(tau); free(dt); free(xp); free(vp); free(a1); free(j1); free(act);
+}
+
+/*
+ * P3T loop (Section 2.2): per step, kick v += T/2 F_R, integrate F_I over T
+ * (orc_hermite), recompute F_R, kick again. F_R is the direct regular sum.
+ * energy [steps+1] (optional): KE + 1/2 sum m (Phi_R + Phi_I), i.e. plain
+ * softened gravity, before the first step and after each.
+ */
+void orc_p3t(int64_t n, double* x, double* v, const double* mass, double r_in, double r_out,
+             double eps, double T, double eta, int steps, double* energy)
+{
+    double* fr = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    double* pr = (double*)malloc(sizeof(double) * (size_t)n);
+    double* fa = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    double* pa = (double*)malloc(sizeof(double) * (size_t)n);
+    orc_direct(n, x, mass, r_in, r_out, eps, n, NULL, fr, pr);
+    for (int st = 0; st <= steps; ++st) {
+        if (energy) {
+            orc_full_direct(n, x, mass, eps, fa, pa);
+            double e = 0.0;
+            for (int64_t i = 0; i < n; ++i)
+                e += 0.5 * mass[i] * (v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2])
+                     + 0.5 * mass[i] * pa[i];
+            energy[st] = e;
+        }
+        if (st == steps) break;
+        for (int64_t k = 0; k < 3 * n; ++k) v[k] += 0.5 * T * fr[k];
+        orc_hermite(n, x, v, mass, fr, r_in, r_out, eps, T, eta, NULL);
+        orc_direct(n, x, mass, r_in, r_out, eps, n, NULL, fr, pr);
+        for (int64_t k = 0; k < 3 * n; ++k) v[k] += 0.5 * T * fr[k];
+    }
+    free(fr); free(pr); free(fa); free(pa);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -408,6 +408,81 @@ def test_core_quantities_covariance():
     assert re4["dt_min"] == pytest.approx(2.0 * res["dt_min"], rel=1e-14)
 
 
+# --- Hermite integration of F_I and the P3T loop (Section 2.2) ----------------
+
+def _kepler(e, m1=0.6, m2=0.4):
+    """Two bodies on a Kepler orbit (a = 1, G = 1) starting at pericentre,
+    centre of mass at rest; period 2 pi sqrt(a^3 / M)."""
+    M = m1 + m2
+    rp = 1.0 - e
+    vp = math.sqrt(M * (1.0 + e) / rp)
+    pos = np.array([[-m2 / M * rp, 0.0, 0.0], [m1 / M * rp, 0.0, 0.0]])
+    vel = np.array([[0.0, -m2 / M * vp, 0.0], [0.0, m1 / M * vp, 0.0]])
+    return pos, vel, np.array([m1, m2]), 2.0 * math.pi / math.sqrt(M)
+
+
+def test_hermite_kepler_fourth_order():
+    # all of the force irregular (step changeover beyond the orbit): a plain
+    # Hermite two-body integration. After one period the orbit closes; the
+    # error of a 4th-order scheme with steps ~ sqrt(eta) falls as eta^2
+    pos, vel, m, P = _kepler(0.5)
+    errs = []
+    for eta in (0.02, 0.02 / 16):
+        x, v, st = oracle.hermite(pos, vel, m, 100.0, 100.0, 0.0, P, eta=eta)
+        assert st["steps"] > 20
+        errs.append(np.linalg.norm((x[1] - x[0]) - (pos[1] - pos[0])))
+    assert errs[1] < 1e-4
+    assert errs[0] / errs[1] > 100.0   # 256 for 4th order; 16 would be 2nd
+
+
+def test_hermite_block_steps_and_free_drift():
+    c = ic.plummer(300, seed=81)
+    r_out = ic.r_out_for_nbar(300, 8.0)
+    T = 1.0 / 64
+    x, v, st = oracle.hermite(c.pos, c.vel, c.mass, 0.1 * r_out, r_out, 1e-4, T, eta=0.02)
+    assert st["blocks"] >= 4 and st["kmax"] >= 1
+    # no irregular force: every particle drifts in 4 steps of T/4
+    x0, v0, st0 = oracle.hermite(c.pos, c.vel, c.mass, 0.0, 0.0, 1e-4, T)
+    assert st0["blocks"] == 4 and st0["kmax"] == 0
+    # four additions of (T/4) v against one of T v: a few ulp of |x|
+    assert np.abs(x0 - (c.pos + T * c.vel)).max() <= 8 * 2.0 ** -52 * np.abs(c.pos).max()
+    assert np.array_equal(v0, c.vel)
+
+
+def test_p3t_without_irregular_force_is_leapfrog():
+    # r_out = 0: F_R is all of gravity and the loop is kick-drift-kick
+    c = ic.plummer(200, seed=82)
+    eps, T = 1e-3, 1.0 / 128
+    x, v, _ = oracle.p3t(c.pos, c.vel, c.mass, 0.0, 0.0, eps, T, steps=3)
+
+    def grav(p):
+        d = p[None, :, :] - p[:, None, :]
+        r2 = (d ** 2).sum(-1) + eps * eps
+        np.fill_diagonal(r2, np.inf)
+        return (c.mass[None, :, None] * d / r2[..., None] ** 1.5).sum(1)
+    xl, vl = c.pos.copy(), c.vel.copy()
+    for _ in range(3):
+        vl = vl + 0.5 * T * grav(xl)
+        xl = xl + T * vl
+        vl = vl + 0.5 * T * grav(xl)
+    assert np.allclose(x, xl, rtol=0, atol=1e-13)
+    assert np.allclose(v, vl, rtol=1e-11, atol=1e-13)
+
+
+def test_p3t_energy_conservation():
+    # the regular kicks form a 2nd-order leapfrog: over a fixed time the energy
+    # error falls four-fold when the regular step is halved (the Hermite part,
+    # 4th order with eta = 0.02, stays below it)
+    c = ic.plummer(256, seed=83)
+    r_out = ic.r_out_for_nbar(256, 12.0)
+    drifts = []
+    for T, steps in ((1.0 / 128, 4), (1.0 / 256, 8)):
+        _, _, e = oracle.p3t(c.pos, c.vel, c.mass, 0.1 * r_out, r_out, 1e-3, T, eta=0.02, steps=steps)
+        drifts.append(abs(e[-1] - e[0]) / abs(e[0]))
+    assert drifts[0] < 1e-5
+    assert 0.2 < drifts[1] / drifts[0] < 0.3
+
+
 # --- P-7: Plummer potential, inward field, virial energy ---------------------
 
 def test_plummer_field_henon_units():
