@@ -276,6 +276,43 @@ pbh_status pbh_core(pbh_ctx* ctx, const double* pos, const double* mass, int64_t
                     pbh_stream_t stream);
 
 /*
+ * Hermite integration of the irregular force over one regular step dt_reg
+ * (Section 2.2, step 3 of the integration algorithm), in place: pos and vel
+ * [n][3] move under F_I only, each particle on its own block step dt_max / 2^k
+ * with dt_max = dt_reg / 4 (eq. dtmax), predicted with eq. p3t-jpred-x and
+ * p3t-jpred-dx (no regular force), corrected with the 4th-order Hermite
+ * corrector, and given the next step by eq. dt (eta; a^(0) = F_I + fr). The
+ * start step is 0.01 |F_I + fr| / |dF_I/dt|; steps at most double and stay
+ * commensurate with the block time; all particles end at dt_reg.
+ *   fr           [n][3] regular force for the step criterion, or NULL
+ *   nbr_off/idx  lists that hold every pair inside r_out throughout the step
+ *                (pbh_force_buffered with a large enough r_buff)
+ *   stats        host int64[3] out or NULL: block steps, particle steps, the
+ *                deepest level k
+ * Waits for the stream once per block step (to know when the step ends).
+ */
+pbh_status pbh_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
+                       const double* fr, double r_in, double r_out, double eps,
+                       const int64_t* nbr_off, const int32_t* nbr_idx, int64_t nbr_cap,
+                       double dt_reg, double eta, int64_t* stats, pbh_stream_t stream);
+
+/*
+ * The P3T loop (Section 2.2, the integration algorithm): regular force and
+ * lists of radius r_out + r_buff at the start (tree walk with theta, the
+ * context's precision); then per step: v += dt_reg/2 F_R (eq. kick); Hermite
+ * integration of F_I over dt_reg (pbh_hermite); regular force and lists
+ * again; v += dt_reg/2 F_R. pos, vel updated in place. energy_out: device
+ * FP64 [steps+1] or NULL: sum m v^2/2 + sum m (Phi_R + Phi_I)/2 (plain
+ * softened gravity) before the first step and after each. stats as in
+ * pbh_hermite, summed over the steps. The library keeps its own neighbour
+ * buffer (grown as needed).
+ */
+pbh_status pbh_p3t(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
+                   double r_in, double r_out, double r_buff, double theta, double eps,
+                   double dt_reg, double eta, int32_t steps, double* energy_out, int64_t* stats,
+                   pbh_stream_t stream);
+
+/*
  * Kick-drift-kick leapfrog under the regular force (Section 2.2, eq. kick and
  * the loop that follows it), with a full tree rebuild every step:
  *   a = F_R(x); repeat steps times { v += dt/2 a; x += dt v; rebuild;

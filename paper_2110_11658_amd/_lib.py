@@ -26,7 +26,7 @@ PBH_MIXED = 1
 EXPORTS = ("pbh_create", "pbh_destroy", "pbh_set_params", "pbh_get_params", "pbh_build",
            "pbh_force", "pbh_force_buffered", "pbh_build_batched", "pbh_force_batched",
            "pbh_force_batched_buffered", "pbh_irregular",
-           "pbh_irregular_batched", "pbh_core", "pbh_kdk", "pbh_kdk_eager",
+           "pbh_irregular_batched", "pbh_core", "pbh_hermite", "pbh_p3t", "pbh_kdk", "pbh_kdk_eager",
            "pbh_get_stats", "pbh_set_timing", "pbh_debug_tree", "pbh_debug_groups",
            "pbh_debug_wave_log", "pbh_last_error", "pbh_status_string")
 
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH):
         "pbh_irregular_batched": (st, [vp, vp, vp, vp, vp, vp, d, vp, vp, i64, i64, vp, vp, vp,
                                        vp, i32, vp]),
         "pbh_core": (st, [vp, vp, vp, i64, vp, d, vp, vp, vp]),
+        "pbh_hermite": (st, [vp, i64, vp, vp, vp, vp, d, d, d, vp, vp, i64, d, d, vp, vp]),
+        "pbh_p3t": (st, [vp, i64, vp, vp, vp, d, d, d, d, d, d, d, i32, vp, vp, vp]),
         "pbh_kdk": (st, [vp, i64, vp, vp, vp, d, i32, d, d, d, d, vp, vp]),
         "pbh_kdk_eager": (st, [vp, i64, vp, vp, vp, d, i32, d, d, d, d, vp, vp]),
         "pbh_get_stats": (st, [vp, vp]),

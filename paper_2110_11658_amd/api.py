@@ -223,6 +223,44 @@ class Pbh:
                "dt_min": info.dt_min}
         return rho, res
 
+    # -- pbh_hermite / pbh_p3t --------------------------------------------------
+    def hermite(self, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor,
+                fr: Optional[torch.Tensor], r_in: float, r_out: float, eps: float,
+                nbr_off: torch.Tensor, nbr_idx: torch.Tensor, dt_reg: float, eta: float = 0.02):
+        """Integrate F_I with block Hermite steps over one regular step, in
+        place (pos, vel). Returns dict(blocks, steps, kmax)."""
+        n = pos.shape[0]
+        _need(pos, (n, 3), "pos")
+        _need(vel, (n, 3), "vel")
+        _need(mass, (n,), "mass")
+        if fr is not None:
+            _need(fr, (n, 3), "fr")
+        _need(nbr_off, (n + 1,), "nbr_off", torch.int64)
+        st = np.zeros(3, dtype=np.int64)
+        check(self.ctx, self.L.pbh_hermite(self.ctx, n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(fr),
+                                           float(r_in), float(r_out), float(eps), _ptr(nbr_off),
+                                           _ptr(nbr_idx), int(nbr_idx.shape[0]), float(dt_reg),
+                                           float(eta), st.ctypes.data_as(C.c_void_p), _stream()))
+        return {"blocks": int(st[0]), "steps": int(st[1]), "kmax": int(st[2])}
+
+    def p3t(self, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor, r_in: float, r_out: float,
+            r_buff: float, theta: float, eps: float, dt_reg: float, eta: float = 0.02, steps: int = 1):
+        """P3T loop in place: per step kick, Hermite F_I over dt_reg, kick.
+        Returns (energy [steps+1] on the device, dict(blocks, steps, kmax))."""
+        n = pos.shape[0]
+        _need(pos, (n, 3), "pos")
+        _need(vel, (n, 3), "vel")
+        _need(mass, (n,), "mass")
+        energy = torch.empty(steps + 1, dtype=torch.float64, device=pos.device)
+        st = np.zeros(3, dtype=np.int64)
+        check(self.ctx, self.L.pbh_p3t(self.ctx, n, _ptr(pos), _ptr(vel), _ptr(mass), float(r_in),
+                                       float(r_out), float(r_buff), float(theta), float(eps),
+                                       float(dt_reg), float(eta), int(steps), _ptr(energy),
+                                       st.ctypes.data_as(C.c_void_p), _stream()))
+        self.n = n
+        self.n_clusters = 1
+        return energy, {"blocks": int(st[0]), "steps": int(st[1]), "kmax": int(st[2])}
+
     def kdk(self, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor, dt: float, steps: int,
             r_in: float, r_out: float, theta: float, eps: float, graph: bool = True,
             energy: Optional[torch.Tensor] = None) -> torch.Tensor:

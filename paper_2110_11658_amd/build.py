@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 OBJDIR = os.path.join(ROOT, "_build", "pbh")
 LIB = os.path.join(HERE, "libpbh.so")
-SOURCES = ["sort.hip", "build.hip", "walk.hip", "nbr.hip", "irr.hip", "core.hip", "kdk.hip", "host.cpp"]
+SOURCES = ["sort.hip", "build.hip", "walk.hip", "nbr.hip", "irr.hip", "core.hip", "herm.hip", "kdk.hip", "host.cpp"]
 ARCH = os.environ.get("PBH_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

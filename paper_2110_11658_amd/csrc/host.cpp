@@ -71,6 +71,22 @@ struct pbh_ctx {
     // irregular-force calls: device flag word of the last call (kIrr* bits)
     unsigned long long* irr_err = nullptr;
 
+    // Hermite / P3T state, kept apart from the build buffers (a rebuild inside
+    // the P3T loop must not free it)
+    struct {
+        int64_t n = -1;
+        double *a = nullptr, *j = nullptr, *a1 = nullptr, *j1 = nullptr, *xp = nullptr, *vp = nullptr;
+        int64_t *tau = nullptr, *dt = nullptr;
+        int32_t* act = nullptr;
+        unsigned long long* ctl = nullptr;
+        double *fr = nullptr, *potr = nullptr, *poti = nullptr, *pott = nullptr, *scr = nullptr,
+               *epart = nullptr;
+        int64_t* off = nullptr;
+        int32_t* idx = nullptr;
+        int64_t cap = 0;
+        std::vector<void*> mem;
+    } herm;
+
     // phase timing: events 0/1 build, 2/3 walk, 4/5 neighbours
     bool timing = false;
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -501,6 +517,8 @@ pbh_status do_force(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, double 
     return PBH_OK;
 }
 
+pbh_status ensure_irr_err(pbh_ctx* ctx);
+
 // Shared part of pbh_irregular and pbh_irregular_batched: p already holds the
 // cluster constants (C, cl_off, cps or cp0).
 pbh_status do_irregular(pbh_ctx* ctx, IrrParams& p, int64_t n, const double* pos, const double* vel,
@@ -515,12 +533,8 @@ pbh_status do_irregular(pbh_ctx* ctx, IrrParams& p, int64_t n, const double* pos
     if (jerk && !vel) return fail(ctx, PBH_E_ARG, "the jerk needs vel");
     if (nbr_cap < 0 || (nbr_cap > 0 && !nbr_idx)) return fail(ctx, PBH_E_ARG, "bad neighbour buffer");
     if (!finite_nonneg(eps)) return fail(ctx, PBH_E_ARG, "eps must be finite and >= 0");
-    if (!ctx->irr_err) {
-        void* q = nullptr;
-        if (hipMalloc(&q, sizeof(unsigned long long)) != hipSuccess)
-            return fail(ctx, PBH_E_OOM, "irregular-force flag word");
-        ctx->irr_err = (unsigned long long*)q;
-    }
+    pbh_status ae = ensure_irr_err(ctx);
+    if (ae != PBH_OK) return ae;
     launch_zero_u64(ctx->irr_err, 1, s);
     p.n = n;
     p.n_tgt = targets ? n_targets : n;
@@ -564,6 +578,134 @@ pbh_status do_irregular(pbh_ctx* ctx, IrrParams& p, int64_t n, const double* pos
         if (err & kIrrBadTarget) return fail(ctx, PBH_E_ARG, "a target index is outside [0, n)");
         if (err & kIrrBadOffsets) return fail(ctx, PBH_E_ARG, "neighbour offsets decrease or pass nbr_cap");
         if (err & kIrrBadIndex) return fail(ctx, PBH_E_ARG, "a neighbour index is outside [0, n)");
+    }
+    return PBH_OK;
+}
+
+pbh_status ensure_irr_err(pbh_ctx* ctx) {
+    if (ctx->irr_err) return PBH_OK;
+    void* q = nullptr;
+    if (hipMalloc(&q, sizeof(unsigned long long)) != hipSuccess)
+        return fail(ctx, PBH_E_OOM, "irregular-force flag word");
+    ctx->irr_err = (unsigned long long*)q;
+    return PBH_OK;
+}
+
+template <typename T>
+bool halloc(pbh_ctx* ctx, T** p, int64_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, sizeof(T) * (size_t)std::max<int64_t>(count, 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    ctx->herm.mem.push_back(q);
+    *p = (T*)q;
+    return true;
+}
+
+pbh_status ensure_herm(pbh_ctx* ctx, int64_t n) {
+    auto& h = ctx->herm;
+    if (h.n >= n) return PBH_OK;
+    for (void* q : h.mem) (void)hipFree(q);
+    h.mem.clear();
+    h.cap = 0;
+    h.idx = nullptr;
+    const int nb = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    if (!halloc(ctx, &h.a, 3 * n) || !halloc(ctx, &h.j, 3 * n) || !halloc(ctx, &h.a1, 3 * n) ||
+        !halloc(ctx, &h.j1, 3 * n) || !halloc(ctx, &h.xp, 3 * n) || !halloc(ctx, &h.vp, 3 * n) ||
+        !halloc(ctx, &h.tau, n) || !halloc(ctx, &h.dt, n) || !halloc(ctx, &h.act, n) ||
+        !halloc(ctx, &h.ctl, kHermCtl) || !halloc(ctx, &h.fr, 3 * n) || !halloc(ctx, &h.potr, n) ||
+        !halloc(ctx, &h.poti, n) || !halloc(ctx, &h.pott, n) || !halloc(ctx, &h.scr, 3 * n) ||
+        !halloc(ctx, &h.epart, nb) || !halloc(ctx, &h.off, n + 1)) {
+        for (void* q : h.mem) (void)hipFree(q);
+        h.mem.clear();
+        h.n = -1;
+        return fail(ctx, PBH_E_OOM, "Hermite state");
+    }
+    h.n = n;
+    return PBH_OK;
+}
+
+// Irregular-force launch parameters of one cluster for the Hermite driver.
+IrrParams herm_irr(pbh_ctx* ctx, int64_t n, double r_in, double r_out, double eps,
+                   const double* mass, const int64_t* off, const int32_t* idx, int64_t cap) {
+    IrrParams ip;
+    ip.n = n;
+    ip.n_tgt = n;
+    ip.C = 1;
+    ip.cp0 = cluster_params(r_in, r_out);
+    ip.eps2 = eps * eps;
+    ip.mass = mass;
+    ip.off = off;
+    ip.idx = idx;
+    ip.cap = cap;
+    ip.err = ctx->irr_err;
+    return ip;
+}
+
+// One regular step of Hermite integration of F_I (see herm.hip), in place.
+constexpr int64_t kHermMaxBlocks = 1ll << 20;
+
+pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
+                      const double* fr, double r_in, double r_out, double eps,
+                      const int64_t* off, const int32_t* idx, int64_t cap, double T, double eta,
+                      int64_t* stats, hipStream_t s) {
+    auto& h = ctx->herm;
+    launch_zero_u64(ctx->irr_err, 1, s);
+    IrrParams ip = herm_irr(ctx, n, r_in, r_out, eps, mass, off, idx, cap);
+    ip.pos = pos;
+    ip.vel = vel;
+    ip.acc = h.a;
+    ip.jerk = h.j;
+    launch_irregular(ip, s);
+    HermParams hp;
+    hp.n = n;
+    hp.x = pos;
+    hp.v = vel;
+    hp.a = h.a;
+    hp.j = h.j;
+    hp.a1 = h.a1;
+    hp.j1 = h.j1;
+    hp.xp = h.xp;
+    hp.vp = h.vp;
+    hp.fr = fr;
+    hp.tau = h.tau;
+    hp.dt = h.dt;
+    hp.act = h.act;
+    hp.ctl = h.ctl;
+    hp.unit = T / (double)(1ll << (kHermK + 2));
+    hp.dtmax = T / 4.0;
+    hp.eta = eta;
+    launch_herm_start(hp, s);
+    launch_zero_u64(h.ctl, kHermCtl, s);
+    ip.pos = h.xp;
+    ip.vel = h.vp;
+    ip.tgt = h.act;
+    ip.n_tgt_dev = h.ctl + kHermNact;
+    ip.acc = h.a1;
+    ip.jerk = h.j1;
+    const unsigned long long tend = 1ull << (kHermK + 2);
+    int64_t blocks = 0;
+    for (;;) {
+        launch_herm_block_front(hp, s);
+        launch_irregular(ip, s);
+        launch_herm_correct(hp, s);
+        ++blocks;
+        unsigned long long tn = 0;
+        HIP_TRY(hipMemcpyAsync(&tn, h.ctl + kHermTn, sizeof(tn), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (tn >= tend) break;
+        if (blocks >= kHermMaxBlocks) return fail(ctx, PBH_E_INTERNAL, "Hermite block steps exceed the limit");
+    }
+    unsigned long long c[kHermCtl], err = 0;
+    HIP_TRY(hipMemcpyAsync(c, h.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&err, ctx->irr_err, sizeof(err), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (err) return fail(ctx, PBH_E_ARG, "malformed neighbour lists in the Hermite integration");
+    if (stats) {
+        stats[0] += blocks;
+        stats[1] += (int64_t)c[kHermSteps];
+        stats[2] = std::max<int64_t>(stats[2], (int64_t)c[kHermKmax]);
     }
     return PBH_OK;
 }
@@ -641,6 +783,7 @@ void pbh_destroy(pbh_ctx* ctx) {
     if (ctx->k_pot) (void)hipFree(ctx->k_pot);
     if (ctx->k_epart) (void)hipFree(ctx->k_epart);
     if (ctx->irr_err) (void)hipFree(ctx->irr_err);
+    for (void* q : ctx->herm.mem) (void)hipFree(q);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
@@ -897,6 +1040,97 @@ pbh_status pbh_core(pbh_ctx* ctx, const double* pos, const double* mass, int64_t
     return PBH_OK;
 }
 
+pbh_status pbh_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
+                       const double* fr, double r_in, double r_out, double eps,
+                       const int64_t* nbr_off, const int32_t* nbr_idx, int64_t nbr_cap, double dt_reg,
+                       double eta, int64_t* stats, pbh_stream_t stream) {
+    if (!ctx) return PBH_E_ARG;
+    if (n < 1 || n >= (1ll << 31) - 1) return fail(ctx, PBH_E_ARG, "need 1 <= n < 2^31");
+    if (!pos || !vel || !mass || !nbr_off) return fail(ctx, PBH_E_ARG, "pos, vel, mass and nbr_off are required");
+    if (nbr_cap < 0 || (nbr_cap > 0 && !nbr_idx)) return fail(ctx, PBH_E_ARG, "bad neighbour buffer");
+    pbh_status st = check_radii(ctx, r_in, r_out);
+    if (st != PBH_OK) return st;
+    if (!finite_nonneg(eps)) return fail(ctx, PBH_E_ARG, "eps must be finite and >= 0");
+    if (!(std::isfinite(dt_reg) && dt_reg > 0.0) || !(std::isfinite(eta) && eta > 0.0))
+        return fail(ctx, PBH_E_ARG, "dt_reg and eta must be finite and > 0");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    if ((st = ensure_irr_err(ctx)) != PBH_OK) return st;
+    if ((st = ensure_herm(ctx, n)) != PBH_OK) return st;
+    if (stats) stats[0] = stats[1] = stats[2] = 0;
+    return do_hermite(ctx, n, pos, vel, mass, fr, r_in, r_out, eps, nbr_off, nbr_idx, nbr_cap, dt_reg,
+                      eta, stats, s);
+}
+
+// regular force and buffered lists at pos (library-owned list buffer, grown on demand)
+static pbh_status p3t_regular(pbh_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                              double r_in, double r_out, double r_buff, double theta, double eps,
+                              hipStream_t s) {
+    auto& h = ctx->herm;
+    pbh_status st = pbh_build(ctx, n, pos, mass, s);
+    if (st != PBH_OK) return st;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        int64_t total = 0;
+        st = pbh_force_buffered(ctx, r_in, r_out, r_buff, theta, eps, h.fr, h.potr, h.off, h.idx, h.cap,
+                                &total, s);
+        if (st != PBH_E_NBR_OVERFLOW) return st;
+        const int64_t want = total + total / 4 + 1024;
+        int32_t* q = nullptr;
+        if (!halloc(ctx, &q, want)) return fail(ctx, PBH_E_OOM, "P3T neighbour lists");
+        h.idx = q;   // the old buffer stays in herm.mem until the context is destroyed or resized
+        h.cap = want;
+    }
+    return fail(ctx, PBH_E_INTERNAL, "neighbour capacity did not settle");
+}
+
+pbh_status pbh_p3t(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
+                   double r_in, double r_out, double r_buff, double theta, double eps, double dt_reg,
+                   double eta, int32_t steps, double* energy_out, int64_t* stats,
+                   pbh_stream_t stream) {
+    if (!ctx) return PBH_E_ARG;
+    if (n < 1 || n >= (1ll << 31) - 1) return fail(ctx, PBH_E_ARG, "need 1 <= n < 2^31");
+    if (!pos || !vel || !mass) return fail(ctx, PBH_E_ARG, "pos, vel and mass are required");
+    if (steps < 0) return fail(ctx, PBH_E_ARG, "steps must be >= 0");
+    pbh_status st = check_radii(ctx, r_in, r_out);
+    if (st != PBH_OK) return st;
+    if (!finite_nonneg(r_buff) || !finite_nonneg(theta) || !finite_nonneg(eps))
+        return fail(ctx, PBH_E_ARG, "r_buff, theta and eps must be finite and >= 0");
+    if (!(std::isfinite(dt_reg) && dt_reg > 0.0) || !(std::isfinite(eta) && eta > 0.0))
+        return fail(ctx, PBH_E_ARG, "dt_reg and eta must be finite and > 0");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    if ((st = ensure_irr_err(ctx)) != PBH_OK) return st;
+    if ((st = ensure_herm(ctx, n)) != PBH_OK) return st;
+    auto& h = ctx->herm;
+    if (stats) stats[0] = stats[1] = stats[2] = 0;
+    const int nb = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    if ((st = p3t_regular(ctx, n, pos, mass, r_in, r_out, r_buff, theta, eps, s)) != PBH_OK) return st;
+    for (int k = 0; k <= steps; ++k) {
+        if (energy_out) {   // E = sum m v^2 / 2 + sum m (Phi_R + Phi_I) / 2
+            launch_zero_u64(ctx->irr_err, 1, s);
+            IrrParams ip = herm_irr(ctx, n, r_in, r_out, eps, mass, h.off, h.idx, h.cap);
+            ip.pos = pos;
+            ip.vel = vel;
+            ip.acc = h.scr;
+            ip.pot = h.poti;
+            launch_irregular(ip, s);
+            launch_add(n, h.potr, h.poti, h.pott, s);
+            launch_energy(vel, mass, h.pott, n, h.epart, nb, energy_out + k, s);
+        }
+        if (k == steps) break;
+        launch_kick(vel, h.fr, 0.5 * dt_reg, n, s);
+        st = do_hermite(ctx, n, pos, vel, mass, h.fr, r_in, r_out, eps, h.off, h.idx, h.cap, dt_reg, eta,
+                        stats, s);
+        if (st != PBH_OK) return st;
+        if ((st = p3t_regular(ctx, n, pos, mass, r_in, r_out, r_buff, theta, eps, s)) != PBH_OK) return st;
+        launch_kick(vel, h.fr, 0.5 * dt_reg, n, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return PBH_OK;
+}
+
 static pbh_status kdk_prepare(pbh_ctx* ctx, int64_t n, double r_in, double r_out, double theta,
                               double eps, hipStream_t s) {
     if (n < 1 || n >= (1ll << 31) - 1) return fail(ctx, PBH_E_ARG, "bad n");
@@ -911,6 +1145,7 @@ static pbh_status kdk_prepare(pbh_ctx* ctx, int64_t n, double r_in, double r_out
         if (ctx->k_pot) (void)hipFree(ctx->k_pot);
         if (ctx->k_epart) (void)hipFree(ctx->k_epart);
     if (ctx->irr_err) (void)hipFree(ctx->irr_err);
+    for (void* q : ctx->herm.mem) (void)hipFree(q);
         ctx->k_acc = ctx->k_pot = ctx->k_epart = nullptr;
         ctx->k_n = -1;
         ctx->k_nblk = (int)std::min<int64_t>(1024, (n + 255) / 256) + 1;

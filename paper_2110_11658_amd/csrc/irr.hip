@@ -220,6 +220,7 @@ __global__ __launch_bounds__(256) void k_irregular(IrrParams p) {
     const unsigned blk = SORTED ? xcd_chunk_block(blockIdx.x, kIrrChunk) : blockIdx.x;
     const int64_t k = (int64_t)blk * blockDim.x + threadIdx.x;
     if (k >= p.n_tgt) return;
+    if (p.n_tgt_dev && k >= (int64_t)*p.n_tgt_dev) return;
     unsigned long long bad = 0;
     const int64_t i = p.tgt ? (int64_t)p.tgt[k] : (p.order ? (int64_t)p.order[k] : k);
     const ClusterParams* cp;

@@ -251,7 +251,8 @@ enum : unsigned long long {
 };
 struct IrrParams {
     int64_t n = 0;              // particles (caller order)
-    int64_t n_tgt = 0;          // targets of this launch
+    int64_t n_tgt = 0;          // targets of this launch (an upper bound if n_tgt_dev is set)
+    const unsigned long long* n_tgt_dev = nullptr;   // target count held on the device, or null
     const int32_t* tgt = nullptr;    // target caller indices (outputs compact), or null = all
     const int32_t* order = nullptr;  // processing order of all targets (key order), or null
     // key-order records: perm [n] (key position -> caller index), rank [n]
@@ -307,6 +308,33 @@ struct CoreLaunch {
 };
 void launch_core(const CoreLaunch& c, hipStream_t s);
 int64_t core_bsum_len(int64_t n);
+
+// herm.hip: Hermite integration of F_I with block steps over one regular step
+constexpr int kHermK = 40;   // block steps dt_max / 2^k, k <= kHermK; times in ticks of dt_max / 2^kHermK
+enum { kHermTn = 0, kHermNact = 1, kHermSteps = 2, kHermKmax = 3, kHermCtl = 4 };
+struct HermParams {
+    int64_t n = 0;
+    double* x = nullptr;         // [n][3] positions (caller's, updated in place)
+    double* v = nullptr;         // [n][3] velocities (caller's, updated in place)
+    double* a = nullptr;         // [n][3] F_I at tau_i
+    double* j = nullptr;         // [n][3] dF_I/dt at tau_i
+    const double* a1 = nullptr;  // [n_active][3] F_I at the predicted state (active list order)
+    const double* j1 = nullptr;
+    double* xp = nullptr;        // [n][3] predicted
+    double* vp = nullptr;
+    const double* fr = nullptr;  // [n][3] regular force (step criterion), or null
+    int64_t* tau = nullptr;      // [n] ticks
+    int64_t* dt = nullptr;       // [n] ticks
+    int32_t* act = nullptr;      // [n] active list
+    unsigned long long* ctl = nullptr;   // [kHermCtl]
+    double unit = 0.0;           // seconds per tick: T / 2^(kHermK + 2)
+    double dtmax = 0.0;          // T / 4
+    double eta = 0.02;
+};
+void launch_herm_start(const HermParams& p, hipStream_t s);
+void launch_herm_block_front(const HermParams& p, hipStream_t s);   // next time, predict, active list
+void launch_herm_correct(const HermParams& p, hipStream_t s);
+void launch_add(int64_t n, const double* a, const double* b, double* out, hipStream_t s);
 
 // kdk.hip
 void launch_kick(double* vel, const double* acc, double h, int64_t n, hipStream_t s);
