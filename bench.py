@@ -16,6 +16,10 @@ Workloads (--workload):
   ensemble64   64 independent clusters, N log-uniform in [1e4, 2e5], each
                with its own r_out for 64 neighbours; one batched build and one
                persistent walk launch per step
+  p3t1m        N = 2^20 with the paper's run parameters (tau = (1/128)(N/2^14)^(-1/3),
+               r_cut = 4 tau, r_buff = 3 tau sigma, dt_reg = 2^-9, eta = 0.02):
+               the whole P3T loop (regular force and buffered lists, kicks,
+               Hermite F_I on block steps); a step = one regular step
   kdk4m        N = 2^22: 32 kick-drift-kick steps of dt = 1/1024 with a full
                rebuild each step, captured once in a hipGraph; reports the
                relative energy drift (a step = one KDK step)
@@ -62,6 +66,7 @@ WORKLOADS = {
     "plummer4m": "plummer4m_kroupa",
     "ensemble64": None,
     "kdk4m": "plummer4m_kroupa",
+    "p3t1m": "plummer1m_kroupa",
 }
 METRIC = "particle-node interactions/s and force evals/s at N=1e6 vs FP32 VALU roofline"
 
@@ -136,6 +141,8 @@ def main():
         sys.exit(2)
     if args.workload == "kdk4m":
         return bench_kdk(args)
+    if args.workload == "p3t1m":
+        return bench_p3t(args)
     return bench_force(args)
 
 
@@ -495,6 +502,46 @@ def bench_kdk(args):
     if "fp64" in out and "mixed" in out:
         rec["energy_diff_mixed_vs_fp64"] = float(np.max(np.abs(out["mixed"]["energy"] - out["fp64"]["energy"])
                                                          / abs(out["fp64"]["energy"][0])))
+    print(json.dumps(rec))
+
+
+def bench_p3t(args):
+    """The P3T loop with the paper's run parameters at N = 2^20."""
+    import torch
+
+    from paper_2110_11658_amd import ic
+    from paper_2110_11658_amd.api import Pbh
+
+    inp, dev = _setup(args, torch)
+    n = inp["n"]
+    pr = ic.paper_radii(n)
+    r_out, r_buff, T = pr["r_cut"], pr["r_buff"], pr["dt_reg"]
+    r_in, eps, eta = 0.1 * r_out, inp["eps"], 0.02
+    steps = args.steps if args.steps != 10 else 4
+    p = Pbh(0, leaf_size=args.leaf, n_crit=args.ncrit, prec=args.prec)
+    vel0 = torch.from_numpy(inp["vel"]).to(dev)
+    pos, vel = inp["pos_d"].clone(), vel0.clone()
+    p.p3t(pos.clone(), vel.clone(), inp["mass_d"], r_in, r_out, r_buff, args.theta, eps, T, eta, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e, st = p.p3t(pos, vel, inp["mass_d"], r_in, r_out, r_buff, args.theta, eps, T, eta, steps)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    e = e.cpu().numpy()
+    rec = {
+        "metric": "P3T regular steps (regular force + buffered lists + kicks + block-step Hermite F_I) at N=2^20",
+        "value": n * steps / secs, "unit": "particle regular-steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": 1e3 * secs / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.prec == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": f"{inp['name']}: {inp['desc'].split(' r_out')[0]} paper rule: "
+                               f"r_cut={r_out:.6f} r_in={r_in:.6f} r_buff={r_buff:.6f} dt_reg={T} "
+                               f"eta={eta} theta={args.theta}", "n": n},
+        "hermite": {"blocks_per_step": st["blocks"] / steps, "particle_steps_per_step": st["steps"] / steps,
+                    "deepest_level": st["kmax"]},
+        "energy_drift": float(np.max(np.abs(e - e[0]) / abs(e[0]))),
+    }
+    p.close()
     print(json.dumps(rec))
 
 

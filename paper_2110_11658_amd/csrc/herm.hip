@@ -7,8 +7,9 @@
 // a = F_I, j = dF_I/dt, its time tau_i and step dt_i = dt_max / 2^k, with
 // dt_max = T / 4 (eq. dtmax) for a regular step T. Times are integer ticks of
 // dt_max / 2^kHermK, so block times add exactly. One block:
-//   tau' = min(tau_i + dt_i); all particles are predicted to tau' with the
-//   P3T predictor (eq. p3t-jpred-x, -dx: no regular force, the kicks carry it)
+//   tau' = min(tau_i + dt_i); the active particles and the members of their
+//   neighbour lists are predicted to tau' with the P3T predictor (eq.
+//   p3t-jpred-x, -dx: no regular force, the kicks carry it)
 //     x_p = x + d v + d^2/2 a + d^3/6 j,   v_p = v + d a + d^2/2 j;
 //   the active particles (tau_i + dt_i = tau') get F_I and its derivative at
 //   the predicted state from their neighbour lists, then the 4th-order Hermite
@@ -63,50 +64,109 @@ __global__ __launch_bounds__(256) void k_herm_start(HermParams p) {
     p.dt[i] = block_step(want, p.dtmax, 0);
 }
 
-// tn = min(tau_i + dt_i) (exact: integer ticks)
-__global__ __launch_bounds__(256) void k_herm_next(HermParams p) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Blocks are enqueued in batches without waiting; once every particle has
+// reached the end of the regular step the remaining blocks of a batch are
+// empty (kHermDone), so the host waits once per batch.
+// Block front, in three passes over the per-particle times (16 bytes each):
+// the next block time tn = min(tau_i + dt_i) (exact: integer ticks) by a
+// two-level reduction, the list of active particles (tau_i + dt_i = tn), and
+// the prediction of the active particles and of every member of their
+// neighbour lists -- the only states the irregular force of the block reads
+// (the other particles keep x, v until their own block).
+constexpr int kHermGrid = 1024;   // grid-stride launches
+
+__global__ __launch_bounds__(256) void k_herm_min_part(HermParams p) {
+    __shared__ unsigned long long red[4];
     unsigned long long v = ~0ull;
-    if (i < p.n) v = (unsigned long long)(p.tau[i] + p.dt[i]);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < p.n; i += (int64_t)gridDim.x * 256) {
+        const unsigned long long t = (unsigned long long)(p.tau[i] + p.dt[i]);
+        v = t < v ? t : v;
+    }
     for (int o = 32; o > 0; o >>= 1) {
         const unsigned long long w = __shfl_xor(v, o, 64);
         v = w < v ? w : v;
     }
-    if (i - (int64_t)(threadIdx.x & 63) < p.n) atomicMin(p.ctl + kHermTn, (threadIdx.x & 63) == 0 ? v : ~0ull);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) v = red[w] < v ? red[w] : v;
+        p.part[blockIdx.x] = v;
+    }
 }
 
-// predict every particle to tn; list the active ones
-__global__ __launch_bounds__(256) void k_herm_predict(HermParams p) {
-#pragma clang fp contract(off)
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t tn = (int64_t)p.ctl[kHermTn];
-    bool act = false;
-    if (i < p.n) {
-        const double d = (double)(tn - p.tau[i]) * p.unit;
-        const double d2 = d * d, d3 = d2 * d;
-        for (int k = 0; k < 3; ++k) {
-            const int64_t q = 3 * i + k;
-            p.xp[q] = p.x[q] + d * p.v[q] + 0.5 * d2 * p.a[q] + d3 / 6.0 * p.j[q];
-            p.vp[q] = p.v[q] + d * p.a[q] + 0.5 * d2 * p.j[q];
-        }
-        act = p.tau[i] + p.dt[i] == tn;
+__global__ __launch_bounds__(256) void k_herm_min_final(HermParams p, int nparts) {
+    __shared__ unsigned long long red[4];
+    unsigned long long v = ~0ull;
+    for (int b = threadIdx.x; b < nparts; b += 256) v = p.part[b] < v ? p.part[b] : v;
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
     }
-    const uint64_t b = __ballot(act);
-    if (!b) return;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) v = red[w] < v ? red[w] : v;
+        // past the end of the regular step (every particle at tend): nothing
+        // matches the sentinel time, and the block does no work
+        const bool done = v > p.tend;
+        p.ctl[kHermTn] = done ? ~0ull : v;
+        p.ctl[kHermNact] = 0ull;
+        if (done) p.ctl[kHermDone] = 1ull;
+        else p.ctl[kHermBlocks] += 1ull;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_herm_active(HermParams p) {
+    const int64_t tn = (int64_t)p.ctl[kHermTn];
     const int lane = threadIdx.x & 63;
-    const unsigned long long base =
-        __shfl(atomicAdd(p.ctl + kHermNact, lane == 0 ? (unsigned long long)__popcll(b) : 0ull), 0, 64);
-    if (act) {
-        const uint64_t below = lane ? (b & ((~0ull) >> (64 - lane))) : 0ull;
-        p.act[base + __popcll(below)] = (int32_t)i;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < p.n; base += (int64_t)gridDim.x * 256) {
+        const int64_t i = base + threadIdx.x;
+        const bool act = i < p.n && p.tau[i] + p.dt[i] == tn;
+        const uint64_t b = __ballot(act);
+        if (!b) continue;
+        const unsigned long long at =
+            __shfl(atomicAdd(p.ctl + kHermNact, lane == 0 ? (unsigned long long)__popcll(b) : 0ull), 0, 64);
+        if (act) {
+            const uint64_t below = lane ? (b & ((~0ull) >> (64 - lane))) : 0ull;
+            p.act[at + __popcll(below)] = (int32_t)i;
+        }
+    }
+}
+
+__device__ inline void predict_one(const HermParams& p, int64_t i, int64_t tn) {
+#pragma clang fp contract(off)
+    const double d = (double)(tn - p.tau[i]) * p.unit;
+    const double d2 = d * d, d3 = d2 * d;
+    for (int k = 0; k < 3; ++k) {
+        const int64_t q = 3 * i + k;
+        p.xp[q] = p.x[q] + d * p.v[q] + 0.5 * d2 * p.a[q] + d3 / 6.0 * p.j[q];
+        p.vp[q] = p.v[q] + d * p.a[q] + 0.5 * d2 * p.j[q];
+    }
+}
+
+// Active particles and their list members (a member shared by several lists
+// is written with the same value by each).
+__global__ __launch_bounds__(256) void k_herm_predict(HermParams p) {
+    const int64_t tn = (int64_t)p.ctl[kHermTn];
+    const int64_t nact = (int64_t)p.ctl[kHermNact];
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nact; k += (int64_t)gridDim.x * 256) {
+        const int64_t i = p.act[k];
+        predict_one(p, i, tn);
+        int64_t b = p.off[i], e = p.off[i + 1];
+        if (b < 0 || e < b || e > p.cap) continue;   // flagged by the force kernel
+        for (; b < e; ++b) {
+            const int64_t j = p.idx[b];
+            if ((uint64_t)j < (uint64_t)p.n) predict_one(p, j, tn);
+        }
     }
 }
 
 // Hermite corrector and new block step of the active particles
 __global__ __launch_bounds__(256) void k_herm_correct(HermParams p) {
 #pragma clang fp contract(off)
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nact = (int64_t)p.ctl[kHermNact];
+    for (int64_t k0 = (int64_t)blockIdx.x * 256; k0 < nact; k0 += (int64_t)gridDim.x * 256) {
+    const int64_t k = k0 + threadIdx.x;
     int level = 0;
     if (k < nact) {
         const int64_t i = p.act[k];
@@ -149,13 +209,6 @@ __global__ __launch_bounds__(256) void k_herm_correct(HermParams p) {
         atomicAdd(p.ctl + kHermSteps, lane == 0 ? (unsigned long long)__popcll(b) : 0ull);
         atomicMax(p.ctl + kHermKmax, lane == 0 ? (unsigned long long)lv : 0ull);
     }
-}
-
-// before each block: tn = +inf, no active particle
-__global__ void k_herm_reset(unsigned long long* ctl) {
-    if (threadIdx.x == 0) {
-        ctl[kHermTn] = ~0ull;
-        ctl[kHermNact] = 0ull;
     }
 }
 
@@ -171,15 +224,23 @@ void launch_herm_start(const HermParams& p, hipStream_t s) {
     hipLaunchKernelGGL(k_herm_start, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, s, p);
 }
 
+static unsigned herm_grid(int64_t n) {
+    const int64_t g = (n + 255) / 256;
+    return (unsigned)(g < kHermGrid ? (g < 1 ? 1 : g) : kHermGrid);
+}
+
+int herm_part_len() { return kHermGrid; }
+
 void launch_herm_block_front(const HermParams& p, hipStream_t s) {
-    const dim3 grid((unsigned)((p.n + 255) / 256));
-    hipLaunchKernelGGL(k_herm_reset, dim3(1), dim3(64), 0, s, p.ctl);
-    hipLaunchKernelGGL(k_herm_next, grid, dim3(256), 0, s, p);
-    hipLaunchKernelGGL(k_herm_predict, grid, dim3(256), 0, s, p);
+    const unsigned g = herm_grid(p.n);
+    hipLaunchKernelGGL(k_herm_min_part, dim3(g), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(k_herm_min_final, dim3(1), dim3(256), 0, s, p, (int)g);
+    hipLaunchKernelGGL(k_herm_active, dim3(g), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(k_herm_predict, dim3(g), dim3(256), 0, s, p);
 }
 
 void launch_herm_correct(const HermParams& p, hipStream_t s) {
-    hipLaunchKernelGGL(k_herm_correct, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(k_herm_correct, dim3(herm_grid(p.n)), dim3(256), 0, s, p);
 }
 
 void launch_add(int64_t n, const double* a, const double* b, double* out, hipStream_t s) {

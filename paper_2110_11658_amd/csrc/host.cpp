@@ -79,6 +79,7 @@ struct pbh_ctx {
         int64_t *tau = nullptr, *dt = nullptr;
         int32_t* act = nullptr;
         unsigned long long* ctl = nullptr;
+        unsigned long long* part = nullptr;
         double *fr = nullptr, *potr = nullptr, *poti = nullptr, *pott = nullptr, *scr = nullptr,
                *epart = nullptr;
         int64_t* off = nullptr;
@@ -614,7 +615,8 @@ pbh_status ensure_herm(pbh_ctx* ctx, int64_t n) {
     if (!halloc(ctx, &h.a, 3 * n) || !halloc(ctx, &h.j, 3 * n) || !halloc(ctx, &h.a1, 3 * n) ||
         !halloc(ctx, &h.j1, 3 * n) || !halloc(ctx, &h.xp, 3 * n) || !halloc(ctx, &h.vp, 3 * n) ||
         !halloc(ctx, &h.tau, n) || !halloc(ctx, &h.dt, n) || !halloc(ctx, &h.act, n) ||
-        !halloc(ctx, &h.ctl, kHermCtl) || !halloc(ctx, &h.fr, 3 * n) || !halloc(ctx, &h.potr, n) ||
+        !halloc(ctx, &h.ctl, kHermCtl) || !halloc(ctx, &h.part, herm_part_len()) ||
+        !halloc(ctx, &h.fr, 3 * n) || !halloc(ctx, &h.potr, n) ||
         !halloc(ctx, &h.poti, n) || !halloc(ctx, &h.pott, n) || !halloc(ctx, &h.scr, 3 * n) ||
         !halloc(ctx, &h.epart, nb) || !halloc(ctx, &h.off, n + 1)) {
         for (void* q : h.mem) (void)hipFree(q);
@@ -645,6 +647,7 @@ IrrParams herm_irr(pbh_ctx* ctx, int64_t n, double r_in, double r_out, double ep
 
 // One regular step of Hermite integration of F_I (see herm.hip), in place.
 constexpr int64_t kHermMaxBlocks = 1ll << 20;
+constexpr int kHermBatch = 16;   // blocks enqueued per wait
 
 pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
                       const double* fr, double r_in, double r_out, double eps,
@@ -673,6 +676,11 @@ pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const d
     hp.dt = h.dt;
     hp.act = h.act;
     hp.ctl = h.ctl;
+    hp.part = h.part;
+    hp.off = off;
+    hp.idx = idx;
+    hp.cap = cap;
+    hp.tend = 1ull << (kHermK + 2);
     hp.unit = T / (double)(1ll << (kHermK + 2));
     hp.dtmax = T / 4.0;
     hp.eta = eta;
@@ -684,18 +692,19 @@ pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const d
     ip.n_tgt_dev = h.ctl + kHermNact;
     ip.acc = h.a1;
     ip.jerk = h.j1;
-    const unsigned long long tend = 1ull << (kHermK + 2);
-    int64_t blocks = 0;
+    int64_t queued = 0;
     for (;;) {
-        launch_herm_block_front(hp, s);
-        launch_irregular(ip, s);
-        launch_herm_correct(hp, s);
-        ++blocks;
-        unsigned long long tn = 0;
-        HIP_TRY(hipMemcpyAsync(&tn, h.ctl + kHermTn, sizeof(tn), hipMemcpyDeviceToHost, s));
+        for (int b = 0; b < kHermBatch; ++b) {
+            launch_herm_block_front(hp, s);
+            launch_irregular(ip, s);
+            launch_herm_correct(hp, s);
+        }
+        queued += kHermBatch;
+        unsigned long long done = 0;
+        HIP_TRY(hipMemcpyAsync(&done, h.ctl + kHermDone, sizeof(done), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        if (tn >= tend) break;
-        if (blocks >= kHermMaxBlocks) return fail(ctx, PBH_E_INTERNAL, "Hermite block steps exceed the limit");
+        if (done) break;
+        if (queued >= kHermMaxBlocks) return fail(ctx, PBH_E_INTERNAL, "Hermite block steps exceed the limit");
     }
     unsigned long long c[kHermCtl], err = 0;
     HIP_TRY(hipMemcpyAsync(c, h.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
@@ -703,7 +712,7 @@ pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const d
     HIP_TRY(hipStreamSynchronize(s));
     if (err) return fail(ctx, PBH_E_ARG, "malformed neighbour lists in the Hermite integration");
     if (stats) {
-        stats[0] += blocks;
+        stats[0] += (int64_t)c[kHermBlocks];
         stats[1] += (int64_t)c[kHermSteps];
         stats[2] = std::max<int64_t>(stats[2], (int64_t)c[kHermKmax]);
     }

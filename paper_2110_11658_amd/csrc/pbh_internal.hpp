@@ -311,7 +311,8 @@ int64_t core_bsum_len(int64_t n);
 
 // herm.hip: Hermite integration of F_I with block steps over one regular step
 constexpr int kHermK = 40;   // block steps dt_max / 2^k, k <= kHermK; times in ticks of dt_max / 2^kHermK
-enum { kHermTn = 0, kHermNact = 1, kHermSteps = 2, kHermKmax = 3, kHermCtl = 4 };
+enum { kHermTn = 0, kHermNact = 1, kHermSteps = 2, kHermKmax = 3, kHermDone = 4, kHermBlocks = 5,
+       kHermCtl = 6 };
 struct HermParams {
     int64_t n = 0;
     double* x = nullptr;         // [n][3] positions (caller's, updated in place)
@@ -327,12 +328,18 @@ struct HermParams {
     int64_t* dt = nullptr;       // [n] ticks
     int32_t* act = nullptr;      // [n] active list
     unsigned long long* ctl = nullptr;   // [kHermCtl]
+    unsigned long long* part = nullptr;  // [herm_part_len()] partial minima
+    const int64_t* off = nullptr;        // neighbour lists (members are predicted with the active)
+    const int32_t* idx = nullptr;
+    int64_t cap = 0;
+    unsigned long long tend = 0; // ticks of one regular step: 2^(kHermK + 2)
     double unit = 0.0;           // seconds per tick: T / 2^(kHermK + 2)
     double dtmax = 0.0;          // T / 4
     double eta = 0.02;
 };
 void launch_herm_start(const HermParams& p, hipStream_t s);
-void launch_herm_block_front(const HermParams& p, hipStream_t s);   // next time, predict, active list
+void launch_herm_block_front(const HermParams& p, hipStream_t s);   // next time, active list, predict
+int herm_part_len();
 void launch_herm_correct(const HermParams& p, hipStream_t s);
 void launch_add(int64_t n, const double* a, const double* b, double* out, hipStream_t s);
 
