@@ -1,0 +1,146 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times (mixed precision, n_leaf = 8, n_crit chosen by the library,
+theta = 0.5), through the C ABI.
+
+* interaction counts: equal to the oracle tree walk's (every opening decision
+  is FP64 without FMA on both sides);
+* FP64 walk: every particle within 1e-6 of the oracle tree walk (same tree,
+  groups and opening rule; only the summation order differs);
+* mixed walk: against FP64 direct sums on sampled particles, median 1e-3
+  (the mixed-precision gate), p99 5e-3;
+* neighbour lists: the total equals the oracle's cell-list count and sampled
+  sets are identical;
+* the 4M kick-drift-kick run: graph replay equals eager launches bit for bit,
+  and the mixed and FP64 energy records agree.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2110_11658_amd import ic
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0) if torch.cuda.is_available() else None
+
+
+def _pbh(**kw):
+    from paper_2110_11658_amd.api import Pbh
+    return Pbh(0, **kw)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
+def _check_lists(pos, r_out, off, idx, sample):
+    o_off, o_idx = oracle.nbr_cells(pos, r_out)
+    assert off[-1] == o_off[-1]
+    for i in sample:
+        assert np.array_equal(np.sort(idx[off[i]:off[i + 1]]), o_idx[o_off[i]:o_off[i + 1]]), i
+
+
+def _run(p, c, w, theta):
+    p.build(_t(c.pos), _t(c.mass))
+    acc, pot, off, idx = p.force(w["r_in"], w["r_out"], theta, w["eps"])
+    torch.cuda.synchronize()
+    return acc.cpu().numpy(), pot.cpu().numpy(), off.cpu().numpy(), idx.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["plummer128k_kroupa", "plummer1m_kroupa"])
+def test_full_size_mixed_walk(name):
+    c, w = ic.workload(name)
+    print(f"full size mixed {name}", flush=True)
+    p = _pbh(leaf_size=8)
+    acc, pot, off, idx = _run(p, c, w, w["theta"])
+    st = p.stats()
+    assert st["error_flags"] == 0
+    prm = p.params()
+    n_crit = 32 if c.n < (1 << 18) else 64   # the library's choice for n_crit = 0
+    _, _, ost = oracle.tree(c.pos, c.mass, w["r_in"], w["r_out"], w["theta"], w["eps"], n_leaf=8,
+                            n_crit=n_crit)
+    assert (st["n_pn"], st["n_pp_far"], st["n_pp_near"]) == (ost["pn"], ost["pp_far"], ost["pp_near"])
+    rng = np.random.default_rng(11)
+    tg = rng.choice(c.n, 512, replace=False)
+    ra, rp = oracle.direct(c.pos, c.mass, w["r_in"], w["r_out"], w["eps"], targets=tg)
+    ea = _rel(acc[tg], ra)
+    ep = np.abs(pot[tg] - rp) / np.abs(rp)
+    assert np.median(ea) < 1e-3 and np.percentile(ea, 99) < 5e-3
+    assert np.median(ep) < 1e-3
+    _check_lists(c.pos, w["r_out"], off, idx, rng.choice(c.n, 2000, replace=False))
+    assert prm["leaf_size"] == 8
+
+
+@pytest.mark.parametrize("name", ["plummer128k_kroupa", "plummer1m_kroupa"])
+def test_full_size_fp64_walk_equals_oracle_tree(name):
+    c, w = ic.workload(name)
+    print(f"full size fp64 {name}", flush=True)
+    n_crit = 32 if c.n < (1 << 18) else 64
+    p = _pbh(leaf_size=8, n_crit=n_crit, prec="fp64")
+    acc, pot, off, idx = _run(p, c, w, w["theta"])
+    oa, op, ost = oracle.tree(c.pos, c.mass, w["r_in"], w["r_out"], w["theta"], w["eps"], n_leaf=8,
+                              n_crit=n_crit)
+    st = p.stats()
+    assert (st["n_pn"], st["n_pp_far"], st["n_pp_near"]) == (ost["pn"], ost["pp_far"], ost["pp_near"])
+    assert _rel(acc, oa).max() < 1e-6
+    assert (np.abs(pot - op) / np.abs(op)).max() < 1e-6
+
+
+def test_full_size_ensemble():
+    # the 64-cluster ensemble (about 3.5 million particles), one batched build
+    # and one walk; three clusters checked against per-cluster oracle walks
+    e = ic.ensemble(n_clusters=64)
+    print(f"full size ensemble n={e.offsets[-1]}", flush=True)
+    eps = 1e-6
+    p = _pbh(leaf_size=8, n_crit=64, prec="fp64")
+    p.build_batched(e.offsets, _t(e.pos), _t(e.mass))
+    acc, pot, off, idx = [v.cpu().numpy() for v in p.force_batched(e.r_in, e.r_out, 0.5, eps)]
+    q = _pbh(leaf_size=8, n_crit=64)
+    q.build_batched(e.offsets, _t(e.pos), _t(e.mass))
+    macc, _, moff, _ = [v.cpu().numpy() for v in q.force_batched(e.r_in, e.r_out, 0.5, eps)]
+    assert np.array_equal(off, moff)
+    sizes = np.diff(e.offsets)
+    for k in (int(np.argmin(sizes)), int(np.argmax(sizes)), 17):
+        a, b = e.offsets[k], e.offsets[k + 1]
+        oa, op, _ = oracle.tree(e.pos[a:b], e.mass[a:b], e.r_in[k], e.r_out[k], 0.5, eps, n_leaf=8,
+                                n_crit=64)
+        assert _rel(acc[a:b], oa).max() < 1e-6
+        assert (np.abs(pot[a:b] - op) / np.abs(op)).max() < 1e-6
+        tg = np.random.default_rng(k).choice(b - a, 128, replace=False)
+        ra, _ = oracle.direct(e.pos[a:b], e.mass[a:b], e.r_in[k], e.r_out[k], eps, targets=tg)
+        assert np.median(_rel(macc[a:b][tg], ra)) < 1e-3
+        o_off, o_idx = oracle.nbr_cells(e.pos[a:b], e.r_out[k])
+        g_off = off[a:b + 1] - off[a]
+        assert np.array_equal(g_off, o_off)
+        for i in tg[:64]:
+            got = np.sort(idx[off[a + i]:off[a + i + 1]] - a)
+            assert np.array_equal(got, o_idx[o_off[i]:o_off[i + 1]])
+
+
+def test_full_size_kdk_4m():
+    # 4M particles, the regular-force leapfrog captured in a graph: replay
+    # equals eager launches bit for bit; mixed and FP64 energies agree
+    c, w = ic.workload("plummer4m_kroupa")
+    print(f"full size kdk n={c.n}", flush=True)
+    steps, dt = 4, 1.0 / 1024
+    res = {}
+    for prec in ("mixed", "fp64"):
+        for graph in (True, False) if prec == "mixed" else (True,):
+            p = _pbh(leaf_size=16, n_crit=64, prec=prec)
+            pos, vel = _t(c.pos), _t(c.vel)
+            e = p.kdk(pos, vel, _t(c.mass), dt, steps, w["r_in"], w["r_out"], w["theta"], w["eps"],
+                      graph=graph)
+            res[(prec, graph)] = (pos.cpu().numpy(), e.cpu().numpy())
+            p.close()
+    gx, ge = res[("mixed", True)]
+    ex, ee = res[("mixed", False)]
+    assert np.array_equal(gx, ex) and np.array_equal(ge, ee)
+    _, fe = res[("fp64", True)]
+    assert np.all(np.isfinite(ge))
+    assert np.max(np.abs(ge - fe)) < 1e-6 * abs(fe[0])
+    assert abs(ge[-1] - ge[0]) < 1e-5 * abs(ge[0])
