@@ -292,6 +292,9 @@ def bench_force(args):
         "phase_ms": {"build": float(np.mean(build_ms)), "walk": walk_avg,
                      "neighbours": float(np.mean(nbr_ms))},
         "interactions_per_step": {"pn": s["n_pn"], "pp_far": s["n_pp_far"], "pp_near": s["n_pp_near"]},
+        "rates_walk_only": {k: v / (walk_avg * 1e-3) for k, v in
+                            (("pn_per_s", s["n_pn"]), ("pp_per_s", s["n_pp_far"] + s["n_pp_near"]),
+                             ("interactions_per_s", per_step_inter))},
         "groups": s["n_groups"],
         "nbr_total": int(off[-1].item()) if neighbours else None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
