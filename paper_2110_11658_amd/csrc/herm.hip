@@ -67,11 +67,11 @@ __global__ __launch_bounds__(256) void k_herm_start(HermParams p) {
 // Blocks are enqueued in batches without waiting; once every particle has
 // reached the end of the regular step the remaining blocks of a batch are
 // empty (kHermDone), so the host waits once per batch.
-// Block front, in three passes over the per-particle times (16 bytes each):
+// Block front, in two passes over the per-particle times (16 bytes each):
 // the next block time tn = min(tau_i + dt_i) (exact: integer ticks) by a
-// two-level reduction, the list of active particles (tau_i + dt_i = tn), and
-// the prediction of the active particles and of every member of their
-// neighbour lists -- the only states the irregular force of the block reads
+// two-level reduction, then the list of active particles (tau_i + dt_i = tn)
+// with the prediction of each active particle and of every member of its
+// neighbour list -- the only states the irregular force of the block reads
 // (the other particles keep x, v until their own block).
 constexpr int kHermGrid = 1024;   // grid-stride launches
 
@@ -116,6 +116,30 @@ __global__ __launch_bounds__(256) void k_herm_min_final(HermParams p, int nparts
     }
 }
 
+__device__ inline void predict_one(const HermParams& p, int64_t i, int64_t tn) {
+#pragma clang fp contract(off)
+    const double d = (double)(tn - p.tau[i]) * p.unit;
+    const double d2 = d * d, d3 = d2 * d;
+    for (int k = 0; k < 3; ++k) {
+        const int64_t q = 3 * i + k;
+        p.xp[q] = p.x[q] + d * p.v[q] + 0.5 * d2 * p.a[q] + d3 / 6.0 * p.j[q];
+        p.vp[q] = p.v[q] + d * p.a[q] + 0.5 * d2 * p.j[q];
+    }
+}
+
+// the active particle i and the members of its list
+__device__ inline void predict_with_list(const HermParams& p, int64_t i, int64_t tn) {
+    predict_one(p, i, tn);
+    int64_t b = p.off[i], e = p.off[i + 1];
+    if (b < 0 || e < b || e > p.cap) return;   // flagged by the force kernel
+    for (; b < e; ++b) {
+        const int64_t j = p.idx[b];
+        if ((uint64_t)j < (uint64_t)p.n) predict_one(p, j, tn);
+    }
+}
+
+// List the active particles and predict them with their list members (a
+// member shared by several lists is written with the same value by each).
 __global__ __launch_bounds__(256) void k_herm_active(HermParams p) {
     const int64_t tn = (int64_t)p.ctl[kHermTn];
     const int lane = threadIdx.x & 63;
@@ -129,34 +153,7 @@ __global__ __launch_bounds__(256) void k_herm_active(HermParams p) {
         if (act) {
             const uint64_t below = lane ? (b & ((~0ull) >> (64 - lane))) : 0ull;
             p.act[at + __popcll(below)] = (int32_t)i;
-        }
-    }
-}
-
-__device__ inline void predict_one(const HermParams& p, int64_t i, int64_t tn) {
-#pragma clang fp contract(off)
-    const double d = (double)(tn - p.tau[i]) * p.unit;
-    const double d2 = d * d, d3 = d2 * d;
-    for (int k = 0; k < 3; ++k) {
-        const int64_t q = 3 * i + k;
-        p.xp[q] = p.x[q] + d * p.v[q] + 0.5 * d2 * p.a[q] + d3 / 6.0 * p.j[q];
-        p.vp[q] = p.v[q] + d * p.a[q] + 0.5 * d2 * p.j[q];
-    }
-}
-
-// Active particles and their list members (a member shared by several lists
-// is written with the same value by each).
-__global__ __launch_bounds__(256) void k_herm_predict(HermParams p) {
-    const int64_t tn = (int64_t)p.ctl[kHermTn];
-    const int64_t nact = (int64_t)p.ctl[kHermNact];
-    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nact; k += (int64_t)gridDim.x * 256) {
-        const int64_t i = p.act[k];
-        predict_one(p, i, tn);
-        int64_t b = p.off[i], e = p.off[i + 1];
-        if (b < 0 || e < b || e > p.cap) continue;   // flagged by the force kernel
-        for (; b < e; ++b) {
-            const int64_t j = p.idx[b];
-            if ((uint64_t)j < (uint64_t)p.n) predict_one(p, j, tn);
+            predict_with_list(p, i, tn);
         }
     }
 }
@@ -236,7 +233,6 @@ void launch_herm_block_front(const HermParams& p, hipStream_t s) {
     hipLaunchKernelGGL(k_herm_min_part, dim3(g), dim3(256), 0, s, p);
     hipLaunchKernelGGL(k_herm_min_final, dim3(1), dim3(256), 0, s, p, (int)g);
     hipLaunchKernelGGL(k_herm_active, dim3(g), dim3(256), 0, s, p);
-    hipLaunchKernelGGL(k_herm_predict, dim3(g), dim3(256), 0, s, p);
 }
 
 void launch_herm_correct(const HermParams& p, hipStream_t s) {

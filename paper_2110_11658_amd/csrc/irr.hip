@@ -214,13 +214,9 @@ constexpr unsigned kIrrChunk = 16;
 
 // MULTI: clusters with their own constants (per lane); otherwise one set, read
 // from the kernel arguments (wave-uniform, so it stays in scalar registers).
+// One target k (a lane): its sums over its list, stored at its output slot.
 template <bool JERK, bool POT, bool SORTED, bool MULTI>
-__global__ __launch_bounds__(256) void k_irregular(IrrParams p) {
-    // key-order targets in chunks per XCD (cache locality and load balance)
-    const unsigned blk = SORTED ? xcd_chunk_block(blockIdx.x, kIrrChunk) : blockIdx.x;
-    const int64_t k = (int64_t)blk * blockDim.x + threadIdx.x;
-    if (k >= p.n_tgt) return;
-    if (p.n_tgt_dev && k >= (int64_t)*p.n_tgt_dev) return;
+__device__ inline void irr_target(const IrrParams& p, int64_t k) {
     unsigned long long bad = 0;
     const int64_t i = p.tgt ? (int64_t)p.tgt[k] : (p.order ? (int64_t)p.order[k] : k);
     const ClusterParams* cp;
@@ -264,6 +260,23 @@ __global__ __launch_bounds__(256) void k_irregular(IrrParams p) {
     if (bad) atomicOr(p.err, bad);
 }
 
+template <bool JERK, bool POT, bool SORTED, bool MULTI>
+__global__ __launch_bounds__(256) void k_irregular(IrrParams p) {
+    if (SORTED) {
+        // key-order targets in chunks per XCD (cache locality and load balance)
+        const unsigned blk = xcd_chunk_block(blockIdx.x, kIrrChunk);
+        const int64_t k = (int64_t)blk * blockDim.x + threadIdx.x;
+        if (k < p.n_tgt) irr_target<JERK, POT, SORTED, MULTI>(p, k);
+        return;
+    }
+    // caller-array route: grid-stride, the count possibly held on the device
+    int64_t nt = p.n_tgt;
+    if (p.n_tgt_dev && (int64_t)*p.n_tgt_dev < nt) nt = (int64_t)*p.n_tgt_dev;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nt;
+         k += (int64_t)gridDim.x * blockDim.x)
+        irr_target<JERK, POT, SORTED, MULTI>(p, k);
+}
+
 template <bool JERK, bool POT, bool MULTI>
 void launch_route(const IrrParams& p, hipStream_t s) {
     const int64_t nb = (p.n_tgt + 255) / 256;
@@ -272,8 +285,9 @@ void launch_route(const IrrParams& p, hipStream_t s) {
         const int64_t round = (int64_t)kQueues * kIrrChunk;
         const dim3 grid((unsigned)((nb + round - 1) / round * round));
         hipLaunchKernelGGL((k_irregular<JERK, POT, true, MULTI>), grid, block, 0, s, p);
-    } else {
-        hipLaunchKernelGGL((k_irregular<JERK, POT, false, MULTI>), dim3((unsigned)nb), block, 0, s, p);
+    } else {   // grid-stride: a count held on the device may be far below n_tgt
+        const int64_t g = p.n_tgt_dev ? (nb < 1024 ? nb : 1024) : nb;
+        hipLaunchKernelGGL((k_irregular<JERK, POT, false, MULTI>), dim3((unsigned)g), block, 0, s, p);
     }
 }
 
