@@ -122,6 +122,9 @@ def parse():
                          "(on MI355X every workload here picks n_leaf=8, n_crit=64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-neighbours", action="store_true")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="before the timed region, run the library's VALU calibration kernel once "
+                         "(4096 waves x 32032 VALU instructions, to scale instruction counters)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed region, copy a buffer of this many MiB once "
                          "(a plain copy kernel of known size, to scale HBM byte counters)")
@@ -239,6 +242,11 @@ def bench_force(args):
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.valu_probe:
+        probe_out = torch.empty(4096, dtype=torch.float32, device=dev)
+        check(ctx, L.pbh_debug_valu_probe(ctx, 4096, 1000, _ptr(probe_out), _stream()))
+        torch.cuda.synchronize()
 
     p.set_timing(True)
     for _ in range(args.warmup):

@@ -368,6 +368,14 @@ pbh_status pbh_debug_groups(pbh_ctx* ctx, int64_t cap, int32_t* begin, int32_t* 
 pbh_status pbh_debug_wave_log(pbh_ctx* ctx, uint64_t* walk, uint64_t* nbr, int64_t cap,
                               int64_t* n_walk, int64_t* n_nbr);
 
+/*
+ * Calibration kernel for hardware instruction counters: `blocks` waves, each
+ * issuing exactly 32 * iters + 32 VALU instructions (32 * iters of them FP32
+ * FMAs). out: device float [blocks], normally left unwritten.
+ */
+pbh_status pbh_debug_valu_probe(pbh_ctx* ctx, int64_t blocks, int32_t iters, float* out,
+                                pbh_stream_t stream);
+
 const char* pbh_last_error(const pbh_ctx* ctx);
 const char* pbh_status_string(pbh_status s);
 

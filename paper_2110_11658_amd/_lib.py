@@ -28,7 +28,7 @@ EXPORTS = ("pbh_create", "pbh_destroy", "pbh_set_params", "pbh_get_params", "pbh
            "pbh_force_batched_buffered", "pbh_irregular",
            "pbh_irregular_batched", "pbh_core", "pbh_hermite", "pbh_p3t", "pbh_kdk", "pbh_kdk_eager",
            "pbh_get_stats", "pbh_set_timing", "pbh_debug_tree", "pbh_debug_groups",
-           "pbh_debug_wave_log", "pbh_last_error", "pbh_status_string")
+           "pbh_debug_wave_log", "pbh_debug_valu_probe", "pbh_last_error", "pbh_status_string")
 
 
 class pbh_params(C.Structure):
@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
         "pbh_debug_tree": (st, [vp, vp, vp, i64, vp, vp, vp]),
         "pbh_debug_groups": (st, [vp, i64, vp, vp, vp, vp]),
         "pbh_debug_wave_log": (st, [vp, vp, vp, i64, vp, vp]),
+        "pbh_debug_valu_probe": (st, [vp, i64, i32, vp, vp]),
         "pbh_last_error": (C.c_char_p, [vp]),
         "pbh_status_string": (C.c_char_p, [C.c_int]),
     }

@@ -1336,6 +1336,17 @@ pbh_status pbh_debug_groups(pbh_ctx* ctx, int64_t cap, int32_t* begin, int32_t* 
     return PBH_OK;
 }
 
+pbh_status pbh_debug_valu_probe(pbh_ctx* ctx, int64_t blocks, int32_t iters, float* out,
+                                pbh_stream_t stream) {
+    if (!ctx) return PBH_E_ARG;
+    if (blocks < 1 || blocks > (1ll << 30) || iters < 0 || !out)
+        return fail(ctx, PBH_E_ARG, "need 1 <= blocks <= 2^30, iters >= 0 and out");
+    HIP_TRY(hipSetDevice(ctx->device));
+    launch_valu_probe(blocks, iters, out, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return PBH_OK;
+}
+
 pbh_status pbh_debug_wave_log(pbh_ctx* ctx, uint64_t* walk, uint64_t* nbr, int64_t cap,
                                          int64_t* n_walk, int64_t* n_nbr) {
     if (!ctx || !ctx->d.wave_log) return PBH_E_ARG;

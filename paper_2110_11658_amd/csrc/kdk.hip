@@ -69,7 +69,29 @@ inline int grid_for(int64_t n) {
     return (int)b;
 }
 
+// Counter calibration: every lane runs `iters` rounds of 32 FP32 FMAs in
+// eight independent chains (the count a VALU instruction counter must see).
+__global__ __launch_bounds__(64) void k_valu_probe(int iters, float seed, float* out) {
+    float a[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) a[c] = seed + (float)(threadIdx.x + c);
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) a[c] = __builtin_fmaf(a[c], 0.999f, 0.5f);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s += a[c];
+    if (s == 1234.5f) out[blockIdx.x] = s;   // keeps the chains live; never true for the seeds used
+}
+
 }  // namespace
+
+void launch_valu_probe(int64_t blocks, int iters, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_valu_probe, dim3((unsigned)blocks), dim3(64), 0, s, iters, 0.25f, out);
+}
 
 void launch_kick(double* vel, const double* acc, double h, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_kick, dim3(grid_for(3 * n)), dim3(256), 0, s, vel, acc, h, 3 * n);

@@ -349,5 +349,8 @@ void launch_drift(double* pos, const double* vel, double dt, int64_t n, hipStrea
 void launch_energy(const double* vel, const double* mass, const double* pot, int64_t n,
                    double* partial, int nblk, double* out, hipStream_t s);
 void launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+// one wave per block, 32 * iters + 32 VALU instructions per wave (counted in
+// the kernel's gfx950 assembly): a known count for instruction counters
+void launch_valu_probe(int64_t blocks, int iters, float* out, hipStream_t s);
 
 }  // namespace pbh
