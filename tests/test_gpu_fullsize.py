@@ -76,6 +76,23 @@ def test_full_size_mixed_walk(name):
     assert prm["leaf_size"] == 8
 
 
+@pytest.mark.parametrize("theta", [0.3, 0.7])
+def test_full_size_theta_sweep(theta):
+    # the other opening angles of the 2^20 workload: counts equal to the oracle
+    # tree walk, sampled forces against direct sums (error grows with theta)
+    c, w = ic.workload("plummer1m_kroupa")
+    print(f"full size theta={theta}", flush=True)
+    p = _pbh(leaf_size=8)
+    acc, pot, off, idx = _run(p, c, w, theta)
+    st = p.stats()
+    _, _, ost = oracle.tree(c.pos, c.mass, w["r_in"], w["r_out"], theta, w["eps"], n_leaf=8, n_crit=64)
+    assert (st["n_pn"], st["n_pp_far"], st["n_pp_near"]) == (ost["pn"], ost["pp_far"], ost["pp_near"])
+    tg = np.random.default_rng(12).choice(c.n, 256, replace=False)
+    ra, _ = oracle.direct(c.pos, c.mass, w["r_in"], w["r_out"], w["eps"], targets=tg)
+    med = np.median(_rel(acc[tg], ra))
+    assert med < (1e-3 if theta < 0.5 else 3e-3)
+
+
 @pytest.mark.parametrize("name", ["plummer128k_kroupa", "plummer1m_kroupa"])
 def test_full_size_fp64_walk_equals_oracle_tree(name):
     c, w = ic.workload(name)
