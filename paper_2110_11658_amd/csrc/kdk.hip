@@ -37,7 +37,7 @@ __global__ __launch_bounds__(E_T) void k_energy_part(const double* __restrict__ 
     s[threadIdx.x] = e;
     __syncthreads();
     for (int o = E_T / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(E_T) void k_energy_final(const double* __restrict__
     s[threadIdx.x] = e;
     __syncthreads();
     for (int o = E_T / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = s[0];
