@@ -33,88 +33,37 @@ __device__ inline double norm3(double x, double y, double z) {
     return sqrt(x * x + y * y + z * z);
 }
 
-// block step in ticks: dt_max / 2^k not above `want`, dividing tau
-__device__ inline int64_t block_step(double want, double dtmax, int64_t tau) {
-    double d = dtmax;
-    int k = 0;
-    while (d > want && k < kHermK) {
-        d *= 0.5;
-        ++k;
-    }
-    int64_t t = (int64_t)1 << (kHermK - k);
-    while (tau % t != 0) t >>= 1;
-    return t;
-}
-
-__device__ inline int step_level(int64_t t) {
-    int k = 0;
-    for (int64_t q = (int64_t)1 << kHermK; q > t; q >>= 1) ++k;
-    return k;
-}
-
-__global__ __launch_bounds__(256) void k_herm_start(HermParams p) {
-#pragma clang fp contract(off)
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n) return;
-    double at[3];
-    for (int k = 0; k < 3; ++k) at[k] = p.a[3 * i + k] + (p.fr ? p.fr[3 * i + k] : 0.0);
-    const double jn = norm3(p.j[3 * i], p.j[3 * i + 1], p.j[3 * i + 2]);
-    const double want = jn > 0.0 ? 0.01 * norm3(at[0], at[1], at[2]) / jn : p.dtmax;
-    p.tau[i] = 0;
-    p.dt[i] = block_step(want, p.dtmax, 0);
-}
-
+// Block schedule by level. A particle at level k has dt_i = 2^(kHermK - k)
+// ticks, and its time tau_i is a multiple of dt_i (the new step is chosen to
+// divide the block time), with tau_i <= t < tau_i + dt_i at the current block
+// time t. Its next time tau_i + dt_i is then the first multiple of dt_i after
+// t, so the next block time tn = min(tau_i + dt_i) is the first multiple of
+// the smallest occupied step after t, and particle i is active at tn exactly
+// when dt_i divides tn, i.e. when k >= k* = kHermK - ctz(tn) (0 if that is
+// negative). Particles are therefore kept in one bucket per level and a block
+// takes whole buckets: no pass over all n particles per block. The corrected
+// particles of a block (levels >= k*) move to their new levels, which are
+// >= k* - 1 (the step at most doubles): buckets >= k* are refilled from zero
+// and bucket k* - 1 is appended to.
+//
+// Level counts are double-buffered by block parity q: the front of a block
+// reads the counts of slot q (cnt, plus the appends newcnt of the previous
+// block, and that block's k*) and writes the merged counts to slot q ^ 1,
+// where the corrector of the same block appends. Every launch of a block
+// reads only what earlier launches wrote.
+//
 // Blocks are enqueued in batches without waiting; once every particle has
 // reached the end of the regular step the remaining blocks of a batch are
 // empty (kHermDone), so the host waits once per batch.
-// Block front, in two passes over the per-particle times (16 bytes each):
-// the next block time tn = min(tau_i + dt_i) (exact: integer ticks) by a
-// two-level reduction, then the list of active particles (tau_i + dt_i = tn)
-// with the prediction of each active particle and of every member of its
-// neighbour list -- the only states the irregular force of the block reads
-// (the other particles keep x, v until their own block).
 constexpr int kHermGrid = 1024;   // grid-stride launches
+constexpr int kHermLanes = 8;     // lanes per active particle in the prediction
+constexpr int kHermAllFrac = 8;   // predict all particles when n_active >= n / 8
+constexpr int kSlotShift = 26;    // per-item scratch: level << 26 | rank in its workgroup
+constexpr uint32_t kSlotMask = (1u << kSlotShift) - 1;
+static_assert(kHermK < 63, "levels fit one wave");
 
-__global__ __launch_bounds__(256) void k_herm_min_part(HermParams p) {
-    __shared__ unsigned long long red[4];
-    unsigned long long v = ~0ull;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < p.n; i += (int64_t)gridDim.x * 256) {
-        const unsigned long long t = (unsigned long long)(p.tau[i] + p.dt[i]);
-        v = t < v ? t : v;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long w = __shfl_xor(v, o, 64);
-        v = w < v ? w : v;
-    }
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < 4; ++w) v = red[w] < v ? red[w] : v;
-        p.part[blockIdx.x] = v;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_herm_min_final(HermParams p, int nparts) {
-    __shared__ unsigned long long red[4];
-    unsigned long long v = ~0ull;
-    for (int b = threadIdx.x; b < nparts; b += 256) v = p.part[b] < v ? p.part[b] : v;
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long w = __shfl_xor(v, o, 64);
-        v = w < v ? w : v;
-    }
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < 4; ++w) v = red[w] < v ? red[w] : v;
-        // past the end of the regular step (every particle at tend): nothing
-        // matches the sentinel time, and the block does no work
-        const bool done = v > p.tend;
-        p.ctl[kHermTn] = done ? ~0ull : v;
-        p.ctl[kHermNact] = 0ull;
-        if (done) p.ctl[kHermDone] = 1ull;
-        else p.ctl[kHermBlocks] += 1ull;
-    }
-}
+__device__ inline unsigned long long* lev_cnt(const HermParams& p, int q) { return p.lev + kLevCnt + 64 * q; }
+__device__ inline unsigned long long* lev_new(const HermParams& p, int q) { return p.lev + kLevNew + 64 * q; }
 
 __device__ inline void predict_one(const HermParams& p, int64_t i, int64_t tn) {
 #pragma clang fp contract(off)
@@ -127,86 +76,212 @@ __device__ inline void predict_one(const HermParams& p, int64_t i, int64_t tn) {
     }
 }
 
-// the active particle i and the members of its list
-__device__ inline void predict_with_list(const HermParams& p, int64_t i, int64_t tn) {
-    predict_one(p, i, tn);
-    int64_t b = p.off[i], e = p.off[i + 1];
-    if (b < 0 || e < b || e > p.cap) return;   // flagged by the force kernel
-    for (; b < e; ++b) {
-        const int64_t j = p.idx[b];
-        if ((uint64_t)j < (uint64_t)p.n) predict_one(p, j, tn);
+// Block front: the next block time and the active buckets (computed by every
+// workgroup from slot q; workgroup 0 publishes them), then the active list
+// (bucket order) with the prediction of each active particle and its list
+// members (a member shared by several lists is written with the same value
+// by each) -- the only states the irregular force of the block reads.
+__global__ __launch_bounds__(256) void k_herm_front(HermParams p, int q) {
+    __shared__ long long s_cnt[64], s_off[64];
+    __shared__ long long s_tn, s_nact;
+    __shared__ int s_ks;
+    if (threadIdx.x < 64) {
+        const int k = threadIdx.x;
+        const int kp = (int)p.lev[kLevKs + q];   // k* of the previous block
+        long long c = 0, add = 0;
+        if (k <= kHermK) {
+            const long long old = (long long)lev_cnt(p, q)[k];
+            add = (long long)lev_new(p, q)[k];
+            c = k >= kp ? add : (k == kp - 1 ? old + add : old);
+        }
+        // deepest new level of the previous corrector (its appends; the first
+        // block's appends are the start levels, not counted)
+        const uint64_t app = __ballot(add > 0);
+        const uint64_t occ = __ballot(c > 0);
+        const int kmax = 63 - __clzll(occ);          // deepest occupied level (n >= 1)
+        const long long t = (long long)p.lev[kLevT + q];
+        const bool done = t >= (long long)p.tend;
+        const int sh = kHermK - kmax;
+        const long long tn = done ? (long long)p.tend : (((t >> sh) + 1) << sh);
+        const int tz = __ffsll((unsigned long long)tn) - 1;
+        const int ks = done ? kHermK + 1 : (tz >= kHermK ? 0 : kHermK - tz);
+        long long a = k >= ks ? c : 0, incl = a;
+        for (int o = 1; o < 64; o <<= 1) {
+            const long long w = __shfl_up(incl, o, 64);
+            if (k >= o) incl += w;
+        }
+        const long long nact = __shfl(incl, 63, 64);
+        s_cnt[k] = c;
+        s_off[k] = incl - a;
+        if (k == 0) {
+            s_tn = tn;
+            s_nact = nact;
+            s_ks = ks;
+        }
+        if (blockIdx.x == 0) {
+            if (k == 0 && t > 0 && app) {
+                const unsigned long long dl = (unsigned long long)(63 - __clzll(app));
+                if (dl > p.ctl[kHermKmax]) p.ctl[kHermKmax] = dl;
+            }
+            if (k <= kHermK) {
+                lev_cnt(p, q ^ 1)[k] = (unsigned long long)c;
+                lev_new(p, q ^ 1)[k] = 0ull;
+            }
+            if (k == 0) {
+                p.lev[kLevT + (q ^ 1)] = (unsigned long long)tn;
+                p.lev[kLevKs + (q ^ 1)] = (unsigned long long)ks;
+                p.ctl[kHermTn] = done ? ~0ull : (unsigned long long)tn;
+                p.ctl[kHermNact] = (unsigned long long)nact;
+                if (done) {
+                    p.ctl[kHermDone] = 1ull;
+                } else {
+                    p.ctl[kHermBlocks] += 1ull;
+                    p.ctl[kHermSteps] += (unsigned long long)nact;
+                }
+            }
+        }
     }
-}
-
-// List the active particles and predict them with their list members (a
-// member shared by several lists is written with the same value by each).
-__global__ __launch_bounds__(256) void k_herm_active(HermParams p) {
-    const int64_t tn = (int64_t)p.ctl[kHermTn];
-    const int lane = threadIdx.x & 63;
-    for (int64_t base = (int64_t)blockIdx.x * 256; base < p.n; base += (int64_t)gridDim.x * 256) {
-        const int64_t i = base + threadIdx.x;
-        const bool act = i < p.n && p.tau[i] + p.dt[i] == tn;
-        const uint64_t b = __ballot(act);
-        if (!b) continue;
-        const unsigned long long at =
-            __shfl(atomicAdd(p.ctl + kHermNact, lane == 0 ? (unsigned long long)__popcll(b) : 0ull), 0, 64);
-        if (act) {
-            const uint64_t below = lane ? (b & ((~0ull) >> (64 - lane))) : 0ull;
-            p.act[at + __popcll(below)] = (int32_t)i;
-            predict_with_list(p, i, tn);
+    __syncthreads();
+    const long long nact = s_nact, tn = s_tn;
+    const int ks = s_ks;
+    const long long stride = (long long)gridDim.x * 256;
+    const long long t0 = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (nact * kHermAllFrac >= p.n) {
+        // a large active set: predict every particle once, in order (the
+        // others are not read by this block), and list the active ones
+        for (long long t = t0; t < p.n; t += stride) predict_one(p, t, tn);
+        for (long long t = t0; t < nact; t += stride) {
+            int k = ks;
+            while (k < kHermK && t >= s_off[k] + s_cnt[k]) ++k;
+            p.act[t] = p.bucket[(int64_t)k * p.n + (t - s_off[k])];
+        }
+        return;
+    }
+    // kHermLanes lanes per active particle: item 0 is the particle, item
+    // m >= 1 the m-th member of its list
+    for (long long t = t0; t < nact * kHermLanes; t += stride) {
+        const long long a = t / kHermLanes;
+        const int g = (int)(t % kHermLanes);
+        int k = ks;
+        while (k < kHermK && a >= s_off[k] + s_cnt[k]) ++k;
+        const int32_t i = p.bucket[(int64_t)k * p.n + (a - s_off[k])];
+        if (g == 0) {
+            p.act[a] = i;
+            predict_one(p, i, tn);
+        }
+        const int64_t b0 = p.off[i], e = p.off[i + 1];
+        if (b0 < 0 || e < b0 || e > p.cap) continue;   // flagged by the force kernel
+        for (int64_t m = b0 + (g == 0 ? kHermLanes - 1 : g - 1); m < e; m += kHermLanes) {
+            const int64_t j = p.idx[m];
+            if ((uint64_t)j < (uint64_t)p.n) predict_one(p, j, tn);
         }
     }
 }
 
-// Hermite corrector and new block step of the active particles
-__global__ __launch_bounds__(256) void k_herm_correct(HermParams p) {
+// Each workgroup takes one contiguous chunk of the n_items items (a multiple of
+// 256, so a small set is one workgroup): `step(k, i)` advances item k (the
+// particle i = list[k], or k without a list) and returns its new level; the
+// workgroup ranks its items per level in LDS, reserves room in each bucket
+// with one device atomic per level (buckets >= ks restart from zero, bucket
+// ks - 1 keeps its members), then stores the particles there. Same-address
+// device atomics serialise, so one per workgroup and level, not per wave.
+template <class Step>
+__device__ inline void step_and_bucket(const HermParams& p, int q, int ks, int64_t n_items,
+                                       const int32_t* list, Step step) {
+    __shared__ int s_h[64];
+    __shared__ long long s_b[64];
+    const int64_t per = ((n_items + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
+    const int64_t c0 = (int64_t)blockIdx.x * per, c1 = c0 + per < n_items ? c0 + per : n_items;
+    if (c0 >= c1) return;   // workgroup-uniform
+    if (threadIdx.x < 64) s_h[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t k = c0 + threadIdx.x; k < c1; k += 256) {
+        const int32_t i = list ? list[k] : (int32_t)k;
+        const int level = step(k, i);
+        const int r = atomicAdd(&s_h[level], 1);
+        p.slot[k] = ((uint32_t)level << kSlotShift) | (uint32_t)r;
+    }
+    __syncthreads();
+    if (threadIdx.x <= kHermK && s_h[threadIdx.x] > 0) {
+        const int k = threadIdx.x;
+        const long long keep = k == ks - 1 ? (long long)lev_cnt(p, q)[k] : 0;
+        s_b[k] = keep + (long long)atomicAdd(lev_new(p, q) + k, (unsigned long long)s_h[k]);
+    }
+    __syncthreads();
+    for (int64_t k = c0 + threadIdx.x; k < c1; k += 256) {   // the same items per thread
+        const uint32_t v = p.slot[k];
+        const int level = (int)(v >> kSlotShift);
+        const int32_t i = list ? list[k] : (int32_t)k;
+        p.bucket[(int64_t)level * p.n + s_b[level] + (int64_t)(v & kSlotMask)] = i;
+    }
+}
+
+// block step in ticks: dt_max / 2^k not above `want`, dividing tau (the
+// largest power of two dividing tau > 0 is its lowest set bit)
+__device__ inline int64_t block_step(double want, double dtmax, int64_t tau) {
+    double d = dtmax;
+    int k = 0;
+    while (d > want && k < kHermK) {
+        d *= 0.5;
+        ++k;
+    }
+    int64_t t = (int64_t)1 << (kHermK - k);
+    const int64_t low = tau & -tau;
+    if (tau != 0 && low < t) t = low;
+    return t;
+}
+
+__device__ inline int step_level(int64_t t) { return kHermK - (63 - __clzll((unsigned long long)t)); }
+
+__global__ __launch_bounds__(256) void k_herm_start(HermParams p) {
+    // slot 0, every level refilled (ks = 0)
+    step_and_bucket(p, 0, 0, p.n, nullptr, [&](int64_t, int32_t i) {
 #pragma clang fp contract(off)
+        double at[3];
+        for (int k = 0; k < 3; ++k) at[k] = p.a[3 * (int64_t)i + k] + (p.fr ? p.fr[3 * (int64_t)i + k] : 0.0);
+        const double jn = norm3(p.j[3 * (int64_t)i], p.j[3 * (int64_t)i + 1], p.j[3 * (int64_t)i + 2]);
+        const double want = jn > 0.0 ? 0.01 * norm3(at[0], at[1], at[2]) / jn : p.dtmax;
+        const int64_t t = block_step(want, p.dtmax, 0);
+        p.tau[i] = 0;
+        p.dt[i] = t;
+        return step_level(t);
+    });
+}
+
+// Hermite corrector, new block step and new bucket of the active particles
+__global__ __launch_bounds__(256) void k_herm_correct(HermParams p, int q) {
     const int64_t nact = (int64_t)p.ctl[kHermNact];
-    for (int64_t k0 = (int64_t)blockIdx.x * 256; k0 < nact; k0 += (int64_t)gridDim.x * 256) {
-    const int64_t k = k0 + threadIdx.x;
-    int level = 0;
-    if (k < nact) {
-        const int64_t i = p.act[k];
-        const int64_t tn = (int64_t)p.ctl[kHermTn];
+    const int ks = (int)p.lev[kLevKs + (q ^ 1)];
+    const int64_t tn = (int64_t)p.ctl[kHermTn];
+    step_and_bucket(p, q ^ 1, ks, nact, p.act, [&](int64_t k, int32_t i) {
+#pragma clang fp contract(off)
         const double d = (double)p.dt[i] * p.unit, d2 = d * d, d3 = d2 * d, d4 = d3 * d, d5 = d4 * d;
         double a2[3], a3[3], a2e[3], at[3];
         for (int c = 0; c < 3; ++c) {
-            const int64_t q = 3 * i + c;
+            const int64_t q3 = 3 * (int64_t)i + c;
             const double a1 = p.a1[3 * k + c], j1 = p.j1[3 * k + c];
-            const double da = p.a[q] - a1;
-            a2[c] = (-6.0 * da - d * (4.0 * p.j[q] + 2.0 * j1)) / d2;
-            a3[c] = (12.0 * da + 6.0 * d * (p.j[q] + j1)) / d3;
-            p.x[q] = p.xp[q] + d4 / 24.0 * a2[c] + d5 / 120.0 * a3[c];
-            p.v[q] = p.vp[q] + d3 / 6.0 * a2[c] + d4 / 24.0 * a3[c];
-            p.a[q] = a1;
-            p.j[q] = j1;
+            const double da = p.a[q3] - a1;
+            a2[c] = (-6.0 * da - d * (4.0 * p.j[q3] + 2.0 * j1)) / d2;
+            a3[c] = (12.0 * da + 6.0 * d * (p.j[q3] + j1)) / d3;
+            p.x[q3] = p.xp[q3] + d4 / 24.0 * a2[c] + d5 / 120.0 * a3[c];
+            p.v[q3] = p.vp[q3] + d3 / 6.0 * a2[c] + d4 / 24.0 * a3[c];
+            p.a[q3] = a1;
+            p.j[q3] = j1;
             a2e[c] = a2[c] + d * a3[c];
-            at[c] = a1 + (p.fr ? p.fr[q] : 0.0);
+            at[c] = a1 + (p.fr ? p.fr[q3] : 0.0);
         }
         const double n0 = norm3(at[0], at[1], at[2]);
-        const double n1 = norm3(p.j[3 * i], p.j[3 * i + 1], p.j[3 * i + 2]);
+        const double n1 = norm3(p.j[3 * (int64_t)i], p.j[3 * (int64_t)i + 1], p.j[3 * (int64_t)i + 2]);
         const double n2 = norm3(a2e[0], a2e[1], a2e[2]);
         const double n3 = norm3(a3[0], a3[1], a3[2]);
         const double num = n0 * n2 + n1 * n1, den = n1 * n3 + n2 * n2;
         double want = den > 0.0 ? sqrt(p.eta * num / den) : p.dtmax;
         if (want > 2.0 * d) want = 2.0 * d;
+        const int64_t t = block_step(want, p.dtmax, tn);
         p.tau[i] = tn;
-        p.dt[i] = block_step(want, p.dtmax, tn);
-        level = step_level(p.dt[i]);
-    }
-    // block statistics: particle steps and the deepest level (wave-combined)
-    const uint64_t b = __ballot(k < nact);
-    int lv = level;
-    for (int o = 32; o > 0; o >>= 1) {
-        const int w = __shfl_xor(lv, o, 64);
-        lv = w > lv ? w : lv;
-    }
-    if (b) {
-        const int lane = threadIdx.x & 63;
-        atomicAdd(p.ctl + kHermSteps, lane == 0 ? (unsigned long long)__popcll(b) : 0ull);
-        atomicMax(p.ctl + kHermKmax, lane == 0 ? (unsigned long long)lv : 0ull);
-    }
-    }
+        p.dt[i] = t;
+        return step_level(t);
+    });
 }
 
 // pot_tot = pot_r + pot_i
@@ -217,26 +292,21 @@ __global__ void k_add(int64_t n, const double* a, const double* b, double* out) 
 
 }  // namespace
 
-void launch_herm_start(const HermParams& p, hipStream_t s) {
-    hipLaunchKernelGGL(k_herm_start, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, s, p);
-}
-
 static unsigned herm_grid(int64_t n) {
     const int64_t g = (n + 255) / 256;
     return (unsigned)(g < kHermGrid ? (g < 1 ? 1 : g) : kHermGrid);
 }
 
-int herm_part_len() { return kHermGrid; }
-
-void launch_herm_block_front(const HermParams& p, hipStream_t s) {
-    const unsigned g = herm_grid(p.n);
-    hipLaunchKernelGGL(k_herm_min_part, dim3(g), dim3(256), 0, s, p);
-    hipLaunchKernelGGL(k_herm_min_final, dim3(1), dim3(256), 0, s, p, (int)g);
-    hipLaunchKernelGGL(k_herm_active, dim3(g), dim3(256), 0, s, p);
+void launch_herm_start(const HermParams& p, hipStream_t s) {
+    hipLaunchKernelGGL(k_herm_start, dim3(herm_grid(p.n)), dim3(256), 0, s, p);
 }
 
-void launch_herm_correct(const HermParams& p, hipStream_t s) {
-    hipLaunchKernelGGL(k_herm_correct, dim3(herm_grid(p.n)), dim3(256), 0, s, p);
+void launch_herm_front(const HermParams& p, int parity, hipStream_t s) {
+    hipLaunchKernelGGL(k_herm_front, dim3(herm_grid(p.n)), dim3(256), 0, s, p, parity);
+}
+
+void launch_herm_correct(const HermParams& p, int parity, hipStream_t s) {
+    hipLaunchKernelGGL(k_herm_correct, dim3(herm_grid(p.n)), dim3(256), 0, s, p, parity);
 }
 
 void launch_add(int64_t n, const double* a, const double* b, double* out, hipStream_t s) {

@@ -79,13 +79,21 @@ struct pbh_ctx {
         int64_t *tau = nullptr, *dt = nullptr;
         int32_t* act = nullptr;
         unsigned long long* ctl = nullptr;
-        unsigned long long* part = nullptr;
+        unsigned long long* lev = nullptr;
+        int32_t* bucket = nullptr;
+        uint32_t* slot = nullptr;
         double *fr = nullptr, *potr = nullptr, *poti = nullptr, *pott = nullptr, *scr = nullptr,
                *epart = nullptr;
         int64_t* off = nullptr;
         int32_t* idx = nullptr;
         int64_t cap = 0;
         std::vector<void*> mem;
+        // one batch of blocks, captured once per set of buffers and parameters
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t gexec = nullptr;
+        std::vector<double> gkey;
+        unsigned long long* done = nullptr;   // pinned [2]: done flags of the last two batches
+        hipEvent_t ev[2] = {nullptr, nullptr};
     } herm;
 
     // phase timing: events 0/1 build, 2/3 walk, 4/5 neighbours
@@ -615,7 +623,8 @@ pbh_status ensure_herm(pbh_ctx* ctx, int64_t n) {
     if (!halloc(ctx, &h.a, 3 * n) || !halloc(ctx, &h.j, 3 * n) || !halloc(ctx, &h.a1, 3 * n) ||
         !halloc(ctx, &h.j1, 3 * n) || !halloc(ctx, &h.xp, 3 * n) || !halloc(ctx, &h.vp, 3 * n) ||
         !halloc(ctx, &h.tau, n) || !halloc(ctx, &h.dt, n) || !halloc(ctx, &h.act, n) ||
-        !halloc(ctx, &h.ctl, kHermCtl) || !halloc(ctx, &h.part, herm_part_len()) ||
+        !halloc(ctx, &h.ctl, kHermCtl) || !halloc(ctx, &h.lev, kLevLen) ||
+        !halloc(ctx, &h.bucket, (int64_t)(kHermK + 1) * n) || !halloc(ctx, &h.slot, n) ||
         !halloc(ctx, &h.fr, 3 * n) || !halloc(ctx, &h.potr, n) ||
         !halloc(ctx, &h.poti, n) || !halloc(ctx, &h.pott, n) || !halloc(ctx, &h.scr, 3 * n) ||
         !halloc(ctx, &h.epart, nb) || !halloc(ctx, &h.off, n + 1)) {
@@ -647,7 +656,8 @@ IrrParams herm_irr(pbh_ctx* ctx, int64_t n, double r_in, double r_out, double ep
 
 // One regular step of Hermite integration of F_I (see herm.hip), in place.
 constexpr int64_t kHermMaxBlocks = 1ll << 20;
-constexpr int kHermBatch = 16;   // blocks enqueued per wait
+constexpr int kHermBatch = 8;    // blocks per graph launch
+static_assert(kHermBatch % 2 == 0, "block parity restarts at each batch");
 
 pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
                       const double* fr, double r_in, double r_out, double eps,
@@ -676,7 +686,9 @@ pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const d
     hp.dt = h.dt;
     hp.act = h.act;
     hp.ctl = h.ctl;
-    hp.part = h.part;
+    hp.lev = h.lev;
+    hp.bucket = h.bucket;
+    hp.slot = h.slot;
     hp.off = off;
     hp.idx = idx;
     hp.cap = cap;
@@ -684,6 +696,7 @@ pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const d
     hp.unit = T / (double)(1ll << (kHermK + 2));
     hp.dtmax = T / 4.0;
     hp.eta = eta;
+    launch_zero_u64(h.lev, kLevLen, s);
     launch_herm_start(hp, s);
     launch_zero_u64(h.ctl, kHermCtl, s);
     ip.pos = h.xp;
@@ -692,19 +705,50 @@ pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const d
     ip.n_tgt_dev = h.ctl + kHermNact;
     ip.acc = h.a1;
     ip.jerk = h.j1;
-    int64_t queued = 0;
-    for (;;) {
-        for (int b = 0; b < kHermBatch; ++b) {
-            launch_herm_block_front(hp, s);
-            launch_irregular(ip, s);
-            launch_herm_correct(hp, s);
+    // Blocks run in batches of kHermBatch, each batch one graph launch. The
+    // done flag of a batch is read while the next batch runs, so the GPU does
+    // not wait for the host; the batch after the last busy one is empty.
+    const std::vector<double> key = {(double)n, (double)(uintptr_t)pos, (double)(uintptr_t)vel,
+                                     (double)(uintptr_t)mass, (double)(uintptr_t)fr, (double)(uintptr_t)off,
+                                     (double)(uintptr_t)idx, (double)cap, r_in, r_out, eps, T, eta,
+                                     (double)(uintptr_t)h.a, (double)(uintptr_t)h.bucket,
+                                     (double)(uintptr_t)ctx->irr_err};
+    if (!h.gexec || h.gkey != key) {
+        if (h.gexec) { (void)hipGraphExecDestroy(h.gexec); h.gexec = nullptr; }
+        if (h.graph) { (void)hipGraphDestroy(h.graph); h.graph = nullptr; }
+        h.gkey.clear();
+        hipStream_t cs = ctx->cap_stream;
+        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int b = 0; b < kHermBatch; ++b) {   // kHermBatch is even: block parity b & 1
+            launch_herm_front(hp, b & 1, cs);
+            launch_irregular(ip, cs);
+            launch_herm_correct(hp, b & 1, cs);
         }
-        queued += kHermBatch;
-        unsigned long long done = 0;
-        HIP_TRY(hipMemcpyAsync(&done, h.ctl + kHermDone, sizeof(done), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (done) break;
-        if (queued >= kHermMaxBlocks) return fail(ctx, PBH_E_INTERNAL, "Hermite block steps exceed the limit");
+        HIP_TRY(hipStreamEndCapture(cs, &h.graph));
+        HIP_TRY(hipGraphInstantiate(&h.gexec, h.graph, nullptr, nullptr, 0));
+        h.gkey = key;
+    }
+    if (!h.done) {
+        HIP_TRY(hipHostMalloc((void**)&h.done, 2 * sizeof(unsigned long long), hipHostMallocDefault));
+        for (auto& e : h.ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    auto enqueue = [&](int slot) -> hipError_t {
+        hipError_t e = hipGraphLaunch(h.gexec, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h.done + slot, h.ctl + kHermDone, sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(h.ev[slot], s);
+        return e;
+    };
+    HIP_TRY(enqueue(0));
+    for (int64_t batch = 0;; ++batch) {
+        if ((batch + 1) * kHermBatch >= kHermMaxBlocks) {
+            HIP_TRY(hipStreamSynchronize(s));
+            return fail(ctx, PBH_E_INTERNAL, "Hermite block steps exceed the limit");
+        }
+        HIP_TRY(enqueue((int)((batch + 1) & 1)));
+        HIP_TRY(hipEventSynchronize(h.ev[batch & 1]));
+        if (h.done[batch & 1]) break;
     }
     unsigned long long c[kHermCtl], err = 0;
     HIP_TRY(hipMemcpyAsync(c, h.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
@@ -793,6 +837,11 @@ void pbh_destroy(pbh_ctx* ctx) {
     if (ctx->k_epart) (void)hipFree(ctx->k_epart);
     if (ctx->irr_err) (void)hipFree(ctx->irr_err);
     for (void* q : ctx->herm.mem) (void)hipFree(q);
+    if (ctx->herm.gexec) (void)hipGraphExecDestroy(ctx->herm.gexec);
+    if (ctx->herm.graph) (void)hipGraphDestroy(ctx->herm.graph);
+    if (ctx->herm.done) (void)hipHostFree(ctx->herm.done);
+    for (auto& e : ctx->herm.ev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
@@ -1153,8 +1202,6 @@ static pbh_status kdk_prepare(pbh_ctx* ctx, int64_t n, double r_in, double r_out
         if (ctx->k_acc) (void)hipFree(ctx->k_acc);
         if (ctx->k_pot) (void)hipFree(ctx->k_pot);
         if (ctx->k_epart) (void)hipFree(ctx->k_epart);
-    if (ctx->irr_err) (void)hipFree(ctx->irr_err);
-    for (void* q : ctx->herm.mem) (void)hipFree(q);
         ctx->k_acc = ctx->k_pot = ctx->k_epart = nullptr;
         ctx->k_n = -1;
         ctx->k_nblk = (int)std::min<int64_t>(1024, (n + 255) / 256) + 1;

@@ -313,6 +313,9 @@ int64_t core_bsum_len(int64_t n);
 constexpr int kHermK = 40;   // block steps dt_max / 2^k, k <= kHermK; times in ticks of dt_max / 2^kHermK
 enum { kHermTn = 0, kHermNact = 1, kHermSteps = 2, kHermKmax = 3, kHermDone = 4, kHermBlocks = 5,
        kHermCtl = 6 };
+// level bookkeeping, two slots by block parity: bucket counts, appends of the
+// last corrector, block time, k* of the last block
+enum { kLevCnt = 0, kLevNew = 128, kLevT = 256, kLevKs = 258, kLevLen = 260 };
 struct HermParams {
     int64_t n = 0;
     double* x = nullptr;         // [n][3] positions (caller's, updated in place)
@@ -328,7 +331,9 @@ struct HermParams {
     int64_t* dt = nullptr;       // [n] ticks
     int32_t* act = nullptr;      // [n] active list
     unsigned long long* ctl = nullptr;   // [kHermCtl]
-    unsigned long long* part = nullptr;  // [herm_part_len()] partial minima
+    unsigned long long* lev = nullptr;   // [kLevLen]
+    int32_t* bucket = nullptr;           // [kHermK + 1][n] particles by level
+    uint32_t* slot = nullptr;            // [n] per-item level and rank (bucket moves)
     const int64_t* off = nullptr;        // neighbour lists (members are predicted with the active)
     const int32_t* idx = nullptr;
     int64_t cap = 0;
@@ -338,9 +343,10 @@ struct HermParams {
     double eta = 0.02;
 };
 void launch_herm_start(const HermParams& p, hipStream_t s);
-void launch_herm_block_front(const HermParams& p, hipStream_t s);   // next time, active list, predict
-int herm_part_len();
-void launch_herm_correct(const HermParams& p, hipStream_t s);
+// one block: front (next time, active list, prediction), then the irregular
+// force of the active list, then the corrector; parity = block number & 1
+void launch_herm_front(const HermParams& p, int parity, hipStream_t s);
+void launch_herm_correct(const HermParams& p, int parity, hipStream_t s);
 void launch_add(int64_t n, const double* a, const double* b, double* out, hipStream_t s);
 
 // kdk.hip
