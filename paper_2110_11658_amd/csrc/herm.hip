@@ -22,6 +22,11 @@
 //   eta_s |a + F_R| / |j| with eta_s = 0.01. The corrector and the start step
 //   are the standard Hermite ones (Makino & Aarseth 1992); the paper defers
 //   both to NBODY6. Expressions are evaluated as written (no contraction).
+//
+// A block is two launches: the front (next block time, active list,
+// prediction) and the force with the corrector; particles are kept in one
+// bucket per level, so neither launch passes over all n particles.
+#include "irr_pair.hpp"
 #include "pbh_internal.hpp"
 
 namespace pbh {
@@ -134,6 +139,7 @@ __global__ __launch_bounds__(256) void k_herm_front(HermParams p, int q) {
                 p.ctl[kHermNact] = (unsigned long long)nact;
                 if (done) {
                     p.ctl[kHermDone] = 1ull;
+                    if (p.done_host) *p.done_host = 1ull;   // read by the host while later blocks run
                 } else {
                     p.ctl[kHermBlocks] += 1ull;
                     p.ctl[kHermSteps] += (unsigned long long)nact;
@@ -248,18 +254,28 @@ __global__ __launch_bounds__(256) void k_herm_start(HermParams p) {
     });
 }
 
-// Hermite corrector, new block step and new bucket of the active particles
-__global__ __launch_bounds__(256) void k_herm_correct(HermParams p, int q) {
+// The irregular force of the block and the corrector, one lane per active
+// particle: F_I and its derivative a1, j1 at the predicted state (the sums of
+// the irregular-force kernel, same operations), then the 4th-order corrector,
+// the new block step and the move to the new bucket. The force reads only
+// predicted states and masses; the corrector writes only the state of its own
+// particle, so neither reads what the other writes.
+__global__ __launch_bounds__(256) void k_herm_force_correct(HermParams p, IrrParams ip, int q) {
     const int64_t nact = (int64_t)p.ctl[kHermNact];
     const int ks = (int)p.lev[kLevKs + (q ^ 1)];
     const int64_t tn = (int64_t)p.ctl[kHermTn];
-    step_and_bucket(p, q ^ 1, ks, nact, p.act, [&](int64_t k, int32_t i) {
+    step_and_bucket(p, q ^ 1, ks, nact, p.act, [&](int64_t, int32_t i) {
 #pragma clang fp contract(off)
+        IrrSums S;   // (the pair sums carry their own contraction setting)
+        unsigned long long bad = 0;
+        irr_sums<true, false, false, false>(ip, i, S, bad);
+        if (bad) atomicOr(ip.err, bad);
+        const double a1v[3] = {S.ax, S.ay, S.az}, j1v[3] = {S.jx, S.jy, S.jz};
         const double d = (double)p.dt[i] * p.unit, d2 = d * d, d3 = d2 * d, d4 = d3 * d, d5 = d4 * d;
         double a2[3], a3[3], a2e[3], at[3];
         for (int c = 0; c < 3; ++c) {
             const int64_t q3 = 3 * (int64_t)i + c;
-            const double a1 = p.a1[3 * k + c], j1 = p.j1[3 * k + c];
+            const double a1 = a1v[c], j1 = j1v[c];
             const double da = p.a[q3] - a1;
             a2[c] = (-6.0 * da - d * (4.0 * p.j[q3] + 2.0 * j1)) / d2;
             a3[c] = (12.0 * da + 6.0 * d * (p.j[q3] + j1)) / d3;
@@ -271,7 +287,7 @@ __global__ __launch_bounds__(256) void k_herm_correct(HermParams p, int q) {
             at[c] = a1 + (p.fr ? p.fr[q3] : 0.0);
         }
         const double n0 = norm3(at[0], at[1], at[2]);
-        const double n1 = norm3(p.j[3 * (int64_t)i], p.j[3 * (int64_t)i + 1], p.j[3 * (int64_t)i + 2]);
+        const double n1 = norm3(j1v[0], j1v[1], j1v[2]);
         const double n2 = norm3(a2e[0], a2e[1], a2e[2]);
         const double n3 = norm3(a3[0], a3[1], a3[2]);
         const double num = n0 * n2 + n1 * n1, den = n1 * n3 + n2 * n2;
@@ -305,8 +321,8 @@ void launch_herm_front(const HermParams& p, int parity, hipStream_t s) {
     hipLaunchKernelGGL(k_herm_front, dim3(herm_grid(p.n)), dim3(256), 0, s, p, parity);
 }
 
-void launch_herm_correct(const HermParams& p, int parity, hipStream_t s) {
-    hipLaunchKernelGGL(k_herm_correct, dim3(herm_grid(p.n)), dim3(256), 0, s, p, parity);
+void launch_herm_force_correct(const HermParams& p, const IrrParams& ip, int parity, hipStream_t s) {
+    hipLaunchKernelGGL(k_herm_force_correct, dim3(herm_grid(p.n)), dim3(256), 0, s, p, ip, parity);
 }
 
 void launch_add(int64_t n, const double* a, const double* b, double* out, hipStream_t s) {

@@ -75,7 +75,7 @@ struct pbh_ctx {
     // the P3T loop must not free it)
     struct {
         int64_t n = -1;
-        double *a = nullptr, *j = nullptr, *a1 = nullptr, *j1 = nullptr, *xp = nullptr, *vp = nullptr;
+        double *a = nullptr, *j = nullptr, *xp = nullptr, *vp = nullptr;
         int64_t *tau = nullptr, *dt = nullptr;
         int32_t* act = nullptr;
         unsigned long long* ctl = nullptr;
@@ -92,7 +92,7 @@ struct pbh_ctx {
         hipGraph_t graph = nullptr;
         hipGraphExec_t gexec = nullptr;
         std::vector<double> gkey;
-        unsigned long long* done = nullptr;   // pinned [2]: done flags of the last two batches
+        unsigned long long* done = nullptr;   // host-coherent pinned: every particle at the end
         hipEvent_t ev[2] = {nullptr, nullptr};
     } herm;
 
@@ -620,8 +620,8 @@ pbh_status ensure_herm(pbh_ctx* ctx, int64_t n) {
     h.cap = 0;
     h.idx = nullptr;
     const int nb = (int)std::min<int64_t>((n + 255) / 256, 4096);
-    if (!halloc(ctx, &h.a, 3 * n) || !halloc(ctx, &h.j, 3 * n) || !halloc(ctx, &h.a1, 3 * n) ||
-        !halloc(ctx, &h.j1, 3 * n) || !halloc(ctx, &h.xp, 3 * n) || !halloc(ctx, &h.vp, 3 * n) ||
+    if (!halloc(ctx, &h.a, 3 * n) || !halloc(ctx, &h.j, 3 * n) ||
+        !halloc(ctx, &h.xp, 3 * n) || !halloc(ctx, &h.vp, 3 * n) ||
         !halloc(ctx, &h.tau, n) || !halloc(ctx, &h.dt, n) || !halloc(ctx, &h.act, n) ||
         !halloc(ctx, &h.ctl, kHermCtl) || !halloc(ctx, &h.lev, kLevLen) ||
         !halloc(ctx, &h.bucket, (int64_t)(kHermK + 1) * n) || !halloc(ctx, &h.slot, n) ||
@@ -656,7 +656,7 @@ IrrParams herm_irr(pbh_ctx* ctx, int64_t n, double r_in, double r_out, double ep
 
 // One regular step of Hermite integration of F_I (see herm.hip), in place.
 constexpr int64_t kHermMaxBlocks = 1ll << 20;
-constexpr int kHermBatch = 8;    // blocks per graph launch
+constexpr int kHermBatch = 16;   // blocks per graph launch
 static_assert(kHermBatch % 2 == 0, "block parity restarts at each batch");
 
 pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
@@ -677,8 +677,6 @@ pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const d
     hp.v = vel;
     hp.a = h.a;
     hp.j = h.j;
-    hp.a1 = h.a1;
-    hp.j1 = h.j1;
     hp.xp = h.xp;
     hp.vp = h.vp;
     hp.fr = fr;
@@ -686,6 +684,11 @@ pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const d
     hp.dt = h.dt;
     hp.act = h.act;
     hp.ctl = h.ctl;
+    if (!h.done) {
+        HIP_TRY(hipHostMalloc((void**)&h.done, sizeof(unsigned long long), hipHostMallocCoherent));
+        for (auto& e : h.ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    HIP_TRY(hipHostGetDevicePointer((void**)&hp.done_host, h.done, 0));
     hp.lev = h.lev;
     hp.bucket = h.bucket;
     hp.slot = h.slot;
@@ -699,15 +702,13 @@ pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const d
     launch_zero_u64(h.lev, kLevLen, s);
     launch_herm_start(hp, s);
     launch_zero_u64(h.ctl, kHermCtl, s);
-    ip.pos = h.xp;
+    ip.pos = h.xp;   // the block's force reads predicted states
     ip.vel = h.vp;
-    ip.tgt = h.act;
-    ip.n_tgt_dev = h.ctl + kHermNact;
-    ip.acc = h.a1;
-    ip.jerk = h.j1;
+    ip.acc = ip.jerk = nullptr;
     // Blocks run in batches of kHermBatch, each batch one graph launch. The
-    // done flag of a batch is read while the next batch runs, so the GPU does
-    // not wait for the host; the batch after the last busy one is empty.
+    // front that finds every particle at the end sets a host flag; the host
+    // reads it once a batch has finished, while the next batch runs, so the GPU
+    // does not wait for the host; the batch after the last busy one is empty.
     const std::vector<double> key = {(double)n, (double)(uintptr_t)pos, (double)(uintptr_t)vel,
                                      (double)(uintptr_t)mass, (double)(uintptr_t)fr, (double)(uintptr_t)off,
                                      (double)(uintptr_t)idx, (double)cap, r_in, r_out, eps, T, eta,
@@ -721,34 +722,25 @@ pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const d
         HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         for (int b = 0; b < kHermBatch; ++b) {   // kHermBatch is even: block parity b & 1
             launch_herm_front(hp, b & 1, cs);
-            launch_irregular(ip, cs);
-            launch_herm_correct(hp, b & 1, cs);
+            launch_herm_force_correct(hp, ip, b & 1, cs);
         }
         HIP_TRY(hipStreamEndCapture(cs, &h.graph));
         HIP_TRY(hipGraphInstantiate(&h.gexec, h.graph, nullptr, nullptr, 0));
         h.gkey = key;
     }
-    if (!h.done) {
-        HIP_TRY(hipHostMalloc((void**)&h.done, 2 * sizeof(unsigned long long), hipHostMallocDefault));
-        for (auto& e : h.ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    }
-    auto enqueue = [&](int slot) -> hipError_t {
-        hipError_t e = hipGraphLaunch(h.gexec, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(h.done + slot, h.ctl + kHermDone, sizeof(unsigned long long),
-                               hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipEventRecord(h.ev[slot], s);
-        return e;
-    };
-    HIP_TRY(enqueue(0));
+    volatile unsigned long long* flag = h.done;
+    *flag = 0ull;   // no launch of an earlier call is pending (each call ends with a wait)
+    HIP_TRY(hipGraphLaunch(h.gexec, s));
+    HIP_TRY(hipEventRecord(h.ev[0], s));
     for (int64_t batch = 0;; ++batch) {
         if ((batch + 1) * kHermBatch >= kHermMaxBlocks) {
             HIP_TRY(hipStreamSynchronize(s));
             return fail(ctx, PBH_E_INTERNAL, "Hermite block steps exceed the limit");
         }
-        HIP_TRY(enqueue((int)((batch + 1) & 1)));
+        HIP_TRY(hipGraphLaunch(h.gexec, s));
+        HIP_TRY(hipEventRecord(h.ev[(batch + 1) & 1], s));
         HIP_TRY(hipEventSynchronize(h.ev[batch & 1]));
-        if (h.done[batch & 1]) break;
+        if (*flag) break;
     }
     unsigned long long c[kHermCtl], err = 0;
     HIP_TRY(hipMemcpyAsync(c, h.ctl, sizeof(c), hipMemcpyDeviceToHost, s));

@@ -322,8 +322,6 @@ struct HermParams {
     double* v = nullptr;         // [n][3] velocities (caller's, updated in place)
     double* a = nullptr;         // [n][3] F_I at tau_i
     double* j = nullptr;         // [n][3] dF_I/dt at tau_i
-    const double* a1 = nullptr;  // [n_active][3] F_I at the predicted state (active list order)
-    const double* j1 = nullptr;
     double* xp = nullptr;        // [n][3] predicted
     double* vp = nullptr;
     const double* fr = nullptr;  // [n][3] regular force (step criterion), or null
@@ -334,6 +332,7 @@ struct HermParams {
     unsigned long long* lev = nullptr;   // [kLevLen]
     int32_t* bucket = nullptr;           // [kHermK + 1][n] particles by level
     uint32_t* slot = nullptr;            // [n] per-item level and rank (bucket moves)
+    unsigned long long* done_host = nullptr;   // host-coherent pinned flag, set once all are at tend
     const int64_t* off = nullptr;        // neighbour lists (members are predicted with the active)
     const int32_t* idx = nullptr;
     int64_t cap = 0;
@@ -344,9 +343,9 @@ struct HermParams {
 };
 void launch_herm_start(const HermParams& p, hipStream_t s);
 // one block: front (next time, active list, prediction), then the irregular
-// force of the active list, then the corrector; parity = block number & 1
+// force of the active list with the corrector; parity = block number & 1
 void launch_herm_front(const HermParams& p, int parity, hipStream_t s);
-void launch_herm_correct(const HermParams& p, int parity, hipStream_t s);
+void launch_herm_force_correct(const HermParams& p, const IrrParams& ip, int parity, hipStream_t s);
 void launch_add(int64_t n, const double* a, const double* b, double* out, hipStream_t s);
 
 // kdk.hip
