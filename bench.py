@@ -544,7 +544,7 @@ def bench_p3t(args):
         "value": n * steps / secs, "unit": "particle regular-steps/s",
         "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": 1e3 * secs / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if args.prec == "mixed" else "f64", "data": "synthetic",
+        "dtype": "f32+f64" if args.prec == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": f"{inp['name']}: {inp['desc'].split(' r_out')[0]} paper rule: "
                                f"r_cut={r_out:.6f} r_in={r_in:.6f} r_buff={r_buff:.6f} dt_reg={T} "
                                f"eta={eta} theta={args.theta}", "n": n},
