@@ -81,6 +81,66 @@ __device__ inline void predict_one(const HermParams& p, int64_t i, int64_t tn) {
     }
 }
 
+// The count of level k (lane k of a wave) after merging the previous block's
+// appends into slot q; `add` returns those appends.
+__device__ inline long long merged_count(const HermParams& p, int q, int k, long long& add) {
+    add = 0;
+    if (k > kHermK) return 0;
+    const int kp = (int)p.lev[kLevKs + q];   // k* of the previous block
+    const long long old = (long long)lev_cnt(p, q)[k];
+    add = (long long)lev_new(p, q)[k];
+    return k >= kp ? add : (k == kp - 1 ? old + add : old);
+}
+
+// The next block from the level counts (one wave, lane k holding count c of
+// level k) and the current time t: its time tn, k*, the number of active
+// particles and lane k's offset in the active list (levels >= k* in order).
+struct BlockPlan {
+    long long tn, nact, off;
+    int ks;
+    bool done;
+};
+
+__device__ inline BlockPlan plan_block(long long c, long long t, unsigned long long tend) {
+    const int k = threadIdx.x & 63;
+    BlockPlan b;
+    const int kmax = 63 - __clzll(__ballot(c > 0));   // deepest occupied level (n >= 1)
+    b.done = t >= (long long)tend;
+    const int sh = kHermK - kmax;
+    b.tn = b.done ? (long long)tend : (((t >> sh) + 1) << sh);
+    const int tz = __ffsll((unsigned long long)b.tn) - 1;
+    b.ks = b.done ? kHermK + 1 : (tz >= kHermK ? 0 : kHermK - tz);
+    const long long a = k >= b.ks ? c : 0;
+    long long incl = a;
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long w = __shfl_up(incl, o, 64);
+        if (k >= o) incl += w;
+    }
+    b.nact = __shfl(incl, 63, 64);
+    b.off = incl - a;
+    return b;
+}
+
+// entry t of the active list: level buckets ks, ks + 1, ... in turn
+__device__ inline int32_t active_at(const HermParams& p, const long long* off, const long long* cnt, int ks,
+                                    long long t) {
+    int k = ks;
+    while (k < kHermK && t >= off[k] + cnt[k]) ++k;
+    return p.bucket[(int64_t)k * p.n + (t - off[k])];
+}
+
+// predict the active particle i (item 0) or member g - 1, g - 1 + kHermLanes, ...
+// of its list (items g, g + kHermLanes, ...): lane g of its lane group
+__device__ inline void predict_items(const HermParams& p, int32_t i, int g, int64_t tn) {
+    if (g == 0) predict_one(p, i, tn);
+    const int64_t b0 = p.off[i], e = p.off[i + 1];
+    if (b0 < 0 || e < b0 || e > p.cap) return;   // flagged by the force kernel
+    for (int64_t m = b0 + (g == 0 ? kHermLanes - 1 : g - 1); m < e; m += kHermLanes) {
+        const int64_t j = p.idx[m];
+        if ((uint64_t)j < (uint64_t)p.n) predict_one(p, j, tn);
+    }
+}
+
 // Block front: the next block time and the active buckets (computed by every
 // workgroup from slot q; workgroup 0 publishes them), then the active list
 // (bucket order) with the prediction of each active particle and its list
@@ -92,36 +152,19 @@ __global__ __launch_bounds__(256) void k_herm_front(HermParams p, int q) {
     __shared__ int s_ks;
     if (threadIdx.x < 64) {
         const int k = threadIdx.x;
-        const int kp = (int)p.lev[kLevKs + q];   // k* of the previous block
-        long long c = 0, add = 0;
-        if (k <= kHermK) {
-            const long long old = (long long)lev_cnt(p, q)[k];
-            add = (long long)lev_new(p, q)[k];
-            c = k >= kp ? add : (k == kp - 1 ? old + add : old);
-        }
+        long long add;
+        const long long c = merged_count(p, q, k, add);
         // deepest new level of the previous corrector (its appends; the first
         // block's appends are the start levels, not counted)
         const uint64_t app = __ballot(add > 0);
-        const uint64_t occ = __ballot(c > 0);
-        const int kmax = 63 - __clzll(occ);          // deepest occupied level (n >= 1)
         const long long t = (long long)p.lev[kLevT + q];
-        const bool done = t >= (long long)p.tend;
-        const int sh = kHermK - kmax;
-        const long long tn = done ? (long long)p.tend : (((t >> sh) + 1) << sh);
-        const int tz = __ffsll((unsigned long long)tn) - 1;
-        const int ks = done ? kHermK + 1 : (tz >= kHermK ? 0 : kHermK - tz);
-        long long a = k >= ks ? c : 0, incl = a;
-        for (int o = 1; o < 64; o <<= 1) {
-            const long long w = __shfl_up(incl, o, 64);
-            if (k >= o) incl += w;
-        }
-        const long long nact = __shfl(incl, 63, 64);
+        const BlockPlan B = plan_block(c, t, p.tend);
         s_cnt[k] = c;
-        s_off[k] = incl - a;
+        s_off[k] = B.off;
         if (k == 0) {
-            s_tn = tn;
-            s_nact = nact;
-            s_ks = ks;
+            s_tn = B.tn;
+            s_nact = B.nact;
+            s_ks = B.ks;
         }
         if (blockIdx.x == 0) {
             if (k == 0 && t > 0 && app) {
@@ -133,16 +176,16 @@ __global__ __launch_bounds__(256) void k_herm_front(HermParams p, int q) {
                 lev_new(p, q ^ 1)[k] = 0ull;
             }
             if (k == 0) {
-                p.lev[kLevT + (q ^ 1)] = (unsigned long long)tn;
-                p.lev[kLevKs + (q ^ 1)] = (unsigned long long)ks;
-                p.ctl[kHermTn] = done ? ~0ull : (unsigned long long)tn;
-                p.ctl[kHermNact] = (unsigned long long)nact;
-                if (done) {
+                p.lev[kLevT + (q ^ 1)] = (unsigned long long)B.tn;
+                p.lev[kLevKs + (q ^ 1)] = (unsigned long long)B.ks;
+                p.ctl[kHermTn] = B.done ? ~0ull : (unsigned long long)B.tn;
+                p.ctl[kHermNact] = (unsigned long long)B.nact;
+                if (B.done) {
                     p.ctl[kHermDone] = 1ull;
                     if (p.done_host) *p.done_host = 1ull;   // read by the host while later blocks run
                 } else {
                     p.ctl[kHermBlocks] += 1ull;
-                    p.ctl[kHermSteps] += (unsigned long long)nact;
+                    p.ctl[kHermSteps] += (unsigned long long)B.nact;
                 }
             }
         }
@@ -156,11 +199,7 @@ __global__ __launch_bounds__(256) void k_herm_front(HermParams p, int q) {
         // a large active set: predict every particle once, in order (the
         // others are not read by this block), and list the active ones
         for (long long t = t0; t < p.n; t += stride) predict_one(p, t, tn);
-        for (long long t = t0; t < nact; t += stride) {
-            int k = ks;
-            while (k < kHermK && t >= s_off[k] + s_cnt[k]) ++k;
-            p.act[t] = p.bucket[(int64_t)k * p.n + (t - s_off[k])];
-        }
+        for (long long t = t0; t < nact; t += stride) p.act[t] = active_at(p, s_off, s_cnt, ks, t);
         return;
     }
     // kHermLanes lanes per active particle: item 0 is the particle, item
@@ -168,19 +207,9 @@ __global__ __launch_bounds__(256) void k_herm_front(HermParams p, int q) {
     for (long long t = t0; t < nact * kHermLanes; t += stride) {
         const long long a = t / kHermLanes;
         const int g = (int)(t % kHermLanes);
-        int k = ks;
-        while (k < kHermK && a >= s_off[k] + s_cnt[k]) ++k;
-        const int32_t i = p.bucket[(int64_t)k * p.n + (a - s_off[k])];
-        if (g == 0) {
-            p.act[a] = i;
-            predict_one(p, i, tn);
-        }
-        const int64_t b0 = p.off[i], e = p.off[i + 1];
-        if (b0 < 0 || e < b0 || e > p.cap) continue;   // flagged by the force kernel
-        for (int64_t m = b0 + (g == 0 ? kHermLanes - 1 : g - 1); m < e; m += kHermLanes) {
-            const int64_t j = p.idx[m];
-            if ((uint64_t)j < (uint64_t)p.n) predict_one(p, j, tn);
-        }
+        const int32_t i = active_at(p, s_off, s_cnt, ks, a);
+        if (g == 0) p.act[a] = i;
+        predict_items(p, i, g, tn);
     }
 }
 
@@ -256,48 +285,62 @@ __global__ __launch_bounds__(256) void k_herm_start(HermParams p) {
 
 // The irregular force of the block and the corrector, one lane per active
 // particle: F_I and its derivative a1, j1 at the predicted state (the sums of
-// the irregular-force kernel, same operations), then the 4th-order corrector,
-// the new block step and the move to the new bucket. The force reads only
+// the irregular-force kernel, same operations), then the 4th-order corrector
+// and the new block step; returns the new level. The force reads only
 // predicted states and masses; the corrector writes only the state of its own
 // particle, so neither reads what the other writes.
+__device__ inline int force_correct(const HermParams& p, const IrrParams& ip, int32_t i, int64_t tn) {
+#pragma clang fp contract(off)
+    // the corrector's own inputs first: their loads overlap the force's gathers
+    const int64_t dti = p.dt[i];
+    double a0[3], j0[3], fr[3], xp[3], vp[3];
+    for (int c = 0; c < 3; ++c) {
+        const int64_t q3 = 3 * (int64_t)i + c;
+        a0[c] = p.a[q3];
+        j0[c] = p.j[q3];
+        fr[c] = p.fr ? p.fr[q3] : 0.0;
+        xp[c] = p.xp[q3];
+        vp[c] = p.vp[q3];
+    }
+    IrrSums S;   // (the pair sums carry their own contraction setting)
+    unsigned long long bad = 0;
+    irr_sums<true, false, false, false>(ip, i, S, bad);
+    if (bad) atomicOr(ip.err, bad);
+    const double a1v[3] = {S.ax, S.ay, S.az}, j1v[3] = {S.jx, S.jy, S.jz};
+    const double d = (double)dti * p.unit, d2 = d * d, d3 = d2 * d, d4 = d3 * d, d5 = d4 * d;
+    double a2[3], a3[3], a2e[3], at[3];
+    for (int c = 0; c < 3; ++c) {
+        const int64_t q3 = 3 * (int64_t)i + c;
+        const double a1 = a1v[c], j1 = j1v[c];
+        const double da = a0[c] - a1;
+        a2[c] = (-6.0 * da - d * (4.0 * j0[c] + 2.0 * j1)) / d2;
+        a3[c] = (12.0 * da + 6.0 * d * (j0[c] + j1)) / d3;
+        p.x[q3] = xp[c] + d4 / 24.0 * a2[c] + d5 / 120.0 * a3[c];
+        p.v[q3] = vp[c] + d3 / 6.0 * a2[c] + d4 / 24.0 * a3[c];
+        p.a[q3] = a1;
+        p.j[q3] = j1;
+        a2e[c] = a2[c] + d * a3[c];
+        at[c] = a1 + fr[c];
+    }
+    const double n0 = norm3(at[0], at[1], at[2]);
+    const double n1 = norm3(j1v[0], j1v[1], j1v[2]);
+    const double n2 = norm3(a2e[0], a2e[1], a2e[2]);
+    const double n3 = norm3(a3[0], a3[1], a3[2]);
+    const double num = n0 * n2 + n1 * n1, den = n1 * n3 + n2 * n2;
+    double want = den > 0.0 ? sqrt(p.eta * num / den) : p.dtmax;
+    if (want > 2.0 * d) want = 2.0 * d;
+    const int64_t t = block_step(want, p.dtmax, tn);
+    p.tau[i] = tn;
+    p.dt[i] = t;
+    return step_level(t);
+}
+
 __global__ __launch_bounds__(256) void k_herm_force_correct(HermParams p, IrrParams ip, int q) {
     const int64_t nact = (int64_t)p.ctl[kHermNact];
     const int ks = (int)p.lev[kLevKs + (q ^ 1)];
     const int64_t tn = (int64_t)p.ctl[kHermTn];
-    step_and_bucket(p, q ^ 1, ks, nact, p.act, [&](int64_t, int32_t i) {
-#pragma clang fp contract(off)
-        IrrSums S;   // (the pair sums carry their own contraction setting)
-        unsigned long long bad = 0;
-        irr_sums<true, false, false, false>(ip, i, S, bad);
-        if (bad) atomicOr(ip.err, bad);
-        const double a1v[3] = {S.ax, S.ay, S.az}, j1v[3] = {S.jx, S.jy, S.jz};
-        const double d = (double)p.dt[i] * p.unit, d2 = d * d, d3 = d2 * d, d4 = d3 * d, d5 = d4 * d;
-        double a2[3], a3[3], a2e[3], at[3];
-        for (int c = 0; c < 3; ++c) {
-            const int64_t q3 = 3 * (int64_t)i + c;
-            const double a1 = a1v[c], j1 = j1v[c];
-            const double da = p.a[q3] - a1;
-            a2[c] = (-6.0 * da - d * (4.0 * p.j[q3] + 2.0 * j1)) / d2;
-            a3[c] = (12.0 * da + 6.0 * d * (p.j[q3] + j1)) / d3;
-            p.x[q3] = p.xp[q3] + d4 / 24.0 * a2[c] + d5 / 120.0 * a3[c];
-            p.v[q3] = p.vp[q3] + d3 / 6.0 * a2[c] + d4 / 24.0 * a3[c];
-            p.a[q3] = a1;
-            p.j[q3] = j1;
-            a2e[c] = a2[c] + d * a3[c];
-            at[c] = a1 + (p.fr ? p.fr[q3] : 0.0);
-        }
-        const double n0 = norm3(at[0], at[1], at[2]);
-        const double n1 = norm3(j1v[0], j1v[1], j1v[2]);
-        const double n2 = norm3(a2e[0], a2e[1], a2e[2]);
-        const double n3 = norm3(a3[0], a3[1], a3[2]);
-        const double num = n0 * n2 + n1 * n1, den = n1 * n3 + n2 * n2;
-        double want = den > 0.0 ? sqrt(p.eta * num / den) : p.dtmax;
-        if (want > 2.0 * d) want = 2.0 * d;
-        const int64_t t = block_step(want, p.dtmax, tn);
-        p.tau[i] = tn;
-        p.dt[i] = t;
-        return step_level(t);
-    });
+    step_and_bucket(p, q ^ 1, ks, nact, p.act,
+                    [&](int64_t, int32_t i) { return force_correct(p, ip, i, tn); });
 }
 
 // pot_tot = pot_r + pot_i

@@ -69,6 +69,43 @@ def test_p3t_matches_oracle():
     assert np.allclose(e.cpu().numpy(), oe, rtol=1e-11, atol=0)
 
 
+@pytest.mark.parametrize("n,seed,T", [(2048, 96, 1.0 / 256), (4096, 97, 1.0 / 128)])
+def test_hermite_larger_n(n, seed, T):
+    # thousands of particles: blocks from every particle active (the front
+    # predicts them all at once) down to a few particles of the deepest level
+    # (lane groups per list); the schedule and the states equal the oracle's
+    print(f"hermite n={n}", flush=True)
+    c, r_in, r_out = _setup(n, seed, 16.0)
+    eps, eta = 1e-4, 0.02
+    r_buff = 3.0 * np.linalg.norm(c.vel, axis=1).max() * T
+    p = _pbh(prec="fp64")
+    pos, vel, mass = _t(c.pos), _t(c.vel), _t(c.mass)
+    p.build(pos, mass)
+    fr, _, off, idx = p.force(r_in, r_out, 0.0, eps, r_buff=r_buff)
+    st = p.hermite(pos, vel, mass, fr, r_in, r_out, eps, off, idx, T, eta)
+    ofr, _ = oracle.direct(c.pos, c.mass, r_in, r_out, eps)
+    ox, ov, ost = oracle.hermite(c.pos, c.vel, c.mass, r_in, r_out, eps, T, eta=eta, fr=ofr)
+    assert st == ost and st["steps"] > 2 * n and st["kmax"] >= 4
+    gx, gv = pos.cpu().numpy(), vel.cpu().numpy()
+    assert np.abs(gx - ox).max() <= 1e-10 * np.abs(ox).max()
+    assert np.abs(gv - ov).max() <= 1e-10 * np.abs(ov).max()
+
+
+def test_p3t_larger_n():
+    print("p3t n=1536", flush=True)
+    c, r_in, r_out = _setup(1536, 98, 12.0)
+    eps, T, eta, steps = 1e-4, 1.0 / 256, 0.02, 2
+    r_buff = 3.0 * np.linalg.norm(c.vel, axis=1).max() * T
+    p = _pbh(prec="fp64")
+    pos, vel, mass = _t(c.pos), _t(c.vel), _t(c.mass)
+    e, st = p.p3t(pos, vel, mass, r_in, r_out, r_buff, 0.0, eps, T, eta, steps)
+    ox, ov, oe = oracle.p3t(c.pos, c.vel, c.mass, r_in, r_out, eps, T, eta=eta, steps=steps)
+    gx, gv = pos.cpu().numpy(), vel.cpu().numpy()
+    assert np.abs(gx - ox).max() <= 1e-10 * np.abs(ox).max()
+    assert np.abs(gv - ov).max() <= 1e-10 * np.abs(ov).max()
+    assert np.allclose(e.cpu().numpy(), oe, rtol=1e-11, atol=0)
+
+
 def test_hermite_kepler_order_on_gpu():
     # two bodies, all of the force irregular: the orbit closes after one period
     # with an error falling as eta^2 (4th order)
