@@ -284,9 +284,9 @@ __global__ __launch_bounds__(256) void k_herm_start(HermParams p) {
 }
 
 // The irregular force of the block and the corrector, one lane per active
-// particle: F_I and its derivative a1, j1 at the predicted state (the sums of
-// the irregular-force kernel, same operations), then the 4th-order corrector
-// and the new block step; returns the new level. The force reads only
+// particle: F_I and its derivative a1, j1 at the predicted state (the pair
+// terms of the irregular-force kernel, summed over the list in order), then
+// the 4th-order corrector and the new block step; returns the new level. The force reads only
 // predicted states and masses; the corrector writes only the state of its own
 // particle, so neither reads what the other writes.
 __device__ inline int force_correct(const HermParams& p, const IrrParams& ip, int32_t i, int64_t tn) {

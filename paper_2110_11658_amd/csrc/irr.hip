@@ -15,17 +15,19 @@
 // any list that holds every j with r_ij < r_out gives the whole sums; lists of
 // a larger search radius work unchanged.
 //
-// One lane per target, its list summed in list order. For all targets (or a
-// long target list) with a build of these n particles, a pre-pass packs every
-// particle into a 64-byte record (x, y, z, m, vx, vy, vz) in the build's key
-// order and stores each caller index's key rank; the targets of a wave are
+// A group of kIrrLanes lanes per target: lane g sums list entries g,
+// g + kIrrLanes, ... in order, and the group adds the lanes' partial sums in a
+// fixed butterfly, so the sums do not depend on the route, the grid or the
+// target order. A wave's list loads are then contiguous runs. For all targets
+// (or a long target list) with a build of these n particles, a pre-pass packs
+// every particle into a 64-byte record (x, y, z, m, vx, vy, vz) in the build's
+// key order and stores each caller index's key rank; the targets of a wave are
 // then consecutive in key order, and its gathers land in a spatially compact
 // range of records that stays in cache. Otherwise (no build, or a short
-// target list) the kernel gathers from the caller's arrays. List entries are
-// taken in batches whose loads issue together (a gather costs cache latency,
-// not arithmetic); the pairs of a batch are then summed in list order, so the
-// sums do not depend on the route or the order. Lists, targets and offsets are
-// range-checked: a bad entry is skipped and flagged, never dereferenced.
+// target list) the kernel gathers from the caller's arrays. A lane's entries
+// are taken in batches whose loads issue together (a gather costs cache
+// latency, not arithmetic). Lists, targets and offsets are range-checked: a
+// bad entry is skipped and flagged, never dereferenced.
 #include "irr_pair.hpp"
 #include "pbh_internal.hpp"
 #include "wave.hpp"
@@ -69,47 +71,49 @@ __device__ inline void store_sums(const IrrParams& p, int64_t slot, const IrrSum
     if (POT) p.pot[slot] = S.ph;
 }
 
-// Blocks (of 256 key-order targets) per XCD chunk.
-constexpr unsigned kIrrChunk = 16;
+// Blocks (of 256 / kIrrLanes = 32 key-order targets) per XCD chunk: 1024 targets.
+constexpr unsigned kIrrChunk = 32;
 
-// One target k (a lane): its sums over its list, stored at its output slot.
+// One target k (a lane group, lane g of it): the group's sums over its list,
+// stored at its output slot by lane 0.
 template <bool JERK, bool POT, bool SORTED, bool MULTI>
-__device__ inline void irr_target(const IrrParams& p, int64_t k) {
+__device__ inline void irr_target(const IrrParams& p, int64_t k, int g) {
     unsigned long long bad = 0;
     const int64_t i = p.tgt ? (int64_t)p.tgt[k] : (p.order ? (int64_t)p.order[k] : k);
     IrrSums S;
-    const bool valid = irr_sums<JERK, POT, SORTED, MULTI>(p, i, S, bad);
-    if (valid || p.tgt) store_sums<JERK, POT>(p, p.tgt ? k : i, S);   // no slot of its own otherwise
+    const bool valid = irr_sums_lanes<JERK, POT, SORTED, MULTI>(p, i, g, S, bad);
+    if (g == 0 && (valid || p.tgt)) store_sums<JERK, POT>(p, p.tgt ? k : i, S);   // no slot of its own otherwise
     if (bad) atomicOr(p.err, bad);
 }
 
 template <bool JERK, bool POT, bool SORTED, bool MULTI>
 __global__ __launch_bounds__(256) void k_irregular(IrrParams p) {
+    const int g = threadIdx.x % kIrrLanes;   // lane groups never straddle a workgroup
     if (SORTED) {
         // key-order targets in chunks per XCD (cache locality and load balance)
         const unsigned blk = xcd_chunk_block(blockIdx.x, kIrrChunk);
-        const int64_t k = (int64_t)blk * blockDim.x + threadIdx.x;
-        if (k < p.n_tgt) irr_target<JERK, POT, SORTED, MULTI>(p, k);
+        const int64_t k = ((int64_t)blk * blockDim.x + threadIdx.x) / kIrrLanes;
+        if (k < p.n_tgt) irr_target<JERK, POT, SORTED, MULTI>(p, k, g);   // group-uniform
         return;
     }
     // caller-array route: grid-stride, the count possibly held on the device
     int64_t nt = p.n_tgt;
     if (p.n_tgt_dev && (int64_t)*p.n_tgt_dev < nt) nt = (int64_t)*p.n_tgt_dev;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nt;
-         k += (int64_t)gridDim.x * blockDim.x)
-        irr_target<JERK, POT, SORTED, MULTI>(p, k);
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nt * kIrrLanes;
+         v += (int64_t)gridDim.x * blockDim.x)
+        irr_target<JERK, POT, SORTED, MULTI>(p, v / kIrrLanes, g);
 }
 
 template <bool JERK, bool POT, bool MULTI>
 void launch_route(const IrrParams& p, hipStream_t s) {
-    const int64_t nb = (p.n_tgt + 255) / 256;
+    const int64_t nb = (p.n_tgt * kIrrLanes + 255) / 256;
     const dim3 block(256);
     if (p.rec) {   // grid padded to whole rounds of chunks over the XCDs
         const int64_t round = (int64_t)kQueues * kIrrChunk;
         const dim3 grid((unsigned)((nb + round - 1) / round * round));
         hipLaunchKernelGGL((k_irregular<JERK, POT, true, MULTI>), grid, block, 0, s, p);
     } else {   // grid-stride: a count held on the device may be far below n_tgt
-        const int64_t g = p.n_tgt_dev ? (nb < 1024 ? nb : 1024) : nb;
+        const int64_t g = p.n_tgt_dev ? (nb < 4096 ? nb : 4096) : nb;
         hipLaunchKernelGGL((k_irregular<JERK, POT, false, MULTI>), dim3((unsigned)g), block, 0, s, p);
     }
 }

@@ -10,8 +10,9 @@ namespace pbh {
 namespace {
 
 // Pair arithmetic is written with explicit fma() and contraction off, so every
-// kernel that inlines it performs the same operations (the routes of the
-// irregular-force kernel and the Hermite corrector give bit-identical sums).
+// kernel that inlines it performs the same operations per pair (the two routes
+// of the irregular-force kernel, which also share a summation order, give
+// bit-identical sums).
 
 // The cluster constants one target needs, held in registers for its loop.
 struct IrrK {
@@ -194,6 +195,77 @@ __device__ inline bool irr_sums(const IrrParams& p, int64_t i, IrrSums& S, unsig
                 if (ok[u]) pair_irr<JERK, POT>(K, p.eps2, me, q[u], S);
         }
     }
+    return valid;
+}
+
+
+// Lane groups: kIrrLanes lanes share one target. Lane g takes list entries
+// g, g + kIrrLanes, g + 2 kIrrLanes, ... in that order (kIrrLaneBatch of them
+// per round, their loads issued together), and the group adds its partial
+// sums with a fixed butterfly (xor 4, 2, 1), so every lane ends with the
+// same total and the order does not depend on the launch. A wave's list loads
+// are then contiguous runs, and its record loads fall on the neighbours of a
+// few targets, close together in key order.
+constexpr int kIrrLanes = 8;
+constexpr int kIrrLaneBatch = 4;
+
+__device__ inline double group_sum(double v) {
+#pragma unroll
+    for (int o = kIrrLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <bool JERK, bool POT, bool SORTED, bool MULTI>
+__device__ inline bool irr_sums_lanes(const IrrParams& p, int64_t i, int g, IrrSums& S,
+                                      unsigned long long& bad) {
+    const ClusterParams* cp;
+    int64_t b, e;
+    const bool valid = target_setup(p, i, cp, b, e, bad);
+    if (g != 0) bad = 0;   // target and offset flags once per group
+    if (valid) {
+        const IrrK K = irr_constants(MULTI ? *cp : p.cp0);
+        const PartJ me = SORTED ? load_rec<JERK>(p.rec, p.rank[i]) : load_caller<JERK>(p, i);
+        for (int64_t m = b + g; m < e; m += kIrrLanes * kIrrLaneBatch) {
+            int32_t jv[kIrrLaneBatch];
+            bool ok[kIrrLaneBatch];
+#pragma unroll
+            for (int u = 0; u < kIrrLaneBatch; ++u) {   // clamped: inside the list whenever m < e
+                const int64_t q = m + (int64_t)kIrrLanes * u;
+                jv[u] = p.idx[q < e ? q : e - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kIrrLaneBatch; ++u) {
+                const bool live = m + (int64_t)kIrrLanes * u < e;
+                const bool inr = (uint64_t)(int64_t)jv[u] < (uint64_t)p.n;
+                if (live && !inr) bad |= kIrrBadIndex;
+                ok[u] = live && inr && jv[u] != i;
+                if (!ok[u]) jv[u] = (int32_t)i;   // a valid index; its pair is not summed
+            }
+            PartJ q[kIrrLaneBatch];
+            if (SORTED) {
+                int32_t rk[kIrrLaneBatch];
+#pragma unroll
+                for (int u = 0; u < kIrrLaneBatch; ++u) rk[u] = p.rank[jv[u]];
+#pragma unroll
+                for (int u = 0; u < kIrrLaneBatch; ++u) q[u] = load_rec<JERK>(p.rec, rk[u]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < kIrrLaneBatch; ++u) q[u] = load_caller<JERK>(p, jv[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kIrrLaneBatch; ++u)
+                if (ok[u]) pair_irr<JERK, POT>(K, p.eps2, me, q[u], S);
+        }
+    }
+    S.ax = group_sum(S.ax);
+    S.ay = group_sum(S.ay);
+    S.az = group_sum(S.az);
+    if (JERK) {
+        S.jx = group_sum(S.jx);
+        S.jy = group_sum(S.jy);
+        S.jz = group_sum(S.jz);
+    }
+    if (POT) S.ph = group_sum(S.ph);
     return valid;
 }
 
