@@ -225,6 +225,10 @@ __device__ inline double block_sum(double v, double* red) {
     return red[0];
 }
 
+// Each thread takes samples t, t + kStatT, ... in order; their loads are
+// issued kStatB at a time (the sums keep that order).
+constexpr int kStatB = 8;
+
 __global__ __launch_bounds__(kStatT) void k_core_stats(int64_t n, int64_t ns, const int32_t* __restrict__ sample,
                                                        const double* __restrict__ pos,
                                                        const double* __restrict__ rho,
@@ -233,14 +237,31 @@ __global__ __launch_bounds__(kStatT) void k_core_stats(int64_t n, int64_t ns, co
     __shared__ double red[kStatT];
     const int t = threadIdx.x;
     double sr = 0, sx = 0, sy = 0, sz = 0;
-    for (int64_t s = t; s < ns; s += kStatT) {
-        const int64_t i = sample[s];
-        if ((uint64_t)i >= (uint64_t)n) continue;   // flagged by the search; never read
-        const double r = rho[s];
-        sr += r;
-        sx += r * pos[3 * i];
-        sy += r * pos[3 * i + 1];
-        sz += r * pos[3 * i + 2];
+    for (int64_t s0 = t; s0 < ns; s0 += (int64_t)kStatT * kStatB) {
+        int64_t iv[kStatB];
+        double rv[kStatB], xv[kStatB], yv[kStatB], zv[kStatB];
+#pragma unroll
+        for (int u = 0; u < kStatB; ++u) {
+            const int64_t s = s0 + (int64_t)kStatT * u;
+            iv[u] = s < ns ? (int64_t)sample[s] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kStatB; ++u) {
+            const bool ok = (uint64_t)iv[u] < (uint64_t)n;   // out of range: flagged by the search; never read
+            const int64_t i = ok ? iv[u] : 0;
+            rv[u] = ok ? rho[s0 + (int64_t)kStatT * u] : 0.0;
+            xv[u] = pos[3 * i];
+            yv[u] = pos[3 * i + 1];
+            zv[u] = pos[3 * i + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < kStatB; ++u) {
+            if ((uint64_t)iv[u] >= (uint64_t)n) continue;
+            sr += rv[u];
+            sx += rv[u] * xv[u];
+            sy += rv[u] * yv[u];
+            sz += rv[u] * zv[u];
+        }
     }
     sr = block_sum(sr, red);
     sx = block_sum(sx, red);
@@ -248,14 +269,32 @@ __global__ __launch_bounds__(kStatT) void k_core_stats(int64_t n, int64_t ns, co
     sz = block_sum(sz, red);
     const double xd = sx / sr, yd = sy / sr, zd = sz / sr;
     double s2 = 0, s2d = 0;
-    for (int64_t s = t; s < ns; s += kStatT) {
-        const int64_t i = sample[s];
-        if ((uint64_t)i >= (uint64_t)n) continue;
-        const double r = rho[s];
-        const double dx = pos[3 * i] - xd, dy = pos[3 * i + 1] - yd, dz = pos[3 * i + 2] - zd;
-        const double dd = dx * dx + dy * dy + dz * dz;
-        s2 += r * r;
-        s2d += r * r * dd;
+    for (int64_t s0 = t; s0 < ns; s0 += (int64_t)kStatT * kStatB) {
+        int64_t iv[kStatB];
+        double rv[kStatB], xv[kStatB], yv[kStatB], zv[kStatB];
+#pragma unroll
+        for (int u = 0; u < kStatB; ++u) {
+            const int64_t s = s0 + (int64_t)kStatT * u;
+            iv[u] = s < ns ? (int64_t)sample[s] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kStatB; ++u) {
+            const bool ok = (uint64_t)iv[u] < (uint64_t)n;
+            const int64_t i = ok ? iv[u] : 0;
+            rv[u] = ok ? rho[s0 + (int64_t)kStatT * u] : 0.0;
+            xv[u] = pos[3 * i];
+            yv[u] = pos[3 * i + 1];
+            zv[u] = pos[3 * i + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < kStatB; ++u) {
+            if ((uint64_t)iv[u] >= (uint64_t)n) continue;
+            const double r = rv[u];
+            const double dx = xv[u] - xd, dy = yv[u] - yd, dz = zv[u] - zd;
+            const double dd = dx * dx + dy * dy + dz * dz;
+            s2 += r * r;
+            s2d += r * r * dd;
+        }
     }
     s2 = block_sum(s2, red);
     s2d = block_sum(s2d, red);
@@ -268,23 +307,32 @@ __global__ __launch_bounds__(kStatT) void k_core_stats(int64_t n, int64_t ns, co
     }
 }
 
-// distance keys about x_d for the half-mass radius, and the core count
+// distance keys about x_d for the half-mass radius, and the core count (one
+// device atomic per workgroup: atomics on one address serialise)
+constexpr int kDistGrid = 1024;
+
 __global__ __launch_bounds__(256) void k_core_dist(int64_t n, const double* __restrict__ pos,
                                                    const double* __restrict__ st,
                                                    uint64_t* __restrict__ key,
                                                    unsigned long long* __restrict__ ncore) {
 #pragma clang fp contract(off)
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool in = false;
-    if (i < n) {
-        const double dx = pos[3 * i] - st[0], dy = pos[3 * i + 1] - st[1], dz = pos[3 * i + 2] - st[2];
+    __shared__ unsigned long long s_cnt[4];
+    const double xd = st[0], yd = st[1], zd = st[2], rc = st[4];
+    unsigned long long cnt = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double dx = pos[3 * i] - xd, dy = pos[3 * i + 1] - yd, dz = pos[3 * i + 2] - zd;
         const double dd = dx * dx + dy * dy + dz * dz;
-        const double rc = st[4];
-        in = dd < rc * rc;
+        cnt += dd < rc * rc ? 1ull : 0ull;
         key[i] = (uint64_t)__double_as_longlong(dd);   // dd >= 0: bit order is numeric order
     }
-    const uint64_t b = __ballot(in);
-    if (b) atomicAdd(ncore, (threadIdx.x & 63) == 0 ? (unsigned long long)__popcll(b) : 0ull);
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) s_cnt[w] = cnt;
+    __syncthreads();
+    if (w == 0) {   // all lanes of wave 0 take part; lane 0 adds the workgroup's count
+        const unsigned long long tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        if (tot) atomicAdd(ncore, lane == 0 ? tot : 0ull);
+    }
 }
 
 // masses in distance order, summed per block of kCrossBlk (fixed order)
@@ -306,30 +354,73 @@ __global__ __launch_bounds__(kCrossBlk) void k_core_bsum(int64_t n, const int32_
 
 // Half-mass radius (first distance at which the running mass reaches half the
 // total, scanning blocks then one block in order) and the regularisation
-// parameters. One thread: the scans are short (n / 1024 blocks, then <= 1024).
-__global__ void k_core_final(int64_t n, int64_t nblk, const int32_t* __restrict__ order,
-                             const uint64_t* __restrict__ key, const double* __restrict__ mass,
-                             const double* __restrict__ bsum, const unsigned long long* ncore,
-                             double eta, double* __restrict__ st) {
+// parameters. The scans are serial (thread 0, in order) over values that the
+// workgroup first stages in LDS, kCrossBlk at a time.
+__global__ __launch_bounds__(kCrossBlk) void k_core_final(int64_t n, int64_t nblk, const int32_t* __restrict__ order,
+                                                          const uint64_t* __restrict__ key,
+                                                          const double* __restrict__ mass,
+                                                          const double* __restrict__ bsum,
+                                                          const unsigned long long* ncore, double eta,
+                                                          double* __restrict__ st) {
 #pragma clang fp contract(off)
-    double mtot = 0.0;
-    for (int64_t b = 0; b < nblk; ++b) mtot += bsum[b];
-    const double half = 0.5 * mtot;
-    double cum = 0.0;
-    int64_t b = 0;
-    while (b < nblk - 1 && cum + bsum[b] < half) cum += bsum[b++];
-    int64_t kk = b * kCrossBlk;
-    const int64_t end = (b + 1) * kCrossBlk < n ? (b + 1) * kCrossBlk : n;
-    for (; kk < end - 1; ++kk) {
-        cum += mass[order[kk]];
-        if (cum >= half) break;
+    __shared__ double v[kCrossBlk];
+    __shared__ double s_tot, s_acc;
+    __shared__ int64_t s_b;
+    __shared__ int s_found;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        s_tot = 0.0;
+        s_acc = 0.0;   // running mass of whole blocks before s_b
+        s_b = 0;
+        s_found = 0;
     }
-    const double rh = sqrt(__longlong_as_double((long long)key[kk]));
-    const double rmin = 4.0 * rh / ((double)n * cbrt(st[3]));
-    st[5] = (double)*ncore;
-    st[6] = rh;
-    st[7] = rmin;
-    st[8] = 0.01 * sqrt(eta / 0.02) * sqrt(rmin * rmin * rmin);
+    for (int64_t c0 = 0; c0 < nblk; c0 += kCrossBlk) {   // total mass
+        __syncthreads();
+        v[t] = c0 + t < nblk ? bsum[c0 + t] : 0.0;
+        __syncthreads();
+        if (t == 0) {
+            double m = s_tot;
+            const int64_t e = nblk - c0 < kCrossBlk ? nblk - c0 : kCrossBlk;
+            for (int64_t k = 0; k < e; ++k) m += v[k];
+            s_tot = m;
+        }
+    }
+    __syncthreads();
+    const double half = 0.5 * s_tot;
+    for (int64_t c0 = 0; c0 < nblk; c0 += kCrossBlk) {   // block holding the half-mass point
+        __syncthreads();
+        if (s_found) break;   // workgroup-uniform
+        v[t] = c0 + t < nblk ? bsum[c0 + t] : 0.0;
+        __syncthreads();
+        if (t == 0) {
+            double cum = s_acc;
+            int64_t b = c0;
+            const int64_t e = c0 + kCrossBlk < nblk ? c0 + kCrossBlk : nblk;
+            while (b < nblk - 1 && b < e && cum + v[b - c0] < half) cum += v[(b++) - c0];
+            s_acc = cum;
+            s_b = b;
+            s_found = b < e;   // stopped inside this chunk (or at the last block)
+        }
+    }
+    __syncthreads();
+    const int64_t b = s_b;
+    const int64_t beg = b * kCrossBlk, end = (b + 1) * kCrossBlk < n ? (b + 1) * kCrossBlk : n;
+    v[t] = beg + t < end ? mass[order[beg + t]] : 0.0;
+    __syncthreads();
+    if (t == 0) {
+        double cum = s_acc;
+        int64_t kk = beg;
+        for (; kk < end - 1; ++kk) {
+            cum += v[kk - beg];
+            if (cum >= half) break;
+        }
+        const double rh = sqrt(__longlong_as_double((long long)key[kk]));
+        const double rmin = 4.0 * rh / ((double)n * cbrt(st[3]));
+        st[5] = (double)*ncore;
+        st[6] = rh;
+        st[7] = rmin;
+        st[8] = 0.01 * sqrt(eta / 0.02) * sqrt(rmin * rmin * rmin);
+    }
 }
 
 }  // namespace
@@ -351,13 +442,14 @@ void launch_core(const CoreLaunch& c, hipStream_t s) {
     hipLaunchKernelGGL(k_core_knn, dim3((unsigned)c.ns), dim3(64), 0, s, p);
     hipLaunchKernelGGL(k_core_stats, dim3(1), dim3(kStatT), 0, s, n, c.ns, c.sample, c.pos, (const double*)c.rho,
                        c.stats);
-    hipLaunchKernelGGL(k_core_dist, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, c.pos,
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_core_dist, dim3((unsigned)(nb < kDistGrid ? nb : kDistGrid)), dim3(256), 0, s, n, c.pos,
                        (const double*)c.stats, c.keys, c.ncore);
     radix_sort_pairs(c.keys, c.vals, c.keys_alt, c.vals_alt, n, 64, c.hist, c.scan_tmp, s, true);
     const int64_t nblk = (n + kCrossBlk - 1) / kCrossBlk;
     hipLaunchKernelGGL(k_core_bsum, dim3((unsigned)nblk), dim3(kCrossBlk), 0, s, n, (const int32_t*)c.vals,
                        c.mass, c.bsum);
-    hipLaunchKernelGGL(k_core_final, dim3(1), dim3(1), 0, s, n, nblk, (const int32_t*)c.vals,
+    hipLaunchKernelGGL(k_core_final, dim3(1), dim3(kCrossBlk), 0, s, n, nblk, (const int32_t*)c.vals,
                        (const uint64_t*)c.keys, c.mass, (const double*)c.bsum,
                        (const unsigned long long*)c.ncore, c.eta, c.stats);
 }
