@@ -427,6 +427,17 @@ def bench_core(p, inp, dev, with_oracle, calls=5):
     return out
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(inp, theta, prm, acc, pot):
     """CPU oracle on the same workload: tree walk over all particles (timed; for
     the ensemble each cluster in turn), plus FP64 direct sums on 512 sampled
@@ -450,7 +461,24 @@ def cpu_baseline(inp, theta, prm, acc, pot):
     base = {"value": inter / dt, "unit": "interactions/s", "cores": oracle.num_threads(),
             "kind": "oracle", "seconds": dt,
             "sample": f"full workload ({inp['n']} particles, {nc} cluster(s)) through the CPU FP64 "
-                      f"tree walk (tree build + walk), {oracle.num_threads()} OpenMP threads"}
+                      f"tree walk (tree build + walk), {oracle.num_threads()} OpenMP threads",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+    # the same on one core, for a bounded sample: the first cluster, or the
+    # first 2^17 particles of a single cluster (the walk over that subset)
+    nthreads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        s = slice(offsets[0], min(offsets[1], offsets[0] + (1 << 17)))
+        t = time.perf_counter()
+        _, _, st = oracle.tree(pos[s], mass[s], r_in[0], r_out[0], theta, inp["eps"],
+                               n_leaf=prm["leaf_size"], n_crit=prm["n_crit"])
+        d1 = time.perf_counter() - t
+    finally:
+        oracle.set_num_threads(nthreads)
+    base["one_core"] = {"value": (st["pn"] + st["pp_far"] + st["pp_near"]) / d1, "unit": "interactions/s",
+                        "seconds": d1, "particles": s.stop - s.start,
+                        "sample": "the first min(N, 2^17) particles of the first cluster as a system of "
+                                  "their own, CPU FP64 tree walk on 1 thread"}
     rng = np.random.default_rng(12345)
     ea, ep = [], []
     per = max(1, 512 // nc)

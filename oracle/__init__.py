@@ -68,6 +68,7 @@ def lib():
         L.orc_group_limit.restype = _d
         L.orc_group_limit.argtypes = [_i64, _p, _p, C.c_int, C.c_int, C.c_int]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -301,3 +302,8 @@ def group_limit(pos, mass, n_leaf=16, n_crit=64, D=21) -> float:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of later calls (timing only; results do not depend on it)."""
+    lib().orc_set_num_threads(int(n))

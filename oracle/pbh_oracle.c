@@ -1397,3 +1397,14 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count of the later parallel loops (timing on fewer cores); no effect
+ * on any result, since every parallel loop writes per-index outputs. */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

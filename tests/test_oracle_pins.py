@@ -799,3 +799,23 @@ def test_paper_parameter_rule():
     assert p["dt_reg"] == 2.0**-9 and p["dt_max"] == 2.0**-11
     p = ic.paper_radii(1 << 22)
     assert p["dt_reg"] == 2.0**-10
+
+
+def test_oracle_thread_count_does_not_change_results():
+    # every parallel loop of the oracle writes per-index outputs: one thread
+    # and all threads give the same bits (the one-core timing relies on it)
+    c = ic.plummer(3000, seed=71, masses="kroupa")
+    r_out = ic.r_out_for_nbar(c.n, 16.0)
+    n0 = oracle.num_threads()
+    outs = []
+    for th in (n0, 1):
+        oracle.set_num_threads(th)
+        try:
+            a, p, st = oracle.tree(c.pos, c.mass, 0.1 * r_out, r_out, 0.5, 1e-4, n_leaf=8, n_crit=32)
+            d, dp = oracle.direct(c.pos, c.mass, 0.1 * r_out, r_out, 1e-4)
+        finally:
+            oracle.set_num_threads(n0)
+        outs.append((a, p, d, dp, st))
+    for x, y in zip(outs[0][:4], outs[1][:4]):
+        assert np.array_equal(x, y)
+    assert outs[0][4] == outs[1][4]
