@@ -476,7 +476,7 @@ def cpu_baseline(inp, theta, prm, acc, pot):
     finally:
         oracle.set_num_threads(nthreads)
     base["one_core"] = {"value": (st["pn"] + st["pp_far"] + st["pp_near"]) / d1, "unit": "interactions/s",
-                        "seconds": d1, "particles": s.stop - s.start,
+                        "seconds": d1, "particles": int(s.stop - s.start),
                         "sample": "the first min(N, 2^17) particles of the first cluster as a system of "
                                   "their own, CPU FP64 tree walk on 1 thread"}
     rng = np.random.default_rng(12345)
