@@ -289,7 +289,11 @@ pbh_status pbh_core(pbh_ctx* ctx, const double* pos, const double* mass, int64_t
  *                (pbh_force_buffered with a large enough r_buff)
  *   stats        host int64[3] out or NULL: block steps, particle steps, the
  *                deepest level k
- * Waits for the stream once per block step (to know when the step ends).
+ * Block steps run in batches of 16 (one captured graph each); the host reads a
+ * done flag once per batch while the next batch runs, and the call returns
+ * after the stream has finished. The context keeps about 0.4 KB of device
+ * state per particle (one bucket per level, 41 x 4 B, is most of it) until it
+ * is destroyed; an allocation failure returns PBH_E_OOM.
  */
 pbh_status pbh_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
                        const double* fr, double r_in, double r_out, double eps,
