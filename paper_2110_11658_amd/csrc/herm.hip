@@ -58,8 +58,9 @@ __device__ inline double norm3(double x, double y, double z) {
 // reads only what earlier launches wrote.
 //
 // Blocks are enqueued in batches without waiting; once every particle has
-// reached the end of the regular step the remaining blocks of a batch are
-// empty (kHermDone), so the host waits once per batch.
+// reached the end of the regular step the remaining blocks are empty
+// (kHermDone), and the front that finds it also sets a host-visible flag,
+// which the host reads after a batch while the next one runs.
 constexpr int kHermGrid = 1024;   // grid-stride launches
 constexpr int kHermLanes = 8;     // lanes per active particle in the prediction
 constexpr int kHermAllFrac = 8;   // predict all particles when n_active >= n / 8
