@@ -220,10 +220,11 @@ __global__ __launch_bounds__(256) void k_herm_front(HermParams p, int q) {
 // workgroup ranks its items per level in LDS, reserves room in each bucket
 // with one device atomic per level (buckets >= ks restart from zero, bucket
 // ks - 1 keeps its members), then stores the particles there. Same-address
-// device atomics serialise, so one per workgroup and level, not per wave.
+// device atomics serialise, so one per workgroup and level, not per wave; a
+// workgroup that holds every item stores its counts without atomics.
 template <class Step>
 __device__ inline void step_and_bucket(const HermParams& p, int q, int ks, int64_t n_items,
-                                       const int32_t* list, Step step) {
+                                       const int32_t* list, int32_t first, Step step) {
     __shared__ int s_h[64];
     __shared__ long long s_b[64];
     const int64_t per = ((n_items + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
@@ -231,20 +232,37 @@ __device__ inline void step_and_bucket(const HermParams& p, int q, int ks, int64
     if (c0 >= c1) return;   // workgroup-uniform
     if (threadIdx.x < 64) s_h[threadIdx.x] = 0;
     __syncthreads();
+    // a thread's first item stays in registers; later ones go through p.slot
+    int lv0 = -1, r0 = 0;
+    int32_t i0 = 0;
     for (int64_t k = c0 + threadIdx.x; k < c1; k += 256) {
-        const int32_t i = list ? list[k] : (int32_t)k;
+        const bool head = k == c0 + threadIdx.x;
+        // (workgroup 0's first items are k = threadIdx.x: `first` holds list[k])
+        const int32_t i = list ? (head && c0 == 0 ? first : list[k]) : (int32_t)k;
         const int level = step(k, i);
         const int r = atomicAdd(&s_h[level], 1);
-        p.slot[k] = ((uint32_t)level << kSlotShift) | (uint32_t)r;
+        if (head) {
+            lv0 = level;
+            r0 = r;
+            i0 = i;
+        } else {
+            p.slot[k] = ((uint32_t)level << kSlotShift) | (uint32_t)r;
+        }
     }
     __syncthreads();
     if (threadIdx.x <= kHermK && s_h[threadIdx.x] > 0) {
         const int k = threadIdx.x;
         const long long keep = k == ks - 1 ? (long long)lev_cnt(p, q)[k] : 0;
-        s_b[k] = keep + (long long)atomicAdd(lev_new(p, q) + k, (unsigned long long)s_h[k]);
+        if (c0 == 0 && c1 == n_items) {   // the only workgroup with items: no other appends
+            s_b[k] = keep;
+            lev_new(p, q)[k] = (unsigned long long)s_h[k];
+        } else {
+            s_b[k] = keep + (long long)atomicAdd(lev_new(p, q) + k, (unsigned long long)s_h[k]);
+        }
     }
     __syncthreads();
-    for (int64_t k = c0 + threadIdx.x; k < c1; k += 256) {   // the same items per thread
+    if (lv0 >= 0) p.bucket[(int64_t)lv0 * p.n + s_b[lv0] + r0] = i0;
+    for (int64_t k = c0 + threadIdx.x + 256; k < c1; k += 256) {   // the same later items per thread
         const uint32_t v = p.slot[k];
         const int level = (int)(v >> kSlotShift);
         const int32_t i = list ? list[k] : (int32_t)k;
@@ -271,7 +289,7 @@ __device__ inline int step_level(int64_t t) { return kHermK - (63 - __clzll((uns
 
 __global__ __launch_bounds__(256) void k_herm_start(HermParams p) {
     // slot 0, every level refilled (ks = 0)
-    step_and_bucket(p, 0, 0, p.n, nullptr, [&](int64_t, int32_t i) {
+    step_and_bucket(p, 0, 0, p.n, nullptr, 0, [&](int64_t, int32_t i) {
 #pragma clang fp contract(off)
         double at[3];
         for (int k = 0; k < 3; ++k) at[k] = p.a[3 * (int64_t)i + k] + (p.fr ? p.fr[3 * (int64_t)i + k] : 0.0);
@@ -337,10 +355,13 @@ __device__ inline int force_correct(const HermParams& p, const IrrParams& ip, in
 }
 
 __global__ __launch_bounds__(256) void k_herm_force_correct(HermParams p, IrrParams ip, int q) {
+    // workgroup 0's first active entries, read alongside the block's counts
+    // (act has n entries; an entry past n_active is never used)
+    const int32_t first = blockIdx.x == 0 && (int64_t)threadIdx.x < p.n ? p.act[threadIdx.x] : 0;
     const int64_t nact = (int64_t)p.ctl[kHermNact];
     const int ks = (int)p.lev[kLevKs + (q ^ 1)];
     const int64_t tn = (int64_t)p.ctl[kHermTn];
-    step_and_bucket(p, q ^ 1, ks, nact, p.act,
+    step_and_bucket(p, q ^ 1, ks, nact, p.act, first,
                     [&](int64_t, int32_t i) { return force_correct(p, ip, i, tn); });
 }
 
