@@ -96,9 +96,8 @@ __global__ __launch_bounds__(256) void k_irregular(IrrParams p) {
         if (k < p.n_tgt) irr_target<JERK, POT, SORTED, MULTI>(p, k, g);   // group-uniform
         return;
     }
-    // caller-array route: grid-stride, the count possibly held on the device
-    int64_t nt = p.n_tgt;
-    if (p.n_tgt_dev && (int64_t)*p.n_tgt_dev < nt) nt = (int64_t)*p.n_tgt_dev;
+    // caller-array route: grid-stride
+    const int64_t nt = p.n_tgt;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nt * kIrrLanes;
          v += (int64_t)gridDim.x * blockDim.x)
         irr_target<JERK, POT, SORTED, MULTI>(p, v / kIrrLanes, g);
@@ -108,12 +107,15 @@ template <bool JERK, bool POT, bool MULTI>
 void launch_route(const IrrParams& p, hipStream_t s) {
     const int64_t nb = (p.n_tgt * kIrrLanes + 255) / 256;
     const dim3 block(256);
-    if (p.rec) {   // grid padded to whole rounds of chunks over the XCDs
+    // the key-order route has one work-item per (target, lane): it needs a grid
+    // below 2^31 work-items; the caller-array route is grid-stride (same sums)
+    const bool fits = p.n_tgt <= ((int64_t)1 << 31) / kIrrLanes - (int64_t)kQueues * kIrrChunk * 256;
+    if (p.rec && fits) {   // grid padded to whole rounds of chunks over the XCDs
         const int64_t round = (int64_t)kQueues * kIrrChunk;
         const dim3 grid((unsigned)((nb + round - 1) / round * round));
         hipLaunchKernelGGL((k_irregular<JERK, POT, true, MULTI>), grid, block, 0, s, p);
-    } else {   // grid-stride: a count held on the device may be far below n_tgt
-        const int64_t g = p.n_tgt_dev ? (nb < 4096 ? nb : 4096) : nb;
+    } else {
+        const int64_t g = nb < (1 << 16) ? nb : (1 << 16);
         hipLaunchKernelGGL((k_irregular<JERK, POT, false, MULTI>), dim3((unsigned)g), block, 0, s, p);
     }
 }

@@ -251,8 +251,7 @@ enum : unsigned long long {
 };
 struct IrrParams {
     int64_t n = 0;              // particles (caller order)
-    int64_t n_tgt = 0;          // targets of this launch (an upper bound if n_tgt_dev is set)
-    const unsigned long long* n_tgt_dev = nullptr;   // target count held on the device, or null
+    int64_t n_tgt = 0;          // targets of this launch
     const int32_t* tgt = nullptr;    // target caller indices (outputs compact), or null = all
     const int32_t* order = nullptr;  // processing order of all targets (key order), or null
     // key-order records: perm [n] (key position -> caller index), rank [n]
