@@ -238,44 +238,50 @@ __device__ inline int64_t run_start(const uint64_t* keys, int64_t i, int64_t cs,
     return hi;
 }
 
+// One thread per node (pre-order index v): its first particle i is the last
+// with p_base[i] <= v (binary search), and it is i's (v - p_base[i])-th node
+// from level p_first[i] down. (A particle that starts nodes on many levels --
+// the first of a cluster starts one on every level -- would otherwise search
+// the runs of all of them in turn.)
 __global__ void k_topo_emit(const uint64_t* __restrict__ keys, const int64_t* __restrict__ cl_off,
                             int64_t n, int D, int n_leaf, const int32_t* __restrict__ p_first,
                             const int32_t* __restrict__ p_base, int64_t cap,
                             int32_t* __restrict__ pre_begin, int32_t* __restrict__ pre_count,
                             int32_t* __restrict__ pre_level, int32_t* __restrict__ pre_nchild,
                             uint64_t* __restrict__ lvl_key, unsigned long long* __restrict__ cnt) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int nn = p_base[i + 1] - p_base[i];
-        if (nn == 0) continue;
+    const int64_t total = p_base[n];
+    if (total > cap && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&cnt[kErr], kErrNodeCap);
+    const int64_t m = total < cap ? total : cap;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < m;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = n;   // p_base[lo] <= v < p_base[hi]
+        while (hi - lo > 1) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if ((int64_t)p_base[mid] <= v) lo = mid;
+            else hi = mid;
+        }
+        const int64_t i = lo;
+        const int k = (int)(v - p_base[i]);
         const uint64_t key = keys[i];
         const int c = cluster_of(key, D);
         const int64_t cs = cl_off[c], ce = cl_off[c + 1];
-        const int lf = p_first[i];
-        for (int k = 0; k < nn; ++k) {
-            const int l = lf + k;
-            const int64_t node = (int64_t)p_base[i] + k;
-            if (node >= cap) {
-                atomicOr(&cnt[kErr], kErrNodeCap);
-                break;
+        const int l = p_first[i] + k;
+        const int64_t e = run_end(keys, i, ce, l, D);
+        pre_begin[v] = (int32_t)i;
+        pre_count[v] = (int32_t)(e - i);
+        pre_level[v] = l;
+        lvl_key[v] = (uint64_t)l;
+        // register with the parent: its node index is known from the particle
+        // that starts it (i itself for k > 0)
+        if (l > 0) {
+            int64_t parent;
+            if (k > 0) {
+                parent = v - 1;
+            } else {
+                const int64_t s = run_start(keys, i, cs, l - 1, D);
+                parent = (int64_t)p_base[s] + (l - 1 - p_first[s]);
             }
-            const int64_t e = run_end(keys, i, ce, l, D);
-            pre_begin[node] = (int32_t)i;
-            pre_count[node] = (int32_t)(e - i);
-            pre_level[node] = l;
-            lvl_key[node] = (uint64_t)l;
-            // register with the parent: its node index is known from the particle
-            // that starts it (i itself for k > 0)
-            if (l > 0) {
-                int64_t parent;
-                if (k > 0) {
-                    parent = node - 1;
-                } else {
-                    const int64_t s = run_start(keys, i, cs, l - 1, D);
-                    parent = (int64_t)p_base[s] + (l - 1 - p_first[s]);
-                }
-                if (parent < cap) atomicAdd(&pre_nchild[parent], 1);
-            }
+            if (parent < cap) atomicAdd(&pre_nchild[parent], 1);
         }
     }
 }
