@@ -62,7 +62,7 @@ __device__ inline double norm3(double x, double y, double z) {
 // (kHermDone), and the front that finds it also sets a host-visible flag,
 // which the host reads after a batch while the next one runs.
 constexpr int kHermGrid = 1024;   // grid-stride launches
-constexpr int kHermLanes = 8;     // lanes per active particle in the prediction
+constexpr int kHermLanes = 32;    // lanes per active particle in the prediction (the particle and its list)
 constexpr int kHermAllFrac = 8;   // predict all particles when n_active >= n / 8
 constexpr int kSlotShift = 26;    // per-item scratch: level << 26 | rank in its workgroup
 constexpr uint32_t kSlotMask = (1u << kSlotShift) - 1;
