@@ -52,7 +52,8 @@ def lib():
         L.orc_full_direct.argtypes = [_i64, _p, _p, _d, _p, _p]
         L.orc_irregular.argtypes = [_i64, _p, _p, _p, _d, _d, _d, _i64, _p, _p, _p, _p, _p]
         L.orc_core.argtypes = [_i64, _p, _p, _i64, _p, _d, _p, _p]
-        L.orc_hermite.argtypes = [_i64, _p, _p, _p, _p, _d, _d, _d, _d, _d, _p]
+        L.orc_irr_derivs.argtypes = [_i64, _p, _p, _p, _p, _p, _d, _d, _d, _i64, _p, _p, _p]
+        L.orc_hermite.argtypes = [_i64, _p, _p, _p, _p, _d, _d, _d, _d, _d, _p, _p]
         L.orc_p3t.argtypes = [_i64, _p, _p, _p, _d, _d, _d, _d, _d, C.c_int, _p]
         L.orc_knn6.argtypes = [_i64, _p, _i64, _p, _p, _p]
         L.orc_nbr_brute.restype = _i64
@@ -192,18 +193,52 @@ def knn6(pos, sample):
     return d2, idx
 
 
-def hermite(pos, vel, mass, r_in, r_out, eps, T, eta=0.02, fr=None):
+def irr_derivs(pos, vel, acc, jrk, mass, r_in, r_out, eps, targets=None):
+    """Second and third time derivatives of F_I (eq. fi) along the motion on
+    which every particle has position pos, velocity vel, acceleration acc and
+    its derivative jrk (all [n,3]); sums over every j != i with s < r_out.
+    Returns (f2 [n_t,3], f3 [n_t,3])."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    vel = _f64(vel, (n, 3))
+    acc = _f64(acc, (n, 3))
+    jrk = _f64(jrk, (n, 3))
+    mass = _f64(mass, (n,))
+    if targets is None:
+        nt, tgt = n, None
+    else:
+        tgt = np.ascontiguousarray(targets, dtype=np.int64)
+        nt = tgt.size
+    f2 = np.zeros((nt, 3))
+    f3 = np.zeros((nt, 3))
+    lib().orc_irr_derivs(n, _ptr(pos), _ptr(vel), _ptr(acc), _ptr(jrk), _ptr(mass), float(r_in),
+                         float(r_out), float(eps), nt, None if tgt is None else _ptr(tgt), _ptr(f2),
+                         _ptr(f3))
+    return f2, f3
+
+
+def hermite(pos, vel, mass, r_in, r_out, eps, T, eta=0.02, fr=None, want=False):
     """Hermite integration of F_I with block time steps over one regular step
-    T (Section 2.2). Returns (x, v, stats) with stats = dict(blocks, steps, kmax)."""
+    T (Section 2.2). Returns (x, v, stats) with stats = dict(blocks, steps, kmax).
+    With want=True stats also holds, per particle, the step eq. dt asked for at
+    the start ("want_start"), at the last corrector step ("want_last", before
+    the doubling cap and block rounding), that last step's length ("d_last")
+    and the length of the step before it ("d_prev", 0 if none this call)."""
     x = _f64(pos).copy()
     n = x.shape[0]
     v = _f64(vel, (n, 3)).copy()
     mass = _f64(mass, (n,))
     f = None if fr is None else _f64(fr, (n, 3))
     st = np.zeros(3, dtype=np.int64)
+    w = np.zeros(4 * n) if want else None
     lib().orc_hermite(n, _ptr(x), _ptr(v), _ptr(mass), None if f is None else _ptr(f), float(r_in),
-                      float(r_out), float(eps), float(T), float(eta), _ptr(st))
-    return x, v, {"blocks": int(st[0]), "steps": int(st[1]), "kmax": int(st[2])}
+                      float(r_out), float(eps), float(T), float(eta), _ptr(st),
+                      None if w is None else _ptr(w))
+    out = {"blocks": int(st[0]), "steps": int(st[1]), "kmax": int(st[2])}
+    if want:
+        out.update(want_start=w[:n].copy(), want_last=w[n:2 * n].copy(), d_last=w[2 * n:3 * n].copy(),
+                   d_prev=w[3 * n:].copy())
+    return x, v, out
 
 
 def p3t(pos, vel, mass, r_in, r_out, eps, T, eta=0.02, steps=1):

@@ -30,6 +30,7 @@
  *                             derivative and the irregular potential
  *   orc_core                  core quantities from the 6 nearest neighbours
  *                             of a particle sample, by brute force
+ *   orc_irr_derivs            its second and third time derivatives
  *   orc_hermite, orc_p3t      Hermite integration of F_I with block time
  *                             steps over one regular step, and the P3T loop
  *   orc_nbr_brute/orc_nbr_cells neighbour sets, brute force and cell list
@@ -332,6 +333,104 @@ void orc_irregular(int64_t n, const double* pos, const double* vel, const double
 }
 
 /* ------------------------------------------------------------------------ */
+/* Second and third time derivatives of the irregular force                  */
+/* (Section 2.1: the text after eq. dt -- the higher derivatives are         */
+/* computed, so that the fourth-order criterion eq. dt sets the first step)  */
+/*                                                                            */
+/* Along a motion on which every particle has position x, velocity v,        */
+/* acceleration acc and its time derivative jrk, each pair term of eq. fi is */
+/* m_j h(s) d with h(s) = K(s) / s^3, d = x_j - x_i, d' = u = v_j - v_i,      */
+/* d'' = w = acc_j - acc_i, d''' = z = jrk_j - jrk_i. With                    */
+/*   s' = d.u / s,  s'' = (u.u + d.w - s'^2) / s,                            */
+/*   s''' = (3 u.w + d.z - 3 s' s'') / s,                                    */
+/* and h_s, h_ss, h_sss the derivatives of K s^-3 with respect to s,          */
+/*   h'   = h_s s',   h'' = h_ss s'^2 + h_s s'',                             */
+/*   h''' = h_sss s'^3 + 3 h_ss s' s'' + h_s s''',                            */
+/*   F^(2) = sum m_j (h'' d + 2 h' u + h w),                                  */
+/*   F^(3) = sum m_j (h''' d + 3 h'' u + 3 h' w + h z).                       */
+/* In the band, with x = (s - r_in)/D: dK/ds = -g'(x)/D,                      */
+/* d2K/ds2 = -g''(x)/D^2, d3K/ds3 = -g'''(x)/D^3, g' = 140 x^3 (1-x)^3,       */
+/* g'' = 420 x^2 (1-x)^2 (1-2x), g''' = 840 x (1-x) (1 - 5x + 5x^2); all      */
+/* three vanish at x = 0 and x = 1, so K is three times continuously          */
+/* differentiable across both radii. Off the band K is constant.              */
+/* ------------------------------------------------------------------------ */
+
+/* K(s) and its first three derivatives with respect to s, Kd[0..3]. */
+static void k_derivs(const phir_t* p, double s, double Kd[4])
+{
+    Kd[1] = Kd[2] = Kd[3] = 0.0;
+    if (p->mode == 0 || s >= p->r_out) { Kd[0] = 0.0; return; }
+    if (p->mode == 1 || s < p->r_in) { Kd[0] = 1.0; return; }
+    double x = (s - p->r_in) / p->D;
+    double omx = 1.0 - x;
+    Kd[0] = 1.0 - g_poly(x);
+    Kd[1] = -140.0 * x * x * x * omx * omx * omx / p->D;
+    Kd[2] = -420.0 * x * x * omx * omx * (1.0 - 2.0 * x) / (p->D * p->D);
+    Kd[3] = -840.0 * x * omx * (1.0 - 5.0 * x + 5.0 * x * x) / (p->D * p->D * p->D);
+}
+
+/* F^(2), F^(3) at particle i from every j != i with s < r_out */
+static void irr_d23_at(const phir_t* p, double eps2, int64_t n, const double* xs, const double* vs,
+                       const double* as, const double* js, const double* mass, int64_t i,
+                       double* f2, double* f3)
+{
+    for (int k = 0; k < 3; ++k) f2[k] = f3[k] = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        double d[3], u[3], w[3], z[3];
+        for (int k = 0; k < 3; ++k) {
+            d[k] = xs[3 * j + k] - xs[3 * i + k];
+            u[k] = vs[3 * j + k] - vs[3 * i + k];
+            w[k] = as[3 * j + k] - as[3 * i + k];
+            z[k] = js[3 * j + k] - js[3 * i + k];
+        }
+        double s2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
+        double s = sqrt(s2);
+        if (p->mode == 0 || s >= p->r_out) continue;
+        double Kd[4];
+        k_derivs(p, s, Kd);
+        double du = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+        double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        double dw = d[0] * w[0] + d[1] * w[1] + d[2] * w[2];
+        double uw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+        double dz = d[0] * z[0] + d[1] * z[1] + d[2] * z[2];
+        double sd1 = du / s;
+        double sd2 = (uu + dw - sd1 * sd1) / s;
+        double sd3 = (3.0 * uw + dz - 3.0 * sd1 * sd2) / s;
+        double s3 = s2 * s, s4 = s2 * s2, s5 = s4 * s, s6 = s4 * s2;
+        double h = Kd[0] / s3;
+        double hs = Kd[1] / s3 - 3.0 * Kd[0] / s4;
+        double hss = Kd[2] / s3 - 6.0 * Kd[1] / s4 + 12.0 * Kd[0] / s5;
+        double hsss = Kd[3] / s3 - 9.0 * Kd[2] / s4 + 36.0 * Kd[1] / s5 - 60.0 * Kd[0] / s6;
+        double h1 = hs * sd1;
+        double h2 = hss * sd1 * sd1 + hs * sd2;
+        double h3 = hsss * sd1 * sd1 * sd1 + 3.0 * hss * sd1 * sd2 + hs * sd3;
+        for (int k = 0; k < 3; ++k) {
+            f2[k] += mass[j] * (h2 * d[k] + 2.0 * h1 * u[k] + h * w[k]);
+            f3[k] += mass[j] * (h3 * d[k] + 3.0 * h2 * u[k] + 3.0 * h1 * w[k] + h * z[k]);
+        }
+    }
+}
+
+/*
+ * F^(2), F^(3) of F_I [n_t][3] for all particles or the n_tgt listed targets,
+ * along the motion given by pos, vel, acc, jrk [n][3].
+ */
+void orc_irr_derivs(int64_t n, const double* pos, const double* vel, const double* acc,
+                    const double* jrk, const double* mass, double r_in, double r_out, double eps,
+                    int64_t n_tgt, const int64_t* tgt, double* f2, double* f3)
+{
+    phir_t p;
+    phir_init(&p, r_in, r_out);
+    int64_t nt = tgt ? n_tgt : n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t i = tgt ? tgt[t] : t;
+        irr_d23_at(&p, eps * eps, n, pos, vel, acc, jrk, mass, i, f2 + 3 * t, f3 + 3 * t);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Core quantities: the sampled core algorithm of Section 3.2 with the       */
 /* density estimator of Casertano & Hut (1985), and the regularisation       */
 /* parameters R_min, dT_min of Section 2.5                                   */
@@ -472,8 +571,12 @@ void orc_knn6(int64_t n, const double* pos, int64_t n_s, const int64_t* sample, 
 /*                                                                            */
 /* Over one regular step of length T every particle carries x, v, a = F_I,    */
 /* j = dF_I/dt, its time tau_i and block step dt_i = dt_max / 2^k.            */
-/*   start: tau = 0, a and j from the state; dt from eta_s |a + F_R| / |j|    */
-/*          (eta_s = 0.01; dt_max when j = 0)                                 */
+/*   start: tau = 0; a and j from the state (after the kick); the second and  */
+/*          third derivatives a^(2), a^(3) of F_I along the motion under F_I  */
+/*          (relative accelerations a_j - a_i and jerks j_j - j_i, computed   */
+/*          by the derivative formulas above); dt from eq. dt with a^(0) =    */
+/*          a + F_R, a^(1) = j, a^(2), a^(3), and dt_max where the           */
+/*          denominator vanishes (an empty list: no irregular force).         */
 /*   block: tau' = min(tau_i + dt_i); the active particles have              */
 /*          tau_i + dt_i = tau'. All particles are predicted to tau' (d =     */
 /*          tau' - tau_i):  x_p = x + d v + d^2/2 a + d^3/6 j,               */
@@ -487,9 +590,11 @@ void orc_knn6(int64_t n, const double* pos, int64_t n_s, const int64_t* sample, 
 /*          a^(2) = a2 + d a3, a^(3) = a3, at most twice the old step and     */
 /*          dt_max, rounded down to dt_max / 2^k and to a divisor of tau'.    */
 /*   until every particle is at tau = T (steps divide T, so they all meet).   */
-/* Reading: eq. dt and the P3T predictor are the paper's; the corrector is   */
-/* the standard 4th-order Hermite one (Makino & Aarseth 1992) and the start   */
-/* step eta_s |a| / |j| the usual one, since the paper defers both to NBODY6. */
+/* Readings: eq. dt, its first-step use with computed derivatives and the    */
+/* P3T predictor are the paper's; steps are set afresh after every regular   */
+/* kick (the new routine that applies the kick also determines new steps);  */
+/* the corrector is the standard 4th-order Hermite one (Makino & Aarseth     */
+/* 1992), which the paper keeps from NBODY6.                                 */
 /* ------------------------------------------------------------------------ */
 
 /* Times are counted in integer ticks of dt_max / 2^HERM_KMAX (a regular step
@@ -540,10 +645,15 @@ static void irr_at(const phir_t* p, double eps2, int64_t n, const double* xs, co
 /*
  * Integrate F_I over one regular step T in place (x, v [n][3]). fr [n][3] is
  * the regular force for the step criterion (may be NULL). stats (optional,
- * int64[3]): block steps, particle steps, smallest k.
+ * int64[3]): block steps, particle steps, smallest k. want_out (optional,
+ * [4n]): per particle the step eq. dt asked for at the start, the one it
+ * asked for at the particle's last corrector step (before the doubling cap
+ * and the rounding to a block step), the length of that last step and of the
+ * step before it (0 when the last step was the first of the regular step).
  */
 void orc_hermite(int64_t n, double* x, double* v, const double* mass, const double* fr,
-                 double r_in, double r_out, double eps, double T, double eta, int64_t* stats)
+                 double r_in, double r_out, double eps, double T, double eta, int64_t* stats,
+                 double* want_out)
 {
     phir_t p;
     phir_init(&p, r_in, r_out);
@@ -562,11 +672,17 @@ void orc_hermite(int64_t n, double* x, double* v, const double* mass, const doub
     int64_t nblock = 0, nsteps = 0, kmin = 0;
 #pragma omp parallel for
     for (int64_t i = 0; i < n; ++i) irr_at(&p, eps2, n, x, v, mass, i, a + 3 * i, jk + 3 * i);
+    /* first steps: eq. dt with a^(2), a^(3) from the derivative formulas
+       (xp, vp hold them here; they are overwritten by the first prediction) */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) irr_d23_at(&p, eps2, n, x, v, a, jk, mass, i, xp + 3 * i, vp + 3 * i);
     for (int64_t i = 0; i < n; ++i) {
         double at[3];
         for (int k = 0; k < 3; ++k) at[k] = a[3 * i + k] + (fr ? fr[3 * i + k] : 0.0);
-        double jn = hnorm(jk + 3 * i);
-        double want = jn > 0.0 ? 0.01 * hnorm(at) / jn : dtmax;
+        double n0 = hnorm(at), n1 = hnorm(jk + 3 * i), n2 = hnorm(xp + 3 * i), n3 = hnorm(vp + 3 * i);
+        double num = n0 * n2 + n1 * n1, den = n1 * n3 + n2 * n2;
+        double want = den > 0.0 ? sqrt(eta * num / den) : dtmax;
+        if (want_out) want_out[i] = want;
         tau[i] = 0;
         dt[i] = block_step(want, dtmax, 0);
     }
@@ -604,6 +720,11 @@ void orc_hermite(int64_t n, double* x, double* v, const double* mass, const doub
             double n0 = hnorm(at), n1 = hnorm(jk + 3 * i), n2 = hnorm(a2e), n3 = hnorm(a3);
             double num = n0 * n2 + n1 * n1, den = n1 * n3 + n2 * n2;
             double want = den > 0.0 ? sqrt(eta * num / den) : dtmax;
+            if (want_out) {
+                want_out[3 * n + i] = tau[i] > 0 ? want_out[2 * n + i] : 0.0;
+                want_out[n + i] = want;
+                want_out[2 * n + i] = d;
+            }
             if (want > 2.0 * d) want = 2.0 * d;
             tau[i] = tn;
             dt[i] = block_step(want, dtmax, tn);
@@ -644,7 +765,7 @@ void orc_p3t(int64_t n, double* x, double* v, const double* mass, double r_in, d
         }
         if (st == steps) break;
         for (int64_t k = 0; k < 3 * n; ++k) v[k] += 0.5 * T * fr[k];
-        orc_hermite(n, x, v, mass, fr, r_in, r_out, eps, T, eta, NULL);
+        orc_hermite(n, x, v, mass, fr, r_in, r_out, eps, T, eta, NULL, NULL);
         orc_direct(n, x, mass, r_in, r_out, eps, n, NULL, fr, pr);
         for (int64_t k = 0; k < 3 * n; ++k) v[k] += 0.5 * T * fr[k];
     }

@@ -421,6 +421,156 @@ def _kepler(e, m1=0.6, m2=0.4):
     return pos, vel, np.array([m1, m2]), 2.0 * math.pi / math.sqrt(M)
 
 
+def _taylor_path(x0, v0, a0, j0, t):
+    """Positions and velocities on the cubic path x0 + v0 t + a0 t^2/2 + j0 t^3/6."""
+    return x0 + v0 * t + a0 * t * t / 2 + j0 * t ** 3 / 6, v0 + a0 * t + j0 * t * t / 2
+
+
+@pytest.mark.parametrize("r_in,r_out,eps,spread", [
+    (0.02, 0.1, 0.0, 1.2),     # pairs inside, across and beyond the band
+    (0.02, 0.1, 0.01, 1.2),    # softened
+    (0.0, 0.1, 0.0, 1.2),      # r_in = 0: the band reaches down to s = 0
+    (0.1, 0.1, 0.0, 0.25),     # step changeover, every pair inside r_out
+])
+def test_irregular_higher_derivatives_are_time_derivatives(r_in, r_out, eps, spread):
+    # Particles move on cubic paths with arbitrary accelerations and jerks.
+    # The jerk of F_I (pinned above by differences of F_I) is evaluated along
+    # the paths; its first and second central differences in time are the
+    # second and third derivatives of F_I, which the derivative formulas must
+    # reproduce (eq. dt needs them as a^(2), a^(3)). A dropped K', K'' or K'''
+    # term, or a wrong factor in the chain rule, fails at O(1).
+    rng = np.random.default_rng(3)
+    n = 40
+    x0 = rng.uniform(-1, 1, (n, 3)) * r_out * spread
+    v0 = rng.normal(size=(n, 3))
+    a0 = rng.normal(size=(n, 3)) * 5
+    j0 = rng.normal(size=(n, 3)) * 20
+    m = rng.uniform(0.5, 1.5, n) / n
+    f2, f3 = oracle.irr_derivs(x0, v0, a0, j0, m, r_in, r_out, eps)
+    h = 1e-4 * r_out
+    J = {}
+    for k in (-2, -1, 0, 1, 2):
+        x, v = _taylor_path(x0, v0, a0, j0, k * h)
+        J[k] = oracle.irregular(x, v, m, r_in, r_out, eps)[1]
+    d2 = (-J[2] + 8 * J[1] - 8 * J[-1] + J[-2]) / (12 * h)
+    d3 = (-J[2] + 16 * J[1] - 30 * J[0] + 16 * J[-1] - J[-2]) / (12 * h * h)
+    assert np.abs(f2).max() > 0 and np.abs(f3).max() > 0
+    # (difference truncation: ~1e-10 and ~1e-8 here, ~1e-7 for the tight clump)
+    assert np.abs(d2 - f2).max() <= 1e-6 * np.abs(f2).max()
+    assert np.abs(d3 - f3).max() <= 1e-6 * np.abs(f3).max()
+    # no pair inside r_out: no derivatives
+    z2, z3 = oracle.irr_derivs(x0 * 1e3, v0, a0, j0, m, r_in, r_out, eps)
+    assert not z2.any() and not z3.any()
+
+
+def _kepler_series(r0, v0, mu, order):
+    """Taylor coefficients c_k of the relative two-body orbit r(t), r'' = -mu r / |r|^3,
+    by series arithmetic (Cauchy products and the power rule for |r|^-3): the
+    exact derivatives r^(k)(0) = k! c_k, with no finite differences."""
+    c = [np.asarray(r0, float), np.asarray(v0, float)]
+    s, q = [], []
+    for k in range(order - 1):
+        s.append(sum(c[j] @ c[k - j] for j in range(k + 1)))
+        if k == 0:
+            q.append(s[0] ** -1.5)
+        else:
+            q.append(sum((-1.5 * j - (k - j)) * s[j] * q[k - j] for j in range(1, k + 1)) / (k * s[0]))
+        c.append(-mu * sum(q[j] * c[k - j] for j in range(k + 1)) / ((k + 1) * (k + 2)))
+    return c
+
+
+def _series_deriv(c, n, t):
+    """n-th derivative at t of the series with coefficients c."""
+    return sum(math.factorial(k) / math.factorial(k - n) * c[k] * t ** (k - n) for k in range(n, len(c)))
+
+
+def _eq_dt(a0, a1, a2, a3, eta):
+    """eq. dt (Section 2.1) from the four derivative vectors, without the dt_max cap."""
+    n0, n1, n2, n3 = (np.linalg.norm(a) for a in (a0, a1, a2, a3))
+    return math.sqrt(eta * (n0 * n2 + n1 * n1) / (n1 * n3 + n2 * n2))
+
+
+def _kepler_at(e, t0, m1=0.6, m2=0.4):
+    """Two bodies (a = 1) a time t0 after pericentre (t0 within the series' reach)."""
+    M = m1 + m2
+    rp = 1.0 - e
+    r, v = np.array([rp, 0.0, 0.0]), np.array([0.0, math.sqrt(M * (1.0 + e) / rp), 0.0])
+    if t0:
+        c = _kepler_series(r, v, M, 30)
+        r, v = _series_deriv(c, 0, t0), _series_deriv(c, 1, t0)
+    pos = np.array([-m2 / M * r, m1 / M * r])
+    vel = np.array([-m2 / M * v, m1 / M * v])
+    return pos, vel, np.array([m1, m2]), 2.0 * math.pi / math.sqrt(M)
+
+
+# Particle 0 feels a = m_1 r / |r|^3 = -(m_1/M) r'', particle 1 the opposite
+# with m_0: the sign and mass factor of each body's derivatives.
+_BODY = ((1, -1.0), (0, 1.0))
+
+
+@pytest.mark.parametrize("e,t0", [(0.0, 0.0), (0.5, 0.0), (0.5, 0.3), (0.8, 0.02)])
+def test_hermite_first_step_is_eq_dt(e, t0):
+    # Section 2.1 (after eq. dt): the first step of a particle comes from the
+    # fourth-order criterion with the higher derivatives computed, and a^(0)
+    # includes the regular force. Two bodies, all of their force irregular
+    # (step changeover beyond the orbit), plus a fixed regular force: the
+    # step asked for equals eq. dt with the exact orbit derivatives.
+    pos, vel, m, P = _kepler_at(e, t0)
+    M = m.sum()
+    fr = np.array([[0.3, -0.2, 0.1], [0.1, 0.4, -0.3]])
+    eta = 0.02
+    _, _, st = oracle.hermite(pos, vel, m, 100.0, 100.0, 0.0, P / 8, eta=eta, fr=fr, want=True)
+    c = _kepler_series(pos[1] - pos[0], vel[1] - vel[0], M, 8)
+    for i, (j, sg) in enumerate(_BODY):
+        der = [sg * m[j] / M * _series_deriv(c, k, 0.0) for k in (2, 3, 4, 5)]
+        der[0] = der[0] + fr[i]
+        assert st["want_start"][i] == pytest.approx(_eq_dt(*der, eta), rel=1e-12)
+    if e == 0.0:   # circular, no regular force: sqrt(eta) / omega exactly
+        _, _, s0 = oracle.hermite(pos, vel, m, 100.0, 100.0, 0.0, P / 8, eta=eta, want=True)
+        assert s0["want_start"] == pytest.approx(math.sqrt(eta) / math.sqrt(M), rel=1e-13)
+
+
+def test_hermite_step_criterion_during_the_step():
+    # After each corrector step the new step is eq. dt with a^(0) = a1 + F_R,
+    # a^(1) = j1 and the corrector's a^(2) at the step's end and a^(3). Against
+    # the exact derivatives at the end of the last step (Taylor series of the
+    # orbit through the final state) the corrector's estimates differ by:
+    # a^(3) is the third derivative at mid-step (Hermite interpolation), and the
+    # forces of a step are taken at the predicted state, whose velocity misses
+    # d^3/6 a^(2): the jerk then errs by (d_k^3/6) m_j T r^(4), the force by
+    # (d_k^4/24) m_j T r^(4) (T = I/r^3 - 3 r r^T/r^5, the tidal tensor), so
+    # a^(3) errs by -m_j T r^(4) [(d^4 - d0^4)/(2 d^3) - (d0^3 + d^3)/d^2] for a
+    # step d after a step d0 (0 after a fresh start), with the sign of r.
+    # With that, the step asked for must agree with eq. dt to O(d^2): the
+    # discrepancy falls four-fold per halved step. Taking a^(2) at the start of
+    # the step, dropping F_R or swapping terms leaves an O(d) or O(1) error.
+    pos, vel, m, P = _kepler_at(0.5, 0.3)
+    M = m.sum()
+    fr = np.array([[0.3, -0.2, 0.1], [0.1, 0.4, -0.3]])
+    worst = []
+    for eta in (0.005, 0.00125, 0.0003125):
+        x, v, st = oracle.hermite(pos, vel, m, 100.0, 100.0, 0.0, P / 16, eta=eta, fr=fr, want=True)
+        r = x[1] - x[0]
+        c = _kepler_series(r, v[1] - v[0], M, 20)
+        rn = np.linalg.norm(r)
+        tid = np.eye(3) / rn ** 3 - 3.0 * np.outer(r, r) / rn ** 5
+        r4 = _series_deriv(c, 4, 0.0)
+        errs = []
+        for i, (j, sg) in enumerate(_BODY):
+            d, d0 = st["d_last"][i], st["d_prev"][i]
+            assert d > 0
+            pec = (d ** 4 - d0 ** 4) / (2 * d ** 3) - (d0 ** 3 + d ** 3) / d ** 2
+            a0 = sg * m[j] / M * _series_deriv(c, 2, 0.0) + fr[i]
+            a1 = sg * m[j] / M * _series_deriv(c, 3, 0.0)
+            a2 = sg * m[j] / M * r4
+            a3 = sg * m[j] / M * _series_deriv(c, 5, -d / 2) + sg * (-m[j] * pec) * (tid @ r4)
+            errs.append(abs(st["want_last"][i] / _eq_dt(a0, a1, a2, a3, eta) - 1.0) / (d * d))
+        worst.append(max(errs))
+    # O(d^2) with a bounded constant (~1.3 here, time unit sqrt(a^3/M))
+    assert max(worst) < 3.0
+    assert worst[-1] == pytest.approx(worst[-2], rel=0.1)
+
+
 def test_hermite_kepler_fourth_order():
     # all of the force irregular (step changeover beyond the orbit): a plain
     # Hermite two-body integration. After one period the orbit closes; the
@@ -754,12 +904,40 @@ def _two_clump_error(R, s):
     return np.linalg.norm(at[0] - acc[0]) / np.linalg.norm(acc[0]), st["pn"]
 
 
+def _two_clump_potential_error(R, s):
+    """Relative potential error at a lone particle from a 2-particle clump at distance R."""
+    rng = np.random.default_rng(6)
+    u = rng.normal(size=3)
+    u /= np.linalg.norm(u)
+    centre = np.array([R, -0.4 * R, 0.25 * R])
+    pos = np.array([[0.0, 0.0, 0.0], centre + 0.6 * s * u, centre - 0.2 * s * u])
+    mass = np.array([1.0, 0.3, 0.9])
+    _, pot = oracle.direct(pos, mass, 0.0, 0.0, 0.0)
+    _, pt, st = oracle.tree(pos, mass, 0.0, 0.0, 1.0, 0.0, n_leaf=1, n_crit=1)
+    # the exact potential at particle 0 from the clump, summed here by hand
+    ref = -sum(mass[k] / np.linalg.norm(pos[k]) for k in (1, 2))
+    assert pot[0] == pytest.approx(ref, rel=1e-14)
+    return abs(pt[0] - pot[0]) / abs(pot[0]), st["pn"]
+
+
 def test_quadrupole_error_scales_as_third_power():
     e1, pn1 = _two_clump_error(1.0, 0.05)
     e2, pn2 = _two_clump_error(1.0, 0.025)
     assert pn1 > 0 and pn2 > 0                    # the clump is taken as a multipole
     ratio = e1 / e2
     assert 6.0 < ratio < 10.5                     # octupole-limited: (s/R)^3
+
+
+def test_quadrupole_potential_error_scales_as_third_power():
+    # The multipole potential -M/s - (1/2) R^T Q R / s^5 about the centre of
+    # mass leaves an octupole error ~ (s/R)^3 of the potential; a missing,
+    # flipped or mis-scaled quadrupole term leaves a (s/R)^2 error (ratio 4).
+    e1, pn1 = _two_clump_potential_error(1.0, 0.05)
+    e2, pn2 = _two_clump_potential_error(1.0, 0.025)
+    e3, _ = _two_clump_potential_error(1.0, 0.0125)
+    assert pn1 > 0 and pn2 > 0
+    assert 6.5 < e1 / e2 < 9.5 and 6.5 < e2 / e3 < 9.5
+    assert e1 < 1e-4
 
 
 def test_quadrupole_beats_monopole_and_theta_order():
