@@ -211,7 +211,7 @@ def bench_force(args):
                                            _ptr(mass), _stream()))
 
         def force(o, ix, cap, tot):
-            return L.pbh_force_batched(ctx, ri.ctypes.data_as(C.c_void_p),
+            return L.pbh_force_batched(ctx, _ptr(pos), _ptr(mass), ri.ctypes.data_as(C.c_void_p),
                                        ro.ctypes.data_as(C.c_void_p), theta, eps, _ptr(acc),
                                        _ptr(pot), o, ix, cap, tot, _stream())
     else:
@@ -219,8 +219,8 @@ def bench_force(args):
             check(ctx, L.pbh_build(ctx, n, _ptr(pos), _ptr(mass), _stream()))
 
         def force(o, ix, cap, tot):
-            return L.pbh_force(ctx, inp["r_in"], inp["r_out"], theta, eps, _ptr(acc), _ptr(pot),
-                               o, ix, cap, tot, _stream())
+            return L.pbh_force(ctx, _ptr(pos), _ptr(mass), inp["r_in"], inp["r_out"], theta, eps,
+                               _ptr(acc), _ptr(pot), o, ix, cap, tot, _stream())
 
     # size the neighbour buffer once (outside the timed region)
     build()

@@ -13,7 +13,7 @@
  *     regular force and fills the neighbour lists (REGF in the routine table
  *     of Appendix A); theta = 0 reduces to direct summation.
  *   - Section 2.2, eq. (kick): the leapfrog velocity kick with the regular
- *     force, used by pbh_kdk.
+ *     force, used by pbh_kdk_graph and pbh_p3t.
  *
  * Conventions (all functions):
  *   - G = 1. r_out is the paper's r_cut; r_in its inner radius.
@@ -60,17 +60,30 @@ typedef enum { PBH_FP64 = 0, PBH_MIXED = 1 } pbh_prec;
 
 /*
  * Tuning parameters; 0 selects the default.
- *   leaf_size  n_leaf: a node with more particles is split (default 8)
- *   n_crit     particles per walk group, 1..64 (0: chosen per build, 32 below
- *              2^18 particles and 64 from there; one wave lane each)
- *   key_bits   Morton bits per axis D, 1..21 (default 21 for one cluster;
- *              batched builds use min(21, (63 - cluster bits) / 3))
- *   prec       PBH_MIXED (FP32 interactions, FP64 positions and sums) or
- *              PBH_FP64 (every interaction in FP64). Default PBH_MIXED.
+ *   leaf_size   n_leaf: a node with more particles is split (default 8)
+ *   n_crit      particles per walk group, 1..64 (0: chosen per build, 32 below
+ *               2^18 particles and 64 from there; one wave lane each)
+ *   walk_tile   entries per LDS interaction tile of the walk: 64, 96 or 128
+ *               (default 64); a tile is evaluated just before it would
+ *               overflow, so larger tiles mean fewer evaluation rounds and
+ *               fewer resident waves per compute unit
+ *   lanes_per_particle  most wave lanes that share one particle of a small
+ *               group, 1..64 (0: as many as fit, 64 / group size; 1: one
+ *               lane per particle). The copies split the interaction tiles
+ *               and their partial sums are merged in copy order.
+ *   key_bits    Morton bits per axis D, 1..21 (default 21 for one cluster;
+ *               batched builds use min(21, (63 - cluster bits) / 3))
+ *   prec        PBH_MIXED (FP32 interactions, FP64 positions and sums) or
+ *               PBH_FP64 (every interaction in FP64). Default PBH_MIXED.
+ * Forces depend on leaf_size, n_crit and key_bits only through the tree's
+ * approximation; walk_tile and lanes_per_particle change the order of the
+ * FP32 tile sums only; neighbour lists depend on none of them.
  */
 typedef struct {
     int32_t leaf_size;
     int32_t n_crit;
+    int32_t walk_tile;
+    int32_t lanes_per_particle;
     int32_t key_bits;
     int32_t prec;
 } pbh_params;
@@ -87,14 +100,22 @@ typedef struct {
     int64_t n_pp_far;     /* particle-particle pairs outside r_out (W = 1) */
     int64_t n_pp_near;    /* pairs inside near leaves (changeover applied; self pairs counted) */
     int64_t nbr_total;    /* neighbour entries of the last force call */
-    int64_t error_flags;  /* device-side guard bits; 0 when healthy (bits 8-10:
-                             malformed input of the last pbh_irregular call) */
+    int64_t error_flags;  /* device-side guard bits; 0 when healthy (bit 5: pos or
+                             mass changed since the build; bits 8-10: malformed
+                             input of the last pbh_irregular call) */
     /* Phase durations of the last build / force call in milliseconds, from
        HIP events recorded on the call's stream; 0 unless timing is enabled
        (pbh_set_timing). walk = the tree-walk kernel alone. */
     double ms_build;
     double ms_walk;
     double ms_nbr;
+    /* Lane slots of the walk's evaluation loops (64 per loop iteration of a
+       wave) for multipole, far-pair and near-pair tiles. n_pn / lane_slots_pn
+       etc. is the fraction of lanes doing useful work (idle lanes of groups
+       smaller than a wave, copies beyond the tile's entries). */
+    int64_t lane_slots_pn;
+    int64_t lane_slots_far;
+    int64_t lane_slots_near;
 } pbh_stats;
 
 /* Core quantities of pbh_core (Casertano & Hut 1985 estimator, see there). */
@@ -128,7 +149,16 @@ pbh_status pbh_build(pbh_ctx* ctx, int64_t n, const double* pos, const double* m
 
 /*
  * Regular force, regular potential and neighbour lists of the last build
- * (Section 2.1 eq. fi / F_R, eq. duncan; Section 2.3; Section 2.4).
+ * (Section 2.1 eq. fi / F_R, eq. duncan; Section 2.3; Section 2.4; the
+ * REGF contract of Appendix A: given the particles, return their regular
+ * forces and neighbour lists).
+ *   pos, mass    the arrays of the last pbh_build, unchanged since. Other
+ *                pointers return PBH_E_STATE at once, as does a context
+ *                without a successful single-cluster build. The walk also
+ *                compares every particle's pos and mass with the build's
+ *                sorted copy: a change in place since the build sets
+ *                error_flags bit 5 (pbh_stats) and, when nbr_total is
+ *                non-NULL (the call waits), returns PBH_E_STATE.
  *   r_in, r_out  changeover radii, 0 <= r_in <= r_out (r_out = 0: plain
  *                softened gravity and empty lists; r_in = r_out: step W)
  *   theta        opening angle >= 0 (0 = direct summation through the tree)
@@ -142,10 +172,9 @@ pbh_status pbh_build(pbh_ctx* ctx, int64_t n, const double* pos, const double* m
  *                and nbr_off are valid; resize and call again: the tree is
  *                reused). If NULL nothing waits; entries beyond nbr_cap are
  *                dropped and error_flags bit 0 is set in pbh_stats.
- * pos/mass must be the arrays of the last build (they are not re-read).
  */
-pbh_status pbh_force(pbh_ctx* ctx, double r_in, double r_out, double theta, double eps,
-                     double* acc, double* pot,
+pbh_status pbh_force(pbh_ctx* ctx, const double* pos, const double* mass, double r_in,
+                     double r_out, double theta, double eps, double* acc, double* pot,
                      int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap, int64_t* nbr_total,
                      pbh_stream_t stream);
 
@@ -159,9 +188,9 @@ pbh_status pbh_force(pbh_ctx* ctx, double r_in, double r_out, double theta, doub
  * pbh_force. The lists feed pbh_irregular unchanged (pairs beyond r_out add
  * nothing there).
  */
-pbh_status pbh_force_buffered(pbh_ctx* ctx, double r_in, double r_out, double r_buff,
-                              double theta, double eps, double* acc, double* pot,
-                              int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap,
+pbh_status pbh_force_buffered(pbh_ctx* ctx, const double* pos, const double* mass, double r_in,
+                              double r_out, double r_buff, double theta, double eps, double* acc,
+                              double* pot, int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap,
                               int64_t* nbr_total, pbh_stream_t stream);
 
 /*
@@ -176,18 +205,20 @@ pbh_status pbh_build_batched(pbh_ctx* ctx, int32_t n_clusters, const int64_t* of
 
 /*
  * Forces of every cluster of the last batched build in one persistent walk
- * launch. r_in/r_out are host arrays [n_clusters] (per-cluster changeover
- * radii); clusters never interact. Other arguments as pbh_force; neighbour
- * indices are global (caller-order) indices.
+ * launch. pos/mass are the arrays of that build (PBH_E_STATE otherwise, as
+ * pbh_force). r_in/r_out are host arrays [n_clusters] (per-cluster
+ * changeover radii); clusters never interact. Other arguments as pbh_force;
+ * neighbour indices are global (caller-order) indices.
  */
-pbh_status pbh_force_batched(pbh_ctx* ctx, const double* r_in, const double* r_out,
-                             double theta, double eps, double* acc, double* pot,
-                             int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap,
-                             int64_t* nbr_total, pbh_stream_t stream);
+pbh_status pbh_force_batched(pbh_ctx* ctx, const double* pos, const double* mass,
+                             const double* r_in, const double* r_out, double theta, double eps,
+                             double* acc, double* pot, int64_t* nbr_off, int32_t* nbr_idx,
+                             int64_t nbr_cap, int64_t* nbr_total, pbh_stream_t stream);
 
 /* pbh_force_batched with per-cluster buffers r_buff (host array [n_clusters],
    or NULL for none), as pbh_force_buffered. */
-pbh_status pbh_force_batched_buffered(pbh_ctx* ctx, const double* r_in, const double* r_out,
+pbh_status pbh_force_batched_buffered(pbh_ctx* ctx, const double* pos, const double* mass,
+                                      const double* r_in, const double* r_out,
                                       const double* r_buff, double theta, double eps,
                                       double* acc, double* pot, int64_t* nbr_off,
                                       int32_t* nbr_idx, int64_t nbr_cap, int64_t* nbr_total,
@@ -282,8 +313,11 @@ pbh_status pbh_core(pbh_ctx* ctx, const double* pos, const double* mass, int64_t
  * with dt_max = dt_reg / 4 (eq. dtmax), predicted with eq. p3t-jpred-x and
  * p3t-jpred-dx (no regular force), corrected with the 4th-order Hermite
  * corrector, and given the next step by eq. dt (eta; a^(0) = F_I + fr). The
- * start step is 0.01 |F_I + fr| / |dF_I/dt|; steps at most double and stay
- * commensurate with the block time; all particles end at dt_reg.
+ * first step of every particle is eq. dt too, with the second and third time
+ * derivatives of F_I computed from the lists along the motion under F_I
+ * (Section 2.1, after eq. dt), and dt_max when the particle has no pair
+ * inside r_out; steps at most double and stay commensurate with the block
+ * time; all particles end at dt_reg.
  *   fr           [n][3] regular force for the step criterion, or NULL
  *   nbr_off/idx  lists that hold every pair inside r_out throughout the step
  *                (pbh_force_buffered with a large enough r_buff)
@@ -326,9 +360,9 @@ pbh_status pbh_p3t(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const doub
  * [steps+1] (energy before the first step, then after each). n is fixed at
  * the first call for this context; later calls with the same n reuse the graph.
  */
-pbh_status pbh_kdk(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
-                   double dt, int32_t steps, double r_in, double r_out, double theta,
-                   double eps, double* energy_out, pbh_stream_t stream);
+pbh_status pbh_kdk_graph(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
+                         double dt, int32_t steps, double r_in, double r_out, double theta,
+                         double eps, double* energy_out, pbh_stream_t stream);
 
 /* Same step sequence launched eagerly (no graph), for replay checks. */
 pbh_status pbh_kdk_eager(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
@@ -371,6 +405,14 @@ pbh_status pbh_debug_groups(pbh_ctx* ctx, int64_t cap, int32_t* begin, int32_t* 
  */
 pbh_status pbh_debug_wave_log(pbh_ctx* ctx, uint64_t* walk, uint64_t* nbr, int64_t cap,
                               int64_t* n_walk, int64_t* n_nbr);
+
+/*
+ * Debug export of the first block step (in ticks of dt_max / 2^40) that the
+ * last pbh_hermite call (or the last regular step of pbh_p3t) gave each
+ * particle, caller order. Host buffer of cap entries, or NULL; the particle
+ * count goes to *n_out. PBH_E_STATE before any integration.
+ */
+pbh_status pbh_debug_herm_first_steps(pbh_ctx* ctx, int64_t cap, int64_t* ticks, int64_t* n_out);
 
 /*
  * Calibration kernel for hardware instruction counters: `blocks` waves, each

@@ -26,21 +26,23 @@ PBH_MIXED = 1
 EXPORTS = ("pbh_create", "pbh_destroy", "pbh_set_params", "pbh_get_params", "pbh_build",
            "pbh_force", "pbh_force_buffered", "pbh_build_batched", "pbh_force_batched",
            "pbh_force_batched_buffered", "pbh_irregular",
-           "pbh_irregular_batched", "pbh_core", "pbh_hermite", "pbh_p3t", "pbh_kdk", "pbh_kdk_eager",
-           "pbh_get_stats", "pbh_set_timing", "pbh_debug_tree", "pbh_debug_groups",
-           "pbh_debug_wave_log", "pbh_debug_valu_probe", "pbh_last_error", "pbh_status_string")
+           "pbh_irregular_batched", "pbh_core", "pbh_hermite", "pbh_p3t", "pbh_kdk_graph",
+           "pbh_kdk_eager", "pbh_get_stats", "pbh_set_timing", "pbh_debug_tree", "pbh_debug_groups",
+           "pbh_debug_wave_log", "pbh_debug_valu_probe", "pbh_debug_herm_first_steps",
+           "pbh_last_error", "pbh_status_string")
 
 
 class pbh_params(C.Structure):
-    _fields_ = [("leaf_size", C.c_int32), ("n_crit", C.c_int32), ("key_bits", C.c_int32),
-                ("prec", C.c_int32)]
+    _fields_ = [("leaf_size", C.c_int32), ("n_crit", C.c_int32), ("walk_tile", C.c_int32),
+                ("lanes_per_particle", C.c_int32), ("key_bits", C.c_int32), ("prec", C.c_int32)]
 
 
 class pbh_stats(C.Structure):
     _fields_ = [(name, C.c_int64) for name in (
         "n", "n_clusters", "n_nodes", "n_leaves", "n_groups", "max_level", "n_pn", "n_pp_far",
         "n_pp_near", "nbr_total", "error_flags")] + [
-        (name, C.c_double) for name in ("ms_build", "ms_walk", "ms_nbr")]
+        (name, C.c_double) for name in ("ms_build", "ms_walk", "ms_nbr")] + [
+        (name, C.c_int64) for name in ("lane_slots_pn", "lane_slots_far", "lane_slots_near")]
 
 
 class pbh_core_info(C.Structure):
@@ -75,11 +77,12 @@ def load(path: str = LIB_PATH):
         "pbh_set_params": (st, [vp, vp]),
         "pbh_get_params": (st, [vp, vp]),
         "pbh_build": (st, [vp, i64, vp, vp, vp]),
-        "pbh_force": (st, [vp, d, d, d, d, vp, vp, vp, vp, i64, vp, vp]),
+        "pbh_force": (st, [vp, vp, vp, d, d, d, d, vp, vp, vp, vp, i64, vp, vp]),
         "pbh_build_batched": (st, [vp, i32, vp, vp, vp, vp]),
-        "pbh_force_batched": (st, [vp, vp, vp, d, d, vp, vp, vp, vp, i64, vp, vp]),
-        "pbh_force_buffered": (st, [vp, d, d, d, d, d, vp, vp, vp, vp, i64, vp, vp]),
-        "pbh_force_batched_buffered": (st, [vp, vp, vp, vp, d, d, vp, vp, vp, vp, i64, vp, vp]),
+        "pbh_force_batched": (st, [vp, vp, vp, vp, vp, d, d, vp, vp, vp, vp, i64, vp, vp]),
+        "pbh_force_buffered": (st, [vp, vp, vp, d, d, d, d, d, vp, vp, vp, vp, i64, vp, vp]),
+        "pbh_force_batched_buffered": (st, [vp, vp, vp, vp, vp, vp, d, d, vp, vp, vp, vp, i64, vp,
+                                            vp]),
         "pbh_irregular": (st, [vp, i64, vp, vp, vp, d, d, d, vp, vp, i64, i64, vp, vp, vp, vp,
                                i32, vp]),
         "pbh_irregular_batched": (st, [vp, vp, vp, vp, vp, vp, d, vp, vp, i64, i64, vp, vp, vp,
@@ -87,7 +90,7 @@ def load(path: str = LIB_PATH):
         "pbh_core": (st, [vp, vp, vp, i64, vp, d, vp, vp, vp]),
         "pbh_hermite": (st, [vp, i64, vp, vp, vp, vp, d, d, d, vp, vp, i64, d, d, vp, vp]),
         "pbh_p3t": (st, [vp, i64, vp, vp, vp, d, d, d, d, d, d, d, i32, vp, vp, vp]),
-        "pbh_kdk": (st, [vp, i64, vp, vp, vp, d, i32, d, d, d, d, vp, vp]),
+        "pbh_kdk_graph": (st, [vp, i64, vp, vp, vp, d, i32, d, d, d, d, vp, vp]),
         "pbh_kdk_eager": (st, [vp, i64, vp, vp, vp, d, i32, d, d, d, d, vp, vp]),
         "pbh_get_stats": (st, [vp, vp]),
         "pbh_set_timing": (st, [vp, i32]),
@@ -95,6 +98,7 @@ def load(path: str = LIB_PATH):
         "pbh_debug_groups": (st, [vp, i64, vp, vp, vp, vp]),
         "pbh_debug_wave_log": (st, [vp, vp, vp, i64, vp, vp]),
         "pbh_debug_valu_probe": (st, [vp, i64, i32, vp, vp]),
+        "pbh_debug_herm_first_steps": (st, [vp, i64, vp, vp]),
         "pbh_last_error": (C.c_char_p, [vp]),
         "pbh_status_string": (C.c_char_p, [C.c_int]),
     }

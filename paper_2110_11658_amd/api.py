@@ -38,31 +38,35 @@ class Pbh:
     """One libpbh context (tree scratch lives on the GPU between calls)."""
 
     def __init__(self, device: int = 0, leaf_size: int = 8, n_crit: int = 0, key_bits: int = 0,
-                 prec: str = "mixed"):
+                 prec: str = "mixed", walk_tile: int = 0, lanes_per_particle: int = 0):
         self.L = _lib.load()
         self.device = device
         self.ctx = C.c_void_p()
-        p = self._params(leaf_size, n_crit, key_bits, prec)
+        p = self._params(leaf_size, n_crit, key_bits, prec, walk_tile, lanes_per_particle)
         st = self.L.pbh_create(device, C.byref(p), C.byref(self.ctx))
         if st != 0:
             raise PbhError(st, self.L.pbh_status_string(st).decode())
         self.n = 0
         self.n_clusters = 0
         self._nbr_cap = 0
+        self._built = (None, None)   # the tensors of the last build (pbh_force takes them again)
 
     @staticmethod
-    def _params(leaf_size, n_crit, key_bits, prec):
+    def _params(leaf_size, n_crit, key_bits, prec, walk_tile=0, lanes_per_particle=0):
         pr = {"mixed": PBH_MIXED, "fp64": PBH_FP64}[prec]
-        return pbh_params(int(leaf_size), int(n_crit), int(key_bits), pr)
+        return pbh_params(int(leaf_size), int(n_crit), int(walk_tile), int(lanes_per_particle),
+                          int(key_bits), pr)
 
-    def set_params(self, leaf_size=8, n_crit=0, key_bits=0, prec="mixed"):
-        p = self._params(leaf_size, n_crit, key_bits, prec)
+    def set_params(self, leaf_size=8, n_crit=0, key_bits=0, prec="mixed", walk_tile=0,
+                   lanes_per_particle=0):
+        p = self._params(leaf_size, n_crit, key_bits, prec, walk_tile, lanes_per_particle)
         check(self.ctx, self.L.pbh_set_params(self.ctx, C.byref(p)))
 
     def params(self) -> dict:
         p = pbh_params()
         check(self.ctx, self.L.pbh_get_params(self.ctx, C.byref(p)))
-        return {"leaf_size": p.leaf_size, "n_crit": p.n_crit, "key_bits": p.key_bits,
+        return {"leaf_size": p.leaf_size, "n_crit": p.n_crit, "walk_tile": p.walk_tile,
+                "lanes_per_particle": p.lanes_per_particle, "key_bits": p.key_bits,
                 "prec": "mixed" if p.prec == PBH_MIXED else "fp64"}
 
     def close(self):
@@ -84,6 +88,7 @@ class Pbh:
         check(self.ctx, self.L.pbh_build(self.ctx, n, _ptr(pos), _ptr(mass), _stream()))
         self.n = n
         self.n_clusters = 1
+        self._built = (pos, mass)
 
     def build_batched(self, offsets: Sequence[int], pos: torch.Tensor, mass: torch.Tensor):
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
@@ -95,6 +100,7 @@ class Pbh:
                                                  _ptr(pos), _ptr(mass), _stream()))
         self.n = n
         self.n_clusters = off.size - 1
+        self._built = (pos, mass)
 
     # -- pbh_force / pbh_force_batched ---------------------------------------
     def _force(self, call, neighbours: bool, nbr_cap: Optional[int]):
@@ -123,10 +129,13 @@ class Pbh:
         """(acc [n,3], pot [n], nbr_off [n+1] | None, nbr_idx [total] | None).
 
         The lists hold every j with r_ij < r_out + r_buff (r_buff = 0: r_out)."""
+        bp, bm = self._built
+
         def call(acc, pot, off, idx, cap, total):
-            return self.L.pbh_force_buffered(self.ctx, float(r_in), float(r_out), float(r_buff),
-                                             float(theta), float(eps), _ptr(acc), _ptr(pot),
-                                             _ptr(off), _ptr(idx), int(cap), total, _stream())
+            return self.L.pbh_force_buffered(self.ctx, _ptr(bp), _ptr(bm), float(r_in), float(r_out),
+                                             float(r_buff), float(theta), float(eps), _ptr(acc),
+                                             _ptr(pot), _ptr(off), _ptr(idx), int(cap), total,
+                                             _stream())
         return self._force(call, neighbours, nbr_cap)
 
     def force_batched(self, r_in: Sequence[float], r_out: Sequence[float], theta: float, eps: float,
@@ -142,9 +151,12 @@ class Pbh:
             if rb.size != self.n_clusters:
                 raise ValueError("need one r_buff per cluster")
 
+        bp, bm = self._built
+
         def call(acc, pot, off, idx, cap, total):
             return self.L.pbh_force_batched_buffered(
-                self.ctx, ri.ctypes.data_as(C.c_void_p), ro.ctypes.data_as(C.c_void_p),
+                self.ctx, _ptr(bp), _ptr(bm), ri.ctypes.data_as(C.c_void_p),
+                ro.ctypes.data_as(C.c_void_p),
                 None if rb is None else rb.ctypes.data_as(C.c_void_p), float(theta), float(eps),
                 _ptr(acc), _ptr(pot), _ptr(off), _ptr(idx), int(cap), total, _stream())
         return self._force(call, neighbours, nbr_cap)
@@ -153,9 +165,10 @@ class Pbh:
         """Forces into caller-owned tensors, no neighbour lists, no host wait."""
         _need(acc, (self.n, 3), "acc")
         _need(pot, (self.n,), "pot")
-        check(self.ctx, self.L.pbh_force(self.ctx, float(r_in), float(r_out), float(theta),
-                                         float(eps), _ptr(acc), _ptr(pot), None, None, 0, None,
-                                         _stream()))
+        bp, bm = self._built
+        check(self.ctx, self.L.pbh_force(self.ctx, _ptr(bp), _ptr(bm), float(r_in), float(r_out),
+                                         float(theta), float(eps), _ptr(acc), _ptr(pot), None, None,
+                                         0, None, _stream()))
 
     # -- pbh_kdk --------------------------------------------------------------
     # -- pbh_irregular / pbh_irregular_batched -------------------------------
@@ -259,6 +272,7 @@ class Pbh:
                                        st.ctypes.data_as(C.c_void_p), _stream()))
         self.n = n
         self.n_clusters = 1
+        self._built = (pos, mass)
         return energy, {"blocks": int(st[0]), "steps": int(st[1]), "kmax": int(st[2])}
 
     def kdk(self, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor, dt: float, steps: int,
@@ -271,12 +285,13 @@ class Pbh:
         if energy is None:
             energy = torch.empty((steps + 1,), dtype=torch.float64, device=pos.device)
         _need(energy, (steps + 1,), "energy")
-        fn = self.L.pbh_kdk if graph else self.L.pbh_kdk_eager
+        fn = self.L.pbh_kdk_graph if graph else self.L.pbh_kdk_eager
         check(self.ctx, fn(self.ctx, n, _ptr(pos), _ptr(vel), _ptr(mass), float(dt), int(steps),
                            float(r_in), float(r_out), float(theta), float(eps), _ptr(energy),
                            _stream()))
         self.n = n
         self.n_clusters = 1
+        self._built = (pos, mass)
         return energy
 
     # -- stats / debug ----------------------------------------------------------
@@ -291,6 +306,16 @@ class Pbh:
             v = getattr(s, name)
             out[name] = float(v) if typ is C.c_double else int(v)
         return out
+
+    def debug_herm_first_steps(self) -> np.ndarray:
+        """First block step (ticks of dt_max / 2^40) of every particle in the
+        last Hermite integration, caller order."""
+        n = C.c_int64(0)
+        check(self.ctx, self.L.pbh_debug_herm_first_steps(self.ctx, 0, None, C.byref(n)))
+        t = np.zeros(n.value, dtype=np.int64)
+        check(self.ctx, self.L.pbh_debug_herm_first_steps(self.ctx, n.value,
+                                                          t.ctypes.data_as(C.c_void_p), C.byref(n)))
+        return t
 
     def debug_groups(self):
         """(begin int32 [G], count int32 [G], box f64 [G,6]) of the last build."""

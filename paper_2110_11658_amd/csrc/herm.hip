@@ -18,10 +18,16 @@
 //     x = x_p + d^4/24 a2 + d^5/120 a3,     v = v_p + d^3/6 a2 + d^4/24 a3
 //   and a new step from eq. dt (eta) with a^(0) = a1 + F_R, a^(1) = j1,
 //   a^(2) = a2 + d a3, a^(3) = a3: at most twice the old step and dt_max,
-//   rounded down to dt_max / 2^k dividing tau'. The start step is
-//   eta_s |a + F_R| / |j| with eta_s = 0.01. The corrector and the start step
-//   are the standard Hermite ones (Makino & Aarseth 1992); the paper defers
-//   both to NBODY6. Expressions are evaluated as written (no contraction).
+//   rounded down to dt_max / 2^k dividing tau'. The corrector is the standard
+//   Hermite one (Makino & Aarseth 1992).
+// First steps (Section 2.1, after eq. dt: the higher derivatives are computed
+// and the fourth-order criterion sets the initial step; steps are set afresh
+// after every regular kick): with a = F_I and j = dF_I/dt of every particle
+// at the start, the second and third derivatives of F_I along the motion
+// under F_I come from the neighbour lists (relative accelerations a_j - a_i,
+// relative jerks j_j - j_i), and eq. dt with a^(0) = a + F_R, a^(1) = j and
+// those derivatives gives the first step; dt_max where its denominator is 0
+// (no pair inside r_out). Expressions are evaluated as written (no contraction).
 //
 // A block is two launches: the front (next block time, active list,
 // prediction) and the force with the corrector; particles are kept in one
@@ -287,17 +293,110 @@ __device__ inline int64_t block_step(double want, double dtmax, int64_t tau) {
 
 __device__ inline int step_level(int64_t t) { return kHermK - (63 - __clzll((unsigned long long)t)); }
 
-__global__ __launch_bounds__(256) void k_herm_start(HermParams p) {
+// Second and third time derivatives of one pair term m K(s) d / s^3 of F_I,
+// added to f2, f3. d, u, w, z: relative position, velocity, acceleration and
+// jerk (j's minus i's); s^2 = |d|^2 + eps^2. The Newtonian part A = m d / s^3
+// follows the usual recurrences in
+//   al = d.u / s^2,  be = (u.u + d.w) / s^2 + al^2,
+//   ga = (3 u.w + d.z) / s^2 + al (3 be - 4 al^2):
+//   dA = m u / s^3 - 3 al A,  d2A = m w / s^3 - 6 al dA - 3 be A,
+//   d3A = m z / s^3 - 9 al d2A - 9 be dA - 3 ga A;
+// along the motion s has the derivatives al s, (be - 2 al^2) s and
+// s ((3 u.w + d.z) / s^2 - 3 al (be - 2 al^2)); in the band the weight has
+// dK/ds = -g1(x)/D, d2K/ds2 = -g2(x)/D^2, d3K/ds3 = -g3(x)/D^3 with
+// g1 = 140 x^3 (1-x)^3, g2 = 420 x^2 (1-x)^2 (1-2x), g3 = 840 x (1-x) (1-5x+5x^2),
+// and the product rule gives the second and third derivatives of K A.
+__device__ inline void pair_d23(const ClusterParams& cp, double eps2, const double* d, const double* u,
+                                const double* w, const double* z, double m, double* f2, double* f3) {
+#pragma clang fp contract(off)
+    const double s2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
+    if (!(s2 < cp.rout2)) return;   // K = 0 with all its derivatives
+    const double s = sqrt(s2);
+    const double i2 = 1.0 / s2;
+    const double mi3 = m / (s2 * s);
+    const double du = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double dw = d[0] * w[0] + d[1] * w[1] + d[2] * w[2];
+    const double uw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+    const double dz = d[0] * z[0] + d[1] * z[1] + d[2] * z[2];
+    const double al = du * i2;
+    const double be = (uu + dw) * i2 + al * al;
+    const double ga = (3.0 * uw + dz) * i2 + al * (3.0 * be - 4.0 * al * al);
+    double K = 1.0, K1 = 0.0, K2 = 0.0, K3 = 0.0;   // K and its time derivatives
+    if (s >= cp.r_in && cp.inv_delta > 0.0) {
+        const double x = (s - cp.r_in) * cp.inv_delta, o = 1.0 - x;
+        const double x2 = x * x;
+        const double id = cp.inv_delta;
+        K = 1.0 - x2 * x2 * (35.0 + x * (-84.0 + x * (70.0 - 20.0 * x)));
+        const double ks1 = -140.0 * x2 * x * o * o * o * id;
+        const double ks2 = -420.0 * x2 * o * o * (1.0 - 2.0 * x) * id * id;
+        const double ks3 = -840.0 * x * o * (1.0 - 5.0 * x + 5.0 * x2) * id * id * id;
+        const double sd1 = al * s;
+        const double q = be - 2.0 * al * al;
+        const double sd2 = q * s;
+        const double sd3 = s * ((3.0 * uw + dz) * i2 - 3.0 * al * q);
+        K1 = ks1 * sd1;
+        K2 = ks2 * sd1 * sd1 + ks1 * sd2;
+        K3 = ks3 * sd1 * sd1 * sd1 + 3.0 * ks2 * sd1 * sd2 + ks1 * sd3;
+    }
+    for (int c = 0; c < 3; ++c) {
+        const double A0 = mi3 * d[c];
+        const double A1 = mi3 * u[c] - 3.0 * al * A0;
+        const double A2 = mi3 * w[c] - 6.0 * al * A1 - 3.0 * be * A0;
+        const double A3 = mi3 * z[c] - 9.0 * al * A2 - 9.0 * be * A1 - 3.0 * ga * A0;
+        f2[c] += K * A2 + 2.0 * K1 * A1 + K2 * A0;
+        f3[c] += K * A3 + 3.0 * K1 * A2 + 3.0 * K2 * A1 + K3 * A0;
+    }
+}
+
+// First steps: one lane per particle sums the derivatives over its list (in
+// list order; lists from the regular-force walk are short), then eq. dt.
+__global__ __launch_bounds__(256) void k_herm_start(HermParams p, IrrParams ip) {
     // slot 0, every level refilled (ks = 0)
     step_and_bucket(p, 0, 0, p.n, nullptr, 0, [&](int64_t, int32_t i) {
 #pragma clang fp contract(off)
+        const int64_t i3 = 3 * (int64_t)i;
+        double xi[3], vi[3], ai[3], ji[3], f2[3] = {0.0, 0.0, 0.0}, f3[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 3; ++c) {
+            xi[c] = p.x[i3 + c];
+            vi[c] = p.v[i3 + c];
+            ai[c] = p.a[i3 + c];
+            ji[c] = p.j[i3 + c];
+        }
+        int64_t b = p.off[i], e = p.off[i + 1];
+        if (b < 0 || e < b || e > p.cap) {   // malformed offsets: flagged, list not read
+            atomicOr(ip.err, kIrrBadOffsets);
+            e = b;
+        }
+        for (int64_t q = b; q < e; ++q) {
+            const int32_t jj = p.idx[q];
+            if ((uint64_t)(int64_t)jj >= (uint64_t)p.n) {
+                atomicOr(ip.err, kIrrBadIndex);
+                continue;
+            }
+            if (jj == i) continue;
+            const int64_t j3 = 3 * (int64_t)jj;
+            double d[3], u[3], w[3], z[3];
+            for (int c = 0; c < 3; ++c) {
+                d[c] = p.x[j3 + c] - xi[c];
+                u[c] = p.v[j3 + c] - vi[c];
+                w[c] = p.a[j3 + c] - ai[c];
+                z[c] = p.j[j3 + c] - ji[c];
+            }
+            pair_d23(ip.cp0, ip.eps2, d, u, w, z, ip.mass[jj], f2, f3);
+        }
         double at[3];
-        for (int k = 0; k < 3; ++k) at[k] = p.a[3 * (int64_t)i + k] + (p.fr ? p.fr[3 * (int64_t)i + k] : 0.0);
-        const double jn = norm3(p.j[3 * (int64_t)i], p.j[3 * (int64_t)i + 1], p.j[3 * (int64_t)i + 2]);
-        const double want = jn > 0.0 ? 0.01 * norm3(at[0], at[1], at[2]) / jn : p.dtmax;
+        for (int c = 0; c < 3; ++c) at[c] = ai[c] + (p.fr ? p.fr[i3 + c] : 0.0);
+        const double n0 = norm3(at[0], at[1], at[2]);
+        const double n1 = norm3(ji[0], ji[1], ji[2]);
+        const double n2 = norm3(f2[0], f2[1], f2[2]);
+        const double n3 = norm3(f3[0], f3[1], f3[2]);
+        const double num = n0 * n2 + n1 * n1, den = n1 * n3 + n2 * n2;
+        const double want = den > 0.0 ? sqrt(p.eta * num / den) : p.dtmax;
         const int64_t t = block_step(want, p.dtmax, 0);
         p.tau[i] = 0;
         p.dt[i] = t;
+        if (p.dt0) p.dt0[i] = t;
         return step_level(t);
     });
 }
@@ -378,8 +477,8 @@ static unsigned herm_grid(int64_t n) {
     return (unsigned)(g < kHermGrid ? (g < 1 ? 1 : g) : kHermGrid);
 }
 
-void launch_herm_start(const HermParams& p, hipStream_t s) {
-    hipLaunchKernelGGL(k_herm_start, dim3(herm_grid(p.n)), dim3(256), 0, s, p);
+void launch_herm_start(const HermParams& p, const IrrParams& ip, hipStream_t s) {
+    hipLaunchKernelGGL(k_herm_start, dim3(herm_grid(p.n)), dim3(256), 0, s, p, ip);
 }
 
 void launch_herm_front(const HermParams& p, int parity, hipStream_t s) {

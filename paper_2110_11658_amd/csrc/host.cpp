@@ -34,7 +34,7 @@ struct Buf {
 
 struct pbh_ctx {
     int device = 0;
-    pbh_params params{16, 64, 0, PBH_MIXED};
+    pbh_params params{8, 0, 64, 0, 0, PBH_MIXED};
     std::string err;
     hipStream_t last = nullptr;
     hipStream_t cap_stream = nullptr;
@@ -43,6 +43,8 @@ struct pbh_ctx {
     // build state
     bool built = false;
     bool batched = false;
+    const double* built_pos = nullptr;    // the caller's arrays of the last build
+    const double* built_mass = nullptr;
     BuildCfg cfg;
     Dev d;
     std::vector<Buf> bufs;
@@ -51,7 +53,8 @@ struct pbh_ctx {
     // allocation sizes
     int64_t a_n = -1, a_cap = -1, a_G = -1, a_C = -1, a_nblk = -1, a_stack = -1;
     int64_t alloc_gen = 0;   // bumped whenever device buffers are reallocated
-    int grid_mixed = 0, grid_fp64 = 0;
+    int grid_mixed = 0, grid_fp64 = 0;   // persistent walk grids at the default tile (the largest)
+    int grid_tile[2][3] = {{0, 0, 0}, {0, 0, 0}};   // [mixed][tile 64, 96, 128]
 
     // kdk
     double* k_acc = nullptr;
@@ -75,8 +78,9 @@ struct pbh_ctx {
     // the P3T loop must not free it)
     struct {
         int64_t n = -1;
+        int64_t last_n = 0;   // particles of the last integration
         double *a = nullptr, *j = nullptr, *xp = nullptr, *vp = nullptr;
-        int64_t *tau = nullptr, *dt = nullptr;
+        int64_t *tau = nullptr, *dt = nullptr, *dt0 = nullptr;
         int32_t* act = nullptr;
         unsigned long long* ctl = nullptr;
         unsigned long long* lev = nullptr;
@@ -144,6 +148,17 @@ int64_t node_capacity(int64_t n, int D, int n_leaf, int C) {
     // leaves <= n, branching inner nodes < leaves, single-child inner nodes
     // <= one per (n_leaf+1) particles per level
     return 2 * n + (int64_t)D * ((n + n_leaf) / (n_leaf + 1)) + C + 64;
+}
+
+// persistent walk grid for the context's precision and tile: resident
+// workgroups per compute unit (LDS and registers) times the compute units
+int walk_grid(pbh_ctx* ctx, int mixed) {
+    const int tile = ctx->params.walk_tile;
+    const int t = tile == 128 ? 2 : (tile == 96 ? 1 : 0);
+    int& g = ctx->grid_tile[mixed ? 1 : 0][t];
+    if (g == 0) g = walk_blocks_per_cu(mixed, tile) * ctx->cus;
+    const int gmax = mixed ? ctx->grid_mixed : ctx->grid_fp64;   // the stacks are sized for this
+    return g < gmax ? g : gmax;
 }
 
 pbh_status ensure_buffers(pbh_ctx* ctx) {
@@ -287,8 +302,8 @@ pbh_status setup_build(pbh_ctx* ctx, int64_t n, int32_t C, const int64_t* offset
     c.n_groups = n;   // capacity; the walk reads the actual count on the device
     ctx->nblk_box = (int)blk_cluster.size();
     if (ctx->grid_mixed == 0) {
-        ctx->grid_mixed = walk_blocks_per_cu(1) * ctx->cus;
-        ctx->grid_fp64 = walk_blocks_per_cu(0) * ctx->cus;
+        ctx->grid_mixed = walk_blocks_per_cu(1, 64) * ctx->cus;
+        ctx->grid_fp64 = walk_blocks_per_cu(0, 64) * ctx->cus;
     }
     pbh_status st = ensure_buffers(ctx);
     if (st != PBH_OK) return st;
@@ -472,10 +487,13 @@ pbh_status finish_build(pbh_ctx* ctx, hipStream_t s) {
     return PBH_OK;
 }
 
-pbh_status do_force(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, double theta, double eps,
+pbh_status do_force(pbh_ctx* ctx, const double* pos, const double* mass,
+                    const std::vector<ClusterParams>& cps, double theta, double eps,
                     double* acc, double* pot, int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap,
                     int64_t* nbr_total, hipStream_t s) {
     if (!ctx->built) return fail(ctx, PBH_E_STATE, "pbh_force called without a successful build");
+    if (pos != ctx->built_pos || mass != ctx->built_mass)
+        return fail(ctx, PBH_E_STATE, "pos and mass must be the arrays of the last build");
     if (!finite_nonneg(theta) || !finite_nonneg(eps)) return fail(ctx, PBH_E_ARG, "theta and eps must be finite and >= 0");
     if (!acc || !pot) return fail(ctx, PBH_E_ARG, "acc and pot are required");
     if (nbr_cap < 0 || (nbr_cap > 0 && !nbr_idx)) return fail(ctx, PBH_E_ARG, "bad neighbour buffer");
@@ -488,8 +506,11 @@ pbh_status do_force(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, double 
     w.theta = theta;
     w.eps = eps;
     w.mixed = ctx->params.prec == PBH_MIXED;
-    const int gmax = w.mixed ? ctx->grid_mixed : ctx->grid_fp64;
-    w.grid = gmax;   // persistent: workgroups leave when the group queue is empty
+    w.tile = ctx->params.walk_tile;
+    w.max_copies = ctx->params.lanes_per_particle ? ctx->params.lanes_per_particle : 64;
+    w.cpos = pos;
+    w.cmass = mass;
+    w.grid = walk_grid(ctx, w.mixed);   // persistent: workgroups leave when the group queue is empty
     w.stack_cap = kStackCap;
     w.count_nbr = nbr_off != nullptr;   // the walk counts the neighbours of every particle
     w.stage_cap = w.count_nbr ? ensure_stage(ctx) : 0;
@@ -519,6 +540,8 @@ pbh_status do_force(pbh_ctx* ctx, const std::vector<ClusterParams>& cps, double 
             unsigned long long err = 0;
             HIP_TRY(hipMemcpyAsync(&err, d.cnt + kErr, sizeof(err), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
+            if (err & kErrStale)
+                return fail(ctx, PBH_E_STATE, "pos or mass changed since the build");
             if (err & (kErrWalkStack | kErrNbrStack))
                 return fail(ctx, PBH_E_INTERNAL, "traversal stack overflow");
         }
@@ -622,7 +645,8 @@ pbh_status ensure_herm(pbh_ctx* ctx, int64_t n) {
     const int nb = (int)std::min<int64_t>((n + 255) / 256, 4096);
     if (!halloc(ctx, &h.a, 3 * n) || !halloc(ctx, &h.j, 3 * n) ||
         !halloc(ctx, &h.xp, 3 * n) || !halloc(ctx, &h.vp, 3 * n) ||
-        !halloc(ctx, &h.tau, n) || !halloc(ctx, &h.dt, n) || !halloc(ctx, &h.act, n) ||
+        !halloc(ctx, &h.tau, n) || !halloc(ctx, &h.dt, n) || !halloc(ctx, &h.dt0, n) ||
+        !halloc(ctx, &h.act, n) ||
         !halloc(ctx, &h.ctl, kHermCtl) || !halloc(ctx, &h.lev, kLevLen) ||
         !halloc(ctx, &h.bucket, (int64_t)(kHermK + 1) * n) || !halloc(ctx, &h.slot, n) ||
         !halloc(ctx, &h.fr, 3 * n) || !halloc(ctx, &h.potr, n) ||
@@ -664,6 +688,7 @@ pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const d
                       const int64_t* off, const int32_t* idx, int64_t cap, double T, double eta,
                       int64_t* stats, hipStream_t s) {
     auto& h = ctx->herm;
+    h.last_n = n;
     launch_zero_u64(ctx->irr_err, 1, s);
     IrrParams ip = herm_irr(ctx, n, r_in, r_out, eps, mass, off, idx, cap);
     ip.pos = pos;
@@ -682,6 +707,7 @@ pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const d
     hp.fr = fr;
     hp.tau = h.tau;
     hp.dt = h.dt;
+    hp.dt0 = h.dt0;
     hp.act = h.act;
     hp.ctl = h.ctl;
     if (!h.done) {
@@ -700,7 +726,7 @@ pbh_status do_hermite(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const d
     hp.dtmax = T / 4.0;
     hp.eta = eta;
     launch_zero_u64(h.lev, kLevLen, s);
-    launch_herm_start(hp, s);
+    launch_herm_start(hp, ip, s);
     launch_zero_u64(h.ctl, kHermCtl, s);
     ip.pos = h.xp;   // the block's force reads predicted states
     ip.vel = h.vp;
@@ -776,13 +802,20 @@ const char* pbh_status_string(pbh_status s) {
 const char* pbh_last_error(const pbh_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 static pbh_status resolve_params(pbh_ctx* ctx, const pbh_params* in, pbh_params* out) {
-    pbh_params p{8, 0, 0, PBH_MIXED};   // n_crit 0: chosen per build from N
+    pbh_params p{8, 0, 64, 0, 0, PBH_MIXED};   // n_crit 0: chosen per build from N
     if (in) {
+        const int t = in->walk_tile;
         if (in->leaf_size < 0 || in->n_crit < 0 || in->n_crit > 64 || in->key_bits < 0 ||
-            in->key_bits > 21 || (in->prec != PBH_FP64 && in->prec != PBH_MIXED))
-            return fail(ctx, PBH_E_ARG, "bad parameters (n_crit <= 64, key_bits <= 21)");
+            in->key_bits > 21 || (in->prec != PBH_FP64 && in->prec != PBH_MIXED) ||
+            (t != 0 && t != 64 && t != 96 && t != 128) || in->lanes_per_particle < 0 ||
+            in->lanes_per_particle > 64)
+            return fail(ctx, PBH_E_ARG,
+                        "bad parameters (n_crit <= 64, walk_tile 64/96/128, lanes_per_particle <= 64, "
+                        "key_bits <= 21)");
         if (in->leaf_size) p.leaf_size = in->leaf_size;
         if (in->n_crit) p.n_crit = in->n_crit;
+        if (t) p.walk_tile = t;
+        p.lanes_per_particle = in->lanes_per_particle;
         p.key_bits = in->key_bits;
         p.prec = in->prec;
     }
@@ -874,6 +907,8 @@ pbh_status pbh_build(pbh_ctx* ctx, int64_t n, const double* pos, const double* m
     if (st != PBH_OK) return st;
     mark(ctx, 1, s);
     ctx->ev_build = ctx->timing;
+    ctx->built_pos = pos;
+    ctx->built_mass = mass;
     return finish_build(ctx, s);
 }
 
@@ -899,13 +934,15 @@ pbh_status pbh_build_batched(pbh_ctx* ctx, int32_t n_clusters, const int64_t* of
     if (st != PBH_OK) return st;
     mark(ctx, 1, s);
     ctx->ev_build = ctx->timing;
+    ctx->built_pos = pos;
+    ctx->built_mass = mass;
     return finish_build(ctx, s);
 }
 
-pbh_status pbh_force_buffered(pbh_ctx* ctx, double r_in, double r_out, double r_buff, double theta,
-                              double eps, double* acc, double* pot, int64_t* nbr_off,
-                              int32_t* nbr_idx, int64_t nbr_cap, int64_t* nbr_total,
-                              pbh_stream_t stream) {
+pbh_status pbh_force_buffered(pbh_ctx* ctx, const double* pos, const double* mass, double r_in,
+                              double r_out, double r_buff, double theta, double eps, double* acc,
+                              double* pot, int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap,
+                              int64_t* nbr_total, pbh_stream_t stream) {
     if (!ctx) return PBH_E_ARG;
     pbh_status st = check_radii(ctx, r_in, r_out);
     if (st != PBH_OK) return st;
@@ -916,17 +953,18 @@ pbh_status pbh_force_buffered(pbh_ctx* ctx, double r_in, double r_out, double r_
     hipStream_t s = (hipStream_t)stream;
     ctx->last = s;
     std::vector<ClusterParams> cps(1, cluster_params(r_in, r_out, r_buff));
-    return do_force(ctx, cps, theta, eps, acc, pot, nbr_off, nbr_idx, nbr_cap, nbr_total, s);
+    return do_force(ctx, pos, mass, cps, theta, eps, acc, pot, nbr_off, nbr_idx, nbr_cap, nbr_total, s);
 }
 
-pbh_status pbh_force(pbh_ctx* ctx, double r_in, double r_out, double theta, double eps,
-                     double* acc, double* pot, int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap,
-                     int64_t* nbr_total, pbh_stream_t stream) {
-    return pbh_force_buffered(ctx, r_in, r_out, 0.0, theta, eps, acc, pot, nbr_off, nbr_idx,
-                              nbr_cap, nbr_total, stream);
+pbh_status pbh_force(pbh_ctx* ctx, const double* pos, const double* mass, double r_in, double r_out,
+                     double theta, double eps, double* acc, double* pot, int64_t* nbr_off,
+                     int32_t* nbr_idx, int64_t nbr_cap, int64_t* nbr_total, pbh_stream_t stream) {
+    return pbh_force_buffered(ctx, pos, mass, r_in, r_out, 0.0, theta, eps, acc, pot, nbr_off,
+                              nbr_idx, nbr_cap, nbr_total, stream);
 }
 
-pbh_status pbh_force_batched_buffered(pbh_ctx* ctx, const double* r_in, const double* r_out,
+pbh_status pbh_force_batched_buffered(pbh_ctx* ctx, const double* pos, const double* mass,
+                                      const double* r_in, const double* r_out,
                                       const double* r_buff, double theta, double eps, double* acc,
                                       double* pot, int64_t* nbr_off, int32_t* nbr_idx,
                                       int64_t nbr_cap, int64_t* nbr_total, pbh_stream_t stream) {
@@ -944,15 +982,15 @@ pbh_status pbh_force_batched_buffered(pbh_ctx* ctx, const double* r_in, const do
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     ctx->last = s;
-    return do_force(ctx, cps, theta, eps, acc, pot, nbr_off, nbr_idx, nbr_cap, nbr_total, s);
+    return do_force(ctx, pos, mass, cps, theta, eps, acc, pot, nbr_off, nbr_idx, nbr_cap, nbr_total, s);
 }
 
-pbh_status pbh_force_batched(pbh_ctx* ctx, const double* r_in, const double* r_out, double theta,
-                             double eps, double* acc, double* pot, int64_t* nbr_off,
-                             int32_t* nbr_idx, int64_t nbr_cap, int64_t* nbr_total,
+pbh_status pbh_force_batched(pbh_ctx* ctx, const double* pos, const double* mass, const double* r_in,
+                             const double* r_out, double theta, double eps, double* acc, double* pot,
+                             int64_t* nbr_off, int32_t* nbr_idx, int64_t nbr_cap, int64_t* nbr_total,
                              pbh_stream_t stream) {
-    return pbh_force_batched_buffered(ctx, r_in, r_out, nullptr, theta, eps, acc, pot, nbr_off,
-                                      nbr_idx, nbr_cap, nbr_total, stream);
+    return pbh_force_batched_buffered(ctx, pos, mass, r_in, r_out, nullptr, theta, eps, acc, pot,
+                                      nbr_off, nbr_idx, nbr_cap, nbr_total, stream);
 }
 
 pbh_status pbh_irregular(pbh_ctx* ctx, int64_t n, const double* pos, const double* vel,
@@ -1014,6 +1052,8 @@ pbh_status pbh_core(pbh_ctx* ctx, const double* pos, const double* mass, int64_t
     const int64_t n = ctx->cfg.n;
     if (n < 7) return fail(ctx, PBH_E_ARG, "need at least 7 particles (6 neighbours each)");
     if (!pos || !mass || !sample || !out) return fail(ctx, PBH_E_ARG, "pos, mass, sample and out are required");
+    if (pos != ctx->built_pos || mass != ctx->built_mass)
+        return fail(ctx, PBH_E_STATE, "pos and mass must be the arrays of the last build");
     if (n_sample < 1 || n_sample > n) return fail(ctx, PBH_E_ARG, "need 1 <= n_sample <= n");
     if (!(std::isfinite(eta) && eta > 0.0)) return fail(ctx, PBH_E_ARG, "eta must be finite and > 0");
     HIP_TRY(hipSetDevice(ctx->device));
@@ -1122,8 +1162,8 @@ static pbh_status p3t_regular(pbh_ctx* ctx, int64_t n, const double* pos, const 
     if (st != PBH_OK) return st;
     for (int attempt = 0; attempt < 3; ++attempt) {
         int64_t total = 0;
-        st = pbh_force_buffered(ctx, r_in, r_out, r_buff, theta, eps, h.fr, h.potr, h.off, h.idx, h.cap,
-                                &total, s);
+        st = pbh_force_buffered(ctx, pos, mass, r_in, r_out, r_buff, theta, eps, h.fr, h.potr, h.off,
+                                h.idx, h.cap, &total, s);
         if (st != PBH_E_NBR_OVERFLOW) return st;
         const int64_t want = total + total / 4 + 1024;
         int32_t* q = nullptr;
@@ -1216,8 +1256,9 @@ static void kdk_force(pbh_ctx* ctx, const double* pos, const double* mass, doubl
     w.theta = theta;
     w.eps = eps;
     w.mixed = ctx->params.prec == PBH_MIXED;
-    const int gmax = w.mixed ? ctx->grid_mixed : ctx->grid_fp64;
-    w.grid = gmax;
+    w.tile = ctx->params.walk_tile;
+    w.max_copies = ctx->params.lanes_per_particle ? ctx->params.lanes_per_particle : 64;
+    w.grid = walk_grid(ctx, w.mixed);
     w.stack_cap = kStackCap;
     w.count_nbr = 0;
     w.stage_cap = 0;
@@ -1287,13 +1328,15 @@ static pbh_status kdk_impl(pbh_ctx* ctx, int64_t n, double* pos, double* vel, co
         }
         for (int k = 0; k < steps; ++k) HIP_TRY(hipGraphLaunch(ctx->gexec, s));
     }
-    ctx->built = true;
+    ctx->built = true;   // the tree of the final positions
+    ctx->built_pos = pos;
+    ctx->built_mass = mass;
     return PBH_OK;
 }
 
-pbh_status pbh_kdk(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
-                   double dt, int32_t steps, double r_in, double r_out, double theta, double eps,
-                   double* energy_out, pbh_stream_t stream) {
+pbh_status pbh_kdk_graph(pbh_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
+                         double dt, int32_t steps, double r_in, double r_out, double theta,
+                         double eps, double* energy_out, pbh_stream_t stream) {
     return kdk_impl(ctx, n, pos, vel, mass, dt, steps, r_in, r_out, theta, eps, energy_out,
                     (hipStream_t)stream, true);
 }
@@ -1342,6 +1385,9 @@ pbh_status pbh_get_stats(pbh_ctx* ctx, pbh_stats* out) {
     out->n_pn = (int64_t)h[kCntPN];
     out->n_pp_far = (int64_t)h[kCntFar];
     out->n_pp_near = (int64_t)h[kCntNear];
+    out->lane_slots_pn = (int64_t)h[kCntSlotPN];
+    out->lane_slots_far = (int64_t)h[kCntSlotFar];
+    out->lane_slots_near = (int64_t)h[kCntSlotNear];
     out->error_flags |= (int64_t)h[kErr];
     if (ctx->ev_build) out->ms_build = event_ms(ctx->ev[0], ctx->ev[1]);
     if (ctx->ev_walk) out->ms_walk = event_ms(ctx->ev[2], ctx->ev[3]);
@@ -1391,7 +1437,7 @@ pbh_status pbh_debug_wave_log(pbh_ctx* ctx, uint64_t* walk, uint64_t* nbr, int64
     if (!ctx || !ctx->d.wave_log) return PBH_E_ARG;
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(hipStreamSynchronize(ctx->last));
-    const int64_t gw = ctx->params.prec == PBH_MIXED ? ctx->grid_mixed : ctx->grid_fp64;
+    const int64_t gw = walk_grid(ctx, ctx->params.prec == PBH_MIXED);
     const int64_t gn = ctx->grid_mixed;
     if (n_walk) *n_walk = gw;
     if (n_nbr) *n_nbr = gn;
@@ -1399,6 +1445,19 @@ pbh_status pbh_debug_wave_log(pbh_ctx* ctx, uint64_t* walk, uint64_t* nbr, int64
         HIP_TRY(hipMemcpy(walk, ctx->d.wave_log, 16 * gw, hipMemcpyDeviceToHost));
     if (nbr && cap >= gn)
         HIP_TRY(hipMemcpy(nbr, ctx->d.wave_log_nbr, 16 * gn, hipMemcpyDeviceToHost));
+    return PBH_OK;
+}
+
+pbh_status pbh_debug_herm_first_steps(pbh_ctx* ctx, int64_t cap, int64_t* ticks, int64_t* n_out) {
+    if (!ctx) return PBH_E_ARG;
+    const auto& h = ctx->herm;
+    if (h.last_n < 1) return fail(ctx, PBH_E_STATE, "no Hermite integration yet");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipStreamSynchronize(ctx->last));
+    if (n_out) *n_out = h.last_n;
+    if (!ticks) return PBH_OK;
+    if (cap < h.last_n) return fail(ctx, PBH_E_ARG, "buffer too small");
+    HIP_TRY(hipMemcpy(ticks, h.dt0, sizeof(int64_t) * h.last_n, hipMemcpyDeviceToHost));
     return PBH_OK;
 }
 

@@ -31,10 +31,14 @@ enum : unsigned long long {
     kErrNodeCap = 4ull,       // node capacity exceeded in the build
     kErrNonFinite = 8ull,     // NaN/Inf in positions or masses
     kErrNbrStack = 16ull,     // neighbour traversal stack full
+    kErrStale = 32ull,        // pos or mass changed since the build (force call)
 };
 
 // slots of the device counter array
+// kCntSlot*: wave-instruction slots of the walk's evaluation loops (64 lanes
+// per loop iteration), beside the interactions they carried (kCntPN, ...)
 enum { kCntNodes = 0, kCntPN = 1, kCntFar = 2, kCntNear = 3, kCntNbrTotal = 4, kErr = 5,
+       kCntSlotPN = 6, kCntSlotFar = 7, kCntSlotNear = 8,
        kCntMaxLevel = 9, kCntLeaves = 10, kCntGroups = 12, kCntFill = 13, kNumCounters = 16 };
 
 struct alignas(16) WNode {
@@ -227,6 +231,10 @@ struct WalkCfg {
     double theta;
     double eps;
     int mixed;
+    int tile = 64;         // LDS tile capacity (64, 96 or 128)
+    int max_copies = 64;   // most sub-wave copies of a small group
+    const double* cpos = nullptr;    // caller's arrays for the stale-input check, or null
+    const double* cmass = nullptr;
     int grid;
     int stack_cap;
     int count_nbr;   // also count neighbours per particle into Dev::nbr_cnt
@@ -235,7 +243,7 @@ struct WalkCfg {
 void launch_rcrit(Dev& d, const BuildCfg& c, double theta, hipStream_t s);
 void launch_walk(Dev& d, const BuildCfg& c, const WalkCfg& w, double* acc, double* pot,
                  hipStream_t s);
-int walk_blocks_per_cu(int mixed);
+int walk_blocks_per_cu(int mixed, int tile);
 
 // nbr.hip
 void launch_nbr_copy(Dev& d, const BuildCfg& c, int stage_cap, const int64_t* off, int32_t* idx,
@@ -326,6 +334,7 @@ struct HermParams {
     const double* fr = nullptr;  // [n][3] regular force (step criterion), or null
     int64_t* tau = nullptr;      // [n] ticks
     int64_t* dt = nullptr;       // [n] ticks
+    int64_t* dt0 = nullptr;      // [n] first step of the regular step (ticks), or null
     int32_t* act = nullptr;      // [n] active list
     unsigned long long* ctl = nullptr;   // [kHermCtl]
     unsigned long long* lev = nullptr;   // [kLevLen]
@@ -340,7 +349,9 @@ struct HermParams {
     double dtmax = 0.0;          // T / 4
     double eta = 0.02;
 };
-void launch_herm_start(const HermParams& p, hipStream_t s);
+// first steps (eq. dt with the computed second and third derivatives of F_I;
+// ip: masses, radii and softening of the irregular force, and its error word)
+void launch_herm_start(const HermParams& p, const IrrParams& ip, hipStream_t s);
 // one block: front (next time, active list, prediction), then the irregular
 // force of the active list with the corrector; parity = block number & 1
 void launch_herm_front(const HermParams& p, int parity, hipStream_t s);

@@ -17,7 +17,7 @@
 //   open   otherwise: a leaf becomes particle-particle work, an inner node
 //          pushes its children.
 // Accepted nodes and leaf particles are compacted with ballot + prefix sums
-// into LDS tiles of up to 64 entries (FP32 in the mixed path: positions
+// into LDS tiles of TC entries (64, 96 or 128; FP32 in the mixed path: positions
 // relative to the group centre, formed in FP64 first); a tile is evaluated
 // just before it would overflow, every lane reading each entry by LDS
 // broadcast. Tile partial sums are
@@ -31,27 +31,31 @@ namespace pbh {
 
 namespace {
 
-constexpr int TCAP = 64;    // tile capacity; a tile is evaluated before it would overflow
-
+// Tile capacity TC (a template parameter, 64, 96 or 128): a tile is evaluated
+// just before it would overflow. One traversal step adds at most 64 entries of
+// a kind, so TC >= 64.
+//
 // Near entries of the FP64 walk keep their original coordinates for the
 // neighbour test; the mixed walk keeps the sorted index instead and reads the
 // coordinates from global memory in the rare case the FP64 test is needed
-// (10 KB of LDS per wave: 16 waves per CU).
-template <typename R>
+// (10 KB of LDS per wave with TC = 64: 16 waves per CU).
+template <typename R, int TC>
 struct NearExtra {
-    double nx[TCAP], ny[TCAP], nz[TCAP];
+    double nx[TC], ny[TC], nz[TC];
 };
-template <>
-struct NearExtra<float> {
-    int nears[TCAP];     // sorted index
+template <int TC>
+struct NearExtra<float, TC> {
+    int nears[TC];     // sorted index
 };
 
-template <typename R>
-struct alignas(16) Tiles : NearExtra<R> {
-    R pn[TCAP][12];      // cx cy cz M | qxx qyy qzz qxy | qxz qyz - -
-    R far[TCAP][4];      // x y z m (relative to the group centre)
-    R nearp[TCAP][4];
-    int nearj[TCAP];     // caller index: skips the self pair, and is the neighbour index
+template <typename R, int TC>
+struct alignas(16) Tiles : NearExtra<R, TC> {
+    static_assert(TC >= 64, "one traversal step adds up to 64 entries");
+    static constexpr int kCap = TC;
+    R pn[TC][12];        // cx cy cz M | qxx qyy qzz qxy | qxz qyz - -
+    R far[TC][4];        // x y z m (relative to the group centre)
+    R nearp[TC][4];
+    int nearj[TC];       // caller index: skips the self pair, and is the neighbour index
     int lf_ex[64];       // leaf expansion: exclusive prefix of particle counts
     int lf_beg[64];
 };
@@ -87,6 +91,9 @@ struct WalkParams {
     int scap;                       // entries per staging row
     int8_t* stage_k;                // per sorted particle: 1 = list staged, 0 = left to the fill pass
     int32_t* fill_list;             // groups left to the fill pass
+    int max_copies;                 // most sub-wave copies of a small group (1..64)
+    const double* cpos;             // caller's pos [n][3] and mass [n]: compared with the
+    const double* cmass;            // build's sorted copy (changed in place: kErrStale), or null
 };
 
 __device__ inline void two_sum_acc(float& hi, float& lo, float v) {
@@ -166,8 +173,8 @@ __device__ inline void for_entries(int cnt, int ksub, int sub, F&& body) {
 
 // Monopole + traceless quadrupole: phi = -M/s - (R^T Q R)/(2 s^5), a = -grad phi
 //   a = -(M/s^3 + (5/2) (R^T Q R)/s^7) R + Q R / s^5,   R = x_i - COM
-template <typename R>
-__device__ inline void eval_pn(const Tiles<R>& T, int cnt, int ksub, int sub, R px, R py, R pz, R eps2,
+template <typename R, int TC>
+__device__ inline void eval_pn(const Tiles<R, TC>& T, int cnt, int ksub, int sub, R px, R py, R pz, R eps2,
                                Acc<R>& A) {
     R ax = 0, ay = 0, az = 0, ph = 0;
     for_entries<2>(cnt, ksub, sub, [&](int e) {
@@ -196,8 +203,8 @@ __device__ inline void eval_pn(const Tiles<R>& T, int cnt, int ksub, int sub, R 
 // tile holds Q' = 2.5 Q, so with q' = Q' R and t' = R.q' / s^5 (= 2.5 t):
 //   cr = M/s^3 + t'/s^2,  a += 0.4 q'/s^5 - cr R,  phi += -M/s - 0.2 t'.
 // The q'/s^5 terms are summed apart and scaled by 0.4 once per tile.
-template <>
-__device__ inline void eval_pn<float>(const Tiles<float>& T, int cnt, int ksub, int sub, float px,
+template <int TC>
+__device__ inline void eval_pn_f32(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
                                       float py, float pz, float eps2, Acc<float>& A) {
     float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
     float bx = 0.f, by = 0.f, bz = 0.f;
@@ -229,8 +236,8 @@ __device__ inline void eval_pn<float>(const Tiles<float>& T, int cnt, int ksub, 
 }
 
 // Pairs of far leaves: every pair is at r >= R >= r_out, where W = 1.
-template <typename R>
-__device__ inline void eval_far(const Tiles<R>& T, int cnt, int ksub, int sub, R px, R py, R pz, R eps2,
+template <typename R, int TC>
+__device__ inline void eval_far(const Tiles<R, TC>& T, int cnt, int ksub, int sub, R px, R py, R pz, R eps2,
                                 Acc<R>& A) {
     R ax = 0, ay = 0, az = 0, ph = 0;
     for_entries<4>(cnt, ksub, sub, [&](int e) {
@@ -248,8 +255,8 @@ __device__ inline void eval_far(const Tiles<R>& T, int cnt, int ksub, int sub, R
     A.add(ax, ay, az, ph);
 }
 
-template <>
-__device__ inline void eval_far<float>(const Tiles<float>& T, int cnt, int ksub, int sub, float px,
+template <int TC>
+__device__ inline void eval_far_f32(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
                                        float py, float pz, float eps2, Acc<float>& A) {
     float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
     for_entries<4>(cnt, ksub, sub, [&](int e) {
@@ -295,8 +302,8 @@ __device__ inline bool is_neighbour(double xj, double yj, double zj, double xi, 
 // optionally also counts the neighbours inside the list radius R (FP64 test).
 // optionally also stores them in the lane's staging row (`srow`, at most
 // `scap` entries, kStageStride apart).
-template <typename R>
-__device__ inline void eval_near(const Tiles<R>& T, int cnt, int ksub, int sub, R px, R py, R pz, R eps2,
+template <typename R, int TC>
+__device__ inline void eval_near(const Tiles<R, TC>& T, int cnt, int ksub, int sub, R px, R py, R pz, R eps2,
                                  int self, const NearK<R>& K, Acc<R>& A, bool count_nbr, double xi,
                                  double yi, double zi, double rlist2, int& nbr, int32_t* srow, int scap) {
     R ax = 0, ay = 0, az = 0, ph = 0;
@@ -333,8 +340,8 @@ __device__ inline void eval_near(const Tiles<R>& T, int cnt, int ksub, int sub, 
 // FP32 form without per-lane branches: the neighbour count and the pole
 // terms (-d0/s + l1 ln s, present when r_in > 0) are compile-time switches,
 // ln s = log2(s) ln 2, and the boundary cases of W and Phi_R are selects.
-template <bool CNT, bool POLE>
-__device__ inline void eval_near_f32(const Tiles<float>& T, int cnt, int ksub, int sub, float px,
+template <bool CNT, bool POLE, int TC>
+__device__ inline void eval_near_f32(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
                                      float py, float pz, float eps2, int self, const NearK<float>& K,
                                      Acc<float>& A, double xi, double yi, double zi, double rlist2,
                                      int& nbr, int32_t* srow, int scap) {
@@ -401,28 +408,42 @@ __device__ inline void eval_near_f32(const Tiles<float>& T, int cnt, int ksub, i
     A.add(ax, ay, az, ph);
 }
 
-template <>
-__device__ inline void eval_near<float>(const Tiles<float>& T, int cnt, int ksub, int sub, float px,
-                                        float py, float pz, float eps2, int self, const NearK<float>& K,
-                                        Acc<float>& A, bool count_nbr, double xi, double yi, double zi,
-                                        double rlist2, int& nbr, int32_t* srow, int scap) {
+// The mixed walk's forms (explicit FMA chains above), chosen per precision.
+template <int TC>
+__device__ inline void eval_pn(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
+                               float py, float pz, float eps2, Acc<float>& A) {
+    eval_pn_f32<TC>(T, cnt, ksub, sub, px, py, pz, eps2, A);
+}
+
+template <int TC>
+__device__ inline void eval_far(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
+                                float py, float pz, float eps2, Acc<float>& A) {
+    eval_far_f32<TC>(T, cnt, ksub, sub, px, py, pz, eps2, A);
+}
+
+template <int TC>
+__device__ inline void eval_near(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
+                                 float py, float pz, float eps2, int self, const NearK<float>& K,
+                                 Acc<float>& A, bool count_nbr, double xi, double yi, double zi,
+                                 double rlist2, int& nbr, int32_t* srow, int scap) {
     if (count_nbr) {
         if (K.pole)
-            eval_near_f32<true, true>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
+            eval_near_f32<true, true, TC>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
         else
-            eval_near_f32<true, false>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
+            eval_near_f32<true, false, TC>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
     } else {
         if (K.pole)
-            eval_near_f32<false, true>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
+            eval_near_f32<false, true, TC>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
         else
-            eval_near_f32<false, false>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
+            eval_near_f32<false, false, TC>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
     }
 }
 
-template <bool MIXED>
+template <bool MIXED, int TC>
 __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
     using R = typename std::conditional<MIXED, float, double>::type;
-    __shared__ Tiles<R> T;
+    constexpr int TCAP = TC;
+    __shared__ Tiles<R, TC> T;
     __shared__ int s_stack[kStackLds];
     const int lane = threadIdx.x;
     const Stack stack{s_stack, p.stack + (int64_t)blockIdx.x * (p.stack_cap - kStackLds), p.stack_cap};
@@ -475,7 +496,8 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
 
         // sub-wave copies of a small group (see for_entries); lanes beyond
         // ksub * gcnt duplicate copy 0 and are ignored at the merge
-        const int ksub = 64 / gcnt;
+        const int kfit = 64 / gcnt;
+        const int ksub = kfit < p.max_copies ? kfit : p.max_copies;
         const int copy = lane / gcnt;
         const int pl = lane - copy * gcnt;
         const int sub = copy < ksub ? copy : 0;
@@ -483,6 +505,13 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
         const int me = gb + pl;
         const double xi = p.x[me], yi = p.y[me], zi = p.z[me];
         const int orig_me = p.perm[me];
+        if (p.cpos) {
+            // the caller's arrays must still hold what the build sorted
+            const int64_t o3 = 3 * (int64_t)orig_me;
+            const bool stale = active && (p.cpos[o3] != xi || p.cpos[o3 + 1] != yi ||
+                                          p.cpos[o3 + 2] != zi || p.cmass[orig_me] != p.m[me]);
+            if (__ballot(stale)) atomicOr(&p.cnt[kErr], lane == 0 ? kErrStale : 0ull);
+        }
         // Neighbour staging. A particle's row holds p.scap entries; an unsplit
         // group uses it whole, a split group gives each copy a sub-row of
         // wrow = p.scap / ksub entries (joined into one list after the walk).
@@ -502,6 +531,8 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
 
         int npn = 0, nfar = 0, nnear = 0;
         unsigned long long c_pn = 0, c_far = 0, c_near = 0;
+        // loop iterations of the evaluations (each occupies all 64 lanes)
+        unsigned long long it_pn = 0, it_far = 0, it_near = 0;
         stack.put(0, root);   // every lane stores the same value
         int top = 1;
         bool overflow = false;
@@ -526,7 +557,8 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                 const int k = uni(__popcll(mk));
                 if (npn + k > TCAP) {
                     __syncthreads();
-                    eval_pn<R>(T, npn, ksub, sub, px, py, pz, eps2, A);
+                    it_pn += (npn + ksub - 1) / ksub;
+                    eval_pn(T, npn, ksub, sub, px, py, pz, eps2, A);
                     npn = 0;
                     __syncthreads();
                 }
@@ -585,8 +617,9 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                     const int add = (total - base) < 64 ? (total - base) : 64;
                     if (fill + add > TCAP) {
                         __syncthreads();
-                        if (cls == 0) eval_far<R>(T, fill, ksub, sub, px, py, pz, eps2, A);
-                        else eval_near<R>(T, fill, ksub, sub, px, py, pz, eps2, orig_me, K, A, count_nbr, xi, yi, zi, rlist2, nbr, srow, scap);
+                        (cls == 0 ? it_far : it_near) += (fill + ksub - 1) / ksub;
+                        if (cls == 0) eval_far(T, fill, ksub, sub, px, py, pz, eps2, A);
+                        else eval_near(T, fill, ksub, sub, px, py, pz, eps2, orig_me, K, A, count_nbr, xi, yi, zi, rlist2, nbr, srow, scap);
                         fill = 0;
                         __syncthreads();
                     }
@@ -613,9 +646,12 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
             }
         }
         __syncthreads();
-        if (npn) eval_pn<R>(T, npn, ksub, sub, px, py, pz, eps2, A);
-        if (nfar) eval_far<R>(T, nfar, ksub, sub, px, py, pz, eps2, A);
-        if (nnear) eval_near<R>(T, nnear, ksub, sub, px, py, pz, eps2, orig_me, K, A, count_nbr, xi, yi, zi, rlist2, nbr, srow, scap);
+        it_pn += (npn + ksub - 1) / ksub;
+        it_far += (nfar + ksub - 1) / ksub;
+        it_near += (nnear + ksub - 1) / ksub;
+        if (npn) eval_pn(T, npn, ksub, sub, px, py, pz, eps2, A);
+        if (nfar) eval_far(T, nfar, ksub, sub, px, py, pz, eps2, A);
+        if (nnear) eval_near(T, nnear, ksub, sub, px, py, pz, eps2, orig_me, K, A, count_nbr, xi, yi, zi, rlist2, nbr, srow, scap);
         __syncthreads();
 
         // a row that overflowed sends the group's lists to the fill pass
@@ -679,6 +715,10 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
         atomicAdd(&p.cnt[kCntPN], c_pn * l0);
         atomicAdd(&p.cnt[kCntFar], c_far * l0);
         atomicAdd(&p.cnt[kCntNear], c_near * l0);
+        const unsigned long long w0 = lane == 0 ? 64ull : 0ull;
+        atomicAdd(&p.cnt[kCntSlotPN], it_pn * w0);
+        atomicAdd(&p.cnt[kCntSlotFar], it_far * w0);
+        atomicAdd(&p.cnt[kCntSlotNear], it_near * w0);
     }
     if (p.wave_log) {
         p.wave_log[2 * blockIdx.x] = (unsigned long long)n_walked;
@@ -696,6 +736,7 @@ __global__ void k_rcrit(WNode* __restrict__ node, const unsigned long long* __re
     if (blockIdx.x == 0 && threadIdx.x < 3 * kQueues) queues[threadIdx.x] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         cnt[kCntPN] = 0; cnt[kCntFar] = 0; cnt[kCntNear] = 0; cnt[kCntFill] = 0;
+        cnt[kCntSlotPN] = 0; cnt[kCntSlotFar] = 0; cnt[kCntSlotNear] = 0;
     }
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n;
          b += (int64_t)gridDim.x * blockDim.x) {
@@ -720,10 +761,15 @@ void launch_rcrit(Dev& d, const BuildCfg& c, double theta, hipStream_t s) {
                        (const unsigned long long*)(d.cnt + kCntNodes), theta, d.cnt, d.queues);
 }
 
-int walk_blocks_per_cu(int mixed) {
+template <bool MIXED>
+static auto walk_kernel(int tile) {
+    return tile == 128 ? k_walk<MIXED, 128> : (tile == 96 ? k_walk<MIXED, 96> : k_walk<MIXED, 64>);
+}
+
+int walk_blocks_per_cu(int mixed, int tile) {
     int nb = 0;
-    if (mixed) hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk<true>, 64, 0);
-    else hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk<false>, 64, 0);
+    if (mixed) hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<true>(tile), 64, 0);
+    else hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<false>(tile), 64, 0);
     return nb > 0 ? nb : 1;
 }
 
@@ -753,8 +799,11 @@ void launch_walk(Dev& d, const BuildCfg& c, const WalkCfg& w, double* acc, doubl
     p.scap = w.stage_cap;
     p.stage_k = d.stage_k;
     p.fill_list = d.fill_list;
-    if (w.mixed) hipLaunchKernelGGL(k_walk<true>, dim3(w.grid), dim3(64), 0, s, p);
-    else hipLaunchKernelGGL(k_walk<false>, dim3(w.grid), dim3(64), 0, s, p);
+    p.max_copies = w.max_copies;
+    p.cpos = w.cpos;
+    p.cmass = w.cmass;
+    if (w.mixed) hipLaunchKernelGGL(walk_kernel<true>(w.tile), dim3(w.grid), dim3(64), 0, s, p);
+    else hipLaunchKernelGGL(walk_kernel<false>(w.tile), dim3(w.grid), dim3(64), 0, s, p);
 }
 
 }  // namespace pbh

@@ -54,6 +54,44 @@ def test_hermite_matches_oracle():
     assert np.abs(gv - ov).max() <= 1e-10 * np.abs(ov).max()
 
 
+def _first_step_ticks(want, dtmax, kmax=40):
+    # dt_max / 2^k not above the wanted step, k <= 40, as ticks of dt_max / 2^40
+    out = np.empty(want.size, dtype=np.int64)
+    for i, w in enumerate(want):
+        d, k = dtmax, 0
+        while d > w and k < kmax:
+            d *= 0.5
+            k += 1
+        out[i] = 1 << (kmax - k)
+    return out
+
+
+@pytest.mark.parametrize("n,seed,nbar,eps", [(2048, 95, 16.0, 1e-4), (1024, 96, 6.0, 0.0)])
+def test_first_steps_are_eq_dt(n, seed, nbar, eps):
+    # Section 2.1 (after eq. dt): every particle starts the regular step on the
+    # step eq. dt asks for with the computed second and third derivatives of
+    # F_I. The GPU's first step of each particle equals the oracle's, exactly;
+    # particles with no pair inside r_out start on dt_max.
+    c, r_in, r_out = _setup(n, seed, nbar)
+    T, eta = 1.0 / 256, 0.02
+    r_buff = 3.0 * np.linalg.norm(c.vel, axis=1).max() * T
+    p = _pbh(prec="fp64")
+    pos, vel, mass = _t(c.pos), _t(c.vel), _t(c.mass)
+    p.build(pos, mass)
+    fr, _, off, idx = p.force(r_in, r_out, 0.0, eps, r_buff=r_buff)
+    p.hermite(pos, vel, mass, fr, r_in, r_out, eps, off, idx, T, eta)
+    ticks = p.debug_herm_first_steps()
+    ofr, _ = oracle.direct(c.pos, c.mass, r_in, r_out, eps)
+    _, _, ost = oracle.hermite(c.pos, c.vel, c.mass, r_in, r_out, eps, T, eta=eta, fr=ofr, want=True)
+    ref = _first_step_ticks(ost["want_start"], T / 4)
+    assert np.array_equal(ticks, ref)
+    assert (ref < (1 << 40)).sum() > n // 4      # most particles start below dt_max
+    o_off, _ = oracle.nbr_brute(c.pos, r_out)
+    lonely = np.diff(o_off) == 0
+    if lonely.any():
+        assert np.all(ticks[lonely] == 1 << 40)
+
+
 def test_p3t_matches_oracle():
     c, r_in, r_out = _setup(384, 92, 12.0)
     eps, T, eta, steps = 1e-4, 1.0 / 256, 0.02, 3

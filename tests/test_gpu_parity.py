@@ -309,8 +309,9 @@ def test_error_paths():
     off = torch.empty(c.n + 1, dtype=torch.int64, device=DEV)
     idx = torch.empty(10, dtype=torch.int32, device=DEV)
     tot = C.c_int64(0)
-    st = p.L.pbh_force(p.ctx, 0.02, 0.2, 0.5, 0.0, _ptr(acc), _ptr(pot), _ptr(off), _ptr(idx), 10,
-                       C.byref(tot), _stream())
+    bp, bm = p._built
+    st = p.L.pbh_force(p.ctx, _ptr(bp), _ptr(bm), 0.02, 0.2, 0.5, 0.0, _ptr(acc), _ptr(pot), _ptr(off),
+                       _ptr(idx), 10, C.byref(tot), _stream())
     assert st == PBH_E_NBR_OVERFLOW and tot.value > 10
     o_off, _ = oracle.nbr_cells(c.pos, 0.2)
     assert tot.value == o_off[-1]
@@ -318,9 +319,57 @@ def test_error_paths():
     oa, _ = oracle.direct(c.pos, c.mass, 0.02, 0.2, 0.0)
     assert np.median(_rel(acc.cpu().numpy(), oa)) < 1e-3
     # overflow without a host wait: entries beyond the capacity are dropped and flagged
-    st = p.L.pbh_force(p.ctx, 0.02, 0.2, 0.5, 0.0, _ptr(acc), _ptr(pot), _ptr(off), _ptr(idx), 10,
-                       None, _stream())
+    st = p.L.pbh_force(p.ctx, _ptr(bp), _ptr(bm), 0.02, 0.2, 0.5, 0.0, _ptr(acc), _ptr(pot), _ptr(off),
+                       _ptr(idx), 10, None, _stream())
     assert st == 0 and p.stats()["error_flags"] & 1
+
+
+def test_force_needs_the_built_arrays():
+    # The REGF-style contract: pbh_force takes the particles again; they must be
+    # the arrays of the last build, unchanged (PBH_E_STATE otherwise)
+    import ctypes as C
+
+    from paper_2110_11658_amd._lib import PBH_E_STATE
+    from paper_2110_11658_amd.api import _ptr, _stream
+    c = ic.plummer(3000, seed=21)
+    p = _pbh()
+    pos, mass = _t(c.pos), _t(c.mass)
+    acc = torch.empty((c.n, 3), dtype=torch.float64, device=DEV)
+    pot = torch.empty(c.n, dtype=torch.float64, device=DEV)
+    off = torch.empty(c.n + 1, dtype=torch.int64, device=DEV)
+    idx = torch.empty(200000, dtype=torch.int32, device=DEV)
+    tot = C.c_int64(0)
+
+    def force(pp, mm, total=True):
+        return p.L.pbh_force(p.ctx, _ptr(pp), _ptr(mm), 0.01, 0.1, 0.5, 0.0, _ptr(acc), _ptr(pot),
+                             _ptr(off), _ptr(idx), idx.shape[0], C.byref(tot) if total else None,
+                             _stream())
+    assert force(pos, mass) == PBH_E_STATE            # no build yet
+    p.build(pos, mass)
+    assert force(pos, mass) == 0
+    a0 = acc.clone()
+    copy = pos.clone()                                 # same values, other array
+    assert force(copy, mass) == PBH_E_STATE
+    assert force(pos, mass.clone()) == PBH_E_STATE
+    assert b"last build" in p.L.pbh_last_error(p.ctx)
+    # moved in place since the build: detected by the walk
+    pos[123, 0] += 1e-9
+    assert force(pos, mass) == PBH_E_STATE
+    assert b"changed" in p.L.pbh_last_error(p.ctx)
+    assert force(pos, mass, total=False) == 0         # no wait: reported in the flags
+    assert p.stats()["error_flags"] & 32
+    mass[7] *= 2.0
+    pos[123, 0] -= 1e-9                                # (may not restore the bits exactly)
+    p.build(pos, mass)
+    assert force(pos, mass) == 0 and not (p.stats()["error_flags"] & 32)
+    assert not torch.equal(acc, a0)                   # mass 7 doubled since the first call
+    # the core quantities take the built arrays too
+    from paper_2110_11658_amd._lib import PbhError
+    sample = torch.arange(0, c.n, 3, dtype=torch.int32, device=DEV)
+    with pytest.raises(PbhError) as e:
+        p.core(copy, mass, sample)
+    assert e.value.status == PBH_E_STATE
+    p.core(pos, mass, sample)
 
 
 def test_deterministic_repeat():
