@@ -74,16 +74,18 @@ def test_core_ties_and_small_inputs():
     mass = rng.uniform(0.5, 1.5, pos.shape[0])
     smp = np.arange(0, pos.shape[0], 5).astype(np.int32)
     p = _pbh(leaf_size=4)
-    p.build(_t(pos), _t(mass))
-    rho, got = p.core(_t(pos), _t(mass), _t(smp))
+    pos_d, mass_d = _t(pos), _t(mass)
+    p.build(pos_d, mass_d)
+    rho, got = p.core(pos_d, mass_d, _t(smp))
     _check(pos, mass, smp, rho.cpu().numpy(), got)
     # seven particles: each one's neighbours are all the others
     pos7 = rng.normal(size=(7, 3))
     m7 = np.ones(7)
     q = _pbh()
-    q.build(_t(pos7), _t(m7))
+    pos7_d, m7_d = _t(pos7), _t(m7)
+    q.build(pos7_d, m7_d)
     smp7 = np.arange(7, dtype=np.int32)
-    rho7, got7 = q.core(_t(pos7), _t(m7), _t(smp7))
+    rho7, got7 = q.core(pos7_d, m7_d, _t(smp7))
     _check(pos7, m7, smp7, rho7.cpu().numpy(), got7)
 
 

@@ -38,8 +38,10 @@ def _setup(n, seed, nbar):
 
 
 def test_hermite_matches_oracle():
+    # a regular step of 1/16 (dt_max = 1/64): eq. dt puts a fifth of the
+    # particles below dt_max and the deepest at level 8
     c, r_in, r_out = _setup(512, 91, 16.0)
-    eps, T, eta = 1e-4, 1.0 / 256, 0.02
+    eps, T, eta = 1e-4, 1.0 / 16, 0.02
     r_buff = 3.0 * np.linalg.norm(c.vel, axis=1).max() * T
     p = _pbh(prec="fp64")
     pos, vel, mass = _t(c.pos), _t(c.vel), _t(c.mass)
@@ -48,7 +50,7 @@ def test_hermite_matches_oracle():
     st = p.hermite(pos, vel, mass, fr, r_in, r_out, eps, off, idx, T, eta)
     ofr, _ = oracle.direct(c.pos, c.mass, r_in, r_out, eps)
     ox, ov, ost = oracle.hermite(c.pos, c.vel, c.mass, r_in, r_out, eps, T, eta=eta, fr=ofr)
-    assert st == ost and st["kmax"] >= 2
+    assert st == ost and st["kmax"] >= 4
     gx, gv = pos.cpu().numpy(), vel.cpu().numpy()
     assert np.abs(gx - ox).max() <= 1e-10 * np.abs(ox).max()
     assert np.abs(gv - ov).max() <= 1e-10 * np.abs(ov).max()
@@ -73,7 +75,7 @@ def test_first_steps_are_eq_dt(n, seed, nbar, eps):
     # F_I. The GPU's first step of each particle equals the oracle's, exactly;
     # particles with no pair inside r_out start on dt_max.
     c, r_in, r_out = _setup(n, seed, nbar)
-    T, eta = 1.0 / 256, 0.02
+    T, eta = 1.0 / 16, 0.02
     r_buff = 3.0 * np.linalg.norm(c.vel, axis=1).max() * T
     p = _pbh(prec="fp64")
     pos, vel, mass = _t(c.pos), _t(c.vel), _t(c.mass)
@@ -85,7 +87,7 @@ def test_first_steps_are_eq_dt(n, seed, nbar, eps):
     _, _, ost = oracle.hermite(c.pos, c.vel, c.mass, r_in, r_out, eps, T, eta=eta, fr=ofr, want=True)
     ref = _first_step_ticks(ost["want_start"], T / 4)
     assert np.array_equal(ticks, ref)
-    assert (ref < (1 << 40)).sum() > n // 4      # most particles start below dt_max
+    assert (ref < (1 << 40)).sum() > n // 4      # many particles start below dt_max
     o_off, _ = oracle.nbr_brute(c.pos, r_out)
     lonely = np.diff(o_off) == 0
     if lonely.any():
@@ -107,7 +109,7 @@ def test_p3t_matches_oracle():
     assert np.allclose(e.cpu().numpy(), oe, rtol=1e-11, atol=0)
 
 
-@pytest.mark.parametrize("n,seed,T", [(2048, 96, 1.0 / 256), (4096, 97, 1.0 / 128)])
+@pytest.mark.parametrize("n,seed,T", [(2048, 96, 1.0 / 32), (4096, 97, 1.0 / 16)])
 def test_hermite_larger_n(n, seed, T):
     # thousands of particles: blocks from every particle active (the front
     # predicts them all at once) down to a few particles of the deepest level
