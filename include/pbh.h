@@ -282,6 +282,32 @@ pbh_status pbh_irregular_batched(pbh_ctx* ctx, const double* pos, const double* 
                                  pbh_stream_t stream);
 
 /*
+ * pbh_irregular for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Arguments, results and errors as pbh_irregular (the same kernels, so the
+ * same sums bit for bit), except:
+ *   - n <= PBH_NOALLOC_MAX_N (2^20); a larger n returns PBH_E_ARG.
+ *   - The call allocates nothing. Its scratch (a flag word, and for the
+ *     key-order route the ranks and 64-byte records of the n particles,
+ *     68 MiB at the maximum n) is one static device array per GPU that the
+ *     library holds from the first pbh_create on that GPU until the process
+ *     ends. The flag word is cleared by a kernel at the start of every call.
+ *   - Every call on one GPU shares that array, from any context: calls that
+ *     overlap in time on one GPU (other streams, other threads, other
+ *     contexts) race and give undefined results. Order them on one stream.
+ *   - With check = 0, malformed input is skipped (never dereferenced) but not
+ *     reported in pbh_stats.error_flags; pass check = 1 to have it reported.
+ * The context's build (if it holds one of these n particles) is used as by
+ * pbh_irregular.
+ */
+#define PBH_NOALLOC_MAX_N 1048576
+pbh_status pbh_irregular_noalloc(pbh_ctx* ctx, int64_t n, const double* pos, const double* vel,
+                                 const double* mass, double r_in, double r_out, double eps,
+                                 const int64_t* nbr_off, const int32_t* nbr_idx, int64_t nbr_cap,
+                                 int64_t n_targets, const int32_t* targets, double* acc,
+                                 double* jerk, double* pot, int32_t check, pbh_stream_t stream);
+
+/*
  * Core quantities and regularisation parameters from the 6 nearest
  * neighbours of a particle sample (Section 3.2: a uniform sample of
  * min(N, sqrt(5000 N)) particles whose 6 nearest neighbours are searched

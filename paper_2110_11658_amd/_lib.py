@@ -22,11 +22,13 @@ PBH_E_STATE = 6
 PBH_E_INTERNAL = 7
 PBH_FP64 = 0
 PBH_MIXED = 1
+PBH_NOALLOC_MAX_N = 1 << 20
 
 EXPORTS = ("pbh_create", "pbh_destroy", "pbh_set_params", "pbh_get_params", "pbh_build",
            "pbh_force", "pbh_force_buffered", "pbh_build_batched", "pbh_force_batched",
            "pbh_force_batched_buffered", "pbh_irregular",
-           "pbh_irregular_batched", "pbh_core", "pbh_hermite", "pbh_p3t", "pbh_kdk_graph",
+           "pbh_irregular_batched", "pbh_irregular_noalloc", "pbh_core", "pbh_hermite", "pbh_p3t",
+           "pbh_kdk_graph",
            "pbh_kdk_eager", "pbh_get_stats", "pbh_set_timing", "pbh_debug_tree", "pbh_debug_groups",
            "pbh_debug_wave_log", "pbh_debug_valu_probe", "pbh_debug_herm_first_steps",
            "pbh_last_error", "pbh_status_string")
@@ -86,6 +88,8 @@ def load(path: str = LIB_PATH):
         "pbh_irregular": (st, [vp, i64, vp, vp, vp, d, d, d, vp, vp, i64, i64, vp, vp, vp, vp,
                                i32, vp]),
         "pbh_irregular_batched": (st, [vp, vp, vp, vp, vp, vp, d, vp, vp, i64, i64, vp, vp, vp,
+                                       vp, i32, vp]),
+        "pbh_irregular_noalloc": (st, [vp, i64, vp, vp, vp, d, d, d, vp, vp, i64, i64, vp, vp, vp,
                                        vp, i32, vp]),
         "pbh_core": (st, [vp, vp, vp, i64, vp, d, vp, vp, vp]),
         "pbh_hermite": (st, [vp, i64, vp, vp, vp, vp, d, d, d, vp, vp, i64, d, d, vp, vp]),

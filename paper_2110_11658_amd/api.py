@@ -218,6 +218,39 @@ class Pbh:
         check(self.ctx, st)
         return acc, jk, ph
 
+    def irregular_noalloc(self, pos: torch.Tensor, vel: Optional[torch.Tensor], mass: torch.Tensor,
+                          r_in: float, r_out: float, eps: float, nbr_off: torch.Tensor,
+                          nbr_idx: torch.Tensor, acc: torch.Tensor, jerk: Optional[torch.Tensor],
+                          pot: Optional[torch.Tensor], targets: Optional[torch.Tensor] = None,
+                          validate: bool = True):
+        """pbh_irregular_noalloc: as ``irregular`` into caller-given outputs
+        (acc, and jerk/pot or None), with no device allocation by the library."""
+        n = pos.shape[0]
+        _need(pos, (n, 3), "pos")
+        _need(mass, (n,), "mass")
+        if jerk is not None:
+            _need(vel, (n, 3), "vel")
+        _need(nbr_off, (n + 1,), "nbr_off", torch.int64)
+        _need(nbr_idx, (nbr_idx.shape[0],), "nbr_idx", torch.int32)
+        rows = n
+        if targets is not None:
+            _need(targets, (targets.shape[0],), "targets", torch.int32)
+            rows = targets.shape[0]
+        _need(acc, (rows, 3), "acc")
+        if jerk is not None:
+            _need(jerk, (rows, 3), "jerk")
+        if pot is not None:
+            _need(pot, (rows,), "pot")
+        if rows == 0:
+            return
+        st = self.L.pbh_irregular_noalloc(self.ctx, n, _ptr(pos), _ptr(vel), _ptr(mass),
+                                          float(r_in), float(r_out), float(eps), _ptr(nbr_off),
+                                          _ptr(nbr_idx), int(nbr_idx.shape[0]),
+                                          int(rows if targets is not None else 0), _ptr(targets),
+                                          _ptr(acc), _ptr(jerk), _ptr(pot), int(bool(validate)),
+                                          _stream())
+        check(self.ctx, st)
+
     # -- pbh_core -----------------------------------------------------------------
     def core(self, pos: torch.Tensor, mass: torch.Tensor, sample: torch.Tensor, eta: float = 0.02,
              densities: bool = True):

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -29,6 +30,47 @@ struct Buf {
     void* p = nullptr;
     size_t bytes = 0;
 };
+
+// Layout of the scratch of pbh_irregular_noalloc: the flag word, then the key
+// ranks (int32) and the key-order records of at most PBH_NOALLOC_MAX_N
+// particles, each part on a 256-byte boundary.
+constexpr size_t kNaRankOff = 256;
+constexpr size_t kNaRecOff = kNaRankOff + ((sizeof(int32_t) * (size_t)PBH_NOALLOC_MAX_N + 255) / 256) * 256;
+constexpr size_t kNaBytes = kNaRecOff + sizeof(IrrRec) * (size_t)PBH_NOALLOC_MAX_N;
+constexpr int kNaMaxDevices = 64;
+
+}  // namespace
+
+// The scratch of pbh_irregular_noalloc. Each device holds its own copy while
+// the library is loaded; host code reaches it only through the address that
+// hipGetSymbolAddress returned for that device (na_scratch_ptr), never by this
+// name, which on the host is a stand-in and not a device address.
+static __device__ __align__(256) unsigned long long scratch[kNaBytes / sizeof(unsigned long long)];
+
+namespace {
+
+std::mutex na_mu;
+void* na_scratch_ptr[kNaMaxDevices] = {};
+
+// Once per device, with that device current: the device address of scratch.
+bool na_scratch_setup(int device) {
+    if (device < 0 || device >= kNaMaxDevices) return false;
+    std::lock_guard<std::mutex> lock(na_mu);
+    if (na_scratch_ptr[device]) return true;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return false;
+    }
+    na_scratch_ptr[device] = ptr;
+    return true;
+}
+
+void* na_scratch(int device) {
+    if (device < 0 || device >= kNaMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(na_mu);
+    return na_scratch_ptr[device];
+}
 
 }  // namespace
 
@@ -551,13 +593,24 @@ pbh_status do_force(pbh_ctx* ctx, const double* pos, const double* mass,
 
 pbh_status ensure_irr_err(pbh_ctx* ctx);
 
-// Shared part of pbh_irregular and pbh_irregular_batched: p already holds the
-// cluster constants (C, cl_off, cps or cp0).
+// Scratch of one irregular-force call: the flag word and, for the key-order
+// route, ranks and records of up to `cap` particles.
+struct IrrScratch {
+    unsigned long long* err = nullptr;
+    int32_t* rank = nullptr;
+    IrrRec* rec = nullptr;
+    int64_t cap = 0;
+};
+
+// Shared part of pbh_irregular, pbh_irregular_batched and
+// pbh_irregular_noalloc: p already holds the cluster constants (C, cl_off,
+// cps or cp0). fixed == nullptr: the context's buffers, allocated on first
+// need; otherwise the given scratch, and nothing is allocated.
 pbh_status do_irregular(pbh_ctx* ctx, IrrParams& p, int64_t n, const double* pos, const double* vel,
                         const double* mass, double eps, const int64_t* nbr_off,
                         const int32_t* nbr_idx, int64_t nbr_cap, int64_t n_targets,
                         const int32_t* targets, double* acc, double* jerk, double* pot,
-                        int32_t check, hipStream_t s) {
+                        int32_t check, hipStream_t s, const IrrScratch* fixed = nullptr) {
     if (n < 1 || n >= (1ll << 31) - 1) return fail(ctx, PBH_E_ARG, "need 1 <= n < 2^31");
     if (targets && n_targets < 0) return fail(ctx, PBH_E_ARG, "n_targets must be >= 0");
     if (targets && n_targets == 0) return PBH_OK;   // an empty target list: nothing to do
@@ -565,9 +618,15 @@ pbh_status do_irregular(pbh_ctx* ctx, IrrParams& p, int64_t n, const double* pos
     if (jerk && !vel) return fail(ctx, PBH_E_ARG, "the jerk needs vel");
     if (nbr_cap < 0 || (nbr_cap > 0 && !nbr_idx)) return fail(ctx, PBH_E_ARG, "bad neighbour buffer");
     if (!finite_nonneg(eps)) return fail(ctx, PBH_E_ARG, "eps must be finite and >= 0");
-    pbh_status ae = ensure_irr_err(ctx);
-    if (ae != PBH_OK) return ae;
-    launch_zero_u64(ctx->irr_err, 1, s);
+    unsigned long long* err = nullptr;
+    if (fixed) {
+        err = fixed->err;
+    } else {
+        pbh_status ae = ensure_irr_err(ctx);
+        if (ae != PBH_OK) return ae;
+        err = ctx->irr_err;
+    }
+    launch_zero_u64(err, 1, s);   // a kernel, not a memset: callers may capture the call
     p.n = n;
     p.n_tgt = targets ? n_targets : n;
     p.tgt = targets;
@@ -578,16 +637,22 @@ pbh_status do_irregular(pbh_ctx* ctx, IrrParams& p, int64_t n, const double* pos
     // (a short list does not pay for a pass over every particle).
     Dev& d = ctx->d;
     if (ctx->built && ctx->cfg.n == n && (!targets || n_targets * kIrrPackRatio >= n)) {
-        if (d.irr_len < n) {
-            if (!dalloc(ctx, &d.irr_rank, n) || !dalloc(ctx, &d.irr_rec, n)) {
-                (void)hipGetLastError();
-                return fail(ctx, PBH_E_OOM, "irregular-force records");
+        if (fixed) {
+            if (fixed->cap < n) return fail(ctx, PBH_E_ARG, "n exceeds the fixed scratch");
+            p.rank = fixed->rank;
+            p.rec = fixed->rec;
+        } else {
+            if (d.irr_len < n) {
+                if (!dalloc(ctx, &d.irr_rank, n) || !dalloc(ctx, &d.irr_rec, n)) {
+                    (void)hipGetLastError();
+                    return fail(ctx, PBH_E_OOM, "irregular-force records");
+                }
+                d.irr_len = n;
             }
-            d.irr_len = n;
+            p.rank = d.irr_rank;
+            p.rec = d.irr_rec;
         }
         p.perm = d.perm;
-        p.rank = d.irr_rank;
-        p.rec = d.irr_rec;
         p.order = targets ? nullptr : d.perm;
     }
     p.pos = pos;
@@ -600,16 +665,16 @@ pbh_status do_irregular(pbh_ctx* ctx, IrrParams& p, int64_t n, const double* pos
     p.acc = acc;
     p.jerk = jerk;
     p.pot = pot;
-    p.err = ctx->irr_err;
+    p.err = err;
     launch_irregular(p, s);
     HIP_TRY(hipGetLastError());
     if (check) {
-        unsigned long long err = 0;
-        HIP_TRY(hipMemcpyAsync(&err, ctx->irr_err, sizeof(err), hipMemcpyDeviceToHost, s));
+        unsigned long long bits = 0;
+        HIP_TRY(hipMemcpyAsync(&bits, err, sizeof(bits), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        if (err & kIrrBadTarget) return fail(ctx, PBH_E_ARG, "a target index is outside [0, n)");
-        if (err & kIrrBadOffsets) return fail(ctx, PBH_E_ARG, "neighbour offsets decrease or pass nbr_cap");
-        if (err & kIrrBadIndex) return fail(ctx, PBH_E_ARG, "a neighbour index is outside [0, n)");
+        if (bits & kIrrBadTarget) return fail(ctx, PBH_E_ARG, "a target index is outside [0, n)");
+        if (bits & kIrrBadOffsets) return fail(ctx, PBH_E_ARG, "neighbour offsets decrease or pass nbr_cap");
+        if (bits & kIrrBadIndex) return fail(ctx, PBH_E_ARG, "a neighbour index is outside [0, n)");
     }
     return PBH_OK;
 }
@@ -844,6 +909,12 @@ pbh_status pbh_create(int device, const pbh_params* params, pbh_ctx** out) {
         delete ctx;
         return PBH_E_HIP;
     }
+    // the allocation-free entry point's scratch on this device (set up once)
+    if (!na_scratch_setup(device)) {
+        (void)hipStreamDestroy(ctx->cap_stream);
+        delete ctx;
+        return PBH_E_HIP;
+    }
     *out = ctx;
     return PBH_OK;
 }
@@ -1041,6 +1112,34 @@ pbh_status pbh_irregular_batched(pbh_ctx* ctx, const double* pos, const double* 
     }
     return do_irregular(ctx, p, ctx->cfg.n, pos, vel, mass, eps, nbr_off, nbr_idx, nbr_cap,
                         n_targets, targets, acc, jerk, pot, check, s);
+}
+
+pbh_status pbh_irregular_noalloc(pbh_ctx* ctx, int64_t n, const double* pos, const double* vel,
+                                 const double* mass, double r_in, double r_out, double eps,
+                                 const int64_t* nbr_off, const int32_t* nbr_idx, int64_t nbr_cap,
+                                 int64_t n_targets, const int32_t* targets, double* acc,
+                                 double* jerk, double* pot, int32_t check, pbh_stream_t stream) {
+    if (!ctx) return PBH_E_ARG;
+    if (n > PBH_NOALLOC_MAX_N)
+        return fail(ctx, PBH_E_ARG, "n exceeds PBH_NOALLOC_MAX_N (2^20 particles), the size of "
+                                    "the allocation-free scratch; use pbh_irregular");
+    pbh_status st = check_radii(ctx, r_in, r_out);
+    if (st != PBH_OK) return st;
+    HIP_TRY(hipSetDevice(ctx->device));
+    char* base = (char*)na_scratch(ctx->device);
+    if (!base) return fail(ctx, PBH_E_STATE, "no scratch address for this device");
+    IrrScratch fixed;
+    fixed.err = (unsigned long long*)base;
+    fixed.rank = (int32_t*)(base + kNaRankOff);
+    fixed.rec = (IrrRec*)(base + kNaRecOff);
+    fixed.cap = PBH_NOALLOC_MAX_N;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    IrrParams p;
+    p.C = 1;
+    p.cp0 = cluster_params(r_in, r_out);
+    return do_irregular(ctx, p, n, pos, vel, mass, eps, nbr_off, nbr_idx, nbr_cap, n_targets,
+                        targets, acc, jerk, pot, check, s, &fixed);
 }
 
 pbh_status pbh_core(pbh_ctx* ctx, const double* pos, const double* mass, int64_t n_sample,
