@@ -77,7 +77,8 @@ __global__ __launch_bounds__(64) void k_nbr_fill(NbrParams p) {
     __shared__ NTile T;
     __shared__ int s_stack[kStackLds];
     const int lane = threadIdx.x;
-    const Stack stack{s_stack, p.stack + (int64_t)blockIdx.x * (p.stack_cap - kStackLds), p.stack_cap};
+    const Stack stack{s_stack, p.stack + (int64_t)blockIdx.x * (p.stack_cap - kStackLds), p.stack_cap,
+                      kStackLds};
     const int64_t G = (int64_t)*p.G;
     int home = blockIdx.x % kQueues;
     const unsigned long long t_start = wall_clock64();

@@ -31,9 +31,15 @@ namespace pbh {
 
 namespace {
 
-// Tile capacity TC (a template parameter, 64, 96 or 128): a tile is evaluated
-// just before it would overflow. One traversal step adds at most 64 entries of
-// a kind, so TC >= 64.
+// Tile capacity TC (a template parameter, 64, 96 or 128). A far or near tile
+// is evaluated just before it would overflow; the multipole tile holds TC + 64
+// entries and is evaluated at the start of a traversal step once it holds more
+// than TC (one step adds at most 64), where the least state is live. One
+// traversal step adds at most 64 entries of a kind, so TC >= 64.
+//
+// The first kWalkStackLds traversal stack entries live in LDS (the rest in the
+// wave's spill region).
+constexpr int kWalkStackLds = 256;
 //
 // Near entries of the FP64 walk keep their original coordinates for the
 // neighbour test; the mixed walk keeps the sorted index instead and reads the
@@ -52,7 +58,7 @@ template <typename R, int TC>
 struct alignas(16) Tiles : NearExtra<R, TC> {
     static_assert(TC >= 64, "one traversal step adds up to 64 entries");
     static constexpr int kCap = TC;
-    R pn[TC][12];        // cx cy cz M | qxx qyy qzz qxy | qxz qyz - -
+    R pn[TC + 64][12];   // cx cy cz M | qxx qyy qzz qxy | qxz qyz - -  (room for one more step)
     R far[TC][4];        // x y z m (relative to the group centre)
     R nearp[TC][4];
     int nearj[TC];       // caller index: skips the self pair, and is the neighbour index
@@ -104,6 +110,12 @@ __device__ inline void two_sum_acc(float& hi, float& lo, float v) {
     lo += e;
 }
 
+// Partial sums of one tile evaluation (one lane).
+template <typename R>
+struct Part {
+    R x, y, z, p;
+};
+
 template <typename R>
 struct Acc;
 
@@ -117,6 +129,7 @@ struct Acc<float> {
         two_sum_acc(hz, lz, az);
         two_sum_acc(hp, lp, ph);
     }
+    __device__ void add(const Part<float>& q) { add(q.x, q.y, q.z, q.p); }
     __device__ void store(float* w) const {
         w[0] = hx; w[1] = lx; w[2] = hy; w[3] = ly; w[4] = hz; w[5] = lz; w[6] = hp; w[7] = lp;
     }
@@ -140,6 +153,7 @@ struct Acc<double> {
     __device__ void add(double ax, double ay, double az, double ph) {
         x += ax; y += ay; z += az; p += ph;
     }
+    __device__ void add(const Part<double>& q) { add(q.x, q.y, q.z, q.p); }
     __device__ void store(double* w) const { w[0] = x; w[1] = y; w[2] = z; w[3] = p; }
     __device__ void merge(const double* w) { x += w[0]; y += w[1]; z += w[2]; p += w[3]; }
     __device__ double gx() const { return x; }
@@ -147,6 +161,10 @@ struct Acc<double> {
     __device__ double gz() const { return z; }
     __device__ double gp() const { return p; }
 };
+
+// the value of lane L ^ 32: lane p < 32 receives lane p + 32's
+template <typename R>
+__device__ inline R shfl_down32(R v) { return __shfl_xor(v, 32, 64); }
 
 __device__ inline float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ inline double rsq(double v) { return rsqrt(v); }
@@ -164,18 +182,26 @@ __device__ inline void for_entries(int cnt, int ksub, int sub, F&& body) {
 #pragma unroll U
         for (int e = 0; e < cnt; ++e) body(e);
     } else {
-        const int nfull = cnt - cnt % ksub;
-#pragma unroll 1
-        for (int e2 = 0; e2 < nfull; e2 += ksub) body(e2 + sub);
-        if (nfull + sub < cnt) body(nfull + sub);
+        int e2 = 0;
+#pragma unroll 2
+        for (; e2 + ksub <= cnt; e2 += ksub) body(e2 + sub);
+        if (e2 + sub < cnt) body(e2 + sub);
     }
+}
+
+// Loop iterations of for_entries, ceil(cnt / ksub), as a multiply and shift:
+// with rcp = ceil(2^16 / ksub), floor(v * rcp / 2^16) = floor(v / ksub) for
+// v < 2^16 / 64 (the error v * (rcp - 2^16 / ksub) / 2^16 stays below 1 / ksub).
+__device__ inline unsigned rounds_rcp(int ksub) { return (65536u + (unsigned)ksub - 1u) / (unsigned)ksub; }
+__device__ inline int entry_rounds(int cnt, int ksub, unsigned rcp) {
+    return (int)(((unsigned)(cnt + ksub - 1) * rcp) >> 16);
 }
 
 // Monopole + traceless quadrupole: phi = -M/s - (R^T Q R)/(2 s^5), a = -grad phi
 //   a = -(M/s^3 + (5/2) (R^T Q R)/s^7) R + Q R / s^5,   R = x_i - COM
 template <typename R, int TC>
-__device__ inline void eval_pn(const Tiles<R, TC>& T, int cnt, int ksub, int sub, R px, R py, R pz, R eps2,
-                               Acc<R>& A) {
+__device__ inline Part<R> eval_pn(const Tiles<R, TC>& T, int cnt, int ksub, int sub, R px, R py, R pz,
+                                  R eps2) {
     R ax = 0, ay = 0, az = 0, ph = 0;
     for_entries<2>(cnt, ksub, sub, [&](int e) {
         const R* q = T.pn[e];
@@ -196,7 +222,7 @@ __device__ inline void eval_pn(const Tiles<R, TC>& T, int cnt, int ksub, int sub
         az += cr * Rz + qz * inv5;
         ph += -q[3] * inv - R(0.5) * rqr * inv5;
     });
-    A.add(ax, ay, az, ph);
+    return Part<R>{ax, ay, az, ph};
 }
 
 // FP32 form written as explicit FMA chains (33 VALU + 1 rsqrt per entry). The
@@ -204,8 +230,8 @@ __device__ inline void eval_pn(const Tiles<R, TC>& T, int cnt, int ksub, int sub
 //   cr = M/s^3 + t'/s^2,  a += 0.4 q'/s^5 - cr R,  phi += -M/s - 0.2 t'.
 // The q'/s^5 terms are summed apart and scaled by 0.4 once per tile.
 template <int TC>
-__device__ inline void eval_pn_f32(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
-                                      float py, float pz, float eps2, Acc<float>& A) {
+__device__ inline Part<float> eval_pn_f32(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
+                                          float py, float pz, float eps2) {
     float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
     float bx = 0.f, by = 0.f, bz = 0.f;
     for_entries<4>(cnt, ksub, sub, [&](int e) {
@@ -232,13 +258,13 @@ __device__ inline void eval_pn_f32(const Tiles<float, TC>& T, int cnt, int ksub,
         az = fmaf(-cr, Rz, az);
         ph = fmaf(-a.w, inv, fmaf(-0.2f, t, ph));
     });
-    A.add(fmaf(0.4f, bx, ax), fmaf(0.4f, by, ay), fmaf(0.4f, bz, az), ph);
+    return Part<float>{fmaf(0.4f, bx, ax), fmaf(0.4f, by, ay), fmaf(0.4f, bz, az), ph};
 }
 
 // Pairs of far leaves: every pair is at r >= R >= r_out, where W = 1.
 template <typename R, int TC>
-__device__ inline void eval_far(const Tiles<R, TC>& T, int cnt, int ksub, int sub, R px, R py, R pz, R eps2,
-                                Acc<R>& A) {
+__device__ inline Part<R> eval_far(const Tiles<R, TC>& T, int cnt, int ksub, int sub, R px, R py, R pz,
+                                   R eps2) {
     R ax = 0, ay = 0, az = 0, ph = 0;
     for_entries<4>(cnt, ksub, sub, [&](int e) {
         const R* q = T.far[e];
@@ -252,12 +278,12 @@ __device__ inline void eval_far(const Tiles<R, TC>& T, int cnt, int ksub, int su
         az += mi3 * dz;
         ph -= mi;
     });
-    A.add(ax, ay, az, ph);
+    return Part<R>{ax, ay, az, ph};
 }
 
 template <int TC>
-__device__ inline void eval_far_f32(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
-                                       float py, float pz, float eps2, Acc<float>& A) {
+__device__ inline Part<float> eval_far_f32(const Tiles<float, TC>& T, int cnt, int ksub, int sub,
+                                           float px, float py, float pz, float eps2) {
     float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
     for_entries<4>(cnt, ksub, sub, [&](int e) {
         const float4 q = *reinterpret_cast<const float4*>(&T.far[e][0]);
@@ -271,7 +297,7 @@ __device__ inline void eval_far_f32(const Tiles<float, TC>& T, int cnt, int ksub
         az = fmaf(mi3, dz, az);
         ph -= mi;
     });
-    A.add(ax, ay, az, ph);
+    return Part<float>{ax, ay, az, ph};
 }
 
 template <typename R>
@@ -303,9 +329,10 @@ __device__ inline bool is_neighbour(double xj, double yj, double zj, double xi, 
 // optionally also stores them in the lane's staging row (`srow`, at most
 // `scap` entries, kStageStride apart).
 template <typename R, int TC>
-__device__ inline void eval_near(const Tiles<R, TC>& T, int cnt, int ksub, int sub, R px, R py, R pz, R eps2,
-                                 int self, const NearK<R>& K, Acc<R>& A, bool count_nbr, double xi,
-                                 double yi, double zi, double rlist2, int& nbr, int32_t* srow, int scap) {
+__device__ inline Part<R> eval_near(const Tiles<R, TC>& T, int cnt, int ksub, int sub, R px, R py, R pz,
+                                    R eps2, int self, const NearK<R>& K, bool count_nbr, int me,
+                                    double rlist2, int& nbr, int32_t* srow, int scap) {
+    const double xi = K.x[me], yi = K.y[me], zi = K.z[me];
     R ax = 0, ay = 0, az = 0, ph = 0;
     for_entries<1>(cnt, ksub, sub, [&](int e) {
         const R* q = T.nearp[e];
@@ -334,17 +361,17 @@ __device__ inline void eval_near(const Tiles<R, TC>& T, int cnt, int ksub, int s
         const R phi = s >= K.r_out ? -inv : (s < K.r_in ? K.inner : mid);
         ph += is_self ? R(0) : q[3] * phi;
     });
-    A.add(ax, ay, az, ph);
+    return Part<R>{ax, ay, az, ph};
 }
 
 // FP32 form without per-lane branches: the neighbour count and the pole
 // terms (-d0/s + l1 ln s, present when r_in > 0) are compile-time switches,
 // ln s = log2(s) ln 2, and the boundary cases of W and Phi_R are selects.
 template <bool CNT, bool POLE, int TC>
-__device__ inline void eval_near_f32(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
-                                     float py, float pz, float eps2, int self, const NearK<float>& K,
-                                     Acc<float>& A, double xi, double yi, double zi, double rlist2,
-                                     int& nbr, int32_t* srow, int scap) {
+__device__ inline Part<float> eval_near_f32(const Tiles<float, TC>& T, int cnt, int ksub, int sub,
+                                            float px, float py, float pz, float eps2, int self,
+                                            const NearK<float>& K, int me, double rlist2, int& nbr,
+                                            int32_t* srow, int scap) {
     const double* __restrict__ gx = K.x;
     const double* __restrict__ gy = K.y;
     const double* __restrict__ gz = K.z;
@@ -378,7 +405,7 @@ __device__ inline void eval_near_f32(const Tiles<float, TC>& T, int cnt, int ksu
             if (__ballot(band)) {
                 if (band) {
                     const int js = T.nears[e];
-                    nb = is_neighbour(gx[js], gy[js], gz[js], xi, yi, zi, rlist2);
+                    nb = is_neighbour(gx[js], gy[js], gz[js], gx[me], gy[me], gz[me], rlist2);
                 }
             }
             nb = nb & other;
@@ -405,48 +432,54 @@ __device__ inline void eval_near_f32(const Tiles<float, TC>& T, int cnt, int ksu
         const float phi = outer ? -inv : (inner ? K.inner : mid);
         ph = other ? fmaf(q.w, phi, ph) : ph;
     });
-    A.add(ax, ay, az, ph);
+    return Part<float>{ax, ay, az, ph};
 }
 
 // The mixed walk's forms (explicit FMA chains above), chosen per precision.
 template <int TC>
-__device__ inline void eval_pn(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
-                               float py, float pz, float eps2, Acc<float>& A) {
-    eval_pn_f32<TC>(T, cnt, ksub, sub, px, py, pz, eps2, A);
+__device__ inline Part<float> eval_pn(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
+                                      float py, float pz, float eps2) {
+    return eval_pn_f32<TC>(T, cnt, ksub, sub, px, py, pz, eps2);
 }
 
 template <int TC>
-__device__ inline void eval_far(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
-                                float py, float pz, float eps2, Acc<float>& A) {
-    eval_far_f32<TC>(T, cnt, ksub, sub, px, py, pz, eps2, A);
+__device__ inline Part<float> eval_far(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
+                                       float py, float pz, float eps2) {
+    return eval_far_f32<TC>(T, cnt, ksub, sub, px, py, pz, eps2);
 }
 
 template <int TC>
-__device__ inline void eval_near(const Tiles<float, TC>& T, int cnt, int ksub, int sub, float px,
-                                 float py, float pz, float eps2, int self, const NearK<float>& K,
-                                 Acc<float>& A, bool count_nbr, double xi, double yi, double zi,
-                                 double rlist2, int& nbr, int32_t* srow, int scap) {
+__device__ inline Part<float> eval_near(const Tiles<float, TC>& T, int cnt, int ksub, int sub,
+                                        float px, float py, float pz, float eps2, int self,
+                                        const NearK<float>& K, bool count_nbr, int me, double rlist2,
+                                        int& nbr, int32_t* srow, int scap) {
     if (count_nbr) {
         if (K.pole)
-            eval_near_f32<true, true, TC>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
-        else
-            eval_near_f32<true, false, TC>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
-    } else {
-        if (K.pole)
-            eval_near_f32<false, true, TC>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
-        else
-            eval_near_f32<false, false, TC>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, A, xi, yi, zi, rlist2, nbr, srow, scap);
+            return eval_near_f32<true, true, TC>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, me, rlist2,
+                                                 nbr, srow, scap);
+        return eval_near_f32<true, false, TC>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, me, rlist2,
+                                              nbr, srow, scap);
     }
+    if (K.pole)
+        return eval_near_f32<false, true, TC>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, me, rlist2,
+                                              nbr, srow, scap);
+    return eval_near_f32<false, false, TC>(T, cnt, ksub, sub, px, py, pz, eps2, self, K, me, rlist2, nbr,
+                                           srow, scap);
 }
 
+// Four waves per SIMD (16 per compute unit, which the 64-entry mixed walk's
+// LDS allows): the register budget is held to 128, which this kernel fits
+// without spilling; left free, the compiler takes more and halves nothing but
+// occupancy. Larger tiles and the FP64 walk are held lower by their LDS.
 template <bool MIXED, int TC>
-__global__ __launch_bounds__(64) void k_walk(WalkParams p) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_walk(WalkParams p) {
     using R = typename std::conditional<MIXED, float, double>::type;
     constexpr int TCAP = TC;
     __shared__ Tiles<R, TC> T;
-    __shared__ int s_stack[kStackLds];
+    __shared__ int s_stack[kWalkStackLds];
     const int lane = threadIdx.x;
-    const Stack stack{s_stack, p.stack + (int64_t)blockIdx.x * (p.stack_cap - kStackLds), p.stack_cap};
+    const Stack stack{s_stack, p.stack + (int64_t)blockIdx.x * (p.stack_cap - kWalkStackLds), p.stack_cap,
+                      kWalkStackLds};
     int home = blockIdx.x % kQueues;
     const R eps2 = (R)p.eps2;
     const int64_t G = (int64_t)*p.G;
@@ -494,50 +527,142 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
             K.band = (h <= 64.0 * cp.rlist) ? (float)(2048.0 * 0x1p-24 * rlist2) : INFINITY;
         }
 
-        // sub-wave copies of a small group (see for_entries); lanes beyond
-        // ksub * gcnt duplicate copy 0 and are ignored at the merge
-        const int kfit = 64 / gcnt;
-        const int ksub = kfit < p.max_copies ? kfit : p.max_copies;
-        const int copy = lane / gcnt;
-        const int pl = lane - copy * gcnt;
-        const int sub = copy < ksub ? copy : 0;
+        // Lane roles. By default a group of g particles takes one pass over
+        // every tile with ksub = min(64 / g, cap) copies, lane = copy * g +
+        // particle (see for_entries; lanes beyond ksub * g repeat copy 0 and
+        // are ignored at the merge), and the copies are merged once per group.
+        // A group of 33..53 particles takes two passes over every multipole
+        // tile instead (split): pass A holds particles 0..31 in two copies
+        // (particle lane & 31, copy lane >> 5), pass B the other rB = g - 32
+        // in kB = min(64 / rB, cap, 8) >= 3 copies counted from lane 32, so
+        // that lane 32 + q holds particle 32 + q in copy 0. Their copies are
+        // merged after every tile into lane p < g, which owns particle p and
+        // takes the group's far and near tiles in one pass.
         const bool active = lane < gcnt;
-        const int me = gb + pl;
-        const double xi = p.x[me], yi = p.y[me], zi = p.z[me];
+        const int rB = gcnt - 32;
+        int kB = 0;
+        if (rB >= 1 && rB <= 21) {
+            const int kfit = 64 / rB;
+            kB = kfit < p.max_copies ? kfit : p.max_copies;
+            kB = kB < 8 ? kB : 8;
+        }
+        const bool split = kB >= 3;
+        int ksubA, subA, plA, copyA;
+        int subB = 0, plB = 0;
+        if (split) {
+            ksubA = 2;
+            copyA = lane >> 5;
+            subA = copyA;
+            plA = lane & 31;
+            const int q = (lane - 32) & 63;
+            const int cB = q / rB;
+            plB = 32 + (q - cB * rB);
+            subB = cB < kB ? cB : 0;
+        } else {
+            const int kfit = 64 / gcnt;
+            ksubA = kfit < p.max_copies ? kfit : p.max_copies;
+            copyA = lane / gcnt;
+            plA = lane - copyA * gcnt;
+            subA = copyA < ksubA ? copyA : 0;
+        }
+        // the particle whose far and near pairs, neighbour list and outputs
+        // this lane handles (a stand-in for the idle lanes of a split group)
+        const int own = split ? (active ? lane : 0) : plA;
+        const int ksubN = split ? 1 : ksubA;
+        const int subN = split ? 0 : subA;
+        const int me = gb + own;
         const int orig_me = p.perm[me];
         if (p.cpos) {
             // the caller's arrays must still hold what the build sorted
             const int64_t o3 = 3 * (int64_t)orig_me;
-            const bool stale = active && (p.cpos[o3] != xi || p.cpos[o3 + 1] != yi ||
-                                          p.cpos[o3 + 2] != zi || p.cmass[orig_me] != p.m[me]);
+            const bool stale = active && (p.cpos[o3] != p.x[me] || p.cpos[o3 + 1] != p.y[me] ||
+                                          p.cpos[o3 + 2] != p.z[me] || p.cmass[orig_me] != p.m[me]);
             if (__ballot(stale)) atomicOr(&p.cnt[kErr], lane == 0 ? kErrStale : 0ull);
         }
-        // Neighbour staging. A particle's row holds p.scap entries; an unsplit
-        // group uses it whole, a split group gives each copy a sub-row of
-        // wrow = p.scap / ksub entries (joined into one list after the walk).
-        // Lanes that repeat copy 0 store nothing (scap = 0).
-        const bool real = copy < ksub;
-        const int wrow = p.scap / ksub;
-        const int scap = (p.stage == nullptr || !real) ? 0 : (ksub == 1 ? p.scap : wrow);
+        // Neighbour staging. A particle's row holds p.scap entries; a lane
+        // that holds it whole (ksubN = 1) uses it whole, copies of a small group
+        // each get a sub-row of wrow = p.scap / ksubN entries (joined into one
+        // list after the walk). Lanes that hold no particle of their own, or
+        // repeat copy 0, store nothing (scap = 0).
+        const bool real = split ? active : copyA < ksubA;
+        const int wrow = p.scap / ksubN;
+        const int scap = (p.stage == nullptr || !real) ? 0 : (ksubN == 1 ? p.scap : wrow);
         int32_t* srow = p.stage != nullptr
-                            ? p.stage + stage_index(me, (ksub == 1 ? 0 : sub * wrow), p.scap)
+                            ? p.stage + stage_index(me, (ksubN == 1 ? 0 : subN * wrow), p.scap)
                             : nullptr;
-        const R px = (R)(xi - ctr[0]);
-        const R py = (R)(yi - ctr[1]);
-        const R pz = (R)(zi - ctr[2]);
+        // positions relative to the group centre: pass A (also the far and
+        // near tiles, except on lanes >= 32 of a split group) and pass B
+        const R pAx = (R)(p.x[gb + plA] - ctr[0]);
+        const R pAy = (R)(p.y[gb + plA] - ctr[1]);
+        const R pAz = (R)(p.z[gb + plA] - ctr[2]);
+        const int pbi = split ? gb + plB : me;
+        const R pBx = (R)(p.x[pbi] - ctr[0]);
+        const R pBy = (R)(p.y[pbi] - ctr[1]);
+        const R pBz = (R)(p.z[pbi] - ctr[2]);
+        const unsigned rcpA = rounds_rcp(ksubA), rcpB = split ? rounds_rcp(kB) : 0u,
+                       rcpN = rounds_rcp(ksubN);
+        const bool hiB = split && lane >= 32;   // lanes whose own particle is pass B's copy 0
+        const bool ownerB = hiB && active;
         const bool count_nbr = p.nbr_cnt != nullptr;
+        int npn = 0, nfar = 0, nnear = 0;
+        unsigned c_pn = 0, c_far = 0, c_near = 0;   // per group: far below 2^32
+        // loop iterations of the evaluations (each occupies all 64 lanes)
+        unsigned it_pn = 0, it_far = 0, it_near = 0;
         int nbr = 0;
         Acc<R> A;
-
-        int npn = 0, nfar = 0, nnear = 0;
-        unsigned long long c_pn = 0, c_far = 0, c_near = 0;
-        // loop iterations of the evaluations (each occupies all 64 lanes)
-        unsigned long long it_pn = 0, it_far = 0, it_near = 0;
+        // one flush of each tile kind; every lane runs it (it_* counts the
+        // loop iterations, each of which occupies the 64 lanes)
+        auto flush_pn = [&](int cnt) {
+            it_pn += entry_rounds(cnt, ksubA, rcpA);
+            Part<R> pa = eval_pn(T, cnt, ksubA, subA, pAx, pAy, pAz, eps2);
+            if (split) {
+                it_pn += entry_rounds(cnt, kB, rcpB);
+                const Part<R> pb = eval_pn(T, cnt, kB, subB, pBx, pBy, pBz, eps2);
+                // pass A: copy 1 (lane p + 32) into lane p
+                pa.x += shfl_down32(pa.x);
+                pa.y += shfl_down32(pa.y);
+                pa.z += shfl_down32(pa.z);
+                pa.p += shfl_down32(pa.p);
+                // pass B: copies in copy order into lane 32 + q, through the
+                // tile's storage (every lane has read the tile)
+                __syncthreads();
+                Part<R>* red = reinterpret_cast<Part<R>*>(&T.pn[0][0]);
+                red[lane] = pb;
+                __syncthreads();
+                Part<R> sb{R(0), R(0), R(0), R(0)};
+                if (ownerB) {
+                    for (int c = 0; c < kB; ++c) {
+                        const Part<R> v = red[(lane + c * rB) & 63];
+                        sb.x += v.x; sb.y += v.y; sb.z += v.z; sb.p += v.p;
+                    }
+                }
+                __syncthreads();
+                if (hiB) pa = sb;   // idle lanes add zero
+            }
+            A.add(pa);
+        };
+        auto flush_far = [&](int cnt) {
+            it_far += entry_rounds(cnt, ksubN, rcpN);
+            A.add(eval_far(T, cnt, ksubN, subN, hiB ? pBx : pAx, hiB ? pBy : pAy, hiB ? pBz : pAz, eps2));
+        };
+        auto flush_near = [&](int cnt) {
+            it_near += entry_rounds(cnt, ksubN, rcpN);
+            A.add(eval_near(T, cnt, ksubN, subN, hiB ? pBx : pAx, hiB ? pBy : pAy, hiB ? pBz : pAz, eps2,
+                            orig_me, K, count_nbr, me, rlist2, nbr, srow, scap));
+        };
         stack.put(0, root);   // every lane stores the same value
         int top = 1;
         bool overflow = false;
 
         while (top > 0) {
+            // multipole tile: evaluated here, where no node state is live,
+            // once it could not take another step's entries (up to 64)
+            if (npn > TCAP) {
+                __syncthreads();
+                flush_pn(npn);
+                npn = 0;
+                __syncthreads();
+            }
             __threadfence_block();
             const int npop = uni(top < 64 ? top : 64);
             top -= npop;
@@ -555,13 +680,6 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
             const uint64_t mk = __ballot(accept);
             if (mk) {
                 const int k = uni(__popcll(mk));
-                if (npn + k > TCAP) {
-                    __syncthreads();
-                    it_pn += (npn + ksub - 1) / ksub;
-                    eval_pn(T, npn, ksub, sub, px, py, pz, eps2, A);
-                    npn = 0;
-                    __syncthreads();
-                }
                 if (accept) {
                     R* e = T.pn[npn + popc_below(mk)];
                     e[0] = (R)(w.com[0] - ctr[0]);
@@ -617,9 +735,8 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
                     const int add = (total - base) < 64 ? (total - base) : 64;
                     if (fill + add > TCAP) {
                         __syncthreads();
-                        (cls == 0 ? it_far : it_near) += (fill + ksub - 1) / ksub;
-                        if (cls == 0) eval_far(T, fill, ksub, sub, px, py, pz, eps2, A);
-                        else eval_near(T, fill, ksub, sub, px, py, pz, eps2, orig_me, K, A, count_nbr, xi, yi, zi, rlist2, nbr, srow, scap);
+                        if (cls == 0) flush_far(fill);
+                        else flush_near(fill);
                         fill = 0;
                         __syncthreads();
                     }
@@ -646,18 +763,16 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
             }
         }
         __syncthreads();
-        it_pn += (npn + ksub - 1) / ksub;
-        it_far += (nfar + ksub - 1) / ksub;
-        it_near += (nnear + ksub - 1) / ksub;
-        if (npn) eval_pn(T, npn, ksub, sub, px, py, pz, eps2, A);
-        if (nfar) eval_far(T, nfar, ksub, sub, px, py, pz, eps2, A);
-        if (nnear) eval_near(T, nnear, ksub, sub, px, py, pz, eps2, orig_me, K, A, count_nbr, xi, yi, zi, rlist2, nbr, srow, scap);
+        if (npn) flush_pn(npn);
+        if (nfar) flush_far(nfar);
+        if (nnear) flush_near(nnear);
         __syncthreads();
 
         // a row that overflowed sends the group's lists to the fill pass
         const bool row_full = count_nbr && real && nbr > scap;
         const bool need_fill = count_nbr && (p.stage == nullptr || __ballot(row_full) != 0);
-        if (ksub > 1) {
+        if (!split && ksubA > 1) {
+            const int ksub = ksubA;
             // merge the copies' partial sums in copy order, into copy 0
             R* red = &T.pn[0][0];
             constexpr int W = Acc<R>::kWords + 1;   // odd stride: no LDS bank conflicts
@@ -712,13 +827,13 @@ __global__ __launch_bounds__(64) void k_walk(WalkParams p) {
         }
         // interaction counters: one contribution per wave (lane 0), others add 0
         const unsigned long long l0 = lane == 0 ? (unsigned long long)gcnt : 0ull;
-        atomicAdd(&p.cnt[kCntPN], c_pn * l0);
-        atomicAdd(&p.cnt[kCntFar], c_far * l0);
-        atomicAdd(&p.cnt[kCntNear], c_near * l0);
+        atomicAdd(&p.cnt[kCntPN], (unsigned long long)c_pn * l0);
+        atomicAdd(&p.cnt[kCntFar], (unsigned long long)c_far * l0);
+        atomicAdd(&p.cnt[kCntNear], (unsigned long long)c_near * l0);
         const unsigned long long w0 = lane == 0 ? 64ull : 0ull;
-        atomicAdd(&p.cnt[kCntSlotPN], it_pn * w0);
-        atomicAdd(&p.cnt[kCntSlotFar], it_far * w0);
-        atomicAdd(&p.cnt[kCntSlotNear], it_near * w0);
+        atomicAdd(&p.cnt[kCntSlotPN], (unsigned long long)it_pn * w0);
+        atomicAdd(&p.cnt[kCntSlotFar], (unsigned long long)it_far * w0);
+        atomicAdd(&p.cnt[kCntSlotNear], (unsigned long long)it_near * w0);
     }
     if (p.wave_log) {
         p.wave_log[2 * blockIdx.x] = (unsigned long long)n_walked;

@@ -95,19 +95,21 @@ __device__ inline double box_pt_d2(const double* lo, const double* hi, const dou
     return g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
 }
 
-// Traversal stack: the first kStackLds entries live in LDS, deeper entries in
-// a per-wave spill region of global memory (rarely reached: the walk of a
-// 2^20-particle Plummer sphere needs < 900 entries).
+// Traversal stack: the first lcap entries live in LDS, deeper entries in a
+// per-wave spill region of global memory (the walk of a 2^20-particle Plummer
+// sphere needs < 900 entries). kStackLds is the LDS part of the neighbour
+// fill pass; the force walk keeps a smaller one (its LDS holds larger tiles).
 constexpr int kStackLds = 1024;
 
 struct Stack {
-    int* lds;        // [kStackLds]
-    int32_t* spill;  // [cap - kStackLds]
+    int* lds;        // [lcap]
+    int32_t* spill;  // [cap - lcap]
     int cap;
-    __device__ int get(int i) const { return i < kStackLds ? lds[i] : spill[i - kStackLds]; }
+    int lcap;
+    __device__ int get(int i) const { return i < lcap ? lds[i] : spill[i - lcap]; }
     __device__ void put(int i, int v) const {
-        if (i < kStackLds) lds[i] = v;
-        else spill[i - kStackLds] = v;
+        if (i < lcap) lds[i] = v;
+        else spill[i - lcap] = v;
     }
 };
 
