@@ -301,6 +301,32 @@ def tree(pos, mass, r_in, r_out, theta, eps, n_leaf=16, n_crit=64, D=21, r_buff=
     return acc, pot, dict(zip(names, (int(v) for v in st)))
 
 
+def kdk(pos, vel, mass, r_in, r_out, theta, eps, dt, steps, n_leaf=16, n_crit=64):
+    """Kick-drift-kick leapfrog under the regular force (Section 2.2, eq. kick
+    and the loop after it), the force from the CPU tree walk (``tree``) after a
+    full rebuild at every step:
+        a = F_R(x); repeat: v += dt/2 a; x += dt v; a = F_R(x); v += dt/2 a.
+    Returns (x, v, energy [steps+1]) with E = sum m v^2/2 + sum m Phi_R/2
+    before the first step and after each."""
+    x = _f64(pos).copy()
+    n = x.shape[0]
+    v = _f64(vel, (n, 3)).copy()
+    mass = _f64(mass, (n,))
+
+    def energy(ph):
+        return 0.5 * np.dot(mass, (v * v).sum(1)) + 0.5 * np.dot(mass, ph)
+
+    a, ph, _ = tree(x, mass, r_in, r_out, theta, eps, n_leaf=n_leaf, n_crit=n_crit)
+    e = [energy(ph)]
+    for _ in range(steps):
+        v += (0.5 * dt) * a
+        x += dt * v
+        a, ph, _ = tree(x, mass, r_in, r_out, theta, eps, n_leaf=n_leaf, n_crit=n_crit)
+        v += (0.5 * dt) * a
+        e.append(energy(ph))
+    return x, v, np.array(e)
+
+
 def tree_nodes(pos, mass, n_leaf=16, D=21):
     """Octree export: (order, ints [nodes,4] = begin,count,nchild,level,
     doubles [nodes,16] = M, com[3], q[6] (xx,yy,zz,xy,xz,yz), lo[3], hi[3])."""
