@@ -9,15 +9,17 @@ Workloads (--workload):
   plummer1m    (default) Plummer sphere N = 2^20, Kroupa masses, Henon units,
                eps = 1e-6, r_out for 64 mean neighbours (0.04077), r_in =
                0.1 r_out, theta = 0.5, quadrupole nodes, FP32 interactions
-               with FP64 positions and sums, n_leaf = 8, n_crit = 64 (the
-               autotuner's choice on MI355X; --autotune re-tunes)
+               with FP64 positions and sums; n_leaf, n_crit and the walk tile
+               from the autotuner, timed on this input before the timed
+               region (--no-autotune: --leaf, --ncrit)
   plummer128k  N = 131072, eps = 1e-5, n_crit = 32 (run with --prec fp64 and mixed)
   plummer4m    N = 2^22, eps = 1e-6
   ensemble64   64 independent clusters, N log-uniform in [1e4, 2e5], each
                with its own r_out for 64 neighbours; one batched build and one
                persistent walk launch per step
   p3t1m        N = 2^20 with the paper's run parameters (tau = (1/128)(N/2^14)^(-1/3),
-               r_cut = 4 tau, r_buff = 3 tau sigma, dt_reg = 2^-9, eta = 0.02):
+               r_cut = 4 tau, r_buff = 3 tau sigma, dt_reg = 2^-9, eta = 0.02,
+               theta = 0.4):
                the whole P3T loop (regular force and buffered lists, kicks,
                Hermite F_I on block steps); a step = one regular step
   kdk4m        N = 2^22: 32 kick-drift-kick steps of dt = 1/1024 with a full
@@ -69,6 +71,11 @@ WORKLOADS = {
     "p3t1m": "plummer1m_kroupa",
 }
 METRIC = "particle-node interactions/s and force evals/s at N=1e6 vs FP32 VALU roofline"
+# The paper's own headline, quoted for context only (whole NBODY6+P3T code,
+# other hardware, not this metric): abstract and Section 3.1.
+CONTEXT = ("paper (context, not comparable): the whole NBODY6+P3T code runs more than 2x faster "
+           "than NBODY6 at N = 10^6 on one NVIDIA V100 with 2 x 14-core Intel Xeon Gold 6132 "
+           "(abstract; Section 3.1)")
 
 
 def clock_mhz(torch):
@@ -111,15 +118,17 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plummer1m", choices=sorted(WORKLOADS))
-    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--theta", type=float, default=None,
+                    help="opening angle (default 0.5; 0.4 for p3t1m, the paper's runs)")
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--leaf", type=int, default=8, help="n_leaf (tree leaf size)")
+    ap.add_argument("--leaf", type=int, default=0,
+                    help="n_leaf (tree leaf size; default 8, 16 for kdk4m, the oracle run's)")
     ap.add_argument("--ncrit", type=int, default=0,
                     help="n_crit (largest walk group); 0 = the library's choice by size "
                          "(32 below 2^18 particles, else 64)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="pick n_leaf and n_crit by timing candidates on this input first "
-                         "(on MI355X every workload here picks n_leaf=8, n_crit=64)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use --leaf/--ncrit as given instead of the autotuner's choice of n_leaf, "
+                         "n_crit and walk tile (timed on this input before the timed region)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-neighbours", action="store_true")
     ap.add_argument("--valu-probe", action="store_true",
@@ -138,6 +147,8 @@ def q(e):
 
 def main():
     args = parse()
+    if args.theta is None:
+        args.theta = 0.4 if args.workload == "p3t1m" else 0.5
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the distant-force "
               "path is measured on a single MI355X.", file=sys.stderr)
@@ -189,9 +200,9 @@ def bench_force(args):
     L, ctx = p.L, p.ctx
 
     tuned = None
-    if not args.autotune:
+    if args.no_autotune:
         ncrit = args.ncrit or (32 if n < (1 << 18) else 64)   # the library's rule for n_crit = 0
-        p.set_params(leaf_size=args.leaf, n_crit=ncrit, prec=args.prec)
+        p.set_params(leaf_size=args.leaf or 8, n_crit=ncrit, prec=args.prec)
     else:
         tuned = autotune.tune(p, pos, mass, inp["r_in"], inp["r_out"], theta, eps, prec=args.prec,
                               neighbours=neighbours, offsets=inp["offsets"])
@@ -292,8 +303,9 @@ def bench_force(args):
         "data": "synthetic",
         "config": {"workload": f"{inp['name']}: {inp['desc']} theta={theta} quadrupole",
                    "n": n, "theta": theta, "precision": args.prec, "leaf_size": prm["leaf_size"],
-                   "n_crit": prm["n_crit"], "neighbours": neighbours,
-                   "autotuned": tuned is not None, "clusters": 64 if batched else 1},
+                   "n_crit": prm["n_crit"], "walk_tile": prm["walk_tile"] or 64,
+                   "neighbours": neighbours, "autotuned": tuned is not None,
+                   "clusters": 64 if batched else 1},
         "force_evals_per_s": n / (ms_step * 1e-3),
         "force_evals_per_s_walk_only": n / (walk_avg * 1e-3),
         "interactions_per_s_walk_only": per_step_inter / (walk_avg * 1e-3),
@@ -317,6 +329,7 @@ def bench_force(args):
     if tuned is not None:
         rec["autotune"] = {k: v for k, v in tuned.items() if k != "cached"}
         rec["autotune"]["cached"] = tuned["cached"]
+    rec["context"] = CONTEXT
 
     if neighbours and not batched:
         total = int(off[-1].item())
@@ -325,6 +338,10 @@ def bench_force(args):
         rec["core"] = bench_core(p, inp, dev, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"], rec["accuracy"] = cpu_baseline(inp, theta, prm, acc, pot)
+    if args.prec == "mixed" and not batched:
+        # after the accuracy check above: this leg overwrites acc and pot
+        rec["fp64_walk"] = fp64_walk_leg(p, build, force, neighbours, off, idx, cap, per_step_inter,
+                                         walk_avg, prm)
     p.close()
     print(json.dumps(rec))
 
@@ -438,6 +455,30 @@ def _cpu_model():
     return "unknown"
 
 
+def fp64_walk_leg(p, build, force, neighbours, off, idx, cap, per_step_inter, mixed_walk_ms, prm):
+    """The same step with every interaction in FP64 (same tree, groups and
+    opening rule): the walk's HIP-event time against the mixed walk's."""
+    import ctypes as C  # noqa: F401
+    from paper_2110_11658_amd.api import _ptr
+    from paper_2110_11658_amd._lib import check
+    p.set_params(leaf_size=prm["leaf_size"], n_crit=prm["n_crit"], walk_tile=prm["walk_tile"],
+                 prec="fp64")
+    ms = []
+    for r in range(4):
+        build()
+        check(p.ctx, force(_ptr(off) if neighbours else None, _ptr(idx) if neighbours else None,
+                           cap if neighbours else 0, None))
+        s = p.stats()
+        if r > 0:
+            ms.append(s["ms_walk"])
+    p.set_params(leaf_size=prm["leaf_size"], n_crit=prm["n_crit"], walk_tile=prm["walk_tile"],
+                 prec=prm["prec"])
+    w = float(np.median(ms))
+    return {"ms_walk": w, "interactions_per_s_walk_only": per_step_inter / (w * 1e-3),
+            "mixed_walk_speedup": w / mixed_walk_ms,
+            "note": "FP64 walk (k_walk<false>) on the same tree, groups and interactions"}
+
+
 def cpu_baseline(inp, theta, prm, acc, pot):
     """CPU oracle on the same workload: tree walk over all particles (timed; for
     the ensemble each cluster in turn), plus FP64 direct sums on 512 sampled
@@ -482,17 +523,38 @@ def cpu_baseline(inp, theta, prm, acc, pot):
     rng = np.random.default_rng(12345)
     ea, ep = [], []
     per = max(1, 512 // nc)
+    t_direct, pairs_direct = 0.0, 0
     for k in range(nc):
         s = slice(offsets[k], offsets[k + 1])
         nk = offsets[k + 1] - offsets[k]
         tg = rng.choice(nk, min(per, nk), replace=False)
+        t = time.perf_counter()
         ra, rp = oracle.direct(pos[s], mass[s], r_in[k], r_out[k], inp["eps"], targets=tg)
+        t_direct += time.perf_counter() - t
+        pairs_direct += len(tg) * nk
         ga = acc_h[s][tg]
         gp = pot_h[s][tg]
         ea.append(np.linalg.norm(ga - ra, axis=1) / np.linalg.norm(ra, axis=1))
         ep.append(np.abs(gp - rp) / np.abs(rp))
     accuracy = {"vs": f"FP64 direct summation on {sum(len(e) for e in ea)} sampled particles",
                 "force_rel": q(np.concatenate(ea)), "pot_rel": q(np.concatenate(ep))}
+    # the O(N^2) definition itself (direct summation), on all cores and on one
+    base["direct"] = {"value": pairs_direct / t_direct, "unit": "pairs/s", "cores": nthreads,
+                      "seconds": t_direct, "sample": f"{sum(len(e) for e in ea)} sampled targets, each "
+                                                     f"summed over every particle of its cluster"}
+    oracle.set_num_threads(1)
+    try:
+        tg = np.arange(min(32, offsets[1] - offsets[0]))
+        s = slice(offsets[0], offsets[1])
+        t = time.perf_counter()
+        oracle.direct(pos[s], mass[s], r_in[0], r_out[0], inp["eps"], targets=tg)
+        d1 = time.perf_counter() - t
+    finally:
+        oracle.set_num_threads(nthreads)
+    base["direct"]["one_core"] = {"value": len(tg) * (offsets[1] - offsets[0]) / d1, "unit": "pairs/s",
+                                  "seconds": d1,
+                                  "sample": f"{len(tg)} targets over all {offsets[1] - offsets[0]} "
+                                            f"particles of the first cluster, 1 thread"}
     return base, accuracy
 
 
@@ -541,6 +603,33 @@ def bench_kdk(args):
     if "fp64" in out and "mixed" in out:
         rec["energy_diff_mixed_vs_fp64"] = float(np.max(np.abs(out["mixed"]["energy"] - out["fp64"]["energy"])
                                                          / abs(out["fp64"]["energy"][0])))
+    # the oracle's leapfrog of the same workload (CPU FP64 tree walk, written to
+    # tests/golden by make_kdk4m_oracle.py): energies and the drift curve
+    gold_path = os.path.join(ROOT, "tests", "golden", "kdk4m_oracle.json")
+    if os.path.exists(gold_path) and leaf == 16 and ncrit == 64 and args.theta == 0.5:
+        gold = json.load(open(gold_path))
+        oe = np.array(gold["energy"])
+        d_orc = (oe - oe[0]) / abs(oe[0])
+        acc = {"vs": "oracle leapfrog (CPU FP64 tree walk, same workload), tests/golden/kdk4m_oracle.json",
+               "oracle_drift_max": float(np.max(np.abs(d_orc)))}
+        for k, v in out.items():
+            e = v["energy"]
+            acc[f"{k}_energy_max_rel_diff"] = float(np.max(np.abs(e - oe)) / abs(oe[0]))
+            acc[f"{k}_drift_max_abs_diff"] = float(np.max(np.abs((e - e[0]) / abs(e[0]) - d_orc)))
+        rec["accuracy"] = acc
+    if not args.no_cpu_baseline:
+        # one force evaluation of the oracle leapfrog (tree build + walk) on the
+        # host cores: one step's worth of the oracle's run
+        import oracle
+        t = time.perf_counter()
+        oracle.tree(inp["pos"], inp["mass"], inp["r_in"], inp["r_out"], args.theta, inp["eps"],
+                    n_leaf=leaf, n_crit=ncrit)
+        d = time.perf_counter() - t
+        rec["cpu_baseline"] = {"value": n / d, "unit": "particle-steps/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "seconds": d,
+                               "sample": "one regular-force evaluation of the oracle leapfrog (CPU FP64 "
+                                         "tree build + walk over all particles), i.e. one of its steps",
+                               "cpu_model": _cpu_model()}
     print(json.dumps(rec))
 
 
@@ -557,7 +646,7 @@ def bench_p3t(args):
     r_out, r_buff, T = pr["r_cut"], pr["r_buff"], pr["dt_reg"]
     r_in, eps, eta = 0.1 * r_out, inp["eps"], 0.02
     steps = args.steps if args.steps != 10 else 4
-    p = Pbh(0, leaf_size=args.leaf, n_crit=args.ncrit, prec=args.prec)
+    p = Pbh(0, leaf_size=args.leaf or 8, n_crit=args.ncrit, prec=args.prec)
     vel0 = torch.from_numpy(inp["vel"]).to(dev)
     pos, vel = inp["pos_d"].clone(), vel0.clone()
     p.p3t(pos.clone(), vel.clone(), inp["mass_d"], r_in, r_out, r_buff, args.theta, eps, T, eta, 1)

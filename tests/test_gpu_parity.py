@@ -457,16 +457,23 @@ def test_autotune_choices_valid_and_cached(tmp_path, monkeypatch):
     monkeypatch.setenv("PBH_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
     c = ic.plummer(20000, seed=21, masses="kroupa")
     p = _pbh()
-    cands = ((8, 32), (16, 64))
-    r = autotune.tune(p, _t(c.pos), _t(c.mass), 0.01, 0.1, 0.5, 1e-5, candidates=cands, reps=1)
-    assert (r["leaf_size"], r["n_crit"]) in cands and not r["cached"]
-    assert len(r["table"]) == 2 and all(t["ms"] > 0 for t in r["table"])
-    assert (p.params()["leaf_size"], p.params()["n_crit"]) == (r["leaf_size"], r["n_crit"])
-    r2 = autotune.tune(p, _t(c.pos), _t(c.mass), 0.01, 0.1, 0.5, 1e-5, candidates=cands, reps=1)
-    assert r2["cached"] and (r2["leaf_size"], r2["n_crit"]) == (r["leaf_size"], r["n_crit"])
+    cands, tiles = ((8, 32), (16, 64)), (64, 128)
+    r = autotune.tune(p, _t(c.pos), _t(c.mass), 0.01, 0.1, 0.5, 1e-5, candidates=cands, tiles=tiles,
+                      reps=1)
+    assert (r["leaf_size"], r["n_crit"]) in cands and r["walk_tile"] in tiles and not r["cached"]
+    # two (n_leaf, n_crit) pairs at the first tile, both timed again, then the
+    # other tile at the better pair
+    assert len(r["table"]) == 5 and all(t["ms"] > 0 for t in r["table"])
+    got = p.params()
+    assert (got["leaf_size"], got["n_crit"], got["walk_tile"]) == (r["leaf_size"], r["n_crit"],
+                                                                   r["walk_tile"])
+    r2 = autotune.tune(p, _t(c.pos), _t(c.mass), 0.01, 0.1, 0.5, 1e-5, candidates=cands, tiles=tiles,
+                       reps=1)
+    assert r2["cached"] and (r2["leaf_size"], r2["n_crit"], r2["walk_tile"]) == (
+        r["leaf_size"], r["n_crit"], r["walk_tile"])
     # every candidate gives the same neighbour sets
     o_off, o_idx = oracle.nbr_cells(c.pos, 0.1)
-    for leaf, ncrit in cands:
-        p.set_params(leaf_size=leaf, n_crit=ncrit)
+    for t in r["table"]:
+        p.set_params(leaf_size=t["leaf_size"], n_crit=t["n_crit"], walk_tile=t["walk_tile"])
         acc, pot, off, idx = _run(p, c, 0.01, 0.1, 0.5, 1e-5)
         _sets_equal(off, idx, o_off, o_idx)
