@@ -146,6 +146,28 @@ def test_p3t_larger_n():
     assert np.allclose(e.cpu().numpy(), oe, rtol=1e-11, atol=0)
 
 
+def test_p3t_paper_parameters_16k():
+    # 16384 particles with the paper's run parameters (tau rule: r_cut = 4 tau,
+    # r_buff = 3 tau sigma, dt_reg the largest power of 1/2 not above tau,
+    # eta = 0.02; Kroupa masses): two regular steps of the whole loop, FP64 and
+    # theta = 0 on the GPU against the oracle loop (direct regular force)
+    n = 16384
+    print(f"p3t paper parameters n={n}", flush=True)
+    c = ic.plummer(n, seed=99, masses="kroupa")
+    pr = ic.paper_radii(n)
+    r_out, r_buff, T = pr["r_cut"], pr["r_buff"], pr["dt_reg"]
+    r_in, eps, eta, steps = 0.1 * r_out, 1e-5, 0.02, 2
+    p = _pbh(prec="fp64")
+    pos, vel, mass = _t(c.pos), _t(c.vel), _t(c.mass)
+    e, st = p.p3t(pos, vel, mass, r_in, r_out, r_buff, 0.0, eps, T, eta, steps)
+    ox, ov, oe = oracle.p3t(c.pos, c.vel, c.mass, r_in, r_out, eps, T, eta=eta, steps=steps)
+    assert st["steps"] >= steps * 4 * n   # every particle takes at least dt_max = dt_reg / 4
+    gx, gv = pos.cpu().numpy(), vel.cpu().numpy()
+    assert np.abs(gx - ox).max() <= 1e-10 * np.abs(ox).max()
+    assert np.abs(gv - ov).max() <= 1e-10 * np.abs(ov).max()
+    assert np.allclose(e.cpu().numpy(), oe, rtol=1e-11, atol=0)
+
+
 def test_hermite_kepler_order_on_gpu():
     # two bodies, all of the force irregular: the orbit closes after one period
     # with an error falling as eta^2 (4th order)
