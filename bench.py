@@ -286,7 +286,7 @@ def bench_force(args):
     achieved = flops / (walk_avg * 1e-3) / 1e12
     per_step_inter = s["n_pn"] + s["n_pp_far"] + s["n_pp_near"]
     peak = PEAK_FP32_TFLOPS if args.prec == "mixed" else PEAK_FP64_TFLOPS
-    kernel = "k_walk<true>" if args.prec == "mixed" else "k_walk<false>"
+    kernel = f"k_walk<{'true' if args.prec == 'mixed' else 'false'}, {prm['walk_tile'] or 64}>"
 
     rec = {
         "metric": METRIC,
@@ -476,7 +476,7 @@ def fp64_walk_leg(p, build, force, neighbours, off, idx, cap, per_step_inter, mi
     w = float(np.median(ms))
     return {"ms_walk": w, "interactions_per_s_walk_only": per_step_inter / (w * 1e-3),
             "mixed_walk_speedup": w / mixed_walk_ms,
-            "note": "FP64 walk (k_walk<false>) on the same tree, groups and interactions"}
+            "note": "FP64 walk (k_walk<false, tile>) on the same tree, groups and interactions"}
 
 
 def cpu_baseline(inp, theta, prm, acc, pot):

@@ -32,14 +32,14 @@ namespace pbh {
 namespace {
 
 // Tile capacity TC (a template parameter, 64, 96 or 128). A far or near tile
-// is evaluated just before it would overflow; the multipole tile holds TC + 64
+// is evaluated just before it would overflow; the multipole tile holds TC + 32
 // entries and is evaluated at the start of a traversal step once it holds more
-// than TC (one step adds at most 64), where the least state is live. One
+// than TC - 32 (one step adds at most 64), where the least state is live. One
 // traversal step adds at most 64 entries of a kind, so TC >= 64.
 //
 // The first kWalkStackLds traversal stack entries live in LDS (the rest in the
 // wave's spill region).
-constexpr int kWalkStackLds = 256;
+constexpr int kWalkStackLds = 640;
 //
 // Near entries of the FP64 walk keep their original coordinates for the
 // neighbour test; the mixed walk keeps the sorted index instead and reads the
@@ -58,7 +58,7 @@ template <typename R, int TC>
 struct alignas(16) Tiles : NearExtra<R, TC> {
     static_assert(TC >= 64, "one traversal step adds up to 64 entries");
     static constexpr int kCap = TC;
-    R pn[TC + 64][12];   // cx cy cz M | qxx qyy qzz qxy | qxz qyz - -  (room for one more step)
+    R pn[TC + 32][12];   // cx cy cz M | qxx qyy qzz qxy | qxz qyz - -  (room for one more step)
     R far[TC][4];        // x y z m (relative to the group centre)
     R nearp[TC][4];
     int nearj[TC];       // caller index: skips the self pair, and is the neighbour index
@@ -657,7 +657,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         while (top > 0) {
             // multipole tile: evaluated here, where no node state is live,
             // once it could not take another step's entries (up to 64)
-            if (npn > TCAP) {
+            if (npn > TCAP - 32) {
                 __syncthreads();
                 flush_pn(npn);
                 npn = 0;
