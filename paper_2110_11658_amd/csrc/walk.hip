@@ -367,6 +367,9 @@ __device__ inline Part<R> eval_near(const Tiles<R, TC>& T, int cnt, int ksub, in
 // FP32 form without per-lane branches: the neighbour count and the pole
 // terms (-d0/s + l1 ln s, present when r_in > 0) are compile-time switches,
 // ln s = log2(s) ln 2, and the boundary cases of W and Phi_R are selects.
+// Each entry yields a force factor f and a potential term, taken either from
+// the far-pair formula (every lane beyond the list radius) or from the
+// changeover forms; the sums are updated in one place after either.
 template <bool CNT, bool POLE, int TC>
 __device__ inline Part<float> eval_near_f32(const Tiles<float, TC>& T, int cnt, int ksub, int sub,
                                             float px, float py, float pz, float eps2, int self,
@@ -377,60 +380,72 @@ __device__ inline Part<float> eval_near_f32(const Tiles<float, TC>& T, int cnt, 
     const double* __restrict__ gz = K.z;
     float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
     const float l1 = K.l1 * 0.693147180559945309f;
+    const float x0 = -K.r_in * K.inv_delta;   // x = (s - r_in) / delta = s / delta + x0
+    // s^2 >= 1e-30 keeps 1/s and 1/s^2 finite: a pair at s = 0 only arises with
+    // eps = 0 (where W = 0 and the self pair is masked); for eps^2 >= 2^-76 the
+    // added term is below half an ulp of s^2 and changes nothing
+    const float e2 = eps2 + 1e-30f;
     for_entries<2>(cnt, ksub, sub, [&](int e) {
         const float4 q = *reinterpret_cast<const float4*>(&T.nearp[e][0]);
-        const int oj = T.nearj[e];
-        const bool other = oj != self;
         const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const float s2 = r2 + eps2;
+        const float s2 = r2 + e2;
         const float dr = r2 - K.rlist2f;
+        const float inv = __builtin_amdgcn_rsqf(s2);
+        float f, pt;
         if (__ballot(dr <= K.band) == 0) {
             // every lane's pair lies beyond R >= r_out by more than the rounding band:
             // no neighbour, W = 1 and Phi_R = -1/s (the far-pair formula)
-            const float inv = __builtin_amdgcn_rsqf(s2);
             const float mi = q.w * inv;
-            const float mi3 = mi * (inv * inv);
-            ax = fmaf(mi3, dx, ax);
-            ay = fmaf(mi3, dy, ay);
-            az = fmaf(mi3, dz, az);
-            ph -= mi;
-            return;
-        }
-        if (CNT) {
-            // FP32 decides outside the band (where it provably agrees with the
-            // FP64 definition), the FP64 test inside it
-            const bool band = fabsf(dr) <= K.band;
-            bool nb = dr < 0.f;
-            if (__ballot(band)) {
-                if (band) {
-                    const int js = T.nears[e];
-                    nb = is_neighbour(gx[js], gy[js], gz[js], gx[me], gy[me], gz[me], rlist2);
+            f = mi * (inv * inv);
+            pt = -mi;
+        } else {
+            // changeover forms first (every lane evaluates them), then the
+            // neighbour test, then the selects
+            const float s = s2 * inv;
+            const float xx = fmaf(s, K.inv_delta, x0);
+            const float x2 = xx * xx;
+            const float gp = (x2 * x2) * fmaf(xx, fmaf(xx, fmaf(-20.f, xx, 70.f), -84.f), 35.f);
+            const float t = s * K.inv_delta;
+            float mid = fmaf(t, fmaf(t, fmaf(t, fmaf(t, fmaf(t, K.e[5], K.e[4]), K.e[3]), K.e[2]), K.e[1]),
+                             K.e[0]);
+            mid = fmaf(t, mid, K.c0);
+            if (POLE) mid = fmaf(-K.d0, inv, fmaf(l1, __builtin_amdgcn_logf(s), mid));
+            // (the empty asm statements keep the polynomial and the selects in
+            // place: sunk under a divergent branch on s < r_out, they cost more in
+            // exec-mask handling than they save)
+            asm volatile("" : "+v"(mid));
+            const bool outer = s >= K.r_out, inner = s < K.r_in;
+            float phi = inner ? K.inner : mid;
+            asm volatile("" : "+v"(phi));
+            phi = outer ? -inv : phi;
+            const int oj = T.nearj[e];
+            const bool other = oj != self;
+            if (CNT) {
+                // FP32 decides outside the band (where it provably agrees with the
+                // FP64 definition), the FP64 test inside it
+                const bool band = fabsf(dr) <= K.band;
+                bool nb = dr < 0.f;
+                if (__ballot(band)) {
+                    if (band) {
+                        const int js = T.nears[e];
+                        nb = is_neighbour(gx[js], gy[js], gz[js], gx[me], gy[me], gz[me], rlist2);
+                    }
                 }
+                nb = nb & other;
+                if (nb & (nbr < scap)) srow[nbr * kStageStride] = oj;
+                nbr += nb ? 1 : 0;
             }
-            nb = nb & other;
-            if (nb & (nbr < scap)) srow[nbr * kStageStride] = oj;
-            nbr += nb ? 1 : 0;
+            const float mq = other ? q.w : 0.f;
+            const float W = outer ? 1.f : (inner ? 0.f : gp);
+            // W first: W = 0 gives f = 0 without forming m / s^3
+            f = ((W * mq) * inv) * (inv * inv);
+            pt = mq * phi;
         }
-        const float inv = __builtin_amdgcn_rsqf(s2);
-        const float s = s2 > 0.f ? s2 * inv : 0.f;
-        const float xx = (s - K.r_in) * K.inv_delta;
-        const float x2 = xx * xx;
-        const float gp = x2 * x2 * fmaf(xx, fmaf(xx, fmaf(-20.f, xx, 70.f), -84.f), 35.f);
-        const bool outer = s >= K.r_out, inner = s < K.r_in;
-        const float W = outer ? 1.f : (inner ? 0.f : gp);
-        const float mi3 = q.w * (inv * inv) * inv;
-        const float f = (W > 0.f) & other ? W * mi3 : 0.f;
         ax = fmaf(f, dx, ax);
         ay = fmaf(f, dy, ay);
         az = fmaf(f, dz, az);
-        const float t = s * K.inv_delta;
-        float mid = fmaf(t, fmaf(t, fmaf(t, fmaf(t, fmaf(t, K.e[5], K.e[4]), K.e[3]), K.e[2]), K.e[1]),
-                         K.e[0]);
-        mid = fmaf(t, mid, K.c0);
-        if (POLE) mid = fmaf(-K.d0, inv, fmaf(l1, __builtin_amdgcn_logf(s), mid));
-        const float phi = outer ? -inv : (inner ? K.inner : mid);
-        ph = other ? fmaf(q.w, phi, ph) : ph;
+        ph += pt;
     });
     return Part<float>{ax, ay, az, ph};
 }
