@@ -92,6 +92,9 @@ struct pbh_ctx {
     std::vector<Buf> bufs;
     std::vector<int64_t> cl_off_h;
     int nblk_box = 0;
+    // cluster offsets and buffer generation of the block tables now on the device
+    std::vector<int64_t> tab_off;
+    int64_t tab_gen = -1;
     // allocation sizes
     int64_t a_n = -1, a_cap = -1, a_G = -1, a_C = -1, a_nblk = -1, a_stack = -1;
     int64_t alloc_gen = 0;   // bumped whenever device buffers are reallocated
@@ -349,6 +352,9 @@ pbh_status setup_build(pbh_ctx* ctx, int64_t n, int32_t C, const int64_t* offset
     }
     pbh_status st = ensure_buffers(ctx);
     if (st != PBH_OK) return st;
+    // the tables on the device still hold these offsets: nothing to upload or wait for
+    if (ctx->tab_gen == ctx->alloc_gen && ctx->tab_off == ctx->cl_off_h) return PBH_OK;
+    ctx->tab_gen = -1;
     // block table: cluster of each block, then per-cluster block offsets
     std::vector<int32_t> tab(blk_cluster);
     tab.insert(tab.end(), cblk.begin(), cblk.end());
@@ -359,6 +365,8 @@ pbh_status setup_build(pbh_ctx* ctx, int64_t n, int32_t C, const int64_t* offset
     HIP_TRY(hipMemcpyAsync(ctx->d.cl_off, ctx->cl_off_h.data(), (C + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));   // the host tables above are temporaries
+    ctx->tab_off = ctx->cl_off_h;
+    ctx->tab_gen = ctx->alloc_gen;
     return PBH_OK;
 }
 
