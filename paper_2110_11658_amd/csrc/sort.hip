@@ -1,8 +1,9 @@
 // sort.hip -- device-wide exclusive scan and stable LSD radix sort (gfx950).
 //
-// Scan: three launches of fixed size (so they can be captured in a graph):
-// per-tile sums, one workgroup scanning the tile sums, per-tile scan plus
-// offset. Radix sort: 8-bit digits; per pass a tile histogram (LDS atomics),
+// Scan: launches of fixed size (so they can be captured in a graph): per-tile
+// sums, then per-tile scans, each tile adding the sums of the tiles before it
+// (summed by its own workgroup while there are at most kScanFuseTiles tiles;
+// beyond that a single workgroup scans the tile sums in a launch between). Radix sort: 8-bit digits; per pass a tile histogram (LDS atomics),
 // a scan of the digit-major histogram table, and a stable scatter in which
 // each wave ranks equal digits with eight ballots (match by bits) and the
 // waves of a workgroup are ordered through LDS.
@@ -120,9 +121,65 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_down(const T* in, int64_t n,
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (O)tmp[nb];
 }
 
+// Per-tile scan with the tile's offset summed here from the tile sums before
+// it (tmp[0 .. blockIdx.x), in index order per thread, then across the
+// workgroup); the last tile also writes the total to out[n].
+constexpr int64_t kScanFuseTiles = 4096;
+
+template <typename T, typename O>
+__global__ __launch_bounds__(SCAN_T) void k_scan_down_fused(const T* in, int64_t n,
+                                                            const int64_t* __restrict__ tmp, O* out,
+                                                            int64_t nb) {
+    __shared__ int64_t s_val[SCAN_TILE];
+    __shared__ int64_t s_wave[SCAN_T / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int64_t part = 0;
+    for (int64_t k = t; k < (int64_t)blockIdx.x; k += SCAN_T) part += tmp[k];
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    if (lane == 0) s_wave[w] = part;
+    __syncthreads();
+    int64_t off = 0;
+    for (int k = 0; k < SCAN_T / 64; ++k) off += s_wave[k];
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        int64_t i = base + k * SCAN_T + t;
+        s_val[k * SCAN_T + t] = (i < n) ? (int64_t)in[i] : 0;
+    }
+    __syncthreads();
+    int64_t v[SCAN_I];
+    int64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        v[k] = s_val[t * SCAN_I + k];
+        sum += v[k];
+    }
+    int64_t tot;
+    int64_t run = block_excl_scan(sum, s_wave, &tot) + off;
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        s_val[t * SCAN_I + k] = run;
+        run += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        int64_t i = base + k * SCAN_T + t;
+        if (i < n) out[i] = (O)s_val[k * SCAN_T + t];
+    }
+    if (blockIdx.x == nb - 1 && t == 0) out[n] = (O)(off + tot);
+}
+
 template <typename T, typename O>
 void scan_impl(const T* in, O* out, int64_t n, int64_t* tmp, hipStream_t s) {
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb >= 1 && nb <= kScanFuseTiles) {
+        hipLaunchKernelGGL((k_scan_reduce<T>), dim3(nb), dim3(SCAN_T), 0, s, in, n, tmp);
+        hipLaunchKernelGGL((k_scan_down_fused<T, O>), dim3(nb), dim3(SCAN_T), 0, s, in, n,
+                           (const int64_t*)tmp, out, nb);
+        return;
+    }
     if (nb == 0) {
         // n == 0: out[0] = 0 through the top kernel with nb = 0
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, (int64_t)0);
