@@ -769,8 +769,21 @@ void launch_bbox(Dev& d, const BuildCfg& c, const double* pos, const double* mas
 }
 
 void launch_keys(Dev& d, const BuildCfg& c, const double* pos, int nblk, hipStream_t s) {
+    // with an odd number of sort passes the keys start in keys_alt, so that the
+    // sorted keys and permutation end in (keys, perm) without a copy
+    uint64_t* out = (radix_passes(3 * c.D + c.cbits) & 1) ? d.keys_alt : d.keys;
     hipLaunchKernelGGL(k_keys, dim3(nblk), dim3(BB_T), 0, s, pos, (const int64_t*)d.blk_range,
-                       (const int32_t*)d.blk_cluster, (const double*)d.cl_box, c.D, d.keys);
+                       (const int32_t*)d.blk_cluster, (const double*)d.cl_box, c.D, out);
+}
+
+void launch_key_sort(Dev& d, const BuildCfg& c, hipStream_t s) {
+    const int nbits = 3 * c.D + c.cbits;
+    if (radix_passes(nbits) & 1)
+        radix_sort_pairs(d.keys_alt, d.vals_alt, d.keys, d.perm, c.n, nbits, d.rs_hist, d.scan_tmp, s,
+                         true, nullptr, true);
+    else
+        radix_sort_pairs(d.keys, d.perm, d.keys_alt, d.vals_alt, c.n, nbits, d.rs_hist, d.scan_tmp, s,
+                         true);
 }
 
 void launch_gather(Dev& d, const BuildCfg& c, const double* pos, const double* mass, hipStream_t s) {
@@ -791,10 +804,11 @@ void launch_topology(Dev& d, const BuildCfg& c, hipStream_t s) {
     hipLaunchKernelGGL(k_topo_emit, dim3(grid_for(n, 256)), dim3(256), 0, s,
                        (const uint64_t*)d.keys, (const int64_t*)d.cl_off, n, c.D, c.n_leaf,
                        (const int32_t*)d.p_first, (const int32_t*)d.p_nn, cap, d.pre_begin,
-                       d.pre_count, d.pre_level, d.pre_nchild, d.lvl_key, d.cnt);
-    // breadth-first order: stable sort of pre-order nodes by level (one 8-bit pass)
-    radix_sort_pairs(d.lvl_key, d.bfs2pre, d.lvl_key_alt, d.lvl_val, cap, 8, d.rs_hist, d.scan_tmp,
-                     s, true, n_nodes);
+                       d.pre_count, d.pre_level, d.pre_nchild, d.lvl_key_alt, d.cnt);
+    // breadth-first order: stable sort of pre-order nodes by level (one 8-bit
+    // pass, from lvl_key_alt into (lvl_key, bfs2pre))
+    radix_sort_pairs(d.lvl_key_alt, d.lvl_val, d.lvl_key, d.bfs2pre, cap, 8, d.rs_hist, d.scan_tmp,
+                     s, true, n_nodes, true);
     hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, (const uint64_t*)d.lvl_key,
                        n_nodes, cap, d.lvl_off, d.cnt);
     hipLaunchKernelGGL(k_invert, dim3(grid_for(cap, 256)), dim3(256), 0, s,

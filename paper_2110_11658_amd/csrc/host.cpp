@@ -411,8 +411,7 @@ void enqueue_build(pbh_ctx* ctx, const double* pos, const double* mass, hipStrea
     launch_zero_u64(d.cnt, kNumCounters - 5, s);   // keep the KDK slots (>= 11)
     launch_bbox(d, c, pos, mass, ctx->nblk_box, s);
     launch_keys(d, c, pos, ctx->nblk_box, s);
-    radix_sort_pairs(d.keys, d.perm, d.keys_alt, d.vals_alt, c.n, 3 * c.D + c.cbits, d.rs_hist,
-                     d.scan_tmp, s, true);
+    launch_key_sort(d, c, s);
     launch_gather(d, c, pos, mass, s);
     launch_topology(d, c, s);
     launch_moments(d, c, s);

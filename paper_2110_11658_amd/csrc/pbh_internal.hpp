@@ -209,18 +209,25 @@ int64_t scan_tmp_need(int64_t n);
 void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp, hipStream_t s);
 int64_t radix_hist_need(int64_t n);
-// Stable LSD radix sort of (key, val) on bits [0, nbits). The result ends in
-// (keys, vals); (keys_alt, vals_alt) are scratch of the same size. With
-// vals_are_iota the input values are taken to be 0..n-1 (vals not read). If
-// n_dev is given the element count is min(n, *n_dev), read on the device.
+// Stable LSD radix sort of (key, val) on bits [0, nbits). The input is in
+// (keys, vals); the result ends in (keys, vals), or with to_alt in (keys_alt,
+// vals_alt), the other pair being scratch of the same size. The passes
+// alternate between the pairs, so the result needs no final copy when the
+// pass count (radix_passes) is even and to_alt is false, or odd and to_alt is
+// true. With vals_are_iota the input values are taken to be 0..n-1 (vals not
+// read). If n_dev is given the element count is min(n, *n_dev), read on the
+// device.
+int radix_passes(int nbits);
 void radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt,
                       int64_t n, int nbits, int64_t* hist, int64_t* scan_tmp, hipStream_t s,
-                      bool vals_are_iota, const int32_t* n_dev = nullptr);
+                      bool vals_are_iota, const int32_t* n_dev = nullptr, bool to_alt = false);
 
 // build.hip
 void launch_bbox(Dev& d, const BuildCfg& c, const double* pos, const double* mass, int nblk,
                  hipStream_t s);
 void launch_keys(Dev& d, const BuildCfg& c, const double* pos, int nblk, hipStream_t s);
+// the key sort of a build: (keys, perm) sorted by key, perm the caller order
+void launch_key_sort(Dev& d, const BuildCfg& c, hipStream_t s);
 void launch_gather(Dev& d, const BuildCfg& c, const double* pos, const double* mass, hipStream_t s);
 void launch_topology(Dev& d, const BuildCfg& c, hipStream_t s);
 void launch_moments(Dev& d, const BuildCfg& c, hipStream_t s);

@@ -3,10 +3,13 @@
 // Scan: launches of fixed size (so they can be captured in a graph): per-tile
 // sums, then per-tile scans, each tile adding the sums of the tiles before it
 // (summed by its own workgroup while there are at most kScanFuseTiles tiles;
-// beyond that a single workgroup scans the tile sums in a launch between). Radix sort: 8-bit digits; per pass a tile histogram (LDS atomics),
-// a scan of the digit-major histogram table, and a stable scatter in which
-// each wave ranks equal digits with eight ballots (match by bits) and the
-// waves of a workgroup are ordered through LDS.
+// beyond that a single workgroup scans the tile sums in a launch between).
+//
+// Radix sort: 8-bit digits. Per pass a tile
+// histogram (LDS atomics), a scan of the digit-major histogram table, and a
+// stable scatter in which each wave ranks equal digits with one ballot per
+// digit bit (match by bits) and the waves of a workgroup are ordered through
+// LDS.
 #include "pbh_internal.hpp"
 
 namespace pbh {
@@ -197,29 +200,34 @@ void scan_impl(const T* in, O* out, int64_t n, int64_t* tmp, hipStream_t s) {
 constexpr int RS_T = 256;
 constexpr int RS_R = 8;             // rounds per tile
 constexpr int RS_TILE = RS_T * RS_R;
-constexpr int RS_BINS = 256;
+constexpr int RS_MAX_BINS = 256;    // bins of the widest digit used
 
+// Tile histogram of one digit (BITS wide, at `shift`), digit-major table.
+template <int BITS>
 __global__ __launch_bounds__(RS_T) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n,
                                                   const int32_t* __restrict__ n_dev, int shift,
                                                   int64_t* __restrict__ hist, int64_t nblk) {
-    __shared__ int s_h[RS_BINS];
+    constexpr int BINS = 1 << BITS;
+    constexpr unsigned MASK = BINS - 1;
+    __shared__ int s_h[BINS];
     if (n_dev) n = min(n, (int64_t)*n_dev);
-    s_h[threadIdx.x] = 0;
+    for (int d = threadIdx.x; d < BINS; d += RS_T) s_h[d] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
 #pragma unroll 4
     for (int r = 0; r < RS_R; ++r) {
         int64_t i = base + r * RS_T + threadIdx.x;
-        if (i < n) atomicAdd(&s_h[(unsigned)(keys[i] >> shift) & 0xFFu], 1);
+        if (i < n) atomicAdd(&s_h[(unsigned)(keys[i] >> shift) & MASK], 1);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = s_h[threadIdx.x];
+    for (int d = threadIdx.x; d < BINS; d += RS_T) hist[(int64_t)d * nblk + blockIdx.x] = s_h[d];
 }
 
 __device__ inline uint64_t lanes_below(int lane) {
     return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 }
 
+template <int BITS>
 __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t* __restrict__ kin,
                                                      const int32_t* __restrict__ vin,
                                                      uint64_t* __restrict__ kout,
@@ -227,13 +235,19 @@ __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t* __restrict_
                                                      const int32_t* __restrict__ n_dev, int shift,
                                                      const int64_t* __restrict__ hist,
                                                      int64_t nblk, int iota) {
+    constexpr int BINS = 1 << BITS;
+    constexpr unsigned MASK = BINS - 1;
+    constexpr int PER = BINS / RS_T;   // bins per thread
     if (n_dev) n = min(n, (int64_t)*n_dev);
-    __shared__ int64_t s_goff[RS_BINS];
-    __shared__ int s_run[RS_BINS];
-    __shared__ int s_wc[RS_T / 64][RS_BINS];
+    __shared__ int64_t s_goff[BINS];
+    __shared__ int s_run[BINS];
+    __shared__ int s_wc[RS_T / 64][BINS];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    s_goff[t] = hist[(int64_t)t * nblk + blockIdx.x];
-    s_run[t] = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        s_goff[t + u * RS_T] = hist[(int64_t)(t + u * RS_T) * nblk + blockIdx.x];
+        s_run[t + u * RS_T] = 0;
+    }
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
     const uint64_t below = lanes_below(lane);
     for (int r = 0; r < RS_R; ++r) {
@@ -241,12 +255,14 @@ __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t* __restrict_
         const bool valid = i < n;
         uint64_t key = valid ? kin[i] : 0ull;
         int32_t val = valid ? (iota ? (int32_t)i : vin[i]) : 0;
-        const unsigned d = (unsigned)(key >> shift) & 0xFFu;
-        for (int k = 0; k < RS_T / 64; ++k) s_wc[k][t] = 0;
+        const unsigned d = (unsigned)(key >> shift) & MASK;
+#pragma unroll
+        for (int u = 0; u < PER; ++u)
+            for (int k = 0; k < RS_T / 64; ++k) s_wc[k][t + u * RS_T] = 0;
         __syncthreads();
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < BITS; ++b) {
             const bool bit = (d >> b) & 1u;
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
@@ -254,14 +270,16 @@ __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t* __restrict_
         const int rank = __popcll(peers & below);
         if (valid && rank == 0) s_wc[w][d] = __popcll(peers);
         __syncthreads();
-        {
-            int run = s_run[t];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int bin = t + u * RS_T;
+            int run = s_run[bin];
             for (int k = 0; k < RS_T / 64; ++k) {
-                int c = s_wc[k][t];
-                s_wc[k][t] = run;
+                int c = s_wc[k][bin];
+                s_wc[k][bin] = run;
                 run += c;
             }
-            s_run[t] = run;
+            s_run[bin] = run;
         }
         __syncthreads();
         if (valid) {
@@ -299,34 +317,42 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int64_t* tmp
 
 int64_t radix_hist_need(int64_t n) {
     const int64_t nblk = (n + RS_TILE - 1) / RS_TILE;
-    return nblk * RS_BINS + 1;
+    return nblk * RS_MAX_BINS + 1;
 }
+
+// 8-bit digits (9-bit digits would save a pass on 63-bit keys, 7 instead of 8,
+// but cost more per pass than that pass at 2^20)
+constexpr int RS_BITS = 8;
+
+int radix_passes(int nbits) { return (nbits + RS_BITS - 1) / RS_BITS; }
 
 void radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt,
                       int64_t n, int nbits, int64_t* hist, int64_t* scan_tmp, hipStream_t s,
-                      bool vals_are_iota, const int32_t* n_dev) {
+                      bool vals_are_iota, const int32_t* n_dev, bool to_alt) {
     if (n <= 0) return;
     const int64_t nblk = (n + RS_TILE - 1) / RS_TILE;
-    const int passes = (nbits + 7) / 8;
+    const int passes = radix_passes(nbits);
     uint64_t* ki = keys;
     int32_t* vi = vals;
     uint64_t* ko = keys_alt;
     int32_t* vo = vals_alt;
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(RS_T), 0, s, (const uint64_t*)ki, n, n_dev,
+        const int shift = RS_BITS * p;
+        const int iota = (int)(vals_are_iota && p == 0);
+        hipLaunchKernelGGL(k_rs_hist<RS_BITS>, dim3(nblk), dim3(RS_T), 0, s, (const uint64_t*)ki, n, n_dev,
                            shift, hist, nblk);
-        scan_impl<int64_t, int64_t>(hist, hist, nblk * RS_BINS, scan_tmp, s);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(RS_T), 0, s, (const uint64_t*)ki,
-                           (const int32_t*)vi, ko, vo, n, n_dev, shift, (const int64_t*)hist,
-                           nblk, (int)(vals_are_iota && p == 0));
+        scan_impl<int64_t, int64_t>(hist, hist, nblk << RS_BITS, scan_tmp, s);
+        hipLaunchKernelGGL(k_rs_scatter<RS_BITS>, dim3(nblk), dim3(RS_T), 0, s, (const uint64_t*)ki,
+                           (const int32_t*)vi, ko, vo, n, n_dev, shift, (const int64_t*)hist, nblk, iota);
         uint64_t* tk = ki; ki = ko; ko = tk;
         int32_t* tv = vi; vi = vo; vo = tv;
     }
-    if (ki != keys) {
+    uint64_t* kd = to_alt ? keys_alt : keys;
+    int32_t* vd = to_alt ? vals_alt : vals;
+    if (ki != kd) {
         const int nb = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
         hipLaunchKernelGGL(k_copy_pairs, dim3(nb), dim3(256), 0, s, (const uint64_t*)ki,
-                           (const int32_t*)vi, keys, vals, n, n_dev);
+                           (const int32_t*)vi, kd, vd, n, n_dev);
     }
 }
 
