@@ -214,10 +214,16 @@ __global__ __launch_bounds__(RS_T) void k_rs_hist(const uint64_t* __restrict__ k
     for (int d = threadIdx.x; d < BINS; d += RS_T) s_h[d] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-#pragma unroll 4
+    uint64_t k[RS_R];
+#pragma unroll
     for (int r = 0; r < RS_R; ++r) {
-        int64_t i = base + r * RS_T + threadIdx.x;
-        if (i < n) atomicAdd(&s_h[(unsigned)(keys[i] >> shift) & MASK], 1);
+        const int64_t i = base + r * RS_T + threadIdx.x;
+        k[r] = i < n ? keys[i] : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < RS_R; ++r) {
+        const int64_t i = base + r * RS_T + threadIdx.x;
+        if (i < n) atomicAdd(&s_h[(unsigned)(k[r] >> shift) & MASK], 1);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < BINS; d += RS_T) hist[(int64_t)d * nblk + blockIdx.x] = s_h[d];
@@ -250,11 +256,23 @@ __global__ __launch_bounds__(RS_T) void k_rs_scatter(const uint64_t* __restrict_
     }
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
     const uint64_t below = lanes_below(lane);
+    // every round's key and value are loaded up front: one memory latency per
+    // tile instead of one per round (the rounds are separated by barriers)
+    uint64_t keys[RS_R];
+    int32_t vals[RS_R];
+#pragma unroll
     for (int r = 0; r < RS_R; ++r) {
         const int64_t i = base + r * RS_T + t;
         const bool valid = i < n;
-        uint64_t key = valid ? kin[i] : 0ull;
-        int32_t val = valid ? (iota ? (int32_t)i : vin[i]) : 0;
+        keys[r] = valid ? kin[i] : 0ull;
+        vals[r] = valid ? (iota ? (int32_t)i : vin[i]) : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < RS_R; ++r) {
+        const int64_t i = base + r * RS_T + t;
+        const bool valid = i < n;
+        const uint64_t key = keys[r];
+        const int32_t val = vals[r];
         const unsigned d = (unsigned)(key >> shift) & MASK;
 #pragma unroll
         for (int u = 0; u < PER; ++u)
