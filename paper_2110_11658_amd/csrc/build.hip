@@ -600,7 +600,7 @@ __device__ inline void emit_group(int begin, int count, double ext, unsigned* hi
 }
 
 template <bool HIST>
-__global__ void k_group_pass(const WNode* __restrict__ node, const uint64_t* __restrict__ lvl,
+__global__ __launch_bounds__(256) void k_group_pass(const WNode* __restrict__ node, const uint64_t* __restrict__ lvl,
                              const unsigned long long* __restrict__ n_dev,
                              const uint64_t* __restrict__ keys, int D, int n_crit,
                              const double* __restrict__ x, const double* __restrict__ y,
@@ -639,11 +639,27 @@ __global__ void k_group_pass(const WNode* __restrict__ node, const uint64_t* __r
         }
         int run_begin = 0, run_count = 0;
         double rlo[3] = {0, 0, 0}, rhi[3] = {0, 0, 0};
-        for (int u = 0; u < w.nchild; ++u) {
-            const WNode& ch = node[w.first_child + u];
-            const double clo[3] = {ch.lo[0], ch.lo[1], ch.lo[2]};
-            const double chi[3] = {ch.hi[0], ch.hi[1], ch.hi[2]};
-            const int cc = ch.count;
+        // the children's boxes and counts are loaded together (one memory
+        // latency per node, not one per child); the loops are unrolled so the
+        // arrays stay in registers
+        const int nch = w.nchild;
+        double alo[8][3], ahi[8][3];
+        int acnt[8], abeg[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (u < nch) {
+                const WNode& ch = node[w.first_child + u];
+                for (int k = 0; k < 3; ++k) { alo[u][k] = ch.lo[k]; ahi[u][k] = ch.hi[k]; }
+                acnt[u] = ch.count;
+                abeg[u] = ch.begin;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (u >= nch) break;
+            const double clo[3] = {alo[u][0], alo[u][1], alo[u][2]};
+            const double chi[3] = {ahi[u][0], ahi[u][1], ahi[u][2]};
+            const int cc = acnt[u];
             if (cc > n_crit || box_extent(clo, chi) > S) {
                 if (run_count > 0) emit_group<HIST>(run_begin, run_count, box_extent(rlo, rhi), h, flag, len);
                 run_count = 0;
@@ -659,7 +675,7 @@ __global__ void k_group_pass(const WNode* __restrict__ node, const uint64_t* __r
                 run_count = 0;
                 for (int k = 0; k < 3; ++k) { ulo[k] = clo[k]; uhi[k] = chi[k]; }
             }
-            if (run_count == 0) run_begin = ch.begin;
+            if (run_count == 0) run_begin = abeg[u];
             run_count += cc;
             for (int k = 0; k < 3; ++k) { rlo[k] = ulo[k]; rhi[k] = uhi[k]; }
         }
@@ -667,30 +683,44 @@ __global__ void k_group_pass(const WNode* __restrict__ node, const uint64_t* __r
     }
 }
 
-// one block of kOctaves threads per cluster: sums the histogram copies, then
-// the size limit from the median octave of the first pass
-__global__ __launch_bounds__(kOctaves) void k_group_limit(const unsigned* __restrict__ hist, int nc,
-                                                          int reps, double* __restrict__ cl_S) {
-    __shared__ int64_t h[kOctaves];
-    const int c = blockIdx.x, i = threadIdx.x;
+// one block per cluster: 8 threads per octave sum the histogram copies (one
+// batch of loads each), then the size limit from the median octave of the
+// first pass (the first octave whose running count reaches half the groups,
+// found by a scan over the octaves)
+constexpr int kLimitT = 8 * kOctaves;
+__global__ __launch_bounds__(kLimitT) void k_group_limit(const unsigned* __restrict__ hist, int nc,
+                                                         int reps, double* __restrict__ cl_S) {
+    static_assert(kOctaves == 128, "two waves scan the octaves");
+    __shared__ int64_t s_part[8][kOctaves];
+    __shared__ int64_t s_w[2];
+    const int c = blockIdx.x, t = threadIdx.x, oct = t & (kOctaves - 1), part = t / kOctaves;
     int64_t v = 0;
-    for (int r = 0; r < reps; ++r) v += hist[((int64_t)r * nc + c) * kOctaves + i];
-    h[i] = v;
+#pragma unroll 8
+    for (int r = part; r < reps; r += 8) v += hist[((int64_t)r * nc + c) * kOctaves + oct];
+    s_part[part][oct] = v;
     __syncthreads();
-    if (i != 0) return;
-    int64_t total = 0;
-    for (int k = 0; k < kOctaves; ++k) total += h[k];
-    const int64_t need = (total + 1) / 2;
-    int64_t cum = 0;
-    int b = kOctaves - 1;
-    for (int k = 0; k < kOctaves; ++k) {
-        cum += h[k];
-        if (cum >= need) {
-            b = k;
-            break;
+    // the first two waves scan the octaves; every wave reaches both barriers
+    const int i = t, lane = i & 63, w = i >> 6;
+    int64_t inc = 0;
+    v = 0;
+    if (i < kOctaves) {
+        for (int k = 0; k < 8; ++k) v += s_part[k][i];
+        inc = v;   // inclusive running count over octaves 0..i
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t u = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += u;
         }
+        if (lane == 63) s_w[w] = inc;
     }
-    cl_S[c] = ldexp(1.0, b - 64 + kGroupLimitLog2);
+    __syncthreads();
+    if (i >= kOctaves) return;
+    if (w == 1) inc += s_w[0];
+    const int64_t total = s_w[0] + s_w[1];
+    const int64_t need = (total + 1) / 2;
+    // the first octave whose running count reaches need (octave 0 when empty)
+    if (inc >= need && inc - v < need) cl_S[c] = ldexp(1.0, i - 64 + kGroupLimitLog2);
+    else if (i == 0 && need == 0) cl_S[c] = ldexp(1.0, -64 + kGroupLimitLog2);
 }
 
 __global__ void k_fill_u32(unsigned* __restrict__ p, int64_t n) {
@@ -849,7 +879,7 @@ void launch_groups(Dev& d, const BuildCfg& c, hipStream_t s) {
                        (const uint64_t*)d.lvl_key, n_nodes, (const uint64_t*)d.keys, c.D, c.n_crit,
                        (const double*)d.x, (const double*)d.y, (const double*)d.z,
                        (const double*)d.cl_S, d.g_hist, c.n_clusters, reps, d.g_flag, d.g_len);
-    hipLaunchKernelGGL(k_group_limit, dim3(c.n_clusters), dim3(kOctaves), 0, s,
+    hipLaunchKernelGGL(k_group_limit, dim3(c.n_clusters), dim3(kLimitT), 0, s,
                        (const unsigned*)d.g_hist, c.n_clusters, reps, d.cl_S);
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, d.g_flag, n + 1, 0);
     hipLaunchKernelGGL(k_group_pass<false>, dim3(gb), dim3(256), 0, s, (const WNode*)d.node,
