@@ -200,14 +200,18 @@ __device__ inline bool irr_sums(const IrrParams& p, int64_t i, IrrSums& S, unsig
 
 
 // Lane groups: kIrrLanes lanes share one target. Lane g takes list entries
-// g, g + kIrrLanes, g + 2 kIrrLanes, ... in that order (kIrrLaneBatch of them
-// per round, their loads issued together), and the group adds its partial
+// g, g + kIrrLanes, g + 2 kIrrLanes, ... in that order (irr_lane_batch of
+// them per round, their loads issued together), and the group adds its partial
 // sums with a fixed butterfly (xor 4, 2, 1), so every lane ends with the
 // same total and the order does not depend on the launch. A wave's list loads
 // are then contiguous runs, and its record loads fall on the neighbours of a
 // few targets, close together in key order.
 constexpr int kIrrLanes = 8;
-constexpr int kIrrLaneBatch = 4;
+// entries per lane and round: 4 for the force alone; 3 with the jerk, whose
+// records and terms would otherwise hold the kernel to 3 waves per SIMD (at
+// 2^20 the force + jerk + potential call is 5 % faster with 3)
+template <bool JERK>
+constexpr int irr_lane_batch() { return JERK ? 3 : 4; }
 
 __device__ inline double group_sum(double v) {
 #pragma unroll
@@ -225,6 +229,7 @@ __device__ inline bool irr_sums_lanes(const IrrParams& p, int64_t i, int g, IrrS
     if (valid) {
         const IrrK K = irr_constants(MULTI ? *cp : p.cp0);
         const PartJ me = SORTED ? load_rec<JERK>(p.rec, p.rank[i]) : load_caller<JERK>(p, i);
+        constexpr int kIrrLaneBatch = irr_lane_batch<JERK>();
         for (int64_t m = b + g; m < e; m += kIrrLanes * kIrrLaneBatch) {
             int32_t jv[kIrrLaneBatch];
             bool ok[kIrrLaneBatch];
