@@ -403,6 +403,17 @@ pbh_status pbh_set_timing(pbh_ctx* ctx, int32_t enable);
 pbh_status pbh_get_stats(pbh_ctx* ctx, pbh_stats* out);
 
 /*
+ * Rate of the device cycle counter (clock64) during the last tree walk, in MHz:
+ * a measurement beside the roofline figures, not a step of the paper's method.
+ * Every workgroup of the walk records the cycle-counter and steady-clock
+ * counts between its start and its end; *mhz is the sum of the cycles over
+ * the sum of the ticks at the device's steady-clock rate. Waits for the
+ * stream. PBH_E_STATE before any walk (or after buffers were reallocated),
+ * PBH_E_ARG for null arguments.
+ */
+pbh_status pbh_walk_clock(pbh_ctx* ctx, double* mhz);
+
+/*
  * Debug export of the last build (waits for the stream). Host buffers:
  *   order [n]          sorted position -> caller index (int32)
  *   keys  [n]          sorted keys (uint64)

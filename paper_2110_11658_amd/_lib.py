@@ -29,7 +29,8 @@ EXPORTS = ("pbh_create", "pbh_destroy", "pbh_set_params", "pbh_get_params", "pbh
            "pbh_force_batched_buffered", "pbh_irregular",
            "pbh_irregular_batched", "pbh_irregular_noalloc", "pbh_core", "pbh_hermite", "pbh_p3t",
            "pbh_kdk_graph",
-           "pbh_kdk_eager", "pbh_get_stats", "pbh_set_timing", "pbh_debug_tree", "pbh_debug_groups",
+           "pbh_kdk_eager", "pbh_get_stats", "pbh_walk_clock", "pbh_set_timing", "pbh_debug_tree",
+           "pbh_debug_groups",
            "pbh_debug_wave_log", "pbh_debug_valu_probe", "pbh_debug_herm_first_steps",
            "pbh_last_error", "pbh_status_string")
 
@@ -97,6 +98,7 @@ def load(path: str = LIB_PATH):
         "pbh_kdk_graph": (st, [vp, i64, vp, vp, vp, d, i32, d, d, d, d, vp, vp]),
         "pbh_kdk_eager": (st, [vp, i64, vp, vp, vp, d, i32, d, d, d, d, vp, vp]),
         "pbh_get_stats": (st, [vp, vp]),
+        "pbh_walk_clock": (st, [vp, vp]),
         "pbh_set_timing": (st, [vp, i32]),
         "pbh_debug_tree": (st, [vp, vp, vp, i64, vp, vp, vp]),
         "pbh_debug_groups": (st, [vp, i64, vp, vp, vp, vp]),

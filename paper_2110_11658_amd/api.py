@@ -340,6 +340,13 @@ class Pbh:
             out[name] = float(v) if typ is C.c_double else int(v)
         return out
 
+    def walk_clock_mhz(self) -> float:
+        """Rate (MHz) of the device cycle counter during the last tree walk,
+        from its workgroups' cycle and steady-clock counts (pbh_walk_clock)."""
+        v = C.c_double(0.0)
+        check(self.ctx, self.L.pbh_walk_clock(self.ctx, C.byref(v)))
+        return float(v.value)
+
     def debug_herm_first_steps(self) -> np.ndarray:
         """First block step (ticks of dt_max / 2^40) of every particle in the
         last Hermite integration, caller order."""

@@ -95,6 +95,8 @@ struct pbh_ctx {
     // cluster offsets and buffer generation of the block tables now on the device
     std::vector<int64_t> tab_off;
     int64_t tab_gen = -1;
+    // grid of the last walk launch (its per-workgroup clock record), 0 before any
+    int64_t last_walk_grid = 0;
     // allocation sizes
     int64_t a_n = -1, a_cap = -1, a_G = -1, a_C = -1, a_nblk = -1, a_stack = -1;
     int64_t alloc_gen = 0;   // bumped whenever device buffers are reallocated
@@ -171,6 +173,7 @@ void free_all(pbh_ctx* ctx) {
     ctx->bufs.clear();
     ctx->d = Dev();
     ctx->a_n = ctx->a_cap = ctx->a_G = ctx->a_C = ctx->a_nblk = ctx->a_stack = -1;
+    ctx->last_walk_grid = 0;
 }
 
 template <typename T>
@@ -243,7 +246,8 @@ pbh_status ensure_buffers(pbh_ctx* ctx) {
               dalloc(ctx, &d.stack, stack) && dalloc(ctx, &d.cnt, kNumCounters) &&
               dalloc(ctx, &d.queues, 32) &&
               dalloc(ctx, &d.wave_log, 2 * (stack / kStackCap)) &&
-              dalloc(ctx, &d.wave_log_nbr, 2 * (stack / kStackCap));
+              dalloc(ctx, &d.wave_log_nbr, 2 * (stack / kStackCap)) &&
+              dalloc(ctx, &d.wave_cyc, stack / kStackCap);
     if (!ok) {
         free_all(ctx);
         return fail(ctx, PBH_E_OOM, "device allocation failed");
@@ -565,6 +569,7 @@ pbh_status do_force(pbh_ctx* ctx, const double* pos, const double* mass,
     w.stage_cap = w.count_nbr ? ensure_stage(ctx) : 0;
     mark(ctx, 2, s);
     launch_walk(d, c, w, acc, pot, s);
+    ctx->last_walk_grid = w.grid;
     mark(ctx, 3, s);
     ctx->ev_walk = ctx->timing;
     ctx->ev_nbr = false;
@@ -1369,6 +1374,7 @@ static void kdk_force(pbh_ctx* ctx, const double* pos, const double* mass, doubl
     w.count_nbr = 0;
     w.stage_cap = 0;
     launch_walk(ctx->d, ctx->cfg, w, ctx->k_acc, ctx->k_pot, s);
+    ctx->last_walk_grid = w.grid;
 }
 
 __global__ void k_energy_store(const double* e, double* out, unsigned long long* cnt) {
@@ -1551,6 +1557,27 @@ pbh_status pbh_debug_wave_log(pbh_ctx* ctx, uint64_t* walk, uint64_t* nbr, int64
         HIP_TRY(hipMemcpy(walk, ctx->d.wave_log, 16 * gw, hipMemcpyDeviceToHost));
     if (nbr && cap >= gn)
         HIP_TRY(hipMemcpy(nbr, ctx->d.wave_log_nbr, 16 * gn, hipMemcpyDeviceToHost));
+    return PBH_OK;
+}
+
+pbh_status pbh_walk_clock(pbh_ctx* ctx, double* mhz) {
+    if (!ctx || !mhz) return PBH_E_ARG;
+    const int64_t gw = ctx->last_walk_grid;
+    if (gw <= 0 || !ctx->d.wave_log) return fail(ctx, PBH_E_STATE, "no walk yet");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipStreamSynchronize(ctx->last));
+    std::vector<uint64_t> lg(2 * gw), cy(gw);
+    HIP_TRY(hipMemcpy(lg.data(), ctx->d.wave_log, 16 * gw, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(cy.data(), ctx->d.wave_cyc, 8 * gw, hipMemcpyDeviceToHost));
+    int wall_khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, ctx->device));
+    double ticks = 0.0, cycles = 0.0;
+    for (int64_t b = 0; b < gw; ++b) {
+        ticks += (double)lg[2 * b + 1];
+        cycles += (double)cy[b];
+    }
+    if (wall_khz <= 0 || ticks <= 0.0) return fail(ctx, PBH_E_STATE, "no clock record");
+    *mhz = cycles / (ticks / (1e3 * wall_khz)) / 1e6;
     return PBH_OK;
 }
 

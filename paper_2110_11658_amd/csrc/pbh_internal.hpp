@@ -201,6 +201,7 @@ struct Dev {
     // per persistent workgroup of the last walk / neighbour count: groups, clock ticks
     unsigned long long* wave_log = nullptr;
     unsigned long long* wave_log_nbr = nullptr;
+    unsigned long long* wave_cyc = nullptr;   // walk: core clock cycles per workgroup
 };
 
 // ---- launchers (all enqueue on `s`, none waits) ----

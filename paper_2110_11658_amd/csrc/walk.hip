@@ -91,7 +91,8 @@ struct WalkParams {
     int stack_cap;
     unsigned long long* cnt;
     unsigned long long* queues;     // [kQueues] group queue heads
-    unsigned long long* wave_log;   // per workgroup: groups walked, clock ticks
+    unsigned long long* wave_log;   // per workgroup: groups walked, steady-clock ticks
+    unsigned long long* wave_cyc;   // per workgroup: core clock cycles over the same span
     int32_t* nbr_cnt;               // neighbour counts per caller index, or null
     int32_t* stage;                 // neighbour staging rows per sorted particle, or null
     int scap;                       // entries per staging row
@@ -499,6 +500,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     const R eps2 = (R)p.eps2;
     const int64_t G = (int64_t)*p.G;
     const unsigned long long t_start = wall_clock64();
+    const unsigned long long c_start = clock64();
     int n_walked = 0;
 
     for (;;) {
@@ -851,8 +853,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         atomicAdd(&p.cnt[kCntSlotNear], (unsigned long long)it_near * w0);
     }
     if (p.wave_log) {
+        const unsigned long long c_end = clock64();
         p.wave_log[2 * blockIdx.x] = (unsigned long long)n_walked;
         p.wave_log[2 * blockIdx.x + 1] = wall_clock64() - t_start;
+        p.wave_cyc[blockIdx.x] = c_end - c_start;
     }
 }
 
@@ -924,6 +928,7 @@ void launch_walk(Dev& d, const BuildCfg& c, const WalkCfg& w, double* acc, doubl
     p.cnt = d.cnt;
     p.queues = d.queues;
     p.wave_log = d.wave_log;
+    p.wave_cyc = d.wave_cyc;
     p.nbr_cnt = w.count_nbr ? d.nbr_cnt : nullptr;
     p.stage = (w.count_nbr && w.stage_cap > 0) ? d.nbr_stage : nullptr;
     p.scap = w.stage_cap;

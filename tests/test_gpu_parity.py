@@ -477,3 +477,20 @@ def test_autotune_choices_valid_and_cached(tmp_path, monkeypatch):
         p.set_params(leaf_size=t["leaf_size"], n_crit=t["n_crit"], walk_tile=t["walk_tile"])
         acc, pot, off, idx = _run(p, c, 0.01, 0.1, 0.5, 1e-5)
         _sets_equal(off, idx, o_off, o_idx)
+
+
+def test_walk_clock():
+    # pbh_walk_clock: PBH_E_STATE before any walk; afterwards the engine clock
+    # of the last walk from its workgroups' cycle and tick counts, within the
+    # range an MI355X engine clock can take (its peak is 2400 MHz).
+    import ctypes as C
+    from paper_2110_11658_amd._lib import PBH_E_STATE
+    c = ic.plummer(20000, seed=5)
+    p = _pbh(leaf_size=8, n_crit=64)
+    v = C.c_double(0.0)
+    assert p.L.pbh_walk_clock(p.ctx, C.byref(v)) == PBH_E_STATE
+    print("walk clock n=20000", flush=True)
+    _run(p, c, 0.004, 0.04, 0.5, 1e-4)
+    mhz = p.walk_clock_mhz()
+    print("walk clock MHz", mhz, flush=True)
+    assert 300.0 < mhz < 2600.0, mhz
