@@ -891,7 +891,7 @@ void launch_groups(Dev& d, const BuildCfg& c, hipStream_t s) {
                        (const int32_t*)d.g_flag, (const int32_t*)d.g_len, (const uint64_t*)d.keys,
                        (const int64_t*)d.cl_off, n, c.D, (const int32_t*)d.p_nn,
                        (const int32_t*)d.pre2bfs, d.g, d.cnt);
-    hipLaunchKernelGGL(k_group_box, dim3(grid_for(n, 64, 8192)), dim3(64), 0, s,
+    hipLaunchKernelGGL(k_group_box, dim3(grid_for(n, 64, 32768)), dim3(64), 0, s,
                        (const unsigned long long*)(d.cnt + kCntGroups), (const double*)d.x,
                        (const double*)d.y, (const double*)d.z, d.g);
 }
