@@ -37,6 +37,7 @@ sample of particles.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -97,7 +98,6 @@ def clock_mhz(torch):
 def walk_traffic(kernel: str):
     """HBM bytes per walk launch from the committed rocprofv3 counter summary,
     or None when the walk source has changed since the counters were taken."""
-    import hashlib
     import re
     src = os.path.join(ROOT, "paper_2110_11658_amd", "csrc", "walk.hip")
     prof = os.path.join(ROOT, "profiles", "k_walk_plummer1m_hbm_traffic.md")
@@ -177,6 +177,12 @@ def _setup(args, torch):
                "desc": f"Plummer N={cl.n} Kroupa eps={w['eps']} r_out={w['r_out']:.5f} "
                        f"r_in={w['r_in']:.6f}"}
     inp["n"] = inp["mass"].size
+    # SHA-256 of the generated positions and masses (FP64, C order): the inputs
+    # of a record can be regenerated from the seed and checked against it
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(inp["pos"], dtype=np.float64).tobytes())
+    h.update(np.ascontiguousarray(inp["mass"], dtype=np.float64).tobytes())
+    inp["sha256"] = h.hexdigest()
     inp["pos_d"] = torch.from_numpy(inp["pos"]).to(dev)
     inp["mass_d"] = torch.from_numpy(inp["mass"]).to(dev)
     return inp, dev
@@ -307,7 +313,9 @@ def bench_force(args):
                    "n_crit": prm["n_crit"], "walk_tile": prm["walk_tile"] or 64,
                    "neighbours": neighbours, "autotuned": tuned is not None,
                    "clusters": 64 if batched else 1},
+        "inputs_sha256": inp["sha256"],
         "force_evals_per_s": n / (ms_step * 1e-3),
+        "force_evals_per_s_build_walk": n / ((float(np.mean(build_ms)) + walk_avg) * 1e-3),
         "force_evals_per_s_walk_only": n / (walk_avg * 1e-3),
         "interactions_per_s_walk_only": per_step_inter / (walk_avg * 1e-3),
         "phase_ms": {"build": float(np.mean(build_ms)), "walk": walk_avg,
