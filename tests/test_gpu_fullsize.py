@@ -15,7 +15,9 @@ theta = 0.5), through the C ABI.
 * the 4M kick-drift-kick run over 32 steps against the oracle's leapfrog
   (tests/golden/kdk4m_oracle.json, written by make_kdk4m_oracle.py from the
   oracle alone): the FP64 path reproduces its energies and sampled final
-  states, and the mixed path's relative energy drift follows the oracle's.
+  states, and the mixed path's relative energy drift follows the oracle's;
+* 9 * 2^20 particles: the neighbour CSR where the count scan takes its
+  three-launch form (offsets, symmetry, sampled sets against brute force).
 """
 import json
 import os
@@ -206,3 +208,37 @@ def test_kdk4m_32_steps_against_oracle_leapfrog():
     # (measured on MI355X: 7e-9 against a peak of 1.2e-6); its own energy error
     # (potential errors of ~1e-5 per particle) largely cancels in the drift
     assert np.max(np.abs(d_mix - d_orc)) <= 0.1 * np.max(np.abs(d_orc))
+
+
+def test_neighbour_scan_beyond_fused_tiles():
+    # 9 * 2^20 particles: the scan of the neighbour counts then has more
+    # tiles (2048 counts each) than its two-launch form takes (4096), so it
+    # runs with a separate pass over the tile sums. The CSR must be the
+    # exclusive scan of the counts: offsets non-decreasing, the total equal to
+    # the list length, the neighbour relation symmetric (a shifted offset
+    # would hand entries to the wrong particle), and sampled sets equal to
+    # brute force (uniform cube, about 4 neighbours each).
+    n = 9 * 2 ** 20
+    rng = np.random.default_rng(77)
+    pos = rng.uniform(-1.0, 1.0, size=(n, 3))
+    mass = np.full(n, 1.0 / n)
+    r_out = (3.0 * 8.0 * 4.0 / (4.0 * np.pi * n)) ** (1.0 / 3.0)
+    print(f"scan n={n} r_out={r_out:.6f}", flush=True)
+    p = _pbh(leaf_size=8, n_crit=64)
+    p.build(_t(pos), _t(mass))
+    _, _, off, idx = p.force(0.1 * r_out, r_out, 0.5, 1e-4)
+    torch.cuda.synchronize()
+    off = off.cpu().numpy()
+    idx = idx.cpu().numpy()
+    assert off[0] == 0 and np.all(np.diff(off) >= 0)
+    assert off[-1] == idx.size and 3.5 * n < idx.size < 4.5 * n
+    i = np.repeat(np.arange(n, dtype=np.int64), np.diff(off))
+    j = idx.astype(np.int64)
+    assert np.all(i != j)
+    assert np.array_equal(np.sort(i * n + j), np.sort(j * n + i))
+    for s in rng.choice(n, size=48, replace=False):
+        d = pos - pos[s]
+        r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        want = np.flatnonzero(r2 < r_out * r_out)
+        want = want[want != s]
+        assert np.array_equal(np.sort(idx[off[s]:off[s + 1]]), want), s
