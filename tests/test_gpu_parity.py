@@ -422,6 +422,33 @@ def test_batched_equals_per_cluster():
         assert np.array_equal(idx[off[s.start]:off[s.stop]], ix + b0)
 
 
+def test_batched_many_clusters_equals_per_cluster():
+    # 300 clusters: the group size limit then comes from one histogram copy per
+    # cluster (fewer clusters spread each over several copies); each cluster's
+    # groups, forces and lists must still equal those of a build of its own
+    # (9 cluster bits leave 18 key bits per axis, used by both builds)
+    e = ic.ensemble(n_clusters=300, seed0=7100, nmin=60, nmax=600, nbar=8)
+    theta, eps = 0.5, 1e-5
+    from paper_2110_11658_amd.api import Pbh
+    pb = Pbh(0, key_bits=18, n_crit=64)
+    pb.build_batched(e.offsets, _t(e.pos), _t(e.mass))
+    acc, pot, off, idx = pb.force_batched(e.r_in, e.r_out, theta, eps)
+    torch.cuda.synchronize()
+    acc, pot, off, idx = (t.cpu().numpy() for t in (acc, pot, off, idx))
+    assert pb.stats()["n_clusters"] == 300
+    ps = Pbh(0, key_bits=18, n_crit=64)
+    print("batched 300 clusters", flush=True)
+    for k in range(300):
+        s = slice(e.offsets[k], e.offsets[k + 1])
+        ps.build(_t(e.pos[s]), _t(e.mass[s]))
+        a, ph, o, ix = ps.force(e.r_in[k], e.r_out[k], theta, eps)
+        assert np.array_equal(acc[s], a.cpu().numpy()), k
+        assert np.array_equal(pot[s], ph.cpu().numpy()), k
+        o = o.cpu().numpy()
+        assert np.array_equal(off[s.start:s.stop + 1] - off[s.start], o), k
+        assert np.array_equal(idx[off[s.start]:off[s.stop]], ix.cpu().numpy() + e.offsets[k]), k
+
+
 # ---------------------------------------------------------------- leapfrog
 def test_kdk_graph_equals_eager_and_oracle():
     c = ic.plummer(4096, seed=15, masses="kroupa")
