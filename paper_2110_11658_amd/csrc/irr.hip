@@ -71,6 +71,127 @@ __device__ inline void store_sums(const IrrParams& p, int64_t slot, const IrrSum
     if (POT) p.pot[slot] = S.ph;
 }
 
+// Key-order route, records loaded cooperatively. A lane's pair needs one
+// 64-byte record (32 bytes without the jerk); loaded by its own lane as
+// 16-byte pieces, the 64 scattered lanes of each load cost the vector L1 64
+// separate accesses. Here CH = 4 (or 2) neighbouring lanes load the CH pieces
+// of one record together, one contiguous access per record, and the pieces
+// reach the lane that owns the pair through a 64-record slot of LDS per wave.
+// Each lane still sums its own entries in list order, so the sums equal those
+// of the per-lane route bit for bit. Every lane of the wave runs the loop until
+// no lane has entries left (the loads serve other lanes' pairs); lanes without
+// a target or past their list take part with no record of their own.
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));   // one 16-byte piece
+
+// Entries per lane and round on the key-order route: 2 with the jerk (120
+// registers, 4 waves per SIMD; 3 entries need 136 and drop to 3 waves), 6 for
+// the force alone (94 registers, 5 waves). Measured at 2^20 against 1 to 3
+// and 2 to 6.
+template <bool JERK>
+constexpr int coop_lane_batch() { return JERK ? 2 : 6; }
+
+template <bool JERK>
+struct CoopPieces {
+    static constexpr int B = coop_lane_batch<JERK>();
+    static constexpr int CH = JERK ? 4 : 2;   // 16-byte pieces per record
+    static constexpr int RPI = 64 / CH;       // records per load instruction
+    u32x4 piece[B][CH];
+};
+
+// Issues every record load of one round: for each entry u, the pieces
+// lane % CH of the records of lanes RPI k + lane / CH (k < CH). rk holds the
+// key rank of each lane's record, or 0 where the lane has no pair: those
+// slots all load record 0, one shared line per instruction, and are ignored.
+template <bool JERK>
+__device__ inline void coop_load(const IrrRec* __restrict__ rec, const int32_t* rk, int lane,
+                                 CoopPieces<JERK>& P) {
+    using C = CoopPieces<JERK>;
+    const int c = lane % C::CH;
+    int rt[C::B][C::CH];
+#pragma unroll
+    for (int u = 0; u < C::B; ++u)
+#pragma unroll
+        for (int k = 0; k < C::CH; ++k)
+            rt[u][k] = __builtin_amdgcn_ds_bpermute((C::RPI * k + lane / C::CH) << 2, rk[u]);
+#pragma unroll
+    for (int u = 0; u < C::B; ++u)
+#pragma unroll
+        for (int k = 0; k < C::CH; ++k)
+            P.piece[u][k] = reinterpret_cast<const u32x4*>(rec + rt[u][k])[c];
+}
+
+// Entry u's record of this lane, passed through the wave's LDS slot.
+template <bool JERK>
+__device__ inline PartJ coop_take(const CoopPieces<JERK>& P, int u, IrrRec* xch, int lane) {
+    using C = CoopPieces<JERK>;
+    const int c = lane % C::CH;
+#pragma unroll
+    for (int k = 0; k < C::CH; ++k)
+        reinterpret_cast<u32x4*>(xch + C::RPI * k + lane / C::CH)[c] = P.piece[u][k];
+    __builtin_amdgcn_wave_barrier();
+    const PartJ q = load_rec<JERK>(xch, lane);   // a lane without a pair reads a slot it ignores
+    __builtin_amdgcn_wave_barrier();             // the slot is rewritten for the next entry
+    return q;
+}
+
+template <bool JERK, bool POT, bool MULTI>
+__device__ inline bool irr_sums_coop(const IrrParams& p, int64_t i, bool have, int g, IrrSums& S,
+                                     unsigned long long& bad, IrrRec* xch) {
+    const int lane = (int)(threadIdx.x & 63);
+    const ClusterParams* cp = &p.cp0;
+    int64_t b = 0, e = 0;
+    const bool valid = have && target_setup(p, i, cp, b, e, bad);
+    if (g != 0) bad = 0;   // target and offset flags once per group
+    const IrrK K = irr_constants(MULTI ? *cp : p.cp0);
+    PartJ me = {};
+    if (valid) me = load_rec<JERK>(p.rec, p.rank[i]);
+    constexpr int B = coop_lane_batch<JERK>();
+    constexpr int64_t STEP = (int64_t)kIrrLanes * B;
+    int64_t m = b + g;
+    if (!valid) m = e = 0;
+    // While any lane of the wave has entries left, some list holds an entry
+    // (so idx[0] exists) and some target is valid (so rank[0] and rec[0] do):
+    // a lane without an entry loads those, and its loads stay in bounds. A
+    // lane with entries clamps to its own last one, e - 1 in [b, cap).
+    const int64_t last = m < e ? e - 1 : 0;
+    while (__builtin_amdgcn_ballot_w64(m < e) != 0) {
+        int32_t jv[B], rk[B];
+        bool ok[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int64_t q = m + (int64_t)kIrrLanes * u;
+            jv[u] = p.idx[q < e ? q : last];
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const bool live = m + (int64_t)kIrrLanes * u < e;
+            const bool inr = (uint64_t)(int64_t)jv[u] < (uint64_t)p.n;
+            if (live && !inr) bad |= kIrrBadIndex;
+            ok[u] = live && inr && jv[u] != i;
+            rk[u] = p.rank[ok[u] ? jv[u] : 0];
+            if (!ok[u]) rk[u] = 0;
+        }
+        CoopPieces<JERK> P;
+        coop_load<JERK>(p.rec, rk, lane, P);
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const PartJ q = coop_take<JERK>(P, u, xch, lane);
+            if (ok[u]) pair_irr<JERK, POT>(K, p.eps2, me, q, S);
+        }
+        m += STEP;
+    }
+    S.ax = group_sum(S.ax);
+    S.ay = group_sum(S.ay);
+    S.az = group_sum(S.az);
+    if (JERK) {
+        S.jx = group_sum(S.jx);
+        S.jy = group_sum(S.jy);
+        S.jz = group_sum(S.jz);
+    }
+    if (POT) S.ph = group_sum(S.ph);
+    return valid;
+}
+
 // Blocks (of 256 / kIrrLanes = 32 key-order targets) per XCD chunk: 1024 targets.
 constexpr unsigned kIrrChunk = 32;
 
@@ -90,10 +211,19 @@ template <bool JERK, bool POT, bool SORTED, bool MULTI>
 __global__ __launch_bounds__(256) void k_irregular(IrrParams p) {
     const int g = threadIdx.x % kIrrLanes;   // lane groups never straddle a workgroup
     if (SORTED) {
-        // key-order targets in chunks per XCD (cache locality and load balance)
+        // key-order targets in chunks per XCD (cache locality and load balance);
+        // every lane takes part in the cooperative loads, with a target or not
+        __shared__ IrrRec xch[256 / 64][64];
         const unsigned blk = xcd_chunk_block(blockIdx.x, kIrrChunk);
         const int64_t k = ((int64_t)blk * blockDim.x + threadIdx.x) / kIrrLanes;
-        if (k < p.n_tgt) irr_target<JERK, POT, SORTED, MULTI>(p, k, g);   // group-uniform
+        const bool have = k < p.n_tgt;   // group-uniform
+        unsigned long long bad = 0;
+        const int64_t kk = have ? k : 0;
+        const int64_t i = p.tgt ? (int64_t)p.tgt[kk] : (p.order ? (int64_t)p.order[kk] : kk);
+        IrrSums S;
+        const bool valid = irr_sums_coop<JERK, POT, MULTI>(p, i, have, g, S, bad, xch[threadIdx.x / 64]);
+        if (have && g == 0 && (valid || p.tgt)) store_sums<JERK, POT>(p, p.tgt ? k : i, S);
+        if (bad) atomicOr(p.err, bad);
         return;
     }
     // caller-array route: grid-stride

@@ -207,9 +207,9 @@ __device__ inline bool irr_sums(const IrrParams& p, int64_t i, IrrSums& S, unsig
 // are then contiguous runs, and its record loads fall on the neighbours of a
 // few targets, close together in key order.
 constexpr int kIrrLanes = 8;
-// entries per lane and round: 4 for the force alone; 3 with the jerk, whose
-// records and terms would otherwise hold the kernel to 3 waves per SIMD (at
-// 2^20 the force + jerk + potential call is 5 % faster with 3)
+// entries per lane and round on the caller-array route: 4 for the force
+// alone; 3 with the jerk, whose records and terms would otherwise hold the
+// kernel to 3 waves per SIMD
 template <bool JERK>
 constexpr int irr_lane_batch() { return JERK ? 3 : 4; }
 
