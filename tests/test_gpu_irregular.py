@@ -207,6 +207,19 @@ def _malformed_cases(p, n, pos, vel, mass, off, good):
     with pytest.raises(PbhError) as e:
         p.irregular(pos, vel, mass, 0.01, 10.0, 1e-3, _t(bad_off), _t(good))
     assert "offsets" in str(e.value)
+    # a range entirely beyond the capacity, and one that ends before it starts:
+    # flagged, and no entry of either list is read
+    wild = off.copy()
+    wild[n - 3] = n + 200
+    wild[n - 2] = n + 210
+    with pytest.raises(PbhError) as e:
+        p.irregular(pos, vel, mass, 0.01, 10.0, 1e-3, _t(wild), _t(good))
+    assert "offsets" in str(e.value)
+    a, _, _ = p.irregular(pos, vel, mass, 0.01, 10.0, 1e-3, _t(wild), _t(good), validate=False)
+    ref = p.irregular(pos, vel, mass, 0.01, 10.0, 1e-3, _t(off), _t(good))
+    rows = np.arange(n) < n - 4
+    assert np.array_equal(_np(a)[rows], _np(ref[0])[rows])
+    assert np.all(_np(a)[n - 4:n - 1] == 0)
     with pytest.raises(PbhError) as e:
         p.irregular(pos, vel, mass, 0.01, 10.0, 1e-3, _t(off), _t(good),
                     targets=_t(np.array([3, -1], np.int32)))
