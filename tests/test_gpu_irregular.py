@@ -140,6 +140,16 @@ def test_irregular_targets_and_order_do_not_change_results():
     # optional outputs off
     a, j, ph = p.irregular(pos, None, mass, r_in, r_out, eps, off, idx, jerk=False, pot=False)
     assert j is None and ph is None and np.array_equal(_np(a), full[0])
+    # every combination of outputs: key-order records and caller arrays agree bit
+    # for bit, and with the full call
+    for want_j, want_p in ((True, False), (False, True), (False, False)):
+        v = vel if want_j else None
+        ka = p.irregular(pos, v, mass, r_in, r_out, eps, off, idx, jerk=want_j, pot=want_p)
+        ca = q.irregular(pos, v, mass, r_in, r_out, eps, off, idx, jerk=want_j, pot=want_p)
+        for k, (x, y) in enumerate(zip(ka, ca)):
+            assert (x is None) == (y is None)
+            if x is not None:
+                assert np.array_equal(_np(x), _np(y)) and np.array_equal(_np(x), full[k])
 
 
 def test_irregular_batched_per_cluster():
