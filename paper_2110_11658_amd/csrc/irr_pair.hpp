@@ -32,10 +32,12 @@ __device__ inline IrrK irr_constants(const ClusterParams& c) {
 // [1/sqrt 2, sqrt 2), ln s = e ln 2 + 2 atanh(t) for t = (m - 1)/(m + 1),
 // |t| <= 0.1716, and atanh t = t + t^3/3 + t^5/5 + ... (the terms through t^19
 // leave a remainder below 2.3e-17 t). m - 1 is exact; 1/(m + 1) is the
-// hardware reciprocal refined by one Newton step; ln 2 is split into a 32-bit
-// head (e ln2_hi is exact) and the rest (Cody and Waite). Within 2 ulp of ln s
-// over 2.7e5 test values in [1e-13, 150], against the 85 instructions of the
-// library's correctly rounded form about 30.
+// hardware reciprocal, good to about single precision, refined by two Newton
+// steps (one leaves errors up to 21 ulp in ln s); ln 2 is split into a 32-bit
+// head (e ln2_hi is exact) and the rest (Cody and Waite). On the device within
+// 2.4 ulp of ln s (mean 0.34 ulp) over 2^20 values in [1e-13, 400] against a
+// long-double reference; about 32 instructions against the 85 of the library's
+// correctly rounded form.
 __device__ inline double log_pos(double s) {
     double m = __builtin_amdgcn_frexp_mant(s);   // [1/2, 1)
     int e = __builtin_amdgcn_frexp_exp(s);
@@ -45,6 +47,7 @@ __device__ inline double log_pos(double s) {
     }
     const double num = m - 1.0, den = m + 1.0;
     double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
     r = fma(r, fma(-den, r, 1.0), r);
     const double t = num * r, t2 = t * t;
     double q = 1.0 / 19.0;
