@@ -84,6 +84,7 @@ struct pbh_ctx {
 
     // build state
     bool built = false;
+    bool irr_rank_ok = false;   // d.irr_rank holds the inverse of the current build's permutation
     bool batched = false;
     const double* built_pos = nullptr;    // the caller's arrays of the last build
     const double* built_mass = nullptr;
@@ -381,6 +382,7 @@ void enqueue_build(pbh_ctx* ctx, const double* pos, const double* mass, hipStrea
 // into a graph once per set of buffers, sizes and parameters (the block tables
 // it reads are uploaded before each launch) and replayed.
 pbh_status launch_build(pbh_ctx* ctx, const double* pos, const double* mass, hipStream_t s) {
+    ctx->irr_rank_ok = false;   // a new permutation
     const BuildCfg& c = ctx->cfg;
     const std::vector<double> key = {(double)(uintptr_t)pos, (double)(uintptr_t)mass, (double)c.n,
                                      (double)c.n_clusters, (double)c.D, (double)c.cbits,
@@ -655,6 +657,7 @@ pbh_status do_irregular(pbh_ctx* ctx, IrrParams& p, int64_t n, const double* pos
             p.rec = fixed->rec;
         } else {
             if (d.irr_len < n) {
+                ctx->irr_rank_ok = false;
                 if (!dalloc(ctx, &d.irr_rank, n) || !dalloc(ctx, &d.irr_rec, n)) {
                     (void)hipGetLastError();
                     return fail(ctx, PBH_E_OOM, "irregular-force records");
@@ -663,6 +666,7 @@ pbh_status do_irregular(pbh_ctx* ctx, IrrParams& p, int64_t n, const double* pos
             }
             p.rank = d.irr_rank;
             p.rec = d.irr_rec;
+            p.rank_fresh = !ctx->irr_rank_ok;
         }
         p.perm = d.perm;
         p.order = targets ? nullptr : d.perm;
@@ -680,6 +684,7 @@ pbh_status do_irregular(pbh_ctx* ctx, IrrParams& p, int64_t n, const double* pos
     p.err = err;
     launch_irregular(p, s);
     HIP_TRY(hipGetLastError());
+    if (p.rec && !fixed) ctx->irr_rank_ok = true;
     if (check) {
         unsigned long long bits = 0;
         HIP_TRY(hipMemcpyAsync(&bits, err, sizeof(bits), hipMemcpyDeviceToHost, s));
@@ -1172,6 +1177,7 @@ pbh_status pbh_core(pbh_ctx* ctx, const double* pos, const double* mass, int64_t
     ctx->last = s;
     Dev& d = ctx->d;
     if (d.irr_len < n) {   // the rank array is shared with the irregular-force records
+        ctx->irr_rank_ok = false;
         if (!dalloc(ctx, &d.irr_rank, n) || !dalloc(ctx, &d.irr_rec, n)) {
             (void)hipGetLastError();
             return fail(ctx, PBH_E_OOM, "rank array");
@@ -1412,6 +1418,7 @@ static pbh_status kdk_impl(pbh_ctx* ctx, int64_t n, double* pos, double* vel, co
         return fail(ctx, PBH_E_ARG, "bad kdk arguments");
     HIP_TRY(hipSetDevice(ctx->device));
     ctx->last = s;
+    ctx->irr_rank_ok = false;   // every step rebuilds the tree
     pbh_status st = kdk_prepare(ctx, n, r_in, r_out, theta, eps, s);
     if (st != PBH_OK) return st;
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, ctx->d.cnt + kCntKdkStep, 0ull);

@@ -36,16 +36,21 @@ namespace pbh {
 
 namespace {
 
-// rank[perm[k]] = k and rec[k] = particle perm[k] (velocity only if given)
-__global__ __launch_bounds__(256) void k_irr_pack(int64_t n, const int32_t* __restrict__ perm,
+// rank[perm[k]] = k: the key position of each caller index (once per build)
+__global__ __launch_bounds__(256) void k_irr_rank(int64_t n, const int32_t* __restrict__ perm,
+                                                  int32_t* __restrict__ rank) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) rank[perm[k]] = (int32_t)k;
+}
+
+// rec[rank[i]] = particle i (velocity only if given): the caller's arrays are
+// read in order and each record is stored whole (64 bytes, aligned)
+__global__ __launch_bounds__(256) void k_irr_pack(int64_t n, const int32_t* __restrict__ rank,
                                                   const double* __restrict__ pos,
                                                   const double* __restrict__ vel,
-                                                  const double* __restrict__ mass,
-                                                  int32_t* __restrict__ rank, IrrRec* __restrict__ rec) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const int64_t i = perm[k];
-    rank[i] = (int32_t)k;
+                                                  const double* __restrict__ mass, IrrRec* __restrict__ rec) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
     IrrRec r;
     r.x = pos[3 * i];
     r.y = pos[3 * i + 1];
@@ -55,7 +60,7 @@ __global__ __launch_bounds__(256) void k_irr_pack(int64_t n, const int32_t* __re
     r.vy = vel ? vel[3 * i + 1] : 0.0;
     r.vz = vel ? vel[3 * i + 2] : 0.0;
     r.pad = 0.0;
-    rec[k] = r;
+    rec[rank[i]] = r;
 }
 
 template <bool JERK, bool POT>
@@ -260,9 +265,12 @@ void launch_multi(const IrrParams& p, hipStream_t s) {
 
 void launch_irregular(const IrrParams& p, hipStream_t s) {
     if (p.n_tgt <= 0) return;
-    if (p.rec)
-        hipLaunchKernelGGL(k_irr_pack, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, s, p.n, p.perm,
-                           p.pos, p.jerk ? p.vel : nullptr, p.mass, p.rank, p.rec);
+    if (p.rec) {
+        const dim3 grid((unsigned)((p.n + 255) / 256));
+        if (p.rank_fresh) hipLaunchKernelGGL(k_irr_rank, grid, dim3(256), 0, s, p.n, p.perm, p.rank);
+        hipLaunchKernelGGL(k_irr_pack, grid, dim3(256), 0, s, p.n, (const int32_t*)p.rank, p.pos,
+                           p.jerk ? p.vel : nullptr, p.mass, p.rec);
+    }
     const bool jerk = p.jerk != nullptr, pot = p.pot != nullptr;
     if (jerk && pot) launch_multi<true, true>(p, s);
     else if (jerk) launch_multi<true, false>(p, s);

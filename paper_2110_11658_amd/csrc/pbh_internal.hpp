@@ -271,11 +271,12 @@ struct IrrParams {
     const int32_t* tgt = nullptr;    // target caller indices (outputs compact), or null = all
     const int32_t* order = nullptr;  // processing order of all targets (key order), or null
     // key-order records: perm [n] (key position -> caller index), rank [n]
-    // (caller index -> key position) and rec [n], the last two written by the
-    // pre-pass; null rec: gather from pos/vel/mass directly
+    // (caller index -> key position, the inverse of perm) and rec [n], written
+    // by the pre-passes; null rec: gather from pos/vel/mass directly
     const int32_t* perm = nullptr;
     int32_t* rank = nullptr;
     IrrRec* rec = nullptr;
+    bool rank_fresh = true;          // recompute rank from perm (false: it already holds the inverse)
     const double* pos = nullptr;     // [n][3]
     const double* vel = nullptr;     // [n][3] (jerk only)
     const double* mass = nullptr;    // [n]

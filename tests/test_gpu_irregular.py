@@ -152,6 +152,34 @@ def test_irregular_targets_and_order_do_not_change_results():
                 assert np.array_equal(_np(x), _np(y)) and np.array_equal(_np(x), full[k])
 
 
+def test_irregular_key_ranks_follow_every_rebuild():
+    # the key rank of each particle is kept from one call to the next of the
+    # same build and found again after every rebuild (a new build, or the
+    # leapfrog's rebuilds): each call equals a context without a build, whose
+    # calls gather from the caller's arrays, bit for bit
+    n = 3000
+    r_out = ic.r_out_for_nbar(n, 30.0)
+    r_in, eps = 0.1 * r_out, 1e-4
+    p, q = _pbh(), _pbh()
+
+    def same(pos, vel, mass, off, idx):
+        a = [_np(g) for g in p.irregular(pos, vel, mass, r_in, r_out, eps, off, idx)]
+        b = [_np(g) for g in q.irregular(pos, vel, mass, r_in, r_out, eps, off, idx)]
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+    for seed in (41, 42, 41):
+        c = ic.plummer(n, seed=seed)
+        off, idx = _lists(p, c.pos, c.mass, r_in, r_out, eps)
+        pos, vel, mass = _t(c.pos), _t(c.vel), _t(c.mass)
+        same(pos, vel, mass, off, idx)
+        same(pos, vel, mass, off, idx)
+    # the leapfrog ends with a tree of its final positions
+    pos, vel = _t(c.pos), _t(c.vel)
+    p.kdk(pos, vel, mass, 1e-3, 2, r_in, r_out, 0.5, eps)
+    same(pos, vel, mass, off, idx)
+
+
 def test_irregular_batched_per_cluster():
     ens = ic.ensemble(n_clusters=6, seed0=4100, nmin=500, nmax=4000)
     eps = 1e-4
