@@ -291,7 +291,8 @@ pbh_status pbh_irregular_batched(pbh_ctx* ctx, const double* pos, const double* 
  *     key-order route the ranks and 64-byte records of the n particles,
  *     68 MiB at the maximum n) is one static device array per GPU that the
  *     library holds from the first pbh_create on that GPU until the process
- *     ends. The flag word is cleared by a kernel at the start of every call.
+ *     ends. The flag word is cleared by a kernel at the start of every call,
+ *     and the ranks are computed afresh by every call.
  *   - Every call on one GPU shares that array, from any context: calls that
  *     overlap in time on one GPU (other streams, other threads, other
  *     contexts) race and give undefined results. Order them on one stream.
