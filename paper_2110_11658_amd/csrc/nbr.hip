@@ -175,13 +175,13 @@ __global__ __launch_bounds__(64) void k_nbr_fill(NbrParams p) {
 // Staged lists into the CSR. One wave per block of 64 consecutive sorted
 // particles (the interleaving unit of the staging rows); stage_k[p] = 1 if
 // the walk staged the list of p (0: the fill pass writes it). The block's
-// lists pass through an LDS tile of 32 entries per particle: entry t of all
-// 64 particles is one 256-byte load, and each store instruction writes 32
-// consecutive CSR entries of two particles (lists in caller order lie
+// lists pass through an LDS tile of 64 entries per particle: entry t of all
+// 64 particles is one 256-byte load, and each store instruction writes 64
+// consecutive CSR entries of one particle (lists in caller order lie
 // scattered over the CSR; one lane per list would write 64 unrelated lines
 // per instruction). Entries beyond the caller's capacity are dropped and
 // flagged.
-constexpr int kCopyTile = 32;
+constexpr int kCopyTile = 64;   // 16 KB of LDS per block; 16, 32, 96 and 128 were slower at 2^20
 
 __global__ __launch_bounds__(64) void k_nbr_copy(int64_t n, const int8_t* __restrict__ stage_k,
                                                  const int32_t* __restrict__ perm,
