@@ -460,6 +460,15 @@ pbh_status pbh_debug_herm_first_steps(pbh_ctx* ctx, int64_t cap, int64_t* ticks,
 pbh_status pbh_debug_valu_probe(pbh_ctx* ctx, int64_t blocks, int32_t iters, float* out,
                                 pbh_stream_t stream);
 
+/*
+ * Debug evaluation of the natural logarithm that the irregular potential uses
+ * for Phi_R (the atanh-series form of the irregular-force kernels, not the
+ * library's): y[k] = ln x[k] for k < n. x: device double [n], each positive
+ * and normal; y: device double [n]. Enqueued on `stream`, nothing allocated.
+ */
+pbh_status pbh_debug_series_log(pbh_ctx* ctx, int64_t n, const double* x, double* y,
+                                pbh_stream_t stream);
+
 const char* pbh_last_error(const pbh_ctx* ctx);
 const char* pbh_status_string(pbh_status s);
 

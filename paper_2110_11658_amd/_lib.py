@@ -32,6 +32,7 @@ EXPORTS = ("pbh_create", "pbh_destroy", "pbh_set_params", "pbh_get_params", "pbh
            "pbh_kdk_eager", "pbh_get_stats", "pbh_walk_clock", "pbh_set_timing", "pbh_debug_tree",
            "pbh_debug_groups",
            "pbh_debug_wave_log", "pbh_debug_valu_probe", "pbh_debug_herm_first_steps",
+           "pbh_debug_series_log",
            "pbh_last_error", "pbh_status_string")
 
 
@@ -104,6 +105,7 @@ def load(path: str = LIB_PATH):
         "pbh_debug_groups": (st, [vp, i64, vp, vp, vp, vp]),
         "pbh_debug_wave_log": (st, [vp, vp, vp, i64, vp, vp]),
         "pbh_debug_valu_probe": (st, [vp, i64, i32, vp, vp]),
+        "pbh_debug_series_log": (st, [vp, i64, vp, vp, vp]),
         "pbh_debug_herm_first_steps": (st, [vp, i64, vp, vp]),
         "pbh_last_error": (C.c_char_p, [vp]),
         "pbh_status_string": (C.c_char_p, [C.c_int]),

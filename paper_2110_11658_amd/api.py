@@ -347,6 +347,15 @@ class Pbh:
         check(self.ctx, self.L.pbh_walk_clock(self.ctx, C.byref(v)))
         return float(v.value)
 
+    def debug_series_log(self, x: torch.Tensor) -> torch.Tensor:
+        """ln x by the logarithm of the irregular potential's Phi_R (device
+        FP64 tensor of positive normal values)."""
+        n = x.shape[0]
+        _need(x, (n,), "x")
+        y = torch.empty_like(x)
+        check(self.ctx, self.L.pbh_debug_series_log(self.ctx, n, _ptr(x), _ptr(y), _stream()))
+        return y
+
     def debug_herm_first_steps(self) -> np.ndarray:
         """First block step (ticks of dt_max / 2^40) of every particle in the
         last Hermite integration, caller order."""

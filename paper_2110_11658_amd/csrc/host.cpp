@@ -1551,6 +1551,17 @@ pbh_status pbh_debug_valu_probe(pbh_ctx* ctx, int64_t blocks, int32_t iters, flo
     return PBH_OK;
 }
 
+pbh_status pbh_debug_series_log(pbh_ctx* ctx, int64_t n, const double* x, double* y,
+                                pbh_stream_t stream) {
+    if (!ctx) return PBH_E_ARG;
+    if (n < 0 || n >= (1ll << 40) || (n > 0 && (!x || !y)))
+        return fail(ctx, PBH_E_ARG, "need 0 <= n < 2^40 and x, y");
+    HIP_TRY(hipSetDevice(ctx->device));
+    launch_series_log(n, x, y, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return PBH_OK;
+}
+
 pbh_status pbh_debug_wave_log(pbh_ctx* ctx, uint64_t* walk, uint64_t* nbr, int64_t cap,
                                          int64_t* n_walk, int64_t* n_nbr) {
     if (!ctx || !ctx->d.wave_log) return PBH_E_ARG;

@@ -261,7 +261,19 @@ void launch_multi(const IrrParams& p, hipStream_t s) {
     else launch_route<JERK, POT, false>(p, s);
 }
 
+// the logarithm of the pair terms over an array (debug export)
+__global__ __launch_bounds__(256) void k_series_log(int64_t n, const double* __restrict__ x,
+                                                    double* __restrict__ y) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) y[k] = log_pos(x[k]);
+}
+
 }  // namespace
+
+void launch_series_log(int64_t n, const double* x, double* y, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_series_log, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, x, y);
+}
 
 void launch_irregular(const IrrParams& p, hipStream_t s) {
     if (p.n_tgt <= 0) return;

@@ -294,6 +294,7 @@ struct IrrParams {
     unsigned long long* err = nullptr;   // kIrr* flag bits (OR)
 };
 void launch_irregular(const IrrParams& p, hipStream_t s);
+void launch_series_log(int64_t n, const double* x, double* y, hipStream_t s);   // debug export
 
 // core.hip: core quantities from the 6 nearest neighbours of a sample
 enum : unsigned long long {

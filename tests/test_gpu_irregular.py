@@ -272,6 +272,23 @@ def _malformed_cases(p, n, pos, vel, mass, off, good):
     assert np.array_equal(_np(a)[rows], _np(ref[0])[rows]) and np.all(_np(a)[10] == 0)
 
 
+def test_series_log_within_a_few_ulp():
+    # the logarithm of Phi_R in the pair terms (atanh series, not the
+    # library's) against numpy's correctly rounded-to-an-ulp log: within 4 ulp
+    # of it (so within 5 of ln x) over six decades and around 1, where the
+    # result is small and the series carries it alone
+    rng = np.random.default_rng(11)
+    x = np.concatenate([np.exp(rng.uniform(-30.0, 6.0, 40000)), 1.0 + rng.uniform(-1e-3, 1e-3, 20000),
+                        rng.uniform(0.5, 2.0, 20000), np.array([1.0, 2.0, 0.5, 1e-300, 1e300])])
+    y = _np(_pbh().debug_series_log(_t(x)))
+    ref = np.log(x)
+    ulp = np.spacing(np.abs(ref))
+    ulp[ref == 0] = np.spacing(0.0)
+    err = np.abs(y - ref) / ulp
+    assert err.max() <= 4.0, f"worst {err.max():.2f} ulp at x = {x[np.argmax(err)]!r}"
+    assert y[-5] == 0.0 and np.isclose(y[-4], np.log(2.0), rtol=0, atol=2e-16)
+
+
 def test_irregular_full_size_sampled():
     # the 2^20-particle Plummer/Kroupa workload with 64 neighbours on average:
     # all particles on the GPU, 384 sampled targets by the oracle's O(S N) sum
