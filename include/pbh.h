@@ -260,7 +260,8 @@ pbh_status pbh_force_batched_buffered(pbh_ctx* ctx, const double* pos, const dou
  *                10 (target)
  * The call needs no build. When the context holds a build of n particles
  * and targets is NULL the particles are processed in its key order (faster;
- * the results are identical).
+ * the results are identical). The first such call after a build also finds
+ * each particle's key position, which the context keeps until the next build.
  */
 pbh_status pbh_irregular(pbh_ctx* ctx, int64_t n, const double* pos, const double* vel,
                          const double* mass, double r_in, double r_out, double eps,
