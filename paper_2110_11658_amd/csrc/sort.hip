@@ -198,7 +198,7 @@ void scan_impl(const T* in, O* out, int64_t n, int64_t* tmp, hipStream_t s) {
 
 // ---------------------------------------------------------------- radix sort
 constexpr int RS_T = 256;
-constexpr int RS_R = 8;             // rounds per tile
+constexpr int RS_R = 16;            // rounds per tile (4096 keys; 4, 8, 12, 20, 24 and 32 built slower at 2^20)
 constexpr int RS_TILE = RS_T * RS_R;
 constexpr int RS_MAX_BINS = 256;    // bins of the widest digit used
 
