@@ -533,7 +533,7 @@ __device__ inline void moments_node(int64_t b, const double* __restrict__ x, con
     q32[b] = f;
 }
 
-__global__ __launch_bounds__(128) void k_moments_level(const int32_t* __restrict__ lvl_off, int level,
+__global__ __launch_bounds__(kMomT) void k_moments_level(const int32_t* __restrict__ lvl_off, int level,
                                 const double* __restrict__ x, const double* __restrict__ y,
                                 const double* __restrict__ z, const double* __restrict__ m,
                                 WNode* __restrict__ node, Mom64* __restrict__ q64,
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(128) void k_moments_level(const int32_t* __restrict
 }
 
 // one workgroup, levels l_hi down to l_lo in order (a barrier between levels)
-__global__ __launch_bounds__(128) void k_moments_levels(const int32_t* __restrict__ lvl_off, int l_hi,
+__global__ __launch_bounds__(kMomT) void k_moments_levels(const int32_t* __restrict__ lvl_off, int l_hi,
                                  int l_lo, const double* __restrict__ x,
                                  const double* __restrict__ y, const double* __restrict__ z,
                                  const double* __restrict__ m, WNode* __restrict__ node,
@@ -853,17 +853,17 @@ void launch_moments(Dev& d, const BuildCfg& c, hipStream_t s) {
     const int hi = c.mom_hi < c.D ? c.mom_hi : c.D;
     const int lo = c.mom_lo;
     if (hi < c.D)
-        hipLaunchKernelGGL(k_moments_levels, dim3(1), dim3(128), 0, s, (const int32_t*)d.lvl_off, c.D,
+        hipLaunchKernelGGL(k_moments_levels, dim3(1), dim3(kMomT), 0, s, (const int32_t*)d.lvl_off, c.D,
                            hi + 1, (const double*)d.x, (const double*)d.y, (const double*)d.z,
                            (const double*)d.m, d.node, d.q64, d.q32);
     for (int l = hi; l > lo; --l) {
-        const int grid = c.mom_grid[l] > 0 ? c.mom_grid[l] : grid_for(c.node_cap, 128, 2048);
-        hipLaunchKernelGGL(k_moments_level, dim3(grid), dim3(128), 0, s,
+        const int grid = c.mom_grid[l] > 0 ? c.mom_grid[l] : grid_for(c.node_cap, kMomT, 2048);
+        hipLaunchKernelGGL(k_moments_level, dim3(grid), dim3(kMomT), 0, s,
                            (const int32_t*)d.lvl_off, l, (const double*)d.x, (const double*)d.y,
                            (const double*)d.z, (const double*)d.m, d.node, d.q64, d.q32);
     }
     if (lo >= 0)
-        hipLaunchKernelGGL(k_moments_levels, dim3(1), dim3(128), 0, s, (const int32_t*)d.lvl_off, lo, 0,
+        hipLaunchKernelGGL(k_moments_levels, dim3(1), dim3(kMomT), 0, s, (const int32_t*)d.lvl_off, lo, 0,
                            (const double*)d.x, (const double*)d.y, (const double*)d.z,
                            (const double*)d.m, d.node, d.q64, d.q32);
 }

@@ -315,7 +315,7 @@ pbh_status setup_build(pbh_ctx* ctx, int64_t n, int32_t C, const int64_t* offset
         c.mom_grid[l] = 0;
         if (l < (int)ctx->lvl_count.size()) {
             // power-of-two bucket of 1.5x the last count (few distinct graphs)
-            const int64_t want = (ctx->lvl_count[l] * 3 / 2 + 127) / 128;
+            const int64_t want = (ctx->lvl_count[l] * 3 / 2 + kMomT - 1) / kMomT;
             int g = 1;
             while (g < want && g < 2048) g <<= 1;
             c.mom_grid[l] = g;

@@ -223,6 +223,9 @@ void radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t
                       int64_t n, int nbits, int64_t* hist, int64_t* scan_tmp, hipStream_t s,
                       bool vals_are_iota, const int32_t* n_dev = nullptr, bool to_alt = false);
 
+// threads per workgroup of the per-level moment kernels (the host sizes their grids)
+constexpr int kMomT = 64;   // 32, 128 and 256 built slower at 2^20
+
 // build.hip
 void launch_bbox(Dev& d, const BuildCfg& c, const double* pos, const double* mass, int nblk,
                  hipStream_t s);

@@ -17,7 +17,7 @@ namespace pbh {
 namespace {
 
 constexpr int SCAN_T = 256;
-constexpr int SCAN_I = 8;
+constexpr int SCAN_I = 4;   // 1024 elements per tile (2, 8 and 16 built slower at 2^20; 2 leaves the fused path at 4M)
 constexpr int SCAN_TILE = SCAN_T * SCAN_I;
 
 __device__ inline int64_t wave_incl_scan64(int64_t v, int lane) {
