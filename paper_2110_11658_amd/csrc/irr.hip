@@ -197,8 +197,9 @@ __device__ inline bool irr_sums_coop(const IrrParams& p, int64_t i, bool have, i
     return valid;
 }
 
-// Blocks (of 256 / kIrrLanes = 32 key-order targets) per XCD chunk: 1024 targets.
-constexpr unsigned kIrrChunk = 32;
+// Blocks (of 256 / kIrrLanes = 32 key-order targets) per XCD chunk: 512 targets
+// (chunks of 4 to 128 blocks measured at 2^20; 8 and 16 were fastest).
+constexpr unsigned kIrrChunk = 16;
 
 // One target k (a lane group, lane g of it): the group's sums over its list,
 // stored at its output slot by lane 0.
