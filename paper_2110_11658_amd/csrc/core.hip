@@ -209,9 +209,17 @@ __global__ void k_core_rank(int64_t n, const int32_t* __restrict__ perm, int32_t
     if (k < n) rank[perm[k]] = (int32_t)k;
 }
 
-// Sums over the sample in one workgroup (fixed order): density centre, then
-// core radius and density. out: [0..2] x_d, [3] rho_core, [4] r_c, ...
-constexpr int kStatT = 1024;
+// Sums over the sample in two levels, each in a fixed order: a workgroup of
+// kStatT threads sums a chunk of kStatCh consecutive samples (thread t takes
+// samples t, t + kStatT, ... of the chunk in that order, loads issued
+// together, then a fixed tree over the threads), and one workgroup sums the
+// chunk totals in chunk order the same way. First the density centre
+// (sum rho, sum rho x), then the core density and radius (sum rho^2,
+// sum rho^2 |x - x_d|^2). out: [0..2] x_d, [3] rho_core, [4] r_c, ...
+// part: [0] the sum of rho; [8 + 4 c ..] the totals of chunk c.
+constexpr int kStatT = 256;
+constexpr int kStatB = 8;
+constexpr int kStatCh = kStatT * kStatB;   // samples per chunk
 
 __device__ inline double block_sum(double v, double* red) {
     const int t = threadIdx.x;
@@ -225,85 +233,118 @@ __device__ inline double block_sum(double v, double* red) {
     return red[0];
 }
 
-// Each thread takes samples t, t + kStatT, ... in order; their loads are
-// issued kStatB at a time (the sums keep that order).
-constexpr int kStatB = 8;
+// the samples of thread t in chunk c: caller index (-1: none or out of range,
+// flagged by the search and never read), density and position
+__device__ inline void chunk_samples(int64_t n, int64_t ns, const int32_t* __restrict__ sample,
+                                     const double* __restrict__ pos, const double* __restrict__ rho,
+                                     int64_t c, int t, int64_t (&iv)[kStatB], double (&rv)[kStatB],
+                                     double (&xv)[kStatB], double (&yv)[kStatB], double (&zv)[kStatB]) {
+#pragma unroll
+    for (int u = 0; u < kStatB; ++u) {
+        const int64_t s = c * kStatCh + t + (int64_t)kStatT * u;
+        iv[u] = s < ns ? (int64_t)sample[s] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kStatB; ++u) {
+        const int64_t s = c * kStatCh + t + (int64_t)kStatT * u;
+        const bool ok = (uint64_t)iv[u] < (uint64_t)n;
+        if (!ok) iv[u] = -1;
+        const int64_t i = ok ? iv[u] : 0;
+        rv[u] = ok ? rho[s] : 0.0;
+        xv[u] = pos[3 * i];
+        yv[u] = pos[3 * i + 1];
+        zv[u] = pos[3 * i + 2];
+    }
+}
 
-__global__ __launch_bounds__(kStatT) void k_core_stats(int64_t n, int64_t ns, const int32_t* __restrict__ sample,
-                                                       const double* __restrict__ pos,
-                                                       const double* __restrict__ rho,
-                                                       double* __restrict__ out) {
+__global__ __launch_bounds__(kStatT) void k_core_sum1(int64_t n, int64_t ns, const int32_t* __restrict__ sample,
+                                                      const double* __restrict__ pos,
+                                                      const double* __restrict__ rho, double* __restrict__ part) {
 #pragma clang fp contract(off)
     __shared__ double red[kStatT];
-    const int t = threadIdx.x;
+    int64_t iv[kStatB];
+    double rv[kStatB], xv[kStatB], yv[kStatB], zv[kStatB];
+    chunk_samples(n, ns, sample, pos, rho, blockIdx.x, threadIdx.x, iv, rv, xv, yv, zv);
     double sr = 0, sx = 0, sy = 0, sz = 0;
-    for (int64_t s0 = t; s0 < ns; s0 += (int64_t)kStatT * kStatB) {
-        int64_t iv[kStatB];
-        double rv[kStatB], xv[kStatB], yv[kStatB], zv[kStatB];
 #pragma unroll
-        for (int u = 0; u < kStatB; ++u) {
-            const int64_t s = s0 + (int64_t)kStatT * u;
-            iv[u] = s < ns ? (int64_t)sample[s] : -1;
-        }
-#pragma unroll
-        for (int u = 0; u < kStatB; ++u) {
-            const bool ok = (uint64_t)iv[u] < (uint64_t)n;   // out of range: flagged by the search; never read
-            const int64_t i = ok ? iv[u] : 0;
-            rv[u] = ok ? rho[s0 + (int64_t)kStatT * u] : 0.0;
-            xv[u] = pos[3 * i];
-            yv[u] = pos[3 * i + 1];
-            zv[u] = pos[3 * i + 2];
-        }
-#pragma unroll
-        for (int u = 0; u < kStatB; ++u) {
-            if ((uint64_t)iv[u] >= (uint64_t)n) continue;
-            sr += rv[u];
-            sx += rv[u] * xv[u];
-            sy += rv[u] * yv[u];
-            sz += rv[u] * zv[u];
-        }
+    for (int u = 0; u < kStatB; ++u) {
+        if (iv[u] < 0) continue;
+        sr += rv[u];
+        sx += rv[u] * xv[u];
+        sy += rv[u] * yv[u];
+        sz += rv[u] * zv[u];
     }
     sr = block_sum(sr, red);
     sx = block_sum(sx, red);
     sy = block_sum(sy, red);
     sz = block_sum(sz, red);
-    const double xd = sx / sr, yd = sy / sr, zd = sz / sr;
+    if (threadIdx.x == 0) {
+        double* q = part + 8 + 4 * (int64_t)blockIdx.x;
+        q[0] = sr; q[1] = sx; q[2] = sy; q[3] = sz;
+    }
+}
+
+// totals of the first k (<= 4) values of every chunk, in chunk order
+template <int K>
+__device__ inline void chunk_totals(int64_t nc, const double* __restrict__ part, double* red, double (&tot)[K]) {
+    double v[K];
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
+    for (int64_t c = threadIdx.x; c < nc; c += kStatT)
+        for (int k = 0; k < K; ++k) v[k] += part[8 + 4 * c + k];
+    for (int k = 0; k < K; ++k) tot[k] = block_sum(v[k], red);
+}
+
+__global__ __launch_bounds__(kStatT) void k_core_centre(int64_t nc, double* __restrict__ part,
+                                                        double* __restrict__ out) {
+#pragma clang fp contract(off)
+    __shared__ double red[kStatT];
+    double tot[4];
+    chunk_totals<4>(nc, part, red, tot);
+    if (threadIdx.x == 0) {
+        part[0] = tot[0];
+        out[0] = tot[1] / tot[0];
+        out[1] = tot[2] / tot[0];
+        out[2] = tot[3] / tot[0];
+    }
+}
+
+__global__ __launch_bounds__(kStatT) void k_core_sum2(int64_t n, int64_t ns, const int32_t* __restrict__ sample,
+                                                      const double* __restrict__ pos,
+                                                      const double* __restrict__ rho,
+                                                      const double* __restrict__ out, double* __restrict__ part) {
+#pragma clang fp contract(off)
+    __shared__ double red[kStatT];
+    const double xd = out[0], yd = out[1], zd = out[2];
+    int64_t iv[kStatB];
+    double rv[kStatB], xv[kStatB], yv[kStatB], zv[kStatB];
+    chunk_samples(n, ns, sample, pos, rho, blockIdx.x, threadIdx.x, iv, rv, xv, yv, zv);
     double s2 = 0, s2d = 0;
-    for (int64_t s0 = t; s0 < ns; s0 += (int64_t)kStatT * kStatB) {
-        int64_t iv[kStatB];
-        double rv[kStatB], xv[kStatB], yv[kStatB], zv[kStatB];
 #pragma unroll
-        for (int u = 0; u < kStatB; ++u) {
-            const int64_t s = s0 + (int64_t)kStatT * u;
-            iv[u] = s < ns ? (int64_t)sample[s] : -1;
-        }
-#pragma unroll
-        for (int u = 0; u < kStatB; ++u) {
-            const bool ok = (uint64_t)iv[u] < (uint64_t)n;
-            const int64_t i = ok ? iv[u] : 0;
-            rv[u] = ok ? rho[s0 + (int64_t)kStatT * u] : 0.0;
-            xv[u] = pos[3 * i];
-            yv[u] = pos[3 * i + 1];
-            zv[u] = pos[3 * i + 2];
-        }
-#pragma unroll
-        for (int u = 0; u < kStatB; ++u) {
-            if ((uint64_t)iv[u] >= (uint64_t)n) continue;
-            const double r = rv[u];
-            const double dx = xv[u] - xd, dy = yv[u] - yd, dz = zv[u] - zd;
-            const double dd = dx * dx + dy * dy + dz * dz;
-            s2 += r * r;
-            s2d += r * r * dd;
-        }
+    for (int u = 0; u < kStatB; ++u) {
+        if (iv[u] < 0) continue;
+        const double r = rv[u];
+        const double dx = xv[u] - xd, dy = yv[u] - yd, dz = zv[u] - zd;
+        const double dd = dx * dx + dy * dy + dz * dz;
+        s2 += r * r;
+        s2d += r * r * dd;
     }
     s2 = block_sum(s2, red);
     s2d = block_sum(s2d, red);
-    if (t == 0) {
-        out[0] = xd;
-        out[1] = yd;
-        out[2] = zd;
-        out[3] = s2 / sr;           // rho_core
-        out[4] = sqrt(s2d / s2);    // r_c
+    if (threadIdx.x == 0) {
+        double* q = part + 8 + 4 * (int64_t)blockIdx.x;
+        q[0] = s2; q[1] = s2d;
+    }
+}
+
+__global__ __launch_bounds__(kStatT) void k_core_radius(int64_t nc, const double* __restrict__ part,
+                                                        double* __restrict__ out) {
+#pragma clang fp contract(off)
+    __shared__ double red[kStatT];
+    double tot[2];
+    chunk_totals<2>(nc, part, red, tot);
+    if (threadIdx.x == 0) {
+        out[3] = tot[0] / part[0];        // rho_core
+        out[4] = sqrt(tot[1] / tot[0]);   // r_c
     }
 }
 
@@ -440,8 +481,13 @@ void launch_core(const CoreLaunch& c, hipStream_t s) {
     p.rho = c.rho;
     p.err = c.err;
     hipLaunchKernelGGL(k_core_knn, dim3((unsigned)c.ns), dim3(64), 0, s, p);
-    hipLaunchKernelGGL(k_core_stats, dim3(1), dim3(kStatT), 0, s, n, c.ns, c.sample, c.pos, (const double*)c.rho,
-                       c.stats);
+    const int64_t nc = (c.ns + kStatCh - 1) / kStatCh;   // sample chunks (ns >= 1)
+    hipLaunchKernelGGL(k_core_sum1, dim3((unsigned)nc), dim3(kStatT), 0, s, n, c.ns, c.sample, c.pos,
+                       (const double*)c.rho, c.bsum);
+    hipLaunchKernelGGL(k_core_centre, dim3(1), dim3(kStatT), 0, s, nc, c.bsum, c.stats);
+    hipLaunchKernelGGL(k_core_sum2, dim3((unsigned)nc), dim3(kStatT), 0, s, n, c.ns, c.sample, c.pos,
+                       (const double*)c.rho, (const double*)c.stats, c.bsum);
+    hipLaunchKernelGGL(k_core_radius, dim3(1), dim3(kStatT), 0, s, nc, (const double*)c.bsum, c.stats);
     const int64_t nb = (n + 255) / 256;
     hipLaunchKernelGGL(k_core_dist, dim3((unsigned)(nb < kDistGrid ? nb : kDistGrid)), dim3(256), 0, s, n, c.pos,
                        (const double*)c.stats, c.keys, c.ncore);
@@ -454,6 +500,11 @@ void launch_core(const CoreLaunch& c, hipStream_t s) {
                        (const unsigned long long*)c.ncore, c.eta, c.stats);
 }
 
-int64_t core_bsum_len(int64_t n) { return (n + kCrossBlk - 1) / kCrossBlk; }
+// the cross-block sums of the half-mass search, and before them the sample
+// sums' chunk totals (n >= the sample size)
+int64_t core_bsum_len(int64_t n) {
+    const int64_t a = (n + kCrossBlk - 1) / kCrossBlk, b = 8 + 4 * ((n + kStatCh - 1) / kStatCh);
+    return a > b ? a : b;
+}
 
 }  // namespace pbh
